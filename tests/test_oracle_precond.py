@@ -1,0 +1,206 @@
+"""Pins for the oracle's preconditioner (Sec. 3) and PCG (Sec. 3.1, 4.1).
+
+P (Sec. 3.4): its range is exactly V_h intersected with H^1_0, checked
+against the null space of an independently built jump/trace operator (exact
+rational polynomials on the face quadrature points, tests/brute_exact.py);
+dim V_C = (N p - 1)^d on uniform meshes; P^T A P = P^T A^ P (jumps vanish).
+LOR (Sec. 3.4): p = 1 gives A~_K = A^_K; A~_K annihilates constants;
+kappa(A~_C^{-1} A_C) stays bounded in p (Prop. lor-conditioning).
+Labels (Sec. 3.3): conforming or h-refined meshes need no V_e (Sec. 1,
+Table 3 first row); the Fig. 1 configuration does.
+B (Sec. 3.1): symmetric positive definite; kappa(BA) bounded in eta for
+B_B + B_C while J_B + B_C grows (Thm. conditioning, Sec. 4.4).
+"""
+from fractions import Fraction as Fr
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import hpinputs as H
+import oracle as O
+from oracle import dg, pcg, precond
+
+import brute_exact
+
+
+def _jump_matrix_exact(md):
+    """Rows: [[phi]] at exact points of every face (and the trace on boundary
+    faces), evaluated from exact polynomials. Enough points per face (p_max+1
+    per direction) that a zero row set means a zero jump."""
+    X = brute_exact.ExactMesh(md)
+    rows = []
+    for (m, lo, hi, a, b, sgn) in X.faces():
+        tdims = [t for t in range(X.d) if t != m]
+        pts1 = [[lo[t] + (hi[t] - lo[t]) * Fr(j, 4) for j in range(5)] for t in tdims]
+        import itertools
+        for pt in itertools.product(*pts1):
+            x = [None] * X.d
+            x[m] = lo[m]
+            for t, v in zip(tdims, pt):
+                x[t] = v
+            row = np.zeros(X.n)
+            for e, s in ([(a, 1)] if b is None else [(a, 1), (b, -1)]):
+                for i, f in enumerate(X.basis[e]):
+                    row[X.off[e] + i] = s * float(f.integrate_box(x, x))
+            rows.append(row)
+    return np.array(rows)
+
+
+@pytest.mark.parametrize("case", ["fig1", "hang2", "hang3"])
+def test_prolongation_spans_conforming_space(case):
+    md = {"fig1": H.fig1_mesh(2, 2, 1),
+          "hang2": H.hanging_mesh(2, 3, pmin=1, pmax=2, seed=4),
+          "hang3": H.hanging_mesh(3, 1, pmin=1, pmax=2, seed=1)}[case]
+    m = O.Mesh(md)
+    P, nc = precond.prolongation(m)
+    J = _jump_matrix_exact(md)
+    s = np.linalg.svd(J, compute_uv=False)
+    null = m.ndof - int(np.sum(s > 1e-10 * s[0]))
+    assert nc == null
+    Pd = P.toarray()
+    assert np.abs(J @ Pd).max() < 1e-13
+    assert np.linalg.matrix_rank(Pd, tol=1e-10) == nc
+
+
+@pytest.mark.parametrize("d,n,p", [(2, 3, 1), (2, 3, 4), (3, 2, 2)])
+def test_conforming_dimension_uniform(d, n, p):
+    m = O.Mesh(H.uniform_mesh(d, n, p))
+    P, nc = precond.prolongation(m)
+    assert nc == (n * p - 1) ** d
+    assert np.all(np.diff(P.indptr) >= 0)
+
+
+def test_variational_restriction_identity():
+    md = H.random_mesh(2, 2, 0.5, 2, 1, 4, seed=3)
+    m = O.Mesh(md)
+    A = dg.assemble_dense(m, O.Opts("sipg", 0, 1.0))
+    P, _ = precond.prolongation(m)
+    Ah = precond.broken_stiffness(m).toarray()
+    Pd = P.toarray()
+    assert np.allclose(Pd.T @ A @ Pd, Pd.T @ Ah @ Pd, rtol=1e-12, atol=1e-11)
+
+
+def test_lor_element():
+    for d in (2, 3):
+        m1 = O.Mesh(H.uniform_mesh(d, 1, 1))
+        assert np.allclose(precond.lor_elem(m1, 0), dg.elem_matrix(m1, 0), atol=1e-14)
+        for p in (2, 5):
+            m = O.Mesh(H.uniform_mesh(d, 1, p))
+            At = precond.lor_elem(m, 0)
+            assert np.abs(At @ np.ones(At.shape[0])).max() < 1e-12
+            assert np.allclose(At, At.T)
+
+
+def test_lor_spectral_equivalence_bounded_in_p():
+    ks = []
+    for p in range(1, 9):
+        m = O.Mesh(H.uniform_mesh(2, 2, p))
+        P, _ = precond.prolongation(m)
+        Ac = (P.T @ precond.broken_stiffness(m) @ P).toarray()
+        At = (P.T @ precond.lor_matrix(m) @ P).toarray()
+        ev = sla.eigh(Ac, At, eigvals_only=True)
+        ks.append(ev[-1] / ev[0])
+    # bounded (the 1D FEM-SEM constant is pi^2/4; its square bounds the tensor
+    # case) and saturating in p
+    assert max(ks) < (np.pi ** 2 / 4) ** 2, ks
+    assert ks[7] - ks[6] < 0.5 * (ks[2] - ks[1]), ks
+
+
+def test_labels_special_cases():
+    # conforming, uniform p; conforming, variable p; h-refinement, uniform p
+    for md in (H.uniform_mesh(2, 3, 3), H.random_mesh(2, 3, 0.0, 0, 1, 6, seed=2),
+               H.random_mesh(2, 3, 0.5, 3, 2, 2, seed=2), H.random_mesh(3, 2, 0.5, 1, 2, 2, seed=2)):
+        m = O.Mesh(md)
+        inJ, inN = precond.labels(m)
+        assert inN.sum() == 0
+    # Fig. 1: coarse p=2 beside fine p=1 leaves: the interface needs V_e
+    m = O.Mesh(H.fig1_mesh(2))
+    inJ, inN = precond.labels(m)
+    blocks = precond.edge_spaces(m, inN)
+    assert len(blocks) == 1 and len(blocks[0]) == inN.sum() > 0
+    # nodes on the coarse leaf's right side, except its two corners, are in N
+    coarse = [e for e in range(m.ne) if m.p[e] == 2][0]
+    ni = m.node_index(coarse)
+    g = m.dofs(coarse)[(ni[:, 0] == 2) & (ni[:, 1] == 1)]
+    assert inN[g].all()
+    # interior DOFs are in neither space
+    ni = m.node_index(coarse)
+    assert not (inJ | inN)[m.dofs(coarse)[(ni[:, 0] == 1) & (ni[:, 1] == 1)]].any()
+
+
+def test_edge_spaces_have_disjoint_jump_support():
+    m = O.Mesh(H.random_mesh(2, 3, 0.4, 2, 1, 5, seed=4))
+    inJ, inN = precond.labels(m)
+    blocks = precond.edge_spaces(m, inN)
+    owner = -np.ones(m.ndof, dtype=int)
+    for b, idx in enumerate(blocks):
+        assert (owner[idx] < 0).all()
+        owner[idx] = b
+    assert (owner >= 0).sum() == inN.sum()
+    for f in m.faces:
+        seen = set()
+        sides = [(f["em"], 1), (f["ep"], 0)] if f["ep"] >= 0 else [(f["em"], f["side"])]
+        for e, up in sides:
+            ni = m.node_index(e)
+            sel = ni[:, f["m"]] == (m.p[e] if up else 0)
+            seen |= {int(owner[g]) for g in m.dofs(e)[sel] if owner[g] >= 0}
+        assert len(seen) <= 1
+
+
+def test_amg_symmetric_spd_and_exact_two_level():
+    m = O.Mesh(H.random_mesh(2, 4, 0.3, 2, 1, 4, seed=6))
+    P, _ = precond.prolongation(m)
+    Ac = (P.T @ precond.lor_matrix(m) @ P).tocsr()
+    amg = precond.AMG(Ac, min_rows=60)
+    assert len(amg.A) >= 2
+    n = Ac.shape[0]
+    V = np.column_stack([amg.vcycle(e) for e in np.eye(n)])
+    assert np.abs(V - V.T).max() < 1e-12 * np.abs(V).max()
+    ev = np.linalg.eigvals(V @ Ac.toarray()).real
+    assert ev.min() > 0 and ev.max() < 2.0 + 1e-9
+    one = precond.AMG(Ac, min_rows=10 ** 9)
+    assert len(one.A) == 1
+    b = np.random.default_rng(0).standard_normal(n)
+    assert np.allclose(Ac @ one.vcycle(b), b, atol=1e-10)
+    # aggregates partition the rows
+    agg, na = precond.aggregate(Ac)
+    assert agg.min() == 0 and agg.max() == na - 1 and len(np.unique(agg)) == na
+
+
+def _kappa(md, eta, variant, coarse="exact", rule=1):
+    m = O.Mesh(md)
+    opts = O.Opts("sipg", rule, eta)
+    pc = precond.Preconditioner(m, opts, variant=variant, coarse=coarse)
+    A = dg.assemble_dense(m, opts)
+    Bm = np.column_stack([pc.apply(e) for e in np.eye(m.ndof)])
+    assert np.abs(Bm - Bm.T).max() < 1e-11 * np.abs(Bm).max()
+    np.linalg.cholesky(Bm)
+    ev = np.sort(sla.eigvals(Bm @ A).real)
+    return ev[-1] / ev[0]
+
+
+def test_theorem_conditioning_eta_independent():
+    md = H.random_mesh(2, 3, 0.4, 2, 1, 5, seed=4)
+    full = [_kappa(md, eta, "full") for eta in (10.0, 1000.0)]
+    jb = [_kappa(md, eta, "jb") for eta in (10.0, 1000.0)]
+    assert full[1] < 1.5 * full[0] and full[1] < 80
+    assert jb[1] > 20 * jb[0]
+
+
+def test_pcg_and_lanczos():
+    md = H.random_mesh(2, 3, 0.4, 2, 1, 4, seed=8)
+    m = O.Mesh(md)
+    opts = O.Opts("sipg", 0, 1.0)
+    pc = precond.Preconditioner(m, opts)
+    A = dg.assemble_dense(m, opts)
+    b = dg.rhs(m, H.gaussian_rhs(m.ndof, 3))
+    x, info = pcg.pcg(lambda v: A @ v, pc.apply, b, rtol=1e-12, maxit=500)
+    assert info["converged"]
+    assert np.linalg.norm(A @ x - b) <= 1e-11 * np.linalg.norm(b)
+    Bm = np.column_stack([pc.apply(e) for e in np.eye(m.ndof)])
+    ev = np.sort(sla.eigvals(Bm @ A).real)
+    assert abs(info["lambda_max"] / ev[-1] - 1) < 1e-6
+    assert abs(info["lambda_min"] / ev[0] - 1) < 1e-3
+    with pytest.raises(FloatingPointError):
+        pcg.pcg(lambda v: -(A @ v), pc.apply, b, rtol=1e-8, maxit=10)
