@@ -1,0 +1,138 @@
+/* hpdg.h -- C ABI of the MI355X hp-DG subspace-correction solver.
+ *
+ * Problem (Sec. 2, eq. fe-problem): find u_h in V_h with A(u_h, v) = (f, v)
+ * for all v in V_h, V_h the discontinuous space of tensor polynomials of
+ * degree p_K on each leaf K of an irregular quadtree (2D) / octree (3D) mesh
+ * of [0,1]^d, A the SIPG form (Sec. 2) or the BR2 form (Sec. 4.4) of
+ * -div(k grad u) = f with homogeneous Dirichlet data. The system is solved
+ * by CG (Sec. 4.1) preconditioned with B = B_J + B_E + P T_C P^T (Sec. 3.1,
+ * eq. TB, Sec. 3.4): point Jacobi on V_J, exact block solves on the V_e,
+ * and one AMG V-cycle on the low-order-refined conforming matrix.
+ *
+ * Conventions (all entry points):
+ *  - Return value: HPDG_OK (0) or a negative hpdg_status; hpdg_last_error()
+ *    gives a message for the calling thread. Argument errors are detected
+ *    before any device work is queued.
+ *  - Vectors passed to the operator calls are DEVICE pointers owned by the
+ *    caller; the library never frees them. DOFs are element-major in input
+ *    leaf order; inside an element the Gauss-Lobatto nodes are ordered
+ *    lexicographically with x fastest. With nrhs > 1 vectors are
+ *    RHS-interleaved: v[dof * nrhs + r].
+ *  - stream: a hipStream_t passed as void*; NULL means the null stream.
+ *    Calls are stream-ordered. A handle is not thread-safe.
+ *  - Mesh input arrays are HOST pointers, copied during the call.
+ */
+#ifndef HPDG_H
+#define HPDG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HPDG_OK = 0,
+  HPDG_E_INVALID = -1,       /* bad argument or mesh */
+  HPDG_E_NOMEM = -2,         /* host or device allocation failed */
+  HPDG_E_HIP = -3,           /* HIP runtime error */
+  HPDG_E_NOT_SPD = -4,       /* CG breakdown: p'Ap <= 0 or r'z <= 0 */
+  HPDG_E_NOT_CONVERGED = -5, /* maxit reached */
+  HPDG_E_UNSUPPORTED = -6
+} hpdg_status;
+
+typedef struct hpdg_mesh hpdg_mesh;
+typedef struct hpdg_operator hpdg_operator;
+
+const char* hpdg_last_error(void);
+
+/* Mesh of leaves (Sec. 2: elements K with affine maps T_K and degree p_K;
+ * Sec. 4.3: piecewise-constant coefficient).
+ *  dim     2 or 3
+ *  n_base  the base grid has n_base^dim cells on [0,1]^dim
+ *  level   [n_elem] refinement level >= 0
+ *  anchor  [n_elem*dim] lower corner in units of 1/(n_base*2^level)
+ *  degree  [n_elem] polynomial degree, 1..8
+ *  kcoef   [n_elem] coefficient k > 0
+ * Validation: the leaves must tile [0,1]^dim exactly (no overlap, no gap).
+ * On success *out owns a host-side topology (faces, neighbours). */
+hpdg_status hpdg_setup_mesh(int dim, int n_base, int64_t n_elem, const int32_t* level,
+                            const int32_t* anchor, const int32_t* degree, const double* kcoef,
+                            hpdg_mesh** out);
+/* ndof: number of DG unknowns; nface: faces of the skeleton (Sec. 2,
+ * sub-faces counted separately, boundary faces included); max_level_jump:
+ * largest level difference across a face. Any output pointer may be NULL. */
+hpdg_status hpdg_mesh_info(const hpdg_mesh* mesh, int64_t* ndof, int64_t* nface, int* max_level_jump);
+void hpdg_mesh_destroy(hpdg_mesh* mesh);
+
+typedef struct {
+  int form;          /* 0 SIPG (Sec. 2), 1 BR2 (Sec. 4.4) */
+  int penalty_rule;  /* SIPG sigma = eta*k_e*pi(p_e)/h_e: 0 -> pi = (p+1)^2, 1 -> pi = p^2 (Sec. 2) */
+  double eta;        /* SIPG eta; BR2 eta (<= 0: 1 + largest face count of an element) */
+  int prec_fp32;     /* 0: FP64 preconditioner; 1: FP32 preconditioner, FP64 CG */
+  int remark_relax;  /* 1: add the Remark-cases DOFs to V_J (Sec. 3.3); default 0 */
+  int jb_only;       /* 1: simplified J_B + B_C (Sec. 4.1): point Jacobi on all of V_B */
+  int max_block;     /* > 0: a V_e larger than this is handled by point Jacobi */
+  int max_nrhs;      /* >= 1 and a divisor of 256: largest nrhs accepted by the operator calls */
+  int host_only;     /* 1: build only the host-side setup data (readable with hpdg_export) and
+                        touch no GPU; the operator calls then fail with HPDG_E_UNSUPPORTED */
+} hpdg_operator_opts;
+
+/* Builds the operator and the preconditioner (host setup, then upload):
+ * faces and penalties, diag(A) and the V_J / V_e split (Sec. 3.3), the V_e
+ * blocks and their inverses, the conforming prolongation P (Sec. 3.4), the
+ * LOR matrix A~_C = P^T A~ P and its AMG hierarchy. The mesh may be destroyed
+ * afterwards. The operator owns all its device memory until destroy. */
+hpdg_status hpdg_setup_operator(const hpdg_mesh* mesh, const hpdg_operator_opts* opts, void* stream,
+                                hpdg_operator** out);
+void hpdg_operator_destroy(hpdg_operator* op);
+
+/* b = M f: load vector (f, v) of Sec. 2 for f given by its values at the DG
+ * nodes (exact element mass matrices). f_nodal, b: device, ndof*nrhs. */
+hpdg_status hpdg_rhs(hpdg_operator* op, const double* f_nodal, double* b, int nrhs, void* stream);
+
+/* y = A x: matrix-free DG operator (Sec. 4.1, component 1): sum-factorised
+ * volume terms and the SIPG/BR2 face terms, FP64. x, y: device, ndof*nrhs,
+ * must not alias. */
+hpdg_status hpdg_apply_A(hpdg_operator* op, const double* x, double* y, int nrhs, void* stream);
+
+/* z = B r (Sec. 3.1 with eq. TB; Sec. 4.1 components 2-5), in the operator's
+ * preconditioner precision, inputs and outputs FP64. r, z: device,
+ * ndof*nrhs, must not alias. */
+hpdg_status hpdg_apply_B(hpdg_operator* op, const double* r, double* z, int nrhs, void* stream);
+
+typedef struct {
+  int iters, converged;
+  double rel_res;       /* recurrence residual ||r_k|| / ||b|| */
+  double true_rel_res;  /* ||b - A x|| / ||b|| recomputed in FP64 at the end */
+  double lambda_min, lambda_max, cond_est;  /* Lanczos from the CG coefficients */
+  double t_solve_s;
+} hpdg_solve_info;
+
+/* PCG (Sec. 4.1) on T = BA, stopping at ||r_k||_2 <= rtol ||b||_2 (per RHS).
+ * x holds the initial guess on entry and the result on exit (device,
+ * ndof*nrhs). Blocks the host until done. info: host array [nrhs] or NULL.
+ * Returns HPDG_E_NOT_SPD on a breakdown and HPDG_E_NOT_CONVERGED at maxit
+ * (x then holds the last iterate and info is filled). */
+hpdg_status hpdg_pcg_solve(hpdg_operator* op, const double* b, double* x, int nrhs, double rtol, int maxit,
+                           void* stream, hpdg_solve_info* info);
+
+/* Host copies of setup data, for tests. what:
+ *  0 diag(A) [ndof] double      1 labels [ndof] int8 (0 interior, 1 V_J, 2 N)
+ *  2 P as CSR: int64 nrows, ncols, nnz, then ptr[nrows+1] int64,
+ *    idx[nnz] int32, val[nnz] double
+ *  3 A~_C as CSR (same layout)  4 V_e blocks: int64 nblocks, ptr[nb+1] int64,
+ *    dofs int64                 5 DG node coordinates [ndof*dim] double
+ *  6 AMG level sizes: int64 nlevels, rows[nlevels] int64
+ *  7 summary: int64[8] = ndof, nconf, nblocks, max block, block entries,
+ *    amg levels, nnz(A~_C), nnz(P)
+ *  100+l  AMG level-l matrix A_l as CSR;  200+l  AMG prolongator P_l as CSR;
+ *  300+l  aggregate index of every row of level l, int64
+ * bytes: in: capacity of buf; out: bytes needed. buf NULL queries the size. */
+hpdg_status hpdg_export(const hpdg_operator* op, int what, void* buf, size_t* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HPDG_H */

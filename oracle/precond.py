@@ -333,7 +333,7 @@ THETA = 0.08
 TIE = 1e-10
 
 
-def aggregate(A):
+def aggregate(A, theta=None):
     """Three-phase greedy aggregation in natural row order.
     Strength: j in S_i iff j != i and |a_ij| >= THETA sqrt(a_ii a_jj).
     Phase 1: a free row whose strong neighbours are all free forms {i} + S_i.
@@ -341,6 +341,7 @@ def aggregate(A):
              phase-1-aggregated neighbour (|a_ij| within relative TIE of the
              maximum count as ties; ties go to the lowest aggregate id).
     Phase 3: a still free row forms {i} + its free strong neighbours."""
+    theta = THETA if theta is None else theta
     A = A.tocsr()
     n = A.shape[0]
     dg_ = A.diagonal()
@@ -349,7 +350,7 @@ def aggregate(A):
         cols = A.indices[A.indptr[i]:A.indptr[i + 1]]
         vals = A.data[A.indptr[i]:A.indptr[i + 1]]
         s = [(int(j), abs(v)) for j, v in zip(cols, vals)
-             if j != i and abs(v) >= THETA * np.sqrt(dg_[i] * dg_[j])]
+             if j != i and abs(v) >= theta * np.sqrt(dg_[i] * dg_[j])]
         strong.append(s)
     agg = -np.ones(n, dtype=np.int64)
     na = 0
@@ -380,11 +381,36 @@ def aggregate(A):
     return agg, na
 
 
+def filtered(A, theta):
+    """Filtered matrix of smoothed aggregation: weak off-diagonal entries
+    (|a_ij| < theta sqrt(a_ii a_jj)) are dropped and added to the diagonal,
+    so row sums are kept."""
+    A = A.tocsr()
+    n = A.shape[0]
+    d = A.diagonal()
+    rows, cols, vals = [], [], []
+    lump = np.zeros(n)
+    for i in range(n):
+        for q in range(A.indptr[i], A.indptr[i + 1]):
+            j, v = int(A.indices[q]), A.data[q]
+            if j == i or abs(v) >= theta * np.sqrt(d[i] * d[j]):
+                rows.append(i)
+                cols.append(j)
+                vals.append(v)
+            else:
+                lump[i] += v
+    F = sp.csr_matrix((vals, (rows, cols)), shape=A.shape) + sp.diags(lump)
+    return F.tocsr()
+
+
 class AMG:
-    """Smoothed aggregation: P_l = (I - w D^{-1} A) P^_l with P^ the 0/1
-    aggregate indicator, w = (4/3)/rho, rho = max_i sum_j |a_ij|/a_ii;
-    A_{l+1} = P_l^T A_l P_l. Stop at n <= 256, 12 levels, or when a coarse
-    level would keep more than 0.8 of the rows. Coarsest level: dense
+    """Smoothed aggregation with a filtered smoother:
+    P_l = (I - w D_F^{-1} A_F) P^_l, P^ the 0/1 aggregate indicator, A_F the
+    filtered matrix (rows whose filtered diagonal is at most 1e-8 a_ii, e.g. a
+    structural zero from a zero row sum, are not smoothed), w = (4/3)/rho, rho = max_i sum_j |a^F_ij| / a^F_ii;
+    A_{l+1} = P_l^T A_l P_l. A level that would keep more than 0.8 of its
+    rows is retried with theta halved, at most twice; if it still stalls,
+    or at n <= 256 or 12 levels, coarsening stops. Coarsest level: dense
     Cholesky. Smoother: l1-Jacobi (d_i = sum_j |a_ij|), one pre- and one
     post-sweep from a zero initial guess. The V(1,1) cycle is symmetric."""
 
@@ -397,14 +423,22 @@ class AMG:
             n = Al.shape[0]
             if n <= min_rows or len(self.A) >= max_levels:
                 break
-            agg, na = aggregate(Al)
+            theta = THETA
+            for _ in range(3):
+                agg, na = aggregate(Al, theta)
+                if na <= max_ratio * n:
+                    break
+                theta *= 0.5
             if na > max_ratio * n:
                 break
             Ph = sp.csr_matrix((np.ones(n), (np.arange(n), agg)), shape=(n, na))
-            d = Al.diagonal()
-            rho = np.max(np.asarray(abs(Al).sum(axis=1)).ravel() / d)
+            F = filtered(Al, theta)
+            d = F.diagonal()
+            ok = d > 1e-8 * Al.diagonal()     # zero row sums lump to a structural 0
+            dinv = np.where(ok, 1.0 / np.where(ok, d, 1.0), 0.0)
+            rho = np.max(np.asarray(abs(F).sum(axis=1)).ravel() * dinv)
             w = (4.0 / 3.0) / rho
-            Pl = (Ph - w * sp.diags(1.0 / d) @ Al @ Ph).tocsr()
+            Pl = (Ph - w * sp.diags(dinv) @ F @ Ph).tocsr()
             Pl.eliminate_zeros()
             Ac = (Pl.T @ Al @ Pl).tocsr()
             self.P.append(Pl)

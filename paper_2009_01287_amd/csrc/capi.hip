@@ -1,0 +1,873 @@
+// C ABI of the hp-DG solver: setup, operator applications, PCG (see
+// include/hpdg.h for the contract of every entry point).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <memory>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "../../include/hpdg.h"
+#include "internal.hpp"
+#include "kernels.hip"
+
+using namespace hpdg;
+
+static thread_local std::string g_err;
+
+extern "C" const char* hpdg_last_error(void) { return g_err.c_str(); }
+
+static hpdg_status fail(int code, const std::string& msg) {
+  g_err = msg;
+  return (hpdg_status)code;
+}
+
+#define HIPCHK(x)                                                                      \
+  do {                                                                                 \
+    hipError_t _e = (x);                                                               \
+    if (_e != hipSuccess) throw Error(HPDG_E_HIP, std::string(#x) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+struct hpdg_mesh {
+  std::unique_ptr<Mesh> M;
+  int64_t anchor_n;
+  std::vector<int32_t> level, anchor, degree;
+  std::vector<double> kcoef;
+  int dim, n_base;
+};
+
+namespace {
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) {
+      if (p) (void)hipFree(p);
+      p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0;
+    }
+    return *this;
+  }
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  void alloc(size_t b) {
+    if (p) { (void)hipFree(p); p = nullptr; }
+    bytes = b;
+    if (b == 0) return;
+    hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess) throw Error(HPDG_E_NOMEM, "hipMalloc of " + std::to_string(b) + " bytes failed");
+  }
+  template <typename T>
+  void upload(const std::vector<T>& v) {
+    alloc(v.size() * sizeof(T));
+    if (!v.empty()) HIPCHK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  }
+  template <typename T>
+  T* as() const { return (T*)p; }
+};
+
+struct DevCSR {
+  int nrows = 0, ncols = 0;
+  int64_t nnz = 0;
+  int lpr = 1;
+  DevBuf ptr, idx, val;
+};
+
+template <typename T>
+void upload_csr(const CSR& A, DevCSR& D) {
+  if (A.idx.size() > (size_t)INT32_MAX) throw Error(HPDG_E_UNSUPPORTED, "matrix too large");
+  D.nrows = (int)A.nrows;
+  D.ncols = (int)A.ncols;
+  D.nnz = (int64_t)A.idx.size();
+  std::vector<int32_t> p32(A.ptr.begin(), A.ptr.end());
+  std::vector<T> v(A.val.begin(), A.val.end());
+  D.ptr.upload(p32);
+  D.idx.upload(A.idx);
+  D.val.upload(v);
+  double avg = D.nrows ? (double)D.nnz / D.nrows : 0;
+  D.lpr = avg > 48 ? 16 : avg > 20 ? 8 : avg > 6 ? 4 : 1;
+}
+
+struct PrecHost {
+  std::vector<double> diag, dinvJ;
+  std::vector<int8_t> lab;
+  std::vector<std::vector<int64_t>> blocks;
+  CSR P, PT, AC;
+  AMGHier amg;
+};
+
+struct LevelDev {
+  DevCSR A, P, R;
+  DevBuf l1inv;          // T
+  DevBuf b, x, r, t;     // T, nrows * max_nrhs
+};
+
+}  // namespace
+
+struct hpdg_operator {
+  int dim = 2, ne = 0, max_nrhs = 1, form = 0, prec32 = 0, host_only = 0;
+  int64_t ndof = 0, nconf = 0;
+  hpdg_operator_opts opts{};
+  // element data
+  DevBuf off, pdeg, hh, kk, sptr, recs, tab;
+  TableLayout TL{};
+  std::vector<std::vector<int32_t>> bucket;  // host: elements per degree
+  std::vector<DevBuf> dbucket;               // device copies (index p)
+  // preconditioner (type T = float or double per prec32)
+  DevBuf dinvJ;
+  DevBuf blk_rowb, blk_rowl, blk_ptr, blk_off, blk_dof, blk_inv;
+  int64_t blk_rows = 0;
+  DevCSR P, PT;
+  std::vector<LevelDev> lv;
+  DevBuf coarse;
+  int ncoarse = 0;
+  DevBuf rT, zT, rc;       // T work vectors (DG and conforming sizes)
+  // CG work (double)
+  DevBuf r, z, pv, Ap, part, scal, act, ahist, bhist;
+  PrecHost host;           // kept for export
+  std::vector<double> coords;
+};
+
+// ---------------------------------------------------------------- helpers
+static inline unsigned nblk(int64_t n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
+
+extern "C" hpdg_status hpdg_setup_mesh(int dim, int n_base, int64_t n_elem, const int32_t* level,
+                                       const int32_t* anchor, const int32_t* degree, const double* kcoef,
+                                       hpdg_mesh** out) {
+  if (!out || !level || !anchor || !degree || !kcoef) return fail(HPDG_E_INVALID, "null argument");
+  *out = nullptr;
+  try {
+    auto* h = new hpdg_mesh();
+    h->M.reset(make_mesh(dim, n_base, n_elem, level, anchor, degree, kcoef));
+    h->dim = dim;
+    h->n_base = n_base;
+    h->level.assign(level, level + n_elem);
+    h->anchor.assign(anchor, anchor + n_elem * dim);
+    h->degree.assign(degree, degree + n_elem);
+    h->kcoef.assign(kcoef, kcoef + n_elem);
+    *out = h;
+    return HPDG_OK;
+  } catch (Error& e) {
+    return fail(e.code, e.what());
+  } catch (std::bad_alloc&) {
+    return fail(HPDG_E_NOMEM, "host allocation failed");
+  }
+}
+
+extern "C" hpdg_status hpdg_mesh_info(const hpdg_mesh* m, int64_t* ndof, int64_t* nface, int* jump) {
+  if (!m) return fail(HPDG_E_INVALID, "null mesh");
+  if (ndof) *ndof = m->M->ndof;
+  if (nface) *nface = (int64_t)m->M->faces.size();
+  if (jump) *jump = m->M->max_dlevel;
+  return HPDG_OK;
+}
+
+extern "C" void hpdg_mesh_destroy(hpdg_mesh* m) { delete m; }
+
+// code of the sub-interval [a, b] (finest units) inside [lo, lo+sz]
+static uint8_t sub_code(int64_t a, int64_t b, int64_t lo, int64_t sz) {
+  int64_t len = b - a;
+  int delta = 0;
+  while ((sz >> delta) > len) ++delta;
+  int64_t idx = (a - lo) / len;
+  return (uint8_t)((1 << delta) + idx);
+}
+
+static void build_tables(hpdg_operator* op, int max_delta) {
+  TableLayout& L = op->TL;
+  L.ncode = 1 << (max_delta + 1);
+  if (L.ncode > 256) throw Error(HPDG_E_UNSUPPORTED, "level jump across a face larger than 7");
+  std::vector<double> T;
+  L.interp = 0;
+  T.assign((size_t)8 * 8 * L.ncode * 81, 0.0);
+  for (int p = 1; p <= kMaxP; ++p) {
+    const Basis1D& B = basis(p);
+    for (int q = 2; q <= 9; ++q) {
+      std::vector<double> gx, gw;
+      gauss_rule(q, gx, gw);
+      for (int code = 1; code < L.ncode; ++code) {
+        int delta = 0;
+        while ((2 << delta) <= code) ++delta;
+        int idx = code - (1 << delta);
+        double len = 1.0 / (double)(1 << delta), a = idx * len;
+        double* dst = &T[interp_index(L, p, q, code)];
+        for (int g = 0; g < q; ++g) lagrange_eval(B.x, a + len * gx[g], dst + g * (p + 1));
+      }
+    }
+  }
+  L.gw = (int64_t)T.size();
+  T.resize(T.size() + 100, 0.0);
+  for (int q = 2; q <= 9; ++q) {
+    std::vector<double> gx, gw;
+    gauss_rule(q, gx, gw);
+    for (int g = 0; g < q; ++g) T[L.gw + q * 10 + g] = gw[g];
+  }
+  L.dside = (int64_t)T.size();
+  T.resize(T.size() + 9 * 2 * 9, 0.0);
+  for (int p = 1; p <= kMaxP; ++p)
+    for (int i = 0; i <= p; ++i) {
+      T[L.dside + (p * 2 + 0) * 9 + i] = basis(p).D0[i];
+      T[L.dside + (p * 2 + 1) * 9 + i] = basis(p).D1[i];
+    }
+  L.minv = (int64_t)T.size();
+  T.resize(T.size() + 9 * 81, 0.0);
+  for (int p = 1; p <= kMaxP; ++p)
+    for (size_t i = 0; i < basis(p).Minv.size(); ++i) T[L.minv + p * 81 + i] = basis(p).Minv[i];
+  L.mk = 0;
+  L.total = (int64_t)T.size();
+  op->tab.upload(T);
+  // constant-memory M, K for the volume kernels
+  static double mk[9][2][81];
+  std::memset(mk, 0, sizeof(mk));
+  for (int p = 1; p <= kMaxP; ++p)
+    for (size_t i = 0; i < basis(p).M.size(); ++i) {
+      mk[p][0][i] = basis(p).M[i];
+      mk[p][1][i] = basis(p).K[i];
+    }
+  HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_MK), mk, sizeof(mk)));
+}
+
+static void spd_inverse(std::vector<double>& A, int n) {
+  // Cholesky then inverse; throws if not positive definite
+  std::vector<double> L(A);
+  for (int j = 0; j < n; ++j) {
+    double s = L[j * n + j];
+    for (int k = 0; k < j; ++k) s -= L[j * n + k] * L[j * n + k];
+    if (!(s > 0)) throw Error(HPDG_E_NOT_SPD, "V_e block is not positive definite");
+    double d = std::sqrt(s);
+    L[j * n + j] = d;
+    for (int i = j + 1; i < n; ++i) {
+      double t = L[i * n + j];
+      for (int k = 0; k < j; ++k) t -= L[i * n + k] * L[j * n + k];
+      L[i * n + j] = t / d;
+    }
+  }
+  std::vector<double> y(n);
+  for (int c = 0; c < n; ++c) {
+    for (int i = 0; i < n; ++i) {
+      double t = i == c ? 1.0 : 0.0;
+      for (int k = 0; k < i; ++k) t -= L[i * n + k] * y[k];
+      y[i] = t / L[i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      double t = y[i];
+      for (int k = i + 1; k < n; ++k) t -= L[k * n + i] * y[k];
+      y[i] = t / L[i * n + i];
+    }
+    for (int i = 0; i < n; ++i) A[i * n + c] = y[i];
+  }
+}
+
+template <typename T>
+static void upload_prec(hpdg_operator* op) {
+  PrecHost& H = op->host;
+  std::vector<T> dj(H.dinvJ.begin(), H.dinvJ.end());
+  op->dinvJ.upload(dj);
+  // blocks
+  std::vector<int32_t> rowb, rowl, bdof;
+  std::vector<int64_t> bptr{0}, boff{0};
+  std::vector<T> binv;
+  for (size_t b = 0; b < H.blocks.size(); ++b) {
+    const auto& B = H.blocks[b];
+    int m = (int)B.size();
+    for (int i = 0; i < m; ++i) { rowb.push_back((int32_t)b); rowl.push_back(i); bdof.push_back((int32_t)B[i]); }
+    bptr.push_back(bptr.back() + m);
+    boff.push_back(boff.back() + (int64_t)m * m);
+  }
+  op->blk_rows = (int64_t)rowb.size();
+  op->blk_rowb.upload(rowb);
+  op->blk_rowl.upload(rowl);
+  op->blk_ptr.upload(bptr);
+  op->blk_off.upload(boff);
+  op->blk_dof.upload(bdof);
+  // block inverses were computed in FP64 (binv64) during setup
+  op->blk_inv.alloc(0);
+  upload_csr<T>(H.P, op->P);
+  upload_csr<T>(H.PT, op->PT);
+  op->lv.clear();
+  op->lv.resize(H.amg.lv.size());
+  for (size_t l = 0; l < H.amg.lv.size(); ++l) {
+    const AMGLevel& L = H.amg.lv[l];
+    LevelDev& D = op->lv[l];
+    upload_csr<T>(L.A, D.A);
+    if (l + 1 < H.amg.lv.size()) {
+      upload_csr<T>(L.P, D.P);
+      upload_csr<T>(L.R, D.R);
+    }
+    std::vector<T> li(L.l1.size());
+    for (size_t i = 0; i < li.size(); ++i) li[i] = (T)(1.0 / L.l1[i]);
+    D.l1inv.upload(li);
+    size_t nb = (size_t)L.A.nrows * op->max_nrhs * sizeof(T);
+    D.b.alloc(nb);
+    D.x.alloc(nb);
+    D.r.alloc(nb);
+    D.t.alloc(nb);
+  }
+  std::vector<T> ci(H.amg.coarse_inv.begin(), H.amg.coarse_inv.end());
+  op->coarse.upload(ci);
+  op->ncoarse = (int)H.amg.nc;
+  op->rT.alloc((size_t)op->ndof * op->max_nrhs * sizeof(T));
+  op->zT.alloc((size_t)op->ndof * op->max_nrhs * sizeof(T));
+}
+
+extern "C" hpdg_status hpdg_setup_operator(const hpdg_mesh* mh, const hpdg_operator_opts* o, void* stream,
+                                          hpdg_operator** out) {
+  (void)stream;
+  if (!mh || !o || !out) return fail(HPDG_E_INVALID, "null argument");
+  *out = nullptr;
+  if (o->form != 0 && o->form != 1) return fail(HPDG_E_INVALID, "form must be 0 (SIPG) or 1 (BR2)");
+  if (o->form == 0 && !(o->eta > 0)) return fail(HPDG_E_INVALID, "SIPG needs eta > 0");
+  if (o->max_nrhs < 1 || o->max_nrhs > 256 || (256 % o->max_nrhs) != 0)
+    return fail(HPDG_E_INVALID, "max_nrhs must divide 256");
+  if (o->penalty_rule != 0 && o->penalty_rule != 1) return fail(HPDG_E_INVALID, "penalty_rule must be 0 or 1");
+  auto op = std::make_unique<hpdg_operator>();
+  try {
+    // a private copy of the mesh: entity tables are built lazily
+    std::unique_ptr<Mesh> Mp(make_mesh(mh->dim, mh->n_base, (int64_t)mh->level.size(), mh->level.data(),
+                                       mh->anchor.data(), mh->degree.data(), mh->kcoef.data()));
+    Mesh& M = *Mp;
+    if (M.ndof > (int64_t)INT32_MAX / 2) throw Error(HPDG_E_UNSUPPORTED, "too many DOFs");
+    op->opts = *o;
+    op->dim = M.dim;
+    op->ne = M.ne;
+    op->ndof = M.ndof;
+    op->max_nrhs = o->max_nrhs;
+    op->form = o->form;
+    op->prec32 = o->prec_fp32 ? 1 : 0;
+    OpOpts oo;
+    oo.form = o->form;
+    oo.penalty_rule = o->penalty_rule;
+    oo.eta = o->eta;
+    oo.remark_relax = o->remark_relax;
+    oo.jb_only = o->jb_only;
+    oo.max_block = o->max_block;
+    double eta2 = o->form == 1 ? br2_eta(M, oo) : 0.0;
+    int d = M.dim;
+    // ---- element data and face records
+    std::vector<int8_t> pd(M.p.begin(), M.p.end());
+    if (!o->host_only) {
+      op->off.upload(M.off);
+      op->pdeg.upload(pd);
+      op->hh.upload(M.h);
+      op->kk.upload(M.k);
+    }
+    std::vector<std::vector<FaceRec>> per(M.ne * 2 * d);
+    for (const Face& f : M.faces) {
+      double sig = penalty_or_br2(M, oo, f, eta2);
+      int tdim[2] = {0, 0}, nt = 0;
+      for (int t = 0; t < d; ++t)
+        if (t != f.m) tdim[nt++] = t;
+      int qv = std::max(M.p[f.em], f.ep >= 0 ? M.p[f.ep] : 0) + 1;
+      auto make = [&](int e, int side, int nb) {
+        FaceRec r;
+        std::memset(&r, 0, sizeof(r));
+        r.nbr = nb;
+        r.side = (int8_t)side;
+        r.m = (int8_t)f.m;
+        r.q = (int8_t)qv;
+        for (int j = 0; j < nt; ++j) {
+          int t = tdim[j];
+          r.oc[j] = sub_code(f.lo[t], f.hi[t], M.lo[3 * e + t], M.sz[e]);
+          if (nb >= 0) r.nc[j] = sub_code(f.lo[t], f.hi[t], M.lo[3 * nb + t], M.sz[nb]);
+        }
+        r.flen = (double)(f.hi[tdim[0]] - f.lo[tdim[0]]) / (double)M.N;
+        r.sig = sig;
+        per[(size_t)e * 2 * d + 2 * f.m + side].push_back(r);
+      };
+      if (f.ep >= 0) {
+        make(f.em, 1, f.ep);
+        make(f.ep, 0, f.em);
+      } else {
+        make(f.em, f.side, -1);
+      }
+    }
+    std::vector<int32_t> sptr{0};
+    std::vector<FaceRec> recs;
+    for (auto& v : per) {
+      for (auto& r : v) recs.push_back(r);
+      sptr.push_back((int32_t)recs.size());
+    }
+    op->host_only = o->host_only ? 1 : 0;
+    op->bucket.assign(kMaxP + 1, {});
+    for (int e = 0; e < M.ne; ++e) op->bucket[M.p[e]].push_back(e);
+    if (!op->host_only) {
+      op->sptr.upload(sptr);
+      op->recs.upload(recs);
+      build_tables(op.get(), M.max_dlevel);
+      op->dbucket.resize(kMaxP + 1);
+      for (int p = 1; p <= kMaxP; ++p) op->dbucket[p].upload(op->bucket[p]);
+    }
+    // ---- preconditioner (host)
+    const bool verbose = std::getenv("HPDG_VERBOSE") != nullptr;
+    auto tlast = std::chrono::steady_clock::now();
+    auto phase = [&](const char* name) {
+      auto now = std::chrono::steady_clock::now();
+      if (verbose) std::fprintf(stderr, "hpdg setup: %-12s %8.3f s\n", name, std::chrono::duration<double>(now - tlast).count());
+      tlast = now;
+    };
+    phase("faces");
+    PrecHost& H = op->host;
+    H.diag = dg_diagonal(M, oo);
+    phase("diagonal");
+    H.lab = dof_labels(M, o->remark_relax);
+    phase("labels");
+    if (o->jb_only)
+      for (auto& l : H.lab)
+        if (l == 2) l = 1;
+    H.blocks = edge_spaces(M, H.lab);
+    if (o->max_block > 0) {
+      std::vector<std::vector<int64_t>> keep;
+      for (auto& b : H.blocks) {
+        if ((int)b.size() > o->max_block) {
+          for (int64_t g : b) H.lab[g] = 1;
+        } else {
+          keep.push_back(std::move(b));
+        }
+      }
+      H.blocks.swap(keep);
+    }
+    H.dinvJ.assign(M.ndof, 0.0);
+    for (int64_t g = 0; g < M.ndof; ++g)
+      if (H.lab[g] == 1) H.dinvJ[g] = 1.0 / H.diag[g];
+    phase("edge spaces");
+    std::vector<double> binv;
+    for (auto& B : H.blocks) {
+      std::vector<double> S = dg_submatrix(M, oo, B, eta2);
+      spd_inverse(S, (int)B.size());
+      binv.insert(binv.end(), S.begin(), S.end());
+    }
+    phase("blocks");
+    H.P = prolongation(M);
+    phase("prolongation");
+    op->nconf = M.nconf;
+    H.PT = csr_transpose(H.P);
+    CSR AP = lor_times(M, H.P);
+    H.AC = csr_matmul(H.PT, AP);
+    phase("lor");
+    H.amg = amg_setup(H.AC);
+    phase("amg");
+    // node coordinates (export)
+    op->coords.assign(M.ndof * d, 0.0);
+    for (int e = 0; e < M.ne; ++e) {
+      const Basis1D& B = basis(M.p[e]);
+      int n = M.p[e] + 1;
+      for (int64_t r = 0; r < M.off[e + 1] - M.off[e]; ++r) {
+        int64_t rr = r;
+        for (int m = 0; m < d; ++m) {
+          int i = (int)(rr % n);
+          rr /= n;
+          op->coords[(M.off[e] + r) * d + m] = ((double)M.lo[3 * e + m] + (double)M.sz[e] * B.x[i]) / (double)M.N;
+        }
+      }
+    }
+    if (op->host_only) {
+      *out = op.release();
+      return HPDG_OK;
+    }
+    // ---- uploads
+    if (op->prec32) {
+      upload_prec<float>(op.get());
+      std::vector<float> bi(binv.begin(), binv.end());
+      op->blk_inv.upload(bi);
+    } else {
+      upload_prec<double>(op.get());
+      op->blk_inv.upload(binv);
+    }
+    size_t nv = (size_t)op->ndof * op->max_nrhs * sizeof(double);
+    op->r.alloc(nv);
+    op->z.alloc(nv);
+    op->pv.alloc(nv);
+    op->Ap.alloc(nv);
+    op->part.alloc((size_t)1024 * 256 * sizeof(double));
+    op->scal.alloc((size_t)16 * 256 * sizeof(double));
+    op->act.alloc((size_t)256 * sizeof(int));
+    HIPCHK(hipDeviceSynchronize());
+    *out = op.release();
+    return HPDG_OK;
+  } catch (Error& e) {
+    return fail(e.code, e.what());
+  } catch (std::bad_alloc&) {
+    return fail(HPDG_E_NOMEM, "host allocation failed");
+  }
+}
+
+extern "C" void hpdg_operator_destroy(hpdg_operator* op) { delete op; }
+
+// ------------------------------------------------------------- launchers
+template <int DIM, int P, int MODE>
+static void launch_vol_p(hpdg_operator* op, int nrhs, const double* x, double* y, hipStream_t s) {
+  using S = VolShape<DIM, P>;
+  int nel = (int)op->bucket[P].size();
+  if (nel == 0) return;
+  int nitems = nel * nrhs;
+  unsigned grid = (unsigned)((nitems + S::E - 1) / S::E);
+  hipLaunchKernelGGL((k_vol<DIM, P, MODE>), dim3(grid), dim3(S::BS), 0, s, op->dbucket[P].as<int32_t>(), nitems,
+                     nrhs, op->off.as<int64_t>(), op->hh.as<double>(), op->kk.as<double>(), x, y);
+}
+
+template <int DIM, int MODE>
+static void launch_vol(hpdg_operator* op, int nrhs, const double* x, double* y, hipStream_t s) {
+  launch_vol_p<DIM, 1, MODE>(op, nrhs, x, y, s);
+  launch_vol_p<DIM, 2, MODE>(op, nrhs, x, y, s);
+  launch_vol_p<DIM, 3, MODE>(op, nrhs, x, y, s);
+  launch_vol_p<DIM, 4, MODE>(op, nrhs, x, y, s);
+  launch_vol_p<DIM, 5, MODE>(op, nrhs, x, y, s);
+  launch_vol_p<DIM, 6, MODE>(op, nrhs, x, y, s);
+  launch_vol_p<DIM, 7, MODE>(op, nrhs, x, y, s);
+  launch_vol_p<DIM, 8, MODE>(op, nrhs, x, y, s);
+}
+
+static void apply_A_dev(hpdg_operator* op, const double* x, double* y, int nrhs, hipStream_t s) {
+  if (op->dim == 2) {
+    launch_vol<2, 0>(op, nrhs, x, y, s);
+    hipLaunchKernelGGL(k_faces<2>, dim3(op->ne * nrhs), dim3(64), 0, s, op->ne * nrhs, nrhs, op->form,
+                       op->off.as<int64_t>(), op->pdeg.as<int8_t>(), op->hh.as<double>(), op->kk.as<double>(),
+                       op->sptr.as<int32_t>(), op->recs.as<FaceRec>(), op->tab.as<double>(), op->TL, x, y);
+  } else {
+    launch_vol<3, 0>(op, nrhs, x, y, s);
+    hipLaunchKernelGGL(k_faces<3>, dim3(op->ne * nrhs), dim3(64), 0, s, op->ne * nrhs, nrhs, op->form,
+                       op->off.as<int64_t>(), op->pdeg.as<int8_t>(), op->hh.as<double>(), op->kk.as<double>(),
+                       op->sptr.as<int32_t>(), op->recs.as<FaceRec>(), op->tab.as<double>(), op->TL, x, y);
+  }
+}
+
+template <typename T, int MODE>
+static void spmv(const DevCSR& A, int nrhs, const T* x, const T* b, const T* d, T* xo, T* y, hipStream_t s) {
+  if (A.nrows == 0) return;
+  if (nrhs == 1) {
+    int64_t nt = (int64_t)A.nrows * A.lpr;
+    switch (A.lpr) {
+      case 1: hipLaunchKernelGGL((k_spmv<T, MODE, 1>), dim3(nblk(nt)), dim3(256), 0, s, A.nrows, A.ptr.as<int32_t>(), A.idx.as<int32_t>(), A.val.as<T>(), x, b, d, xo, y); break;
+      case 4: hipLaunchKernelGGL((k_spmv<T, MODE, 4>), dim3(nblk(nt)), dim3(256), 0, s, A.nrows, A.ptr.as<int32_t>(), A.idx.as<int32_t>(), A.val.as<T>(), x, b, d, xo, y); break;
+      case 8: hipLaunchKernelGGL((k_spmv<T, MODE, 8>), dim3(nblk(nt)), dim3(256), 0, s, A.nrows, A.ptr.as<int32_t>(), A.idx.as<int32_t>(), A.val.as<T>(), x, b, d, xo, y); break;
+      default: hipLaunchKernelGGL((k_spmv<T, MODE, 16>), dim3(nblk(nt)), dim3(256), 0, s, A.nrows, A.ptr.as<int32_t>(), A.idx.as<int32_t>(), A.val.as<T>(), x, b, d, xo, y); break;
+    }
+  } else {
+    int64_t nt = (int64_t)A.nrows * nrhs;
+    hipLaunchKernelGGL((k_spmm<T, MODE>), dim3(nblk(nt)), dim3(256), 0, s, A.nrows, nrhs, A.ptr.as<int32_t>(),
+                       A.idx.as<int32_t>(), A.val.as<T>(), x, b, d, xo, y);
+  }
+}
+
+template <typename T>
+static void vcycle(hpdg_operator* op, size_t l, int nrhs, hipStream_t s) {
+  LevelDev& L = op->lv[l];
+  int n = L.A.nrows;
+  if (l + 1 == op->lv.size()) {
+    int nt = op->ncoarse * nrhs;
+    if (nt > 0)
+      hipLaunchKernelGGL(k_dense_gemv<T>, dim3(nblk(nt)), dim3(256), 0, s, op->ncoarse, nrhs, op->coarse.as<T>(),
+                         L.b.as<T>(), L.x.as<T>());
+    return;
+  }
+  LevelDev& C = op->lv[l + 1];
+  // pre-smoothing from zero and residual: x = D b, r = b - A D b
+  spmv<T, 3>(L.A, nrhs, L.b.as<T>(), nullptr, L.l1inv.as<T>(), L.x.as<T>(), L.r.as<T>(), s);
+  // restriction b_c = P^T r
+  spmv<T, 0>(L.R, nrhs, L.r.as<T>(), nullptr, nullptr, nullptr, C.b.as<T>(), s);
+  vcycle<T>(op, l + 1, nrhs, s);
+  // t = x + P x_c ; x = t + D (b - A t)
+  spmv<T, 2>(L.P, nrhs, C.x.as<T>(), L.x.as<T>(), nullptr, nullptr, L.t.as<T>(), s);
+  spmv<T, 4>(L.A, nrhs, L.t.as<T>(), L.b.as<T>(), L.l1inv.as<T>(), nullptr, L.x.as<T>(), s);
+  (void)n;
+}
+
+template <typename T>
+static void apply_B_dev(hpdg_operator* op, const double* r, double* z, int nrhs, hipStream_t s) {
+  int64_t n = op->ndof * nrhs;
+  const T* rt;
+  if (std::is_same<T, double>::value) rt = (const T*)r;
+  else {
+    hipLaunchKernelGGL((k_cast<double, T>), dim3(nblk(n)), dim3(256), 0, s, n, r, op->rT.as<T>());
+    rt = op->rT.as<T>();
+  }
+  T* zb = op->zT.as<T>();
+  hipLaunchKernelGGL(k_diag_scale<T>, dim3(nblk(n)), dim3(256), 0, s, n, nrhs, op->dinvJ.as<T>(), rt, zb);
+  if (op->blk_rows > 0) {
+    int64_t nt = op->blk_rows * nrhs;
+    hipLaunchKernelGGL(k_block_gemv<T>, dim3(nblk(nt)), dim3(256), 0, s, op->blk_rows, nrhs,
+                       op->blk_rowb.as<int32_t>(), op->blk_rowl.as<int32_t>(), op->blk_ptr.as<int64_t>(),
+                       op->blk_off.as<int64_t>(), op->blk_dof.as<int32_t>(), op->blk_inv.as<T>(), rt, zb);
+  }
+  LevelDev& L0 = op->lv[0];
+  spmv<T, 0>(op->PT, nrhs, rt, nullptr, nullptr, nullptr, L0.b.as<T>(), s);
+  vcycle<T>(op, 0, nrhs, s);
+  int64_t nt = op->ndof * nrhs;
+  hipLaunchKernelGGL(k_prolong_out<T>, dim3(nblk(nt)), dim3(256), 0, s, (int)op->ndof, nrhs,
+                     op->P.ptr.as<int32_t>(), op->P.idx.as<int32_t>(), op->P.val.as<T>(), L0.x.as<T>(), zb, z);
+}
+
+static hpdg_status check_vec_args(hpdg_operator* op, const void* a, const void* b, int nrhs) {
+  if (!op) return fail(HPDG_E_INVALID, "null operator");
+  if (op->host_only) return fail(HPDG_E_UNSUPPORTED, "operator was built with host_only");
+  if (!a || !b) return fail(HPDG_E_INVALID, "null vector");
+  if (a == b) return fail(HPDG_E_INVALID, "input and output must not alias");
+  if (nrhs < 1 || nrhs > op->max_nrhs || 256 % nrhs != 0) return fail(HPDG_E_INVALID, "bad nrhs");
+  return HPDG_OK;
+}
+
+extern "C" hpdg_status hpdg_apply_A(hpdg_operator* op, const double* x, double* y, int nrhs, void* stream) {
+  hpdg_status st = check_vec_args(op, x, y, nrhs);
+  if (st != HPDG_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  apply_A_dev(op, x, y, nrhs, s);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(HPDG_E_HIP, hipGetErrorString(e));
+  return HPDG_OK;
+}
+
+extern "C" hpdg_status hpdg_apply_B(hpdg_operator* op, const double* r, double* z, int nrhs, void* stream) {
+  hpdg_status st = check_vec_args(op, r, z, nrhs);
+  if (st != HPDG_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if (op->prec32) apply_B_dev<float>(op, r, z, nrhs, s);
+  else apply_B_dev<double>(op, r, z, nrhs, s);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(HPDG_E_HIP, hipGetErrorString(e));
+  return HPDG_OK;
+}
+
+extern "C" hpdg_status hpdg_rhs(hpdg_operator* op, const double* f, double* b, int nrhs, void* stream) {
+  hpdg_status st = check_vec_args(op, f, b, nrhs);
+  if (st != HPDG_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if (op->dim == 2) launch_vol<2, 1>(op, nrhs, f, b, s);
+  else launch_vol<3, 1>(op, nrhs, f, b, s);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(HPDG_E_HIP, hipGetErrorString(e));
+  return HPDG_OK;
+}
+
+// dot products of interleaved vectors into out[nrhs] (device)
+static void dot_dev(hpdg_operator* op, const double* a, const double* b, int nrhs, double* out, hipStream_t s) {
+  int64_t n = op->ndof * nrhs;
+  int nb = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n + 255) / 256));
+  hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(256), 0, s, n, nrhs, a, b, op->part.as<double>());
+  hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, s, nb, nrhs, op->part.as<double>(), out);
+}
+
+// extreme eigenvalues of the symmetric tridiagonal Lanczos matrix by bisection
+static void tridiag_extremes(const std::vector<double>& a, const std::vector<double>& b, double& lmin, double& lmax) {
+  int n = (int)a.size();
+  if (n == 0) { lmin = lmax = NAN; return; }
+  double lo = 1e300, hi = -1e300;
+  for (int i = 0; i < n; ++i) {
+    double r = (i > 0 ? std::fabs(b[i - 1]) : 0) + (i + 1 < n ? std::fabs(b[i]) : 0);
+    lo = std::min(lo, a[i] - r);
+    hi = std::max(hi, a[i] + r);
+  }
+  auto count_below = [&](double x) {
+    int c = 0;
+    double d = 1.0;
+    for (int i = 0; i < n; ++i) {
+      double bb = i > 0 ? b[i - 1] * b[i - 1] : 0.0;
+      d = a[i] - x - (i > 0 ? bb / d : 0.0);
+      if (d == 0.0) d = -1e-300;
+      if (d < 0) ++c;
+    }
+    return c;
+  };
+  auto kth = [&](int k) {
+    double l = lo, h = hi;
+    for (int it = 0; it < 200; ++it) {
+      double mid = 0.5 * (l + h);
+      if (count_below(mid) > k) h = mid;
+      else l = mid;
+    }
+    return 0.5 * (l + h);
+  };
+  lmin = kth(0);
+  lmax = kth(n - 1);
+}
+
+extern "C" hpdg_status hpdg_pcg_solve(hpdg_operator* op, const double* b, double* x, int nrhs, double rtol,
+                                      int maxit, void* stream, hpdg_solve_info* info) {
+  hpdg_status st = check_vec_args(op, b, x, nrhs);
+  if (st != HPDG_OK) return st;
+  if (!(rtol > 0) || maxit < 0) return fail(HPDG_E_INVALID, "bad rtol or maxit");
+  hipStream_t s = (hipStream_t)stream;
+  try {
+    auto t0 = std::chrono::steady_clock::now();
+    int64_t n = op->ndof * nrhs;
+    double* r = op->r.as<double>();
+    double* z = op->z.as<double>();
+    double* p = op->pv.as<double>();
+    double* Ap = op->Ap.as<double>();
+    double* S = op->scal.as<double>();
+    // scalar slots of nrhs doubles: 0 rz, 1 pAp, 2 rr, 3 bb, 4 rznew, 5 beta
+    double *rz = S, *pAp = S + 256, *rr = S + 512, *bb = S + 768, *rzn = S + 1024, *beta = S + 1280;
+    int* act = op->act.as<int>();
+    auto applyB = [&](const double* in, double* outv) {
+      if (op->prec32) apply_B_dev<float>(op, in, outv, nrhs, s);
+      else apply_B_dev<double>(op, in, outv, nrhs, s);
+    };
+    // r = b - A x
+    apply_A_dev(op, x, Ap, nrhs, s);
+    hipLaunchKernelGGL(k_sub, dim3(nblk(n)), dim3(256), 0, s, n, b, Ap, r);
+    dot_dev(op, b, b, nrhs, bb, s);
+    dot_dev(op, r, r, nrhs, rr, s);
+    applyB(r, z);
+    HIPCHK(hipMemcpyAsync(p, z, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    dot_dev(op, r, z, nrhs, rz, s);
+    std::vector<double> hbb(nrhs), hrr(nrhs), hrz(nrhs), hpap(nrhs);
+    std::vector<int> hact(nrhs, 1);
+    HIPCHK(hipMemcpyAsync(hbb.data(), bb, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hrr.data(), rr, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hrz.data(), rz, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    std::vector<std::vector<double>> al(nrhs), be(nrhs);
+    std::vector<int> iters(nrhs, 0);
+    bool breakdown = false;
+    for (int c = 0; c < nrhs; ++c) {
+      if (!std::isfinite(hbb[c]) || !std::isfinite(hrr[c])) throw Error(HPDG_E_INVALID, "non-finite right-hand side");
+      if (std::sqrt(hrr[c]) <= rtol * std::sqrt(hbb[c])) hact[c] = 0;
+    }
+    HIPCHK(hipMemcpyAsync(act, hact.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, s));
+    int it = 0;
+    auto any_active = [&]() { for (int c = 0; c < nrhs; ++c) if (hact[c]) return true; return false; };
+    std::vector<double> hrzn(nrhs), hbeta(nrhs);
+    while (any_active() && it < maxit) {
+      apply_A_dev(op, p, Ap, nrhs, s);
+      dot_dev(op, p, Ap, nrhs, pAp, s);
+      hipLaunchKernelGGL(k_cg_update, dim3(nblk(n)), dim3(256), 0, s, n, nrhs, rz, pAp, act, p, Ap, x, r);
+      dot_dev(op, r, r, nrhs, rr, s);
+      HIPCHK(hipMemcpyAsync(hpap.data(), pAp, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(hrr.data(), rr, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      ++it;
+      bool changed = false;
+      for (int c = 0; c < nrhs; ++c) {
+        if (!hact[c]) continue;
+        if (!(hpap[c] > 0) || !(hrz[c] > 0)) { breakdown = true; hact[c] = 0; changed = true; continue; }
+        al[c].push_back(hrz[c] / hpap[c]);
+        iters[c] = it;
+        if (std::sqrt(hrr[c]) <= rtol * std::sqrt(hbb[c])) { hact[c] = 0; changed = true; }
+      }
+      if (changed) HIPCHK(hipMemcpyAsync(act, hact.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, s));
+      if (!any_active()) break;
+      applyB(r, z);
+      dot_dev(op, r, z, nrhs, rzn, s);
+      HIPCHK(hipMemcpyAsync(hrzn.data(), rzn, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      for (int c = 0; c < nrhs; ++c) {
+        hbeta[c] = hact[c] ? hrzn[c] / hrz[c] : 0.0;
+        if (hact[c]) { be[c].push_back(hbeta[c]); hrz[c] = hrzn[c]; }
+      }
+      HIPCHK(hipMemcpyAsync(beta, hbeta.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, s));
+      HIPCHK(hipMemcpyAsync(rz, hrz.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, s));
+      hipLaunchKernelGGL(k_cg_dir, dim3(nblk(n)), dim3(256), 0, s, n, nrhs, beta, act, z, p);
+    }
+    // true residual in FP64
+    apply_A_dev(op, x, Ap, nrhs, s);
+    hipLaunchKernelGGL(k_sub, dim3(nblk(n)), dim3(256), 0, s, n, b, Ap, r);
+    dot_dev(op, r, r, nrhs, rr, s);
+    std::vector<double> htr(nrhs);
+    HIPCHK(hipMemcpyAsync(htr.data(), rr, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    bool all_conv = true;
+    for (int c = 0; c < nrhs; ++c) {
+      double bn = std::sqrt(hbb[c]);
+      bool conv = !hact[c] && !breakdown;
+      // recurrence residual of the last iterate
+      double rel = bn > 0 ? std::sqrt(hrr[c]) / bn : 0.0;
+      all_conv &= conv;
+      if (info) {
+        hpdg_solve_info& I = info[c];
+        I.iters = iters[c];
+        I.converged = conv;
+        I.true_rel_res = bn > 0 ? std::sqrt(htr[c]) / bn : 0.0;
+        I.rel_res = rel;
+        // Lanczos tridiagonal of BA from the CG coefficients
+        size_t k = al[c].size();
+        std::vector<double> da(k), db(k > 0 ? k - 1 : 0);
+        for (size_t j = 0; j < k; ++j) {
+          da[j] = 1.0 / al[c][j] + (j > 0 ? be[c][j - 1] / al[c][j - 1] : 0.0);
+          if (j + 1 < k) db[j] = std::sqrt(be[c][j]) / al[c][j];
+        }
+        tridiag_extremes(da, db, I.lambda_min, I.lambda_max);
+        I.cond_est = I.lambda_max / I.lambda_min;
+        I.t_solve_s = secs;
+      }
+    }
+    if (breakdown) return fail(HPDG_E_NOT_SPD, "CG breakdown: p'Ap <= 0 or r'z <= 0");
+    if (!all_conv) return fail(HPDG_E_NOT_CONVERGED, "maximum number of iterations reached");
+    return HPDG_OK;
+  } catch (Error& e) {
+    return fail(e.code, e.what());
+  }
+}
+
+template <typename V>
+static hpdg_status put(const V* src, size_t n, void* buf, size_t* bytes) {
+  size_t need = n * sizeof(V);
+  size_t cap = *bytes;
+  *bytes = need;
+  if (!buf) return HPDG_OK;
+  if (cap < need) return fail(HPDG_E_INVALID, "export buffer too small");
+  std::memcpy(buf, src, need);
+  return HPDG_OK;
+}
+
+static std::vector<char> pack_csr(const CSR& A) {
+  std::vector<char> out;
+  int64_t hdr[3] = {A.nrows, A.ncols, (int64_t)A.idx.size()};
+  auto app = [&](const void* p, size_t b) { const char* c = (const char*)p; out.insert(out.end(), c, c + b); };
+  app(hdr, sizeof(hdr));
+  app(A.ptr.data(), A.ptr.size() * 8);
+  app(A.idx.data(), A.idx.size() * 4);
+  app(A.val.data(), A.val.size() * 8);
+  return out;
+}
+
+extern "C" hpdg_status hpdg_export(const hpdg_operator* op, int what, void* buf, size_t* bytes) {
+  if (!op || !bytes) return fail(HPDG_E_INVALID, "null argument");
+  const PrecHost& H = op->host;
+  switch (what) {
+    case 0: return put(H.diag.data(), H.diag.size(), buf, bytes);
+    case 1: return put(H.lab.data(), H.lab.size(), buf, bytes);
+    case 2: { auto v = pack_csr(H.P); return put(v.data(), v.size(), buf, bytes); }
+    case 3: { auto v = pack_csr(H.AC); return put(v.data(), v.size(), buf, bytes); }
+    case 4: {
+      std::vector<int64_t> v{(int64_t)H.blocks.size(), 0};
+      for (auto& b : H.blocks) v.push_back(v.back() + (int64_t)b.size());
+      for (auto& b : H.blocks) v.insert(v.end(), b.begin(), b.end());
+      return put(v.data(), v.size(), buf, bytes);
+    }
+    case 5: return put(op->coords.data(), op->coords.size(), buf, bytes);
+    case 6: {
+      std::vector<int64_t> v{(int64_t)H.amg.lv.size()};
+      for (auto& L : H.amg.lv) v.push_back(L.A.nrows);
+      return put(v.data(), v.size(), buf, bytes);
+    }
+    case 7: {
+      int64_t mx = 0, ent = 0;
+      for (auto& b : H.blocks) { mx = std::max<int64_t>(mx, b.size()); ent += (int64_t)b.size() * b.size(); }
+      std::vector<int64_t> v{op->ndof, op->nconf, (int64_t)H.blocks.size(), mx, ent, (int64_t)H.amg.lv.size(),
+                             (int64_t)H.AC.idx.size(), (int64_t)H.P.idx.size()};
+      return put(v.data(), v.size(), buf, bytes);
+    }
+    default:
+      if (what >= 100 && what < 100 + (int)H.amg.lv.size()) {
+        auto v = pack_csr(H.amg.lv[what - 100].A);
+        return put(v.data(), v.size(), buf, bytes);
+      }
+      if (what >= 200 && what + 1 < 200 + (int)H.amg.lv.size()) {
+        auto v = pack_csr(H.amg.lv[what - 200].P);
+        return put(v.data(), v.size(), buf, bytes);
+      }
+      if (what >= 300 && what < 300 + (int)H.amg.aggs.size())
+        return put(H.amg.aggs[what - 300].data(), H.amg.aggs[what - 300].size(), buf, bytes);
+      return fail(HPDG_E_INVALID, "unknown export item");
+  }
+}

@@ -1,0 +1,40 @@
+// Device-side data layout shared by the HIP kernels and the C-ABI layer.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace hpdg {
+
+// One face as seen from one of its two elements (or the only one on the
+// boundary). 32 bytes.
+struct FaceRec {
+  int32_t nbr;      // neighbour element, -1 on the boundary
+  int8_t side;      // side of the own element: 0 lower (normal -e_m), 1 upper
+  int8_t m;         // normal dimension
+  int8_t q;         // Gauss points per tangential dimension (max p + 1)
+  int8_t pad0;
+  uint8_t oc[2];    // sub-interval code of the face inside the own side, per tangential slot
+  uint8_t nc[2];    // same inside the neighbour's side
+  int32_t pad1;
+  double flen;      // physical face side length
+  double sig;       // SIPG penalty sigma, or eta*k_e for BR2
+};
+static_assert(sizeof(FaceRec) == 32, "FaceRec layout");
+
+// Tables of the 1D basis, all degrees, in one device buffer (doubles).
+struct TableLayout {
+  int ncode;          // sub-interval codes: 1..ncode-1, code = 2^delta + index
+  int64_t interp;     // offset of I[p][q][code][g][i] blocks of 81
+  int64_t gw;         // Gauss weights gw[q*10+g]
+  int64_t dside;      // l_i'(0), l_i'(1): dside[(p*2+s)*9+i]
+  int64_t minv;       // inverse 1D mass: minv[p*81+i*(p+1)+j]
+  int64_t mk;         // M, K: mk[(p*2+0)*81 + i*(p+1)+j] is M, +1 is K
+  int64_t total;
+};
+
+__host__ __device__ inline int64_t interp_index(const TableLayout& L, int p, int q, int code) {
+  return L.interp + ((int64_t)(((p - 1) * 8 + (q - 2)) * L.ncode + code)) * 81;
+}
+
+}  // namespace hpdg

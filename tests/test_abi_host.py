@@ -1,0 +1,105 @@
+"""CPU tests of the native library: it loads, exports every symbol the
+header declares, validates meshes, and its host-side setup (built with
+host_only=1, no GPU touched) matches the oracle: diagonal, V_J/N labels
+(bit-exact), V_e blocks (bit-exact), conforming prolongation P, LOR matrix
+A~_C and the AMG hierarchy sizes."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import hpinputs as H
+import oracle as O
+from oracle import dg, precond
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+G = pytest.importorskip("paper_2009_01287_amd")
+
+
+def _lib_or_skip():
+    try:
+        return G.lib()
+    except ImportError as e:
+        pytest.fail(str(e))
+
+
+def test_library_exports_header_symbols():
+    L = _lib_or_skip()
+    hdr = open(os.path.join(ROOT, "include", "hpdg.h")).read()
+    names = sorted(set(re.findall(r"\b(hpdg_[A-Za-z_]+)\s*\(", hdr)))
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(G.SYMBOLS)
+
+
+def test_mesh_validation_errors():
+    _lib_or_skip()
+    md = H.uniform_mesh(2, 2, 2)
+    bad = dict(md, level=md["level"][:-1], anchor=md["anchor"][:-1], degree=md["degree"][:-1],
+               kcoef=md["kcoef"][:-1])
+    with pytest.raises(G.HpdgError) as ei:
+        G.Mesh(bad)
+    assert ei.value.code == -1
+    with pytest.raises(G.HpdgError):
+        G.Mesh(dict(md, degree=np.array([1, 2, 9, 1], np.int32)))
+    with pytest.raises(G.HpdgError):
+        G.Mesh(dict(md, kcoef=np.array([1, 1, -1, 1.0])))
+    m = G.Mesh(H.fig1_mesh(3))
+    assert m.max_level_jump == 3
+    assert m.nface == len(O.Mesh(H.fig1_mesh(3)).faces)
+
+
+def test_operator_calls_rejected_when_host_only():
+    _lib_or_skip()
+    op = G.Operator(G.Mesh(H.uniform_mesh(2, 2, 1)), host_only=True)
+    L = G.lib()
+    code = L.hpdg_apply_A(op.h, ctypes.c_void_p(8), ctypes.c_void_p(16), 1, None)
+    assert code == -6
+
+
+CASES = [
+    ("fig1", lambda: H.fig1_mesh(3), "sipg", 1.0, 0),
+    ("hang2", lambda: H.hanging_mesh(2, 3, seed=3), "sipg", 1.0, 0),
+    ("rand2", lambda: H.random_mesh(2, 4, 0.3, 3, 1, 8, seed=11), "sipg", 1.0, 0),
+    ("rand2br2", lambda: H.random_mesh(2, 3, 0.4, 2, 1, 6, seed=12), "br2", 0.0, 0),
+    ("rand3", lambda: H.random_mesh(3, 2, 0.4, 1, 1, 3, seed=5), "sipg", 1.0, 0),
+    ("rand3k", lambda: H.random_mesh(3, 2, 0.4, 2, 1, 4, seed=5, k_logrange=(-2, 2)), "br2", 0.0, 128),
+    ("hang3br2", lambda: H.hanging_mesh(3, 2, seed=2), "br2", 0.0, 0),
+]
+
+
+@pytest.mark.parametrize("name,mk,form,eta,cap", CASES, ids=[c[0] for c in CASES])
+def test_host_setup_matches_oracle(name, mk, form, eta, cap):
+    _lib_or_skip()
+    md = mk()
+    m = O.Mesh(md)
+    opts = O.Opts(form, 0, eta)
+    op = G.Operator(G.Mesh(md), form=form, eta=eta, host_only=True, max_block=cap)
+    dO = dg.diagonal(m, opts)
+    assert np.abs(op.diag() - dO).max() <= 1e-13 * np.abs(dO).max()
+    inJ, inN = precond.labels(m)
+    if cap:
+        for b in precond.edge_spaces(m, inN):
+            if len(b) > cap:
+                inJ[b], inN[b] = True, False
+    lab = np.where(inJ, 1, np.where(inN, 2, 0)).astype(np.int8)
+    assert np.array_equal(op.labels(), lab)
+    bo = precond.edge_spaces(m, inN)
+    bg = op.blocks()
+    assert len(bo) == len(bg) and all(np.array_equal(a, b) for a, b in zip(bo, bg))
+    P, nc = precond.prolongation(m)
+    PG = op.prolongation()
+    assert PG.shape == P.shape
+    assert abs(P - PG).max() <= 1e-13
+    AC = (P.T @ precond.lor_matrix(m) @ P).tocsr()
+    assert abs(AC - op.lor_conforming()).max() <= 1e-13 * abs(AC).max()
+    amg = precond.AMG(AC)
+    assert [a.shape[0] for a in amg.A] == op.amg_levels()
+    for l, Al in enumerate(amg.A):
+        assert abs(op._csr(op.export(100 + l)) - Al).max() <= 1e-12 * abs(Al).max()
+        if l < len(amg.P):
+            assert np.array_equal(op.export(300 + l).view(np.int64), amg.aggs[l])
+            assert abs(op._csr(op.export(200 + l)) - amg.P[l]).max() <= 1e-11

@@ -1,0 +1,219 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Tolerances: FP64 operator and preconditioner applications agree with the
+oracle to 1e-12 in relative 2-norm (the paper's operations are exact up to
+rounding; both sides sum O(p^d) terms per entry). Solves stop at the
+recurrence residual rtol and are checked on the FP64 true residual; the
+error against the oracle's direct solution is bounded by cond(A) * rtol.
+"""
+import numpy as np
+import pytest
+
+import hpinputs as H
+import oracle as O
+from oracle import dg, pcg, precond
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+G = pytest.importorskip("paper_2009_01287_amd")
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+MESHES = {
+    "uniform2": lambda: H.uniform_mesh(2, 3, 3),
+    "fig1": lambda: H.fig1_mesh(3),
+    "hang2": lambda: H.hanging_mesh(2, 3, seed=3, pmin=1, pmax=8),
+    "rand2": lambda: H.random_mesh(2, 4, 0.3, 3, 1, 8, seed=11),
+    "rand2k": lambda: H.random_mesh(2, 3, 0.4, 2, 1, 6, seed=12, k_logrange=(-2, 2)),
+    "hang3": lambda: H.hanging_mesh(3, 2, seed=2, pmin=1, pmax=4),
+    "rand3": lambda: H.random_mesh(3, 2, 0.4, 2, 1, 6, seed=5, k_logrange=(-2, 2)),
+}
+
+
+@pytest.mark.parametrize("name", list(MESHES))
+@pytest.mark.parametrize("form", ["sipg", "br2"])
+def test_apply_A_matches_oracle(name, form):
+    md = MESHES[name]()
+    m = O.Mesh(md)
+    eta = 1.0 if form == "sipg" else 0.0
+    op = G.Operator(G.Mesh(md), form=form, eta=eta, max_block=64)
+    x = np.random.default_rng(1).standard_normal(m.ndof)
+    y = torch.empty(m.ndof, dtype=torch.float64, device="cuda")
+    op.apply_A(_dev(x), y)
+    yo = dg.apply(m, O.Opts(form, 0, eta), x)
+    assert _rel(_host(y), yo) <= 1e-12
+
+
+@pytest.mark.parametrize("name", ["hang2", "hang3"])
+def test_rhs_matches_oracle(name):
+    md = MESHES[name]()
+    m = O.Mesh(md)
+    op = G.Operator(G.Mesh(md))
+    f = np.random.default_rng(2).standard_normal(m.ndof)
+    b = torch.empty(m.ndof, dtype=torch.float64, device="cuda")
+    op.rhs(_dev(f), b)
+    assert _rel(_host(b), dg.rhs(m, f)) <= 1e-13
+
+
+@pytest.mark.parametrize("name,form", [("fig1", "sipg"), ("rand2", "sipg"), ("rand2k", "br2"),
+                                       ("hang3", "sipg"), ("rand3", "br2")])
+def test_apply_B_matches_oracle(name, form):
+    md = MESHES[name]()
+    m = O.Mesh(md)
+    eta = 1.0 if form == "sipg" else 0.0
+    cap = 128 if m.dim == 3 else 0     # 3D: larger V_e fall back to point Jacobi
+    op = G.Operator(G.Mesh(md), form=form, eta=eta, max_block=cap)
+    pc = precond.Preconditioner(m, O.Opts(form, 0, eta), max_block=cap)
+    assert [a.shape[0] for a in pc.amg.A] == op.amg_levels()
+    assert np.array_equal(op.labels(), np.where(pc.inJ, 1, np.where(pc.inN, 2, 0)))
+    r = np.random.default_rng(3).standard_normal(m.ndof)
+    z = torch.empty(m.ndof, dtype=torch.float64, device="cuda")
+    op.apply_B(_dev(r), z)
+    assert _rel(_host(z), pc.apply(r)) <= 1e-12
+
+
+@pytest.mark.parametrize("name,form", [("rand2", "sipg"), ("hang3", "br2")])
+def test_pcg_matches_oracle(name, form):
+    md = MESHES[name]()
+    m = O.Mesh(md)
+    eta = 1.0 if form == "sipg" else 0.0
+    opts = O.Opts(form, 0, eta)
+    cap = 128 if m.dim == 3 else 0
+    op = G.Operator(G.Mesh(md), form=form, eta=eta, max_block=cap)
+    pc = precond.Preconditioner(m, opts, max_block=cap)
+    f = H.gaussian_rhs(m.ndof, 7)
+    b = dg.rhs(m, f)
+    xo, io = pcg.pcg(lambda v: dg.apply(m, opts, v), pc.apply, b, 1e-10, 2000)
+    x = torch.zeros(m.ndof, dtype=torch.float64, device="cuda")
+    info = op.pcg_solve(_dev(b), x, rtol=1e-10, maxit=2000)[0]
+    assert info["converged"] and info["true_rel_res"] <= 2e-10
+    assert abs(info["iters"] - io["iters"]) <= 1
+    assert _rel(_host(x), xo) <= 1e-8
+    assert abs(info["cond_est"] / io["cond"] - 1) < 1e-3
+
+
+def test_cfg1_solve():
+    md = H.config_mesh(1)
+    m = O.Mesh(md)
+    op = G.Operator(G.Mesh(md))
+    X = dg.node_coords(m)
+    assert np.allclose(op.node_coords(), X, atol=1e-15)
+    f = 2 * np.pi ** 2 * np.sin(np.pi * X[:, 0]) * np.sin(np.pi * X[:, 1])
+    b = torch.empty(m.ndof, dtype=torch.float64, device="cuda")
+    op.rhs(_dev(f), b)
+    x = torch.zeros_like(b)
+    info = op.pcg_solve(b, x, rtol=1e-10, maxit=500)[0]
+    A = dg.assemble_dense(m, O.Opts("sipg", 0, 1.0))
+    xs = np.linalg.solve(A, dg.rhs(m, f))
+    assert info["true_rel_res"] <= 1e-10
+    assert _rel(_host(x), xs) <= 1e-8
+    u = np.sin(np.pi * X[:, 0]) * np.sin(np.pi * X[:, 1])
+    assert np.abs(_host(x) - u).max() < 5e-3       # discretisation error, p=2, h=1/4
+
+
+def test_cfg2_full_size():
+    """cfg2 at its full size (155k DOFs): apply_A on sampled elements against
+    the oracle, B symmetric, PCG to 1e-8 with the FP64 true residual."""
+    md = H.config_mesh(2)
+    m = O.Mesh(md)
+    op = G.Operator(G.Mesh(md))
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal(m.ndof)
+    y = torch.empty(m.ndof, dtype=torch.float64, device="cuda")
+    op.apply_A(_dev(x), y)
+    yh = _host(y)
+    els = sorted(rng.choice(m.ne, 40, replace=False).tolist())
+    yo = dg.apply(m, O.Opts("sipg", 0, 1.0), x, elems=els)
+    rows = np.concatenate([m.dofs(e) for e in els])
+    assert _rel(yh[rows], yo[rows]) <= 1e-12
+    u, v = rng.standard_normal(m.ndof), rng.standard_normal(m.ndof)
+    Bu, Bv = torch.empty_like(y), torch.empty_like(y)
+    op.apply_B(_dev(u), Bu)
+    op.apply_B(_dev(v), Bv)
+    a, b = v @ _host(Bu), u @ _host(Bv)
+    assert abs(a - b) <= 1e-11 * abs(a)
+    assert u @ _host(Bu) > 0
+    f = H.config_rhs(2, m.ndof)
+    bb = torch.empty_like(y)
+    op.rhs(_dev(f), bb)
+    xs = torch.zeros_like(y)
+    info = op.pcg_solve(bb, xs, rtol=1e-8, maxit=2000)[0]
+    assert info["converged"] and info["true_rel_res"] <= 1e-8
+
+
+def test_fp32_preconditioner_solve():
+    md = MESHES["rand2"]()
+    m = O.Mesh(md)
+    op32 = G.Operator(G.Mesh(md), prec_fp32=True)
+    op64 = G.Operator(G.Mesh(md))
+    b = torch.empty(m.ndof, dtype=torch.float64, device="cuda")
+    op64.rhs(_dev(H.gaussian_rhs(m.ndof, 9)), b)
+    x32, x64 = torch.zeros_like(b), torch.zeros_like(b)
+    i32 = op32.pcg_solve(b, x32, rtol=1e-8)[0]
+    i64 = op64.pcg_solve(b, x64, rtol=1e-8)[0]
+    assert i32["true_rel_res"] <= 1e-8 and i64["true_rel_res"] <= 1e-8
+    assert abs(i32["iters"] - i64["iters"]) <= 3
+    r = np.random.default_rng(5).standard_normal(m.ndof)
+    z32, z64 = torch.empty_like(b), torch.empty_like(b)
+    op32.apply_B(_dev(r), z32)
+    op64.apply_B(_dev(r), z64)
+    assert _rel(_host(z32), _host(z64)) <= 1e-5
+
+
+def test_multi_rhs_equals_single():
+    md = MESHES["hang2"]()
+    m = O.Mesh(md)
+    nr = 4
+    op = G.Operator(G.Mesh(md), max_nrhs=nr)
+    F = H.gaussian_rhs(m.ndof, 11, nrhs=nr)
+    fb = _dev(F.reshape(-1))
+    B = torch.empty_like(fb)
+    op.rhs(fb, B, nrhs=nr)
+    Y = torch.empty_like(fb)
+    op.apply_A(B, Y, nrhs=nr)
+    Z = torch.empty_like(fb)
+    op.apply_B(B, Z, nrhs=nr)
+    X = torch.zeros_like(fb)
+    infos = op.pcg_solve(B, X, nrhs=nr, rtol=1e-10)
+    Bh, Yh, Zh, Xh = (_host(t).reshape(m.ndof, nr) for t in (B, Y, Z, X))
+    for r in range(nr):
+        b1 = _dev(Bh[:, r])
+        y1, z1, x1 = torch.empty_like(b1), torch.empty_like(b1), torch.zeros_like(b1)
+        op.apply_A(b1, y1)
+        op.apply_B(b1, z1)
+        i1 = op.pcg_solve(b1, x1, rtol=1e-10)[0]
+        assert _rel(Yh[:, r], _host(y1)) <= 1e-14
+        assert _rel(Zh[:, r], _host(z1)) <= 1e-14
+        assert infos[r]["iters"] == i1["iters"]
+        assert _rel(Xh[:, r], _host(x1)) <= 1e-12
+
+
+def test_error_paths():
+    md = MESHES["hang2"]()
+    m = O.Mesh(md)
+    op = G.Operator(G.Mesh(md))
+    b = torch.full((m.ndof,), float("nan"), dtype=torch.float64, device="cuda")
+    x = torch.zeros_like(b)
+    with pytest.raises(G.HpdgError) as ei:
+        op.pcg_solve(b, x)
+    assert ei.value.code == -1
+    b = _dev(np.random.default_rng(0).standard_normal(m.ndof))
+    code, info = op.pcg_solve(b, x, maxit=1, raise_on_error=False)
+    assert code == -5 and info[0]["iters"] == 1 and not info[0]["converged"]
+    with pytest.raises(G.HpdgError):
+        op.apply_A(b, b)
+    with pytest.raises(G.HpdgError):
+        op.apply_A(b, x, nrhs=3)
