@@ -58,6 +58,12 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with python -m paper_2009_01287_amd.build")
+    # torch ships its own HIP runtime with the same soname as the system one;
+    # loading torch first makes the library bind to that single runtime
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(LIB_PATH)
     vp, i32p, f64p = C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_double)
     L.hpdg_last_error.restype = C.c_char_p
@@ -72,9 +78,6 @@ def lib():
         getattr(L, f).argtypes = [vp, vp, vp, C.c_int, vp]
     L.hpdg_pcg_solve.argtypes = [vp, vp, vp, C.c_int, C.c_double, C.c_int, vp, C.POINTER(SolveInfo)]
     L.hpdg_export.argtypes = [vp, C.c_int, vp, C.POINTER(C.c_size_t)]
-    for f in SYMBOLS[1:]:
-        if getattr(L, f).restype is C.c_int or f not in ("hpdg_mesh_destroy", "hpdg_operator_destroy"):
-            pass
     _lib = L
     return L
 

@@ -65,7 +65,8 @@ struct DevBuf {
     bytes = b;
     if (b == 0) return;
     hipError_t e = hipMalloc(&p, b);
-    if (e != hipSuccess) throw Error(HPDG_E_NOMEM, "hipMalloc of " + std::to_string(b) + " bytes failed");
+    if (e != hipSuccess)
+      throw Error(HPDG_E_NOMEM, "hipMalloc of " + std::to_string(b) + " bytes failed: " + hipGetErrorString(e));
   }
   template <typename T>
   void upload(const std::vector<T>& v) {
