@@ -7,7 +7,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <map>
 #include <memory>
+#include <array>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -80,9 +82,11 @@ struct DevBuf {
 struct DevCSR {
   int nrows = 0, ncols = 0;
   int64_t nnz = 0;
-  int lpr = 1;
-  DevBuf ptr, idx, val;
+  int lpr = 1;                 // lanes per short row
+  int nlong = 0;               // rows longer than kLongRow, one wavefront each
+  DevBuf ptr, idx, val, rows;  // rows: long rows first, then short rows
 };
+constexpr int kLongRow = 32;
 
 template <typename T>
 void upload_csr(const CSR& A, DevCSR& D) {
@@ -95,8 +99,18 @@ void upload_csr(const CSR& A, DevCSR& D) {
   D.ptr.upload(p32);
   D.idx.upload(A.idx);
   D.val.upload(v);
-  double avg = D.nrows ? (double)D.nnz / D.nrows : 0;
-  D.lpr = avg > 48 ? 16 : avg > 20 ? 8 : avg > 6 ? 4 : 1;
+  std::vector<int32_t> lr, sr;
+  int64_t snnz = 0;
+  for (int64_t i = 0; i < A.nrows; ++i) {
+    int64_t len = A.ptr[i + 1] - A.ptr[i];
+    if (len > kLongRow) lr.push_back((int32_t)i);
+    else { sr.push_back((int32_t)i); snnz += len; }
+  }
+  D.nlong = (int)lr.size();
+  lr.insert(lr.end(), sr.begin(), sr.end());
+  D.rows.upload(lr);
+  double avg = sr.empty() ? 0.0 : (double)snnz / (double)sr.size();
+  D.lpr = avg > 12 ? 16 : avg > 6 ? 8 : avg > 2.5 ? 4 : avg > 1.5 ? 2 : 1;
 }
 
 struct PrecHost {
@@ -117,10 +131,11 @@ struct LevelDev {
 
 struct hpdg_operator {
   int dim = 2, ne = 0, max_nrhs = 1, form = 0, prec32 = 0, host_only = 0;
+  int generic_faces = 0;   // HPDG_GENERIC_FACES=1: use the one-block-per-element face kernel
   int64_t ndof = 0, nconf = 0;
   hpdg_operator_opts opts{};
   // element data
-  DevBuf off, pdeg, hh, kk, sptr, recs, tab;
+  DevBuf off, pdeg, hh, kk, sptr, recs, tab, ftab;
   TableLayout TL{};
   std::vector<std::vector<int32_t>> bucket;  // host: elements per degree
   std::vector<DevBuf> dbucket;               // device copies (index p)
@@ -224,7 +239,13 @@ static void build_tables(hpdg_operator* op, int max_delta) {
   T.resize(T.size() + 9 * 81, 0.0);
   for (int p = 1; p <= kMaxP; ++p)
     for (size_t i = 0; i < basis(p).Minv.size(); ++i) T[L.minv + p * 81 + i] = basis(p).Minv[i];
-  L.mk = 0;
+  L.mk = (int64_t)T.size();
+  T.resize(T.size() + 9 * 2 * 81, 0.0);
+  for (int p = 1; p <= kMaxP; ++p)
+    for (size_t i = 0; i < basis(p).M.size(); ++i) {
+      T[L.mk + (p * 2 + 0) * 81 + i] = basis(p).M[i];
+      T[L.mk + (p * 2 + 1) * 81 + i] = basis(p).K[i];
+    }
   L.total = (int64_t)T.size();
   op->tab.upload(T);
   // constant-memory M, K for the volume kernels
@@ -363,6 +384,45 @@ extern "C" hpdg_status hpdg_setup_operator(const hpdg_mesh* mh, const hpdg_opera
       op->kk.upload(M.k);
     }
     std::vector<std::vector<FaceRec>> per(M.ne * 2 * d);
+    // 1D face-mass matrices F[j][j'] = sum_g w_g l^a_j(x^a_g) l^b_j'(x^b_g) of the
+    // face's sub-intervals in each side (unit length), deduplicated by type
+    std::map<std::array<int, 5>, int32_t> fmap;
+    std::vector<double> ftab;
+    auto sub_vals = [&](int p, int code, int q, std::vector<double>& out) {
+      std::vector<double> gx, gw;
+      gauss_rule(q, gx, gw);
+      int delta = 0;
+      while ((2 << delta) <= code) ++delta;
+      double len = 1.0 / (double)(1 << delta), a = (code - (1 << delta)) * len;
+      out.assign(q * (p + 1), 0.0);
+      for (int g = 0; g < q; ++g) lagrange_eval(basis(p).x, a + len * gx[g], &out[g * (p + 1)]);
+      return gw;
+    };
+    auto face_mats = [&](int p, int oc, int po, int nc, int q) -> int32_t {
+      std::array<int, 5> key{p, oc, po, nc, q};
+      auto it = fmap.find(key);
+      if (it != fmap.end()) return it->second;
+      int32_t at = (int32_t)ftab.size();
+      std::vector<double> Io, In;
+      std::vector<double> gw = sub_vals(p, oc, q, Io);
+      int n = p + 1, no = po + 1;
+      auto mass = [&](const std::vector<double>& A, int na, const std::vector<double>& B, int nb) {
+        for (int j = 0; j < na; ++j)
+          for (int jj = 0; jj < nb; ++jj) {
+            double s = 0;
+            for (int g = 0; g < q; ++g) s += gw[g] * A[g * na + j] * B[g * nb + jj];
+            ftab.push_back(s);
+          }
+      };
+      mass(Io, n, Io, n);
+      if (po > 0) {
+        sub_vals(po, nc, q, In);
+        mass(Io, n, In, no);
+        mass(In, no, In, no);
+      }
+      fmap.emplace(key, at);
+      return at;
+    };
     for (const Face& f : M.faces) {
       double sig = penalty_or_br2(M, oo, f, eta2);
       int tdim[2] = {0, 0}, nt = 0;
@@ -383,6 +443,7 @@ extern "C" hpdg_status hpdg_setup_operator(const hpdg_mesh* mh, const hpdg_opera
         }
         r.flen = (double)(f.hi[tdim[0]] - f.lo[tdim[0]]) / (double)M.N;
         r.sig = sig;
+        r.ftype = d == 2 ? face_mats(M.p[e], r.oc[0], nb >= 0 ? M.p[nb] : 0, r.nc[0], qv) : 0;
         per[(size_t)e * 2 * d + 2 * f.m + side].push_back(r);
       };
       if (f.ep >= 0) {
@@ -399,11 +460,14 @@ extern "C" hpdg_status hpdg_setup_operator(const hpdg_mesh* mh, const hpdg_opera
       sptr.push_back((int32_t)recs.size());
     }
     op->host_only = o->host_only ? 1 : 0;
+    op->generic_faces = std::getenv("HPDG_GENERIC_FACES") != nullptr;
     op->bucket.assign(kMaxP + 1, {});
     for (int e = 0; e < M.ne; ++e) op->bucket[M.p[e]].push_back(e);
+    if (ftab.size() > (size_t)INT32_MAX) throw Error(HPDG_E_UNSUPPORTED, "face table too large");
     if (!op->host_only) {
       op->sptr.upload(sptr);
       op->recs.upload(recs);
+      op->ftab.upload(ftab);
       build_tables(op.get(), M.max_dlevel);
       op->dbucket.resize(kMaxP + 1);
       for (int p = 1; p <= kMaxP; ++p) op->dbucket[p].upload(op->bucket[p]);
@@ -529,7 +593,11 @@ static void launch_vol(hpdg_operator* op, int nrhs, const double* x, double* y, 
 }
 
 static void apply_A_dev(hpdg_operator* op, const double* x, double* y, int nrhs, hipStream_t s) {
-  if (op->dim == 2) {
+  if (op->dim == 2 && nrhs == 1 && !op->generic_faces) {
+    hipLaunchKernelGGL(k_elem2d, dim3(op->ne), dim3(64), 0, s, op->ne, op->form, op->off.as<int64_t>(),
+                       op->pdeg.as<int8_t>(), op->hh.as<double>(), op->kk.as<double>(), op->sptr.as<int32_t>(),
+                       op->recs.as<FaceRec>(), op->ftab.as<double>(), op->tab.as<double>(), op->TL, x, y);
+  } else if (op->dim == 2) {
     launch_vol<2, 0>(op, nrhs, x, y, s);
     hipLaunchKernelGGL(k_faces<2>, dim3(op->ne * nrhs), dim3(64), 0, s, op->ne * nrhs, nrhs, op->form,
                        op->off.as<int64_t>(), op->pdeg.as<int8_t>(), op->hh.as<double>(), op->kk.as<double>(),
@@ -542,16 +610,25 @@ static void apply_A_dev(hpdg_operator* op, const double* x, double* y, int nrhs,
   }
 }
 
+template <typename T, int MODE, int LPR>
+static void spmv_launch(const DevCSR& A, const T* x, const T* b, const T* d, T* xo, T* y, hipStream_t s) {
+  int nshort = A.nrows - A.nlong;
+  int nlb = (A.nlong + 3) / 4;
+  unsigned grid = (unsigned)(nlb + nblk((int64_t)nshort * LPR));
+  hipLaunchKernelGGL((k_spmv<T, MODE, LPR>), dim3(grid), dim3(256), 0, s, A.nlong, nlb, nshort,
+                     A.rows.as<int32_t>(), A.ptr.as<int32_t>(), A.idx.as<int32_t>(), A.val.as<T>(), x, b, d, xo, y);
+}
+
 template <typename T, int MODE>
 static void spmv(const DevCSR& A, int nrhs, const T* x, const T* b, const T* d, T* xo, T* y, hipStream_t s) {
   if (A.nrows == 0) return;
   if (nrhs == 1) {
-    int64_t nt = (int64_t)A.nrows * A.lpr;
     switch (A.lpr) {
-      case 1: hipLaunchKernelGGL((k_spmv<T, MODE, 1>), dim3(nblk(nt)), dim3(256), 0, s, A.nrows, A.ptr.as<int32_t>(), A.idx.as<int32_t>(), A.val.as<T>(), x, b, d, xo, y); break;
-      case 4: hipLaunchKernelGGL((k_spmv<T, MODE, 4>), dim3(nblk(nt)), dim3(256), 0, s, A.nrows, A.ptr.as<int32_t>(), A.idx.as<int32_t>(), A.val.as<T>(), x, b, d, xo, y); break;
-      case 8: hipLaunchKernelGGL((k_spmv<T, MODE, 8>), dim3(nblk(nt)), dim3(256), 0, s, A.nrows, A.ptr.as<int32_t>(), A.idx.as<int32_t>(), A.val.as<T>(), x, b, d, xo, y); break;
-      default: hipLaunchKernelGGL((k_spmv<T, MODE, 16>), dim3(nblk(nt)), dim3(256), 0, s, A.nrows, A.ptr.as<int32_t>(), A.idx.as<int32_t>(), A.val.as<T>(), x, b, d, xo, y); break;
+      case 1: spmv_launch<T, MODE, 1>(A, x, b, d, xo, y, s); break;
+      case 2: spmv_launch<T, MODE, 2>(A, x, b, d, xo, y, s); break;
+      case 4: spmv_launch<T, MODE, 4>(A, x, b, d, xo, y, s); break;
+      case 8: spmv_launch<T, MODE, 8>(A, x, b, d, xo, y, s); break;
+      default: spmv_launch<T, MODE, 16>(A, x, b, d, xo, y, s); break;
     }
   } else {
     int64_t nt = (int64_t)A.nrows * nrhs;
@@ -566,7 +643,11 @@ static void vcycle(hpdg_operator* op, size_t l, int nrhs, hipStream_t s) {
   int n = L.A.nrows;
   if (l + 1 == op->lv.size()) {
     int nt = op->ncoarse * nrhs;
-    if (nt > 0)
+    if (nt == 0) return;
+    if (nrhs == 1)
+      hipLaunchKernelGGL(k_dense_gemv1<T>, dim3((op->ncoarse + 3) / 4), dim3(256), 0, s, op->ncoarse,
+                         op->coarse.as<T>(), L.b.as<T>(), L.x.as<T>());
+    else
       hipLaunchKernelGGL(k_dense_gemv<T>, dim3(nblk(nt)), dim3(256), 0, s, op->ncoarse, nrhs, op->coarse.as<T>(),
                          L.b.as<T>(), L.x.as<T>());
     return;
@@ -595,10 +676,17 @@ static void apply_B_dev(hpdg_operator* op, const double* r, double* z, int nrhs,
   T* zb = op->zT.as<T>();
   hipLaunchKernelGGL(k_diag_scale<T>, dim3(nblk(n)), dim3(256), 0, s, n, nrhs, op->dinvJ.as<T>(), rt, zb);
   if (op->blk_rows > 0) {
-    int64_t nt = op->blk_rows * nrhs;
-    hipLaunchKernelGGL(k_block_gemv<T>, dim3(nblk(nt)), dim3(256), 0, s, op->blk_rows, nrhs,
-                       op->blk_rowb.as<int32_t>(), op->blk_rowl.as<int32_t>(), op->blk_ptr.as<int64_t>(),
-                       op->blk_off.as<int64_t>(), op->blk_dof.as<int32_t>(), op->blk_inv.as<T>(), rt, zb);
+    if (nrhs == 1) {
+      int64_t nt = op->blk_rows * 16;
+      hipLaunchKernelGGL((k_block_gemv1<T, 16>), dim3(nblk(nt)), dim3(256), 0, s, op->blk_rows,
+                         op->blk_rowb.as<int32_t>(), op->blk_rowl.as<int32_t>(), op->blk_ptr.as<int64_t>(),
+                         op->blk_off.as<int64_t>(), op->blk_dof.as<int32_t>(), op->blk_inv.as<T>(), rt, zb);
+    } else {
+      int64_t nt = op->blk_rows * nrhs;
+      hipLaunchKernelGGL(k_block_gemv<T>, dim3(nblk(nt)), dim3(256), 0, s, op->blk_rows, nrhs,
+                         op->blk_rowb.as<int32_t>(), op->blk_rowl.as<int32_t>(), op->blk_ptr.as<int64_t>(),
+                         op->blk_off.as<int64_t>(), op->blk_dof.as<int32_t>(), op->blk_inv.as<T>(), rt, zb);
+    }
   }
   LevelDev& L0 = op->lv[0];
   spmv<T, 0>(op->PT, nrhs, rt, nullptr, nullptr, nullptr, L0.b.as<T>(), s);

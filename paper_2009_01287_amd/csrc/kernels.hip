@@ -364,6 +364,202 @@ __global__ __launch_bounds__(64) void k_faces(int nitems, int nrhs, int form,
   for (int i = lane; i < nn; i += 64) y[(base + i) * nrhs + rr] += Yacc[i];
 }
 
+// 2D element kernel: volume and face terms of one element per 64-lane block,
+// all degrees in one launch, y written once.
+//  volume: y_K = k (K x M + M x K) x_K, 1D contractions through LDS.
+//  faces:  lanes (side, j) hold the side's trace T and normal derivative D
+//          at its nodes. With the 1D face-mass matrices of the face
+//          A_oo = I_o^T W I_o, A_on = I_o^T W I_n, A_nn = I_n^T W I_n
+//          (W = unit-length Gauss weights, I = Lagrange values of each
+//          side's basis at the face's Gauss points) the tests against phi
+//          (G1) and against d phi/dn (G2) are, with jump v = A_oo To - A_on Tn:
+//          SIPG  G1 += L (sigma v - sgn/2 (k A_oo Do + k_o A_on Dn)),
+//                G2 += -k sgn L v / 2                       (interior)
+//                G1 += L (sigma A_oo To - sgn k A_oo Do), G2 += -k sgn L A_oo To
+//          BR2   sigma v -> c^2 eta k_e L [s_o A_oo Minv_o v
+//                                          + s_n A_on Minv_n (A_on^T To - A_nn Tn)]
+//          with L the face length, s = m00 / h^2 (Sec. 2; Sec. 4.4).
+__global__ __launch_bounds__(64) void k_elem2d(int ne, int form, const int64_t* __restrict__ off,
+                                               const int8_t* __restrict__ pdeg, const double* __restrict__ hh,
+                                               const double* __restrict__ kk, const int32_t* __restrict__ sptr,
+                                               const FaceRec* __restrict__ recs, const double* __restrict__ ftab,
+                                               const double* __restrict__ tab, TableLayout TL,
+                                               const double* __restrict__ x, double* __restrict__ y) {
+  __shared__ double sX[81], sA[81], sB[81], sM[81], sK[81];
+  __shared__ double sTo[4][9], sDo[4][9], sTn[4][9], sDn[4][9], sV[4][9], sW[4][9];
+  __shared__ double sG1[4][9], sG2[4][9];
+  __shared__ double sF[4][243];
+  __shared__ int sCnt[4];
+  const int e = blockIdx.x;
+  if (e >= ne) return;
+  const int lane = threadIdx.x;
+  const int p = pdeg[e], n = p + 1, nn = n * n;
+  const double h = hh[e], k = kk[e];
+  const int64_t base = off[e];
+  for (int i = lane; i < nn; i += 64) {
+    sX[i] = x[base + i];
+    sM[i] = tab[TL.mk + (p * 2 + 0) * 81 + i];
+    sK[i] = tab[TL.mk + (p * 2 + 1) * 81 + i];
+  }
+  if (lane < 4) sCnt[lane] = sptr[e * 4 + lane + 1] - sptr[e * 4 + lane];
+  __syncthreads();
+  // volume, phase 1 (dimension 0)
+  for (int i = lane; i < nn; i += 64) {
+    const int i0 = i % n, i1 = i / n;
+    double t1 = 0.0, t2 = 0.0;
+    for (int a = 0; a < n; ++a) {
+      double xa = sX[i1 * n + a];
+      t1 += xa * sK[a * n + i0];
+      t2 += xa * sM[a * n + i0];
+    }
+    sA[i] = t1;
+    sB[i] = t2;
+  }
+  // own traces: lane = 9*side + j
+  const int sidx = lane / 9, j = lane - 9 * (lane / 9);
+  const bool grp = lane < 36;
+  const int m = sidx >> 1, s = sidx & 1;
+  const int stm = m == 0 ? 1 : n, stt = m == 0 ? n : 1;
+  const double sgn = s ? 1.0 : -1.0;
+  if (grp && j < n) {
+    const double* Ds = tab + TL.dside + (p * 2 + s) * 9;
+    double dv = 0.0;
+    for (int a = 0; a < n; ++a) dv += Ds[a] * sX[a * stm + j * stt];
+    sTo[sidx][j] = sX[(s ? p : 0) * stm + j * stt];
+    sDo[sidx][j] = dv / h;
+  }
+  __syncthreads();
+  // volume, phase 2 (dimension 1)
+  double yv[2] = {0.0, 0.0};
+  for (int i = lane, c = 0; i < nn; i += 64, ++c) {
+    const int i0 = i % n, i1 = i / n;
+    double acc = 0.0;
+    for (int b = 0; b < n; ++b) acc += sM[i1 * n + b] * sA[b * n + i0] + sK[i1 * n + b] * sB[b * n + i0];
+    yv[c] = k * acc;
+  }
+  // faces
+  double G1 = 0.0, G2 = 0.0;
+  const int maxf = max(max(sCnt[0], sCnt[1]), max(sCnt[2], sCnt[3]));
+  const int rb = grp ? sptr[e * 4 + sidx] : 0;
+  const int cnt = grp ? sCnt[sidx] : 0;
+  for (int fi = 0; fi < maxf; ++fi) {
+    const bool have = fi < cnt;
+    FaceRec f;
+    f.nbr = -1;
+    f.q = 0;
+    f.ftype = 0;
+    f.flen = 0.0;
+    f.sig = 0.0;
+    if (have) f = recs[rb + fi];
+    const bool inner = have && f.nbr >= 0;
+    int po = 0, no = 0;
+    double ho = 1.0, ko = 0.0;
+    if (inner) {
+      po = pdeg[f.nbr];
+      no = po + 1;
+      ho = hh[f.nbr];
+      ko = kk[f.nbr];
+    }
+    // stage this face's matrices (A_oo n*n, A_on n*no, A_nn no*no) in LDS
+    const int fsz = have ? n * n + (inner ? n * no + no * no : 0) : 0;
+    for (int t = j; t < fsz; t += 9) sF[sidx][t] = ftab[f.ftype + t];
+    if (inner && j < no) {
+      const int so = 1 - s;
+      const int som = m == 0 ? 1 : no, sot = m == 0 ? no : 1;
+      const int64_t bo = off[f.nbr];
+      const double* Dso = tab + TL.dside + (po * 2 + so) * 9;
+      double dv = 0.0;
+      for (int a = 0; a < no; ++a) dv += Dso[a] * x[bo + a * som + j * sot];
+      sTn[sidx][j] = x[bo + (so ? po : 0) * som + j * sot];
+      sDn[sidx][j] = dv / ho;
+    }
+    __syncthreads();
+    const double* Aoo = sF[sidx];
+    const double* Aon = sF[sidx] + n * n;
+    const double* Ann = Aon + n * no;
+    double v = 0.0, dsum = 0.0;
+    if (have && j < n) {
+      for (int a = 0; a < n; ++a) {
+        v += Aoo[j * n + a] * sTo[sidx][a];
+        dsum += k * Aoo[j * n + a] * sDo[sidx][a];
+      }
+      for (int a = 0; a < no; ++a) {
+        v -= Aon[j * no + a] * sTn[sidx][a];
+        dsum += ko * Aon[j * no + a] * sDn[sidx][a];
+      }
+      const double csym = inner ? 0.5 : 1.0;
+      G1 -= f.flen * csym * sgn * dsum;
+      G2 -= csym * k * sgn * f.flen * v;
+      if (form == 0) G1 += f.flen * f.sig * v;
+      sV[sidx][j] = v;
+    }
+    if (form == 1) {
+      const double c2 = inner ? 0.25 : 1.0;
+      const double L2 = c2 * f.sig * f.flen * f.flen;
+      // own lifting: G1 += L2 s_o A_oo Minv_o v
+      __syncthreads();
+      if (have && j < n) {
+        const double* Mi = tab + TL.minv + p * 81;
+        double w = 0.0;
+        for (int a = 0; a < n; ++a) w += Mi[j * n + a] * sV[sidx][a];
+        sW[sidx][j] = w;
+      }
+      __syncthreads();
+      if (have && j < n) {
+        const double* Mi = tab + TL.minv + p * 81;
+        const int sk = s ? p : 0;
+        const double so = Mi[sk * n + sk] / (h * h);
+        double acc = 0.0;
+        for (int a = 0; a < n; ++a) acc += Aoo[j * n + a] * sW[sidx][a];
+        G1 += L2 * so * acc;
+      }
+      // neighbour lifting: G1 += L2 s_n A_on Minv_n (A_on^T To - A_nn Tn)
+      __syncthreads();
+      if (inner && j < no) {
+        double vn = 0.0;
+        for (int a = 0; a < n; ++a) vn += Aon[a * no + j] * sTo[sidx][a];
+        for (int a = 0; a < no; ++a) vn -= Ann[j * no + a] * sTn[sidx][a];
+        sV[sidx][j] = vn;
+      }
+      __syncthreads();
+      if (inner && j < no) {
+        const double* Mi = tab + TL.minv + po * 81;
+        double w = 0.0;
+        for (int a = 0; a < no; ++a) w += Mi[j * no + a] * sV[sidx][a];
+        sW[sidx][j] = w;
+      }
+      __syncthreads();
+      if (inner && j < n) {
+        const double* Mi = tab + TL.minv + po * 81;
+        const int sk = (1 - s) ? po : 0;
+        const double sn = Mi[sk * no + sk] / (ho * ho);
+        double acc = 0.0;
+        for (int a = 0; a < no; ++a) acc += Aon[j * no + a] * sW[sidx][a];
+        G1 += L2 * sn * acc;
+      }
+    }
+    __syncthreads();
+  }
+  if (grp && j < n) {
+    sG1[sidx][j] = G1;
+    sG2[sidx][j] = G2 / h;
+  }
+  __syncthreads();
+  const double* D0 = tab + TL.dside + (p * 2 + 0) * 9;
+  const double* D1 = tab + TL.dside + (p * 2 + 1) * 9;
+  for (int i = lane, c = 0; i < nn; i += 64, ++c) {
+    const int i0 = i % n, i1 = i / n;
+    double v = yv[c];
+    v += D0[i0] * sG2[0][i1] + D1[i0] * sG2[1][i1];
+    if (i0 == 0) v += sG1[0][i1];
+    if (i0 == p) v += sG1[1][i1];
+    v += D0[i1] * sG2[2][i0] + D1[i1] * sG2[3][i0];
+    if (i1 == 0) v += sG1[2][i0];
+    if (i1 == p) v += sG1[3][i0];
+    y[base + i] = v;
+  }
+}
+
 // ---------------------------------------------------------- vector kernels
 template <typename TI, typename TO>
 __global__ void k_cast(int64_t n, const TI* __restrict__ a, TO* __restrict__ b) {
@@ -396,13 +592,22 @@ __global__ __launch_bounds__(256) void k_dot_partial(int64_t n, int nrhs, const 
   if (tid < nrhs) part[blockIdx.x * nrhs + tid] = sm[tid];
 }
 
-// out[r] = sum over blocks of part (fixed order)
-__global__ void k_dot_final(int nblocks, int nrhs, const double* __restrict__ part, double* __restrict__ out) {
-  int r = threadIdx.x;
-  if (r >= nrhs) return;
+// out[r] = sum over blocks of part; one block of 256 threads, thread t sums
+// blocks t/nrhs, t/nrhs + 256/nrhs, ... of RHS t % nrhs, then a fixed tree
+__global__ __launch_bounds__(256) void k_dot_final(int nblocks, int nrhs, const double* __restrict__ part,
+                                                   double* __restrict__ out) {
+  __shared__ double sm[256];
+  const int t = threadIdx.x;
+  const int c = t % nrhs, g = t / nrhs, ng = 256 / nrhs;
   double s = 0.0;
-  for (int b = 0; b < nblocks; ++b) s += part[b * nrhs + r];
-  out[r] = s;
+  for (int b = g; b < nblocks; b += ng) s += part[b * nrhs + c];
+  sm[t] = s;
+  __syncthreads();
+  for (int w = 128; w >= nrhs; w >>= 1) {
+    if (t < w) sm[t] += sm[t + w];
+    __syncthreads();
+  }
+  if (t < nrhs) out[t] = sm[t];
 }
 
 // x += alpha p ; r -= alpha Ap, alpha[r] = act ? rz/pAp : 0
@@ -435,25 +640,12 @@ __global__ void k_sub(int64_t n, const double* __restrict__ a, const double* __r
 // modes: 0 y = A x; 1 y = b - A x; 2 y = b + A x;
 //        3 (pre-smoother from zero) xo = d.b, y = b - A (d.b);
 //        4 (post-smoother) y = x + d.(b - A x)
-template <typename T, int MODE, int LPR>
-__global__ __launch_bounds__(256) void k_spmv(int nrows, const int32_t* __restrict__ ptr,
-                                              const int32_t* __restrict__ idx, const T* __restrict__ val,
-                                              const T* __restrict__ x, const T* __restrict__ b,
-                                              const T* __restrict__ d, T* __restrict__ xo, T* __restrict__ y) {
-  const int gt = blockIdx.x * 256 + threadIdx.x;
-  const int row = gt / LPR;
-  const int sub = gt % LPR;
-  if (row >= nrows) return;
-  T acc = 0;
-  const int q0 = ptr[row], q1 = ptr[row + 1];
-  for (int q = q0 + sub; q < q1; q += LPR) {
-    int j = idx[q];
-    T xv = MODE == 3 ? d[j] * x[j] : x[j];
-    acc += val[q] * xv;
-  }
-#pragma unroll
-  for (int o = LPR / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, LPR);
-  if (sub != 0) return;
+// Rows are binned at setup: the first nlong_blk blocks take the long rows
+// (one wavefront per row, 4 per block), the others the short rows (LPR
+// lanes per row). rows[] lists long rows first, then short rows.
+template <typename T, int MODE>
+__device__ inline void spmv_row_out(int row, T acc, const T* __restrict__ x, const T* __restrict__ b,
+                                    const T* __restrict__ d, T* __restrict__ xo, T* __restrict__ y) {
   if (MODE == 0) y[row] = acc;
   else if (MODE == 1) y[row] = b[row] - acc;
   else if (MODE == 2) y[row] = b[row] + acc;
@@ -463,6 +655,43 @@ __global__ __launch_bounds__(256) void k_spmv(int nrows, const int32_t* __restri
   } else {
     y[row] = x[row] + d[row] * (b[row] - acc);
   }
+}
+
+template <typename T, int MODE, int LPR>
+__global__ __launch_bounds__(256) void k_spmv(int nlong, int nlong_blk, int nshort,
+                                              const int32_t* __restrict__ rows,
+                                              const int32_t* __restrict__ ptr,
+                                              const int32_t* __restrict__ idx, const T* __restrict__ val,
+                                              const T* __restrict__ x, const T* __restrict__ b,
+                                              const T* __restrict__ d, T* __restrict__ xo, T* __restrict__ y) {
+  if ((int)blockIdx.x < nlong_blk) {
+    const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (w >= nlong) return;
+    const int row = rows[w];
+    T acc = 0;
+    for (int q = ptr[row] + lane; q < ptr[row + 1]; q += 64) {
+      int j = idx[q];
+      acc += val[q] * (MODE == 3 ? d[j] * x[j] : x[j]);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (lane == 0) spmv_row_out<T, MODE>(row, acc, x, b, d, xo, y);
+    return;
+  }
+  const int gt = (blockIdx.x - nlong_blk) * 256 + threadIdx.x;
+  const int r = gt / LPR;
+  const int sub = gt % LPR;
+  if (r >= nshort) return;
+  const int row = rows[nlong + r];
+  T acc = 0;
+  for (int q = ptr[row] + sub; q < ptr[row + 1]; q += LPR) {
+    int j = idx[q];
+    acc += val[q] * (MODE == 3 ? d[j] * x[j] : x[j]);
+  }
+#pragma unroll
+  for (int o = LPR / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, LPR);
+  if (sub == 0) spmv_row_out<T, MODE>(row, acc, x, b, d, xo, y);
 }
 
 // same with nrhs interleaved columns: one thread per (row, rhs)
@@ -508,7 +737,31 @@ __global__ __launch_bounds__(256) void k_prolong_out(int nrows, int nrhs, const 
   z[row * nrhs + c] = (double)(zb[row * nrhs + c] + acc);
 }
 
-// exact V_e solves: one thread per (block row, rhs)
+// exact V_e solves: LPR lanes per block row (coalesced row reads), nrhs == 1
+template <typename T, int LPR>
+__global__ __launch_bounds__(256) void k_block_gemv1(int64_t nrows, const int32_t* __restrict__ row_blk,
+                                                     const int32_t* __restrict__ row_loc,
+                                                     const int64_t* __restrict__ bptr,
+                                                     const int64_t* __restrict__ boff,
+                                                     const int32_t* __restrict__ bdof, const T* __restrict__ binv,
+                                                     const T* __restrict__ r, T* __restrict__ z) {
+  const int64_t gt = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t rw = gt / LPR;
+  const int sub = (int)(gt % LPR);
+  if (rw >= nrows) return;
+  const int b = row_blk[rw];
+  const int i = row_loc[rw];
+  const int64_t s0 = bptr[b];
+  const int m = (int)(bptr[b + 1] - s0);
+  const T* row = binv + boff[b] + (int64_t)i * m;
+  T acc = 0;
+  for (int j = sub; j < m; j += LPR) acc += row[j] * r[bdof[s0 + j]];
+#pragma unroll
+  for (int o = LPR / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, LPR);
+  if (sub == 0) z[bdof[s0 + i]] = acc;
+}
+
+// exact V_e solves, interleaved RHS: one thread per (block row, rhs)
 template <typename T>
 __global__ __launch_bounds__(256) void k_block_gemv(int64_t nrows, int nrhs, const int32_t* __restrict__ row_blk,
                                                     const int32_t* __restrict__ row_loc,
@@ -530,7 +783,21 @@ __global__ __launch_bounds__(256) void k_block_gemv(int64_t nrows, int nrhs, con
   z[(int64_t)bdof[s0 + i] * nrhs + c] = acc;
 }
 
-// coarsest level: x = C b (dense inverse), one thread per (row, rhs)
+// coarsest level: x = C b (dense inverse). nrhs == 1: one wavefront per row
+// (coalesced row reads); otherwise one thread per (row, rhs)
+template <typename T>
+__global__ __launch_bounds__(256) void k_dense_gemv1(int n, const T* __restrict__ C, const T* __restrict__ b,
+                                                     T* __restrict__ x) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= n) return;
+  T acc = 0;
+  for (int j = lane; j < n; j += 64) acc += C[(int64_t)row * n + j] * b[j];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if (lane == 0) x[row] = acc;
+}
+
 template <typename T>
 __global__ void k_dense_gemv(int n, int nrhs, const T* __restrict__ C, const T* __restrict__ b, T* __restrict__ x) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;

@@ -16,7 +16,7 @@ struct FaceRec {
   int8_t pad0;
   uint8_t oc[2];    // sub-interval code of the face inside the own side, per tangential slot
   uint8_t nc[2];    // same inside the neighbour's side
-  int32_t pad1;
+  int32_t ftype;    // offset (doubles) of the face's 1D face-mass matrices A_oo, A_on, A_nn
   double flen;      // physical face side length
   double sig;       // SIPG penalty sigma, or eta*k_e for BR2
 };
