@@ -1,16 +1,18 @@
-"""Benchmark: PCG solves of the hp-DG system on one MI355X.
+"""Benchmark: preconditioned CG solves of the hp-DG system on one MI355X.
 
-A step is one full solve of the cfg2 workload (2D random hp mesh, 32x32 base
-quads refined with probability 0.3 up to 3 levels, p ~ U{1..8}, SIPG, k=1,
-f = seeded Gaussian nodal values, 155,228 DOFs) from x0 = 0 to 1e-8 relative
-residual with the FP64 subspace-correction preconditioner: every iteration
-applies the matrix-free DG operator and B = B_J + B_E + P V(A~_C) P^T.
-Inputs are resident on the GPU before the timed region.
+Workload (default --config 2): the 2D random hp mesh of 32x32 base quads,
+each refined with probability 0.3 up to 3 levels, degrees U{1..8}, SIPG with
+sigma = (p+1)^2/h, k = 1, right-hand side from seeded N(0,1) nodal values,
+155,228 DOFs. A step is one full solve from x0 = 0 to 1e-8 relative residual
+with the FP64 subspace-correction preconditioner B = B_J + B_E + P V(A~_C) P^T;
+every iteration applies the matrix-free DG operator and B. Inputs are
+resident in GPU memory before the timed region; setup is reported apart.
 
-Prints one JSON line. Besides the contract fields it reports the DG apply
-rate (GDOF/s) and its fraction of the HBM roofline measured with HIP events
-on the library's stream, a rocprof-comparable per-kernel figure for the
-dominant kernel, and the oracle's CPU time on a bounded sample.
+Reported: solves/s (value), per-solve p50/p99 latency, the DG apply rate in
+GDOF/s, and the roofline of the dominant kernel (the 2D element kernel:
+volume and face terms in one launch) from HIP events on the stream the
+library launches on. cpu_baseline times the FP64 oracle on this host on a
+bounded sample (see its "sample" field).
 """
 import argparse
 import json
@@ -21,8 +23,9 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-HBM_PEAK = 8.0e12          # B/s, MI355X
-WORKLOADS = {2: "cfg2_random2d_32x32_q0.3_L3_p1-8_sipg_fp64",
+HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
+WORKLOADS = {1: "cfg1_uniform4x4_p2_sipg_fp64",
+             2: "cfg2_random2d_32x32_q0.3_L3_p1-8_sipg_fp64",
              3: "cfg3_random3d_16^3_q0.2_L2_p1-6_br2_fp32prec",
              4: "cfg4_cfg2mesh_64rhs_fp32prec"}
 
@@ -30,14 +33,18 @@ WORKLOADS = {2: "cfg2_random2d_32x32_q0.3_L3_p1-8_sipg_fp64",
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--apply-reps", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--apply-only", action="store_true",
+                    help="only run apply_A --apply-reps times and one calibration copy of "
+                         "256 MiB (for hardware-counter runs), then exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
+        print("bench.py: this build runs on one GPU; --gpus must be 1 (no multi-GPU path here)",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -57,26 +64,46 @@ def main():
                     max_block=256 if md["dim"] == 3 else 0)
     t_setup = time.time() - t0
     n = mesh.ndof
-    f = torch.from_numpy(np.ascontiguousarray(H.config_rhs(cfg, n).reshape(-1))).cuda()
+    if cfg == 1:
+        X = op.node_coords()
+        fn = 2 * np.pi ** 2 * np.sin(np.pi * X[:, 0]) * np.sin(np.pi * X[:, 1])
+    else:
+        fn = H.config_rhs(cfg, n).reshape(-1)
+    f = torch.from_numpy(np.ascontiguousarray(fn)).cuda()
     b = torch.empty_like(f)
     op.rhs(f, b, nrhs=nrhs)
     x = torch.zeros_like(b)
     torch.cuda.synchronize()
+    if args.apply_only:
+        y = torch.empty_like(b)
+        for _ in range(args.apply_reps):
+            op.apply_A(b, y, nrhs=nrhs)
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)                      # calibration: 256 MiB read + 256 MiB written
+        torch.cuda.synchronize()
+        print(json.dumps({"apply_only": True, "ndof": n, "reps": args.apply_reps,
+                          "calibration_copy_bytes": src.numel() * 8}))
+        return
 
     infos = None
     for _ in range(args.warmup):
         x.zero_()
         infos = op.pcg_solve(b, x, nrhs=nrhs, rtol=c["rtol"], maxit=5000)
     torch.cuda.synchronize()
+    lat = []
     t1 = time.perf_counter()
     for _ in range(args.steps):
+        ts = time.perf_counter()
         x.zero_()
         infos = op.pcg_solve(b, x, nrhs=nrhs, rtol=c["rtol"], maxit=5000)
+        lat.append(time.perf_counter() - ts)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t1) / args.steps
     solves_per_s = nrhs / dt
 
-    # DG apply rate, HIP events on the stream the library launches on
+    # apply_A: for 2D with one RHS this is exactly one launch of the element
+    # kernel; HIP events on torch's current stream, which the library uses
     y = torch.empty_like(b)
     for _ in range(10):
         op.apply_A(b, y, nrhs=nrhs)
@@ -87,14 +114,14 @@ def main():
     e1.record()
     torch.cuda.synchronize()
     t_apply = e0.elapsed_time(e1) / 1e3 / args.apply_reps
-    apply_bytes = 16.0 * n * nrhs
-    gdofs = n * nrhs / t_apply / 1e9
+    algo_bytes = 16.0 * n * nrhs          # x read once + y written once, FP64
+    achieved = algo_bytes / t_apply / 1e9
     it = infos[0]["iters"]
+    kernel = ("k_elem2d (volume + all face terms, one launch)" if md["dim"] == 2 and nrhs == 1
+              else "apply_A (volume kernels + face kernel)")
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(md, c, it)
-
+    cpu = None if args.no_cpu_baseline else cpu_baseline(cfg, c, it, n)
+    lat_ms = np.array(lat) * 1e3
     out = {
         "metric": "DG apply GDOF/s + %HBM peak; solves/s and p50/p99 latency at 1e-8 residual",
         "value": solves_per_s,
@@ -106,50 +133,55 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if not c["prec_fp32"] else "f64 (A, CG) + f32 (B)",
+        "dtype": "f64" if not c["prec_fp32"] else "f64 (operator, CG) + f32 (preconditioner)",
         "data": "synthetic",
         "config": {"workload": WORKLOADS.get(cfg, str(cfg)), "ndof": n, "nrhs": nrhs,
                    "elements": int(len(md["level"])), "rtol": c["rtol"]},
+        "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
         "solve": {"iters": it, "true_rel_res": max(i["true_rel_res"] for i in infos),
                   "cond_est": infos[0]["cond_est"], "setup_s": t_setup},
-        "apply": {"gdof_per_s": gdofs, "us_per_apply": t_apply * 1e6,
-                  "hbm_frac_16B_per_dof": apply_bytes / t_apply / HBM_PEAK},
-        "roofline": {"bound": "hbm", "achieved": apply_bytes / t_apply / 1e9, "peak": HBM_PEAK / 1e9,
-                     "unit": "GB/s", "frac": apply_bytes / t_apply / HBM_PEAK, "traffic": None,
-                     "kernel": "apply_A (volume + face kernels), 16 B/DOF"},
+        "apply": {"gdof_per_s": n * nrhs / t_apply / 1e9, "us_per_apply": t_apply * 1e6},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": kernel, "bytes_per_launch": algo_bytes,
+                     "us_per_launch": t_apply * 1e6},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
 
 
-def cpu_baseline(md, c, gpu_iters):
-    """The oracle (numpy/scipy FP64) on this host: setup excluded, a bounded
-    sample of PCG iterations (one A apply and one B apply each), scaled to
-    the GPU's iteration count to give solves/s."""
+def cpu_baseline(cfg, c, gpu_iters, n_full, iters=10):
+    """The FP64 oracle (numpy/scipy) on this host, on a bounded sample: the
+    same refinement recipe with n_base/4 (1/16 of the elements), `iters`
+    oracle PCG iterations (one matrix-free A apply and one B apply each, the
+    oracle's own preconditioner, setup excluded), scaled to the full
+    workload by DOFs x iterations."""
     import numpy as np
+    import hpinputs as H
     import oracle as O
-    from oracle import dg, precond
+    from oracle import dg, pcg, precond
+    if cfg not in (1, 2):
+        return None
     try:
         from threadpoolctl import threadpool_info
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:
         threads = 1
+    md = H.config_mesh(cfg, scale=4 if cfg == 2 else 1)
     m = O.Mesh(md)
     opts = O.Opts(c["form"], c["penalty_rule"], c["eta"])
     pc = precond.Preconditioner(m, opts)
-    r = np.random.default_rng(0).standard_normal(m.ndof)
-    k = 0
+    b = dg.rhs(m, H.gaussian_rhs(m.ndof, 2002))
     t0 = time.perf_counter()
-    while time.perf_counter() - t0 < 15.0 and k < 50:
-        y = dg.apply(m, opts, r)
-        r = pc.apply(y / np.linalg.norm(y))
-        k += 1
-    per_it = (time.perf_counter() - t0) / k
-    return {"value": 1.0 / (per_it * gpu_iters), "unit": "solves/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"{k} oracle PCG iterations (matrix-free A + B) on the full mesh, "
-                      f"{per_it:.2f} s each, scaled to {gpu_iters} iterations; setup excluded; "
-                      f"host cores {os.cpu_count()}"}
+    _, info = pcg.pcg(lambda v: dg.apply(m, opts, v), pc.apply, b, 1e-30, iters)
+    t = time.perf_counter() - t0
+    per_dof_it = t / (m.ndof * max(info["iters"], 1))
+    t_full = per_dof_it * n_full * gpu_iters
+    return {"value": 1.0 / t_full, "unit": "solves/s", "cores": threads, "kind": "oracle",
+            "sample": (f"{info['iters']} oracle PCG iterations (matrix-free A and B applies) on the same "
+                       f"recipe at n_base/4 ({m.ndof} DOFs), {t:.1f} s, setup excluded; scaled by "
+                       f"DOFs x iterations to {n_full} DOFs and {gpu_iters} iterations; "
+                       f"host os.cpu_count()={os.cpu_count()}, BLAS threads {threads}")}
 
 
 if __name__ == "__main__":

@@ -125,8 +125,8 @@ hpdg_status hpdg_pcg_solve(hpdg_operator* op, const double* b, double* x, int nr
  *  3 A~_C as CSR (same layout)  4 V_e blocks: int64 nblocks, ptr[nb+1] int64,
  *    dofs int64                 5 DG node coordinates [ndof*dim] double
  *  6 AMG level sizes: int64 nlevels, rows[nlevels] int64
- *  7 summary: int64[8] = ndof, nconf, nblocks, max block, block entries,
- *    amg levels, nnz(A~_C), nnz(P)
+ *  7 summary: int64[9] = ndof, nconf, nblocks, max block, block entries,
+ *    amg levels, nnz(A~_C), nnz(P), bytes of the face-matrix table
  *  100+l  AMG level-l matrix A_l as CSR;  200+l  AMG prolongator P_l as CSR;
  *  300+l  aggregate index of every row of level l, int64
  * bytes: in: capacity of buf; out: bytes needed. buf NULL queries the size. */

@@ -221,5 +221,6 @@ class Operator:
         return v[1:1 + int(v[0])].tolist()
 
     def summary(self):
-        keys = ["ndof", "nconf", "nblocks", "max_block", "block_entries", "amg_levels", "nnz_AC", "nnz_P"]
+        keys = ["ndof", "nconf", "nblocks", "max_block", "block_entries", "amg_levels", "nnz_AC", "nnz_P",
+                "face_table_bytes"]
         return dict(zip(keys, (int(v) for v in self.export(7).view(np.int64))))

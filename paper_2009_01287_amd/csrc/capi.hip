@@ -149,7 +149,11 @@ struct hpdg_operator {
   int ncoarse = 0;
   DevBuf rT, zT, rc;       // T work vectors (DG and conforming sizes)
   // CG work (double)
-  DevBuf r, z, pv, Ap, part, scal, act, ahist, bhist;
+  DevBuf r, z, pv, Ap, part, scal, iscal, ticket, act, ahist, bhist;
+  int64_t hist_cap = 0;
+  int64_t ftab_bytes = 0;
+  int* hpoll = nullptr;     // pinned host flags
+  ~hpdg_operator() { if (hpoll) (void)hipHostFree(hpoll); }
   PrecHost host;           // kept for export
   std::vector<double> coords;
 };
@@ -398,28 +402,23 @@ extern "C" hpdg_status hpdg_setup_operator(const hpdg_mesh* mh, const hpdg_opera
       for (int g = 0; g < q; ++g) lagrange_eval(basis(p).x, a + len * gx[g], &out[g * (p + 1)]);
       return gw;
     };
-    auto face_mats = [&](int p, int oc, int po, int nc, int q) -> int32_t {
-      std::array<int, 5> key{p, oc, po, nc, q};
+    // exact integrals: the matrices depend on the degrees and codes only
+    auto face_mat = [&](int p, int oc, int po, int nc) -> int32_t {
+      std::array<int, 5> key{p, oc, po, nc, 0};
       auto it = fmap.find(key);
       if (it != fmap.end()) return it->second;
       int32_t at = (int32_t)ftab.size();
+      int q = std::max(p, po) + 1;
       std::vector<double> Io, In;
       std::vector<double> gw = sub_vals(p, oc, q, Io);
+      sub_vals(po, nc, q, In);
       int n = p + 1, no = po + 1;
-      auto mass = [&](const std::vector<double>& A, int na, const std::vector<double>& B, int nb) {
-        for (int j = 0; j < na; ++j)
-          for (int jj = 0; jj < nb; ++jj) {
-            double s = 0;
-            for (int g = 0; g < q; ++g) s += gw[g] * A[g * na + j] * B[g * nb + jj];
-            ftab.push_back(s);
-          }
-      };
-      mass(Io, n, Io, n);
-      if (po > 0) {
-        sub_vals(po, nc, q, In);
-        mass(Io, n, In, no);
-        mass(In, no, In, no);
-      }
+      for (int j = 0; j < n; ++j)
+        for (int jj = 0; jj < no; ++jj) {
+          double s = 0;
+          for (int g = 0; g < q; ++g) s += gw[g] * Io[g * n + j] * In[g * no + jj];
+          ftab.push_back(s);
+        }
       fmap.emplace(key, at);
       return at;
     };
@@ -443,7 +442,13 @@ extern "C" hpdg_status hpdg_setup_operator(const hpdg_mesh* mh, const hpdg_opera
         }
         r.flen = (double)(f.hi[tdim[0]] - f.lo[tdim[0]]) / (double)M.N;
         r.sig = sig;
-        r.ftype = d == 2 ? face_mats(M.p[e], r.oc[0], nb >= 0 ? M.p[nb] : 0, r.nc[0], qv) : 0;
+        if (d == 2) {
+          r.foo = face_mat(M.p[e], r.oc[0], M.p[e], r.oc[0]);
+          if (nb >= 0) {
+            r.fon = face_mat(M.p[e], r.oc[0], M.p[nb], r.nc[0]);
+            r.fnn = face_mat(M.p[nb], r.nc[0], M.p[nb], r.nc[0]);
+          }
+        }
         per[(size_t)e * 2 * d + 2 * f.m + side].push_back(r);
       };
       if (f.ep >= 0) {
@@ -464,6 +469,7 @@ extern "C" hpdg_status hpdg_setup_operator(const hpdg_mesh* mh, const hpdg_opera
     op->bucket.assign(kMaxP + 1, {});
     for (int e = 0; e < M.ne; ++e) op->bucket[M.p[e]].push_back(e);
     if (ftab.size() > (size_t)INT32_MAX) throw Error(HPDG_E_UNSUPPORTED, "face table too large");
+    op->ftab_bytes = (int64_t)(ftab.size() * sizeof(double));
     if (!op->host_only) {
       op->sptr.upload(sptr);
       op->recs.upload(recs);
@@ -501,9 +507,13 @@ extern "C" hpdg_status hpdg_setup_operator(const hpdg_mesh* mh, const hpdg_opera
       }
       H.blocks.swap(keep);
     }
+    // inverse diagonal on V_J, +0 on interior DOFs, -0 on V_e DOFs (marks
+    // the DOFs that the block solves write)
     H.dinvJ.assign(M.ndof, 0.0);
-    for (int64_t g = 0; g < M.ndof; ++g)
+    for (int64_t g = 0; g < M.ndof; ++g) {
       if (H.lab[g] == 1) H.dinvJ[g] = 1.0 / H.diag[g];
+      else if (H.lab[g] == 2) H.dinvJ[g] = -0.0;
+    }
     phase("edge spaces");
     std::vector<double> binv;
     for (auto& B : H.blocks) {
@@ -555,7 +565,12 @@ extern "C" hpdg_status hpdg_setup_operator(const hpdg_mesh* mh, const hpdg_opera
     op->Ap.alloc(nv);
     op->part.alloc((size_t)1024 * 256 * sizeof(double));
     op->scal.alloc((size_t)16 * 256 * sizeof(double));
+    op->iscal.alloc((size_t)4 * 256 * sizeof(int));
     op->act.alloc((size_t)256 * sizeof(int));
+    op->ticket.alloc(64 * sizeof(unsigned));
+    HIPCHK(hipMemset(op->ticket.p, 0, 64 * sizeof(unsigned)));
+    HIPCHK(hipMemset(op->iscal.p, 0, 4 * 256 * sizeof(int)));
+    HIPCHK(hipHostMalloc((void**)&op->hpoll, 256 * sizeof(int), hipHostMallocDefault));
     HIPCHK(hipDeviceSynchronize());
     *out = op.release();
     return HPDG_OK;
@@ -594,7 +609,8 @@ static void launch_vol(hpdg_operator* op, int nrhs, const double* x, double* y, 
 
 static void apply_A_dev(hpdg_operator* op, const double* x, double* y, int nrhs, hipStream_t s) {
   if (op->dim == 2 && nrhs == 1 && !op->generic_faces) {
-    hipLaunchKernelGGL(k_elem2d, dim3(op->ne), dim3(64), 0, s, op->ne, op->form, op->off.as<int64_t>(),
+    const unsigned grid = 8u * (unsigned)((op->ne + 7) / 8);   // k_elem2d needs a multiple of 8
+    hipLaunchKernelGGL(k_elem2d, dim3(grid), dim3(64), 0, s, op->ne, op->form, op->off.as<int64_t>(),
                        op->pdeg.as<int8_t>(), op->hh.as<double>(), op->kk.as<double>(), op->sptr.as<int32_t>(),
                        op->recs.as<FaceRec>(), op->ftab.as<double>(), op->tab.as<double>(), op->TL, x, y);
   } else if (op->dim == 2) {
@@ -674,24 +690,42 @@ static void apply_B_dev(hpdg_operator* op, const double* r, double* z, int nrhs,
     rt = op->rT.as<T>();
   }
   T* zb = op->zT.as<T>();
-  hipLaunchKernelGGL(k_diag_scale<T>, dim3(nblk(n)), dim3(256), 0, s, n, nrhs, op->dinvJ.as<T>(), rt, zb);
-  if (op->blk_rows > 0) {
-    if (nrhs == 1) {
-      int64_t nt = op->blk_rows * 16;
-      hipLaunchKernelGGL((k_block_gemv1<T, 16>), dim3(nblk(nt)), dim3(256), 0, s, op->blk_rows,
-                         op->blk_rowb.as<int32_t>(), op->blk_rowl.as<int32_t>(), op->blk_ptr.as<int64_t>(),
-                         op->blk_off.as<int64_t>(), op->blk_dof.as<int32_t>(), op->blk_inv.as<T>(), rt, zb);
-    } else {
+  LevelDev& L0 = op->lv[0];
+  if (nrhs == 1) {
+    const DevCSR& A = op->PT;
+    int nb_diag = (int)nblk(op->ndof);
+    int nb_blk = (int)nblk(op->blk_rows * 16);
+    int nlb = (A.nlong + 3) / 4;
+    int nshort = A.nrows - A.nlong;
+    auto launch = [&](auto lprp) {
+      constexpr int LP = decltype(lprp)::value;
+      unsigned grid = (unsigned)(nb_diag + nb_blk + nlb + (int)nblk((int64_t)nshort * LP));
+      hipLaunchKernelGGL((k_front<T, 16, LP>), dim3(grid), dim3(256), 0, s, op->ndof, nb_diag, op->dinvJ.as<T>(),
+                         op->blk_rows, nb_blk, op->blk_rowb.as<int32_t>(), op->blk_rowl.as<int32_t>(),
+                         op->blk_ptr.as<int64_t>(), op->blk_off.as<int64_t>(), op->blk_dof.as<int32_t>(),
+                         op->blk_inv.as<T>(), A.nlong, nlb, nshort, A.rows.as<int32_t>(), A.ptr.as<int32_t>(),
+                         A.idx.as<int32_t>(), A.val.as<T>(), rt, zb, L0.b.as<T>());
+    };
+    switch (A.lpr) {
+      case 1: launch(std::integral_constant<int, 1>()); break;
+      case 2: launch(std::integral_constant<int, 2>()); break;
+      case 4: launch(std::integral_constant<int, 4>()); break;
+      case 8: launch(std::integral_constant<int, 8>()); break;
+      default: launch(std::integral_constant<int, 16>()); break;
+    }
+  } else {
+    hipLaunchKernelGGL(k_diag_scale<T>, dim3(nblk(n)), dim3(256), 0, s, n, nrhs, op->dinvJ.as<T>(), rt, zb);
+    if (op->blk_rows > 0) {
       int64_t nt = op->blk_rows * nrhs;
       hipLaunchKernelGGL(k_block_gemv<T>, dim3(nblk(nt)), dim3(256), 0, s, op->blk_rows, nrhs,
                          op->blk_rowb.as<int32_t>(), op->blk_rowl.as<int32_t>(), op->blk_ptr.as<int64_t>(),
                          op->blk_off.as<int64_t>(), op->blk_dof.as<int32_t>(), op->blk_inv.as<T>(), rt, zb);
     }
+    spmv<T, 0>(op->PT, nrhs, rt, nullptr, nullptr, nullptr, L0.b.as<T>(), s);
   }
-  LevelDev& L0 = op->lv[0];
-  spmv<T, 0>(op->PT, nrhs, rt, nullptr, nullptr, nullptr, L0.b.as<T>(), s);
   vcycle<T>(op, 0, nrhs, s);
   int64_t nt = op->ndof * nrhs;
+  (void)L0;
   hipLaunchKernelGGL(k_prolong_out<T>, dim3(nblk(nt)), dim3(256), 0, s, (int)op->ndof, nrhs,
                      op->P.ptr.as<int32_t>(), op->P.idx.as<int32_t>(), op->P.val.as<T>(), L0.x.as<T>(), zb, z);
 }
@@ -779,6 +813,16 @@ static void tridiag_extremes(const std::vector<double>& a, const std::vector<dou
   lmax = kth(n - 1);
 }
 
+// dot product with a scalar epilogue: per-block partials, then one block
+// that sums them in a fixed order and updates the CG scalars
+static void dot_ep(hpdg_operator* op, const double* a, const double* b, int nrhs, int mode, const CGScal& S,
+                   hipStream_t s) {
+  int64_t n = op->ndof * nrhs;
+  int nb = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n + 1023) / 1024));
+  hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(256), 0, s, n, nrhs, a, b, op->part.as<double>());
+  hipLaunchKernelGGL(k_dot_final_ep, dim3(1), dim3(256), 0, s, nb, nrhs, op->part.as<double>(), mode, S);
+}
+
 extern "C" hpdg_status hpdg_pcg_solve(hpdg_operator* op, const double* b, double* x, int nrhs, double rtol,
                                       int maxit, void* stream, hpdg_solve_info* info) {
   hpdg_status st = check_vec_args(op, b, x, nrhs);
@@ -792,101 +836,102 @@ extern "C" hpdg_status hpdg_pcg_solve(hpdg_operator* op, const double* b, double
     double* z = op->z.as<double>();
     double* p = op->pv.as<double>();
     double* Ap = op->Ap.as<double>();
-    double* S = op->scal.as<double>();
-    // scalar slots of nrhs doubles: 0 rz, 1 pAp, 2 rr, 3 bb, 4 rznew, 5 beta
-    double *rz = S, *pAp = S + 256, *rr = S + 512, *bb = S + 768, *rzn = S + 1024, *beta = S + 1280;
-    int* act = op->act.as<int>();
+    if ((int64_t)maxit + 1 > op->hist_cap) {
+      op->hist_cap = std::max<int64_t>((int64_t)maxit + 1, 1024);
+      op->ahist.alloc((size_t)op->hist_cap * 256 * sizeof(double));
+      op->bhist.alloc((size_t)op->hist_cap * 256 * sizeof(double));
+    }
+    double* D = op->scal.as<double>();
+    int* I = op->iscal.as<int>();
+    CGScal S;
+    S.rz = D; S.pAp = D + 256; S.rr = D + 512; S.bb = D + 768; S.alpha = D + 1024; S.beta = D + 1280;
+    S.tol2 = D + 1536;
+    S.act = I; S.iters = I + 256; S.err = I + 512;
+    S.ahist = op->ahist.as<double>();
+    S.bhist = op->bhist.as<double>();
+    S.maxit = (int)op->hist_cap;
+    std::vector<double> tol2(nrhs, rtol * rtol);
+    HIPCHK(hipMemcpyAsync(S.tol2, tol2.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, s));
     auto applyB = [&](const double* in, double* outv) {
       if (op->prec32) apply_B_dev<float>(op, in, outv, nrhs, s);
       else apply_B_dev<double>(op, in, outv, nrhs, s);
     };
-    // r = b - A x
+    // r = b - A x ; z = B r ; p = z
     apply_A_dev(op, x, Ap, nrhs, s);
     hipLaunchKernelGGL(k_sub, dim3(nblk(n)), dim3(256), 0, s, n, b, Ap, r);
-    dot_dev(op, b, b, nrhs, bb, s);
-    dot_dev(op, r, r, nrhs, rr, s);
+    dot_ep(op, b, b, nrhs, EP_BB, S, s);
+    dot_ep(op, r, r, nrhs, EP_RR0, S, s);
     applyB(r, z);
     HIPCHK(hipMemcpyAsync(p, z, n * sizeof(double), hipMemcpyDeviceToDevice, s));
-    dot_dev(op, r, z, nrhs, rz, s);
-    std::vector<double> hbb(nrhs), hrr(nrhs), hrz(nrhs), hpap(nrhs);
-    std::vector<int> hact(nrhs, 1);
-    HIPCHK(hipMemcpyAsync(hbb.data(), bb, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(hrr.data(), rr, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(hrz.data(), rz, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+    dot_ep(op, r, z, nrhs, EP_RZ0, S, s);
+    std::vector<double> hbb(nrhs);
+    HIPCHK(hipMemcpyAsync(hbb.data(), S.bb, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    std::vector<std::vector<double>> al(nrhs), be(nrhs);
-    std::vector<int> iters(nrhs, 0);
-    bool breakdown = false;
-    for (int c = 0; c < nrhs; ++c) {
-      if (!std::isfinite(hbb[c]) || !std::isfinite(hrr[c])) throw Error(HPDG_E_INVALID, "non-finite right-hand side");
-      if (std::sqrt(hrr[c]) <= rtol * std::sqrt(hbb[c])) hact[c] = 0;
-    }
-    HIPCHK(hipMemcpyAsync(act, hact.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, s));
+    for (int c = 0; c < nrhs; ++c)
+      if (!std::isfinite(hbb[c])) throw Error(HPDG_E_INVALID, "non-finite right-hand side");
+    int* poll = op->hpoll;   // pinned: act[nrhs]
     int it = 0;
-    auto any_active = [&]() { for (int c = 0; c < nrhs; ++c) if (hact[c]) return true; return false; };
-    std::vector<double> hrzn(nrhs), hbeta(nrhs);
-    while (any_active() && it < maxit) {
+    const int check_every = 4;
+    while (it < maxit) {
       apply_A_dev(op, p, Ap, nrhs, s);
-      dot_dev(op, p, Ap, nrhs, pAp, s);
-      hipLaunchKernelGGL(k_cg_update, dim3(nblk(n)), dim3(256), 0, s, n, nrhs, rz, pAp, act, p, Ap, x, r);
-      dot_dev(op, r, r, nrhs, rr, s);
-      HIPCHK(hipMemcpyAsync(hpap.data(), pAp, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipMemcpyAsync(hrr.data(), rr, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipStreamSynchronize(s));
-      ++it;
-      bool changed = false;
-      for (int c = 0; c < nrhs; ++c) {
-        if (!hact[c]) continue;
-        if (!(hpap[c] > 0) || !(hrz[c] > 0)) { breakdown = true; hact[c] = 0; changed = true; continue; }
-        al[c].push_back(hrz[c] / hpap[c]);
-        iters[c] = it;
-        if (std::sqrt(hrr[c]) <= rtol * std::sqrt(hbb[c])) { hact[c] = 0; changed = true; }
-      }
-      if (changed) HIPCHK(hipMemcpyAsync(act, hact.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, s));
-      if (!any_active()) break;
+      dot_ep(op, p, Ap, nrhs, EP_PAP, S, s);
+      hipLaunchKernelGGL(k_cg_update2, dim3(nblk(n)), dim3(256), 0, s, n, nrhs, S.alpha, p, Ap, x, r);
+      dot_ep(op, r, r, nrhs, EP_RR, S, s);
       applyB(r, z);
-      dot_dev(op, r, z, nrhs, rzn, s);
-      HIPCHK(hipMemcpyAsync(hrzn.data(), rzn, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipStreamSynchronize(s));
-      for (int c = 0; c < nrhs; ++c) {
-        hbeta[c] = hact[c] ? hrzn[c] / hrz[c] : 0.0;
-        if (hact[c]) { be[c].push_back(hbeta[c]); hrz[c] = hrzn[c]; }
+      dot_ep(op, r, z, nrhs, EP_RZ, S, s);
+      hipLaunchKernelGGL(k_cg_dir2, dim3(nblk(n)), dim3(256), 0, s, n, nrhs, S.beta, S.act, z, p);
+      ++it;
+      if (it % check_every == 0 || it == maxit || it == 1) {
+        HIPCHK(hipMemcpyAsync(poll, S.act, nrhs * sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        bool any = false;
+        for (int c = 0; c < nrhs; ++c) any |= poll[c] != 0;
+        if (!any) break;
       }
-      HIPCHK(hipMemcpyAsync(beta, hbeta.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, s));
-      HIPCHK(hipMemcpyAsync(rz, hrz.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, s));
-      hipLaunchKernelGGL(k_cg_dir, dim3(nblk(n)), dim3(256), 0, s, n, nrhs, beta, act, z, p);
     }
     // true residual in FP64
     apply_A_dev(op, x, Ap, nrhs, s);
     hipLaunchKernelGGL(k_sub, dim3(nblk(n)), dim3(256), 0, s, n, b, Ap, r);
-    dot_dev(op, r, r, nrhs, rr, s);
-    std::vector<double> htr(nrhs);
-    HIPCHK(hipMemcpyAsync(htr.data(), rr, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+    std::vector<double> hrr(nrhs), htr(nrhs);
+    HIPCHK(hipMemcpyAsync(hrr.data(), S.rr, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+    dot_ep(op, r, r, nrhs, EP_TRUE, S, s);
+    std::vector<int> hact(nrhs), hit(nrhs), herr(nrhs);
+    HIPCHK(hipMemcpyAsync(hact.data(), S.act, nrhs * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hit.data(), S.iters, nrhs * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(herr.data(), S.err, nrhs * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(htr.data(), S.rr, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+    int maxi = 0;
     HIPCHK(hipStreamSynchronize(s));
+    for (int c = 0; c < nrhs; ++c) maxi = std::max(maxi, hit[c]);
+    std::vector<double> ha((size_t)maxi * 256), hb((size_t)maxi * 256);
+    if (maxi > 0) {
+      HIPCHK(hipMemcpyAsync(ha.data(), S.ahist, (size_t)maxi * 256 * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(hb.data(), S.bhist, (size_t)maxi * 256 * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+    }
     double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    bool all_conv = true;
+    bool all_conv = true, breakdown = false;
     for (int c = 0; c < nrhs; ++c) {
       double bn = std::sqrt(hbb[c]);
-      bool conv = !hact[c] && !breakdown;
-      // recurrence residual of the last iterate
-      double rel = bn > 0 ? std::sqrt(hrr[c]) / bn : 0.0;
+      bool conv = !hact[c] && !herr[c];
+      breakdown |= herr[c] != 0;
       all_conv &= conv;
       if (info) {
-        hpdg_solve_info& I = info[c];
-        I.iters = iters[c];
-        I.converged = conv;
-        I.true_rel_res = bn > 0 ? std::sqrt(htr[c]) / bn : 0.0;
-        I.rel_res = rel;
-        // Lanczos tridiagonal of BA from the CG coefficients
-        size_t k = al[c].size();
-        std::vector<double> da(k), db(k > 0 ? k - 1 : 0);
-        for (size_t j = 0; j < k; ++j) {
-          da[j] = 1.0 / al[c][j] + (j > 0 ? be[c][j - 1] / al[c][j - 1] : 0.0);
-          if (j + 1 < k) db[j] = std::sqrt(be[c][j]) / al[c][j];
+        hpdg_solve_info& In = info[c];
+        In.iters = hit[c];
+        In.converged = conv;
+        In.rel_res = bn > 0 ? std::sqrt(hrr[c]) / bn : 0.0;
+        In.true_rel_res = bn > 0 ? std::sqrt(htr[c]) / bn : 0.0;
+        int kk = hit[c];
+        std::vector<double> da(kk), db(kk > 0 ? kk - 1 : 0);
+        for (int q = 0; q < kk; ++q) {
+          double aq = ha[(size_t)q * 256 + c];
+          da[q] = 1.0 / aq + (q > 0 ? hb[(size_t)(q - 1) * 256 + c] / ha[(size_t)(q - 1) * 256 + c] : 0.0);
+          if (q + 1 < kk) db[q] = std::sqrt(hb[(size_t)q * 256 + c]) / aq;
         }
-        tridiag_extremes(da, db, I.lambda_min, I.lambda_max);
-        I.cond_est = I.lambda_max / I.lambda_min;
-        I.t_solve_s = secs;
+        tridiag_extremes(da, db, In.lambda_min, In.lambda_max);
+        In.cond_est = In.lambda_max / In.lambda_min;
+        In.t_solve_s = secs;
       }
     }
     if (breakdown) return fail(HPDG_E_NOT_SPD, "CG breakdown: p'Ap <= 0 or r'z <= 0");
@@ -943,7 +988,7 @@ extern "C" hpdg_status hpdg_export(const hpdg_operator* op, int what, void* buf,
       int64_t mx = 0, ent = 0;
       for (auto& b : H.blocks) { mx = std::max<int64_t>(mx, b.size()); ent += (int64_t)b.size() * b.size(); }
       std::vector<int64_t> v{op->ndof, op->nconf, (int64_t)H.blocks.size(), mx, ent, (int64_t)H.amg.lv.size(),
-                             (int64_t)H.AC.idx.size(), (int64_t)H.P.idx.size()};
+                             (int64_t)H.AC.idx.size(), (int64_t)H.P.idx.size(), op->ftab_bytes};
       return put(v.data(), v.size(), buf, bytes);
     }
     default:

@@ -385,22 +385,23 @@ __global__ __launch_bounds__(64) void k_elem2d(int ne, int form, const int64_t* 
                                                const FaceRec* __restrict__ recs, const double* __restrict__ ftab,
                                                const double* __restrict__ tab, TableLayout TL,
                                                const double* __restrict__ x, double* __restrict__ y) {
-  __shared__ double sX[81], sA[81], sB[81], sM[81], sK[81];
+  __shared__ double sX[81], sA[81], sB[81];
   __shared__ double sTo[4][9], sDo[4][9], sTn[4][9], sDn[4][9], sV[4][9], sW[4][9];
   __shared__ double sG1[4][9], sG2[4][9];
-  __shared__ double sF[4][243];
   __shared__ int sCnt[4];
-  const int e = blockIdx.x;
+  // XCD-aware order: workgroups go round-robin to the 8 XCDs, so block b
+  // takes element (b % 8) * per + b / 8 and each XCD walks a contiguous range
+  // of the (space-filling ordered) element list; neighbours then share its L2
+  const int per = (int)(gridDim.x >> 3);
+  const int e = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
   if (e >= ne) return;
   const int lane = threadIdx.x;
   const int p = pdeg[e], n = p + 1, nn = n * n;
   const double h = hh[e], k = kk[e];
   const int64_t base = off[e];
-  for (int i = lane; i < nn; i += 64) {
-    sX[i] = x[base + i];
-    sM[i] = tab[TL.mk + (p * 2 + 0) * 81 + i];
-    sK[i] = tab[TL.mk + (p * 2 + 1) * 81 + i];
-  }
+  const double* sM = tab + TL.mk + (p * 2 + 0) * 81;    // 1D mass / stiffness (cached)
+  const double* sK = tab + TL.mk + (p * 2 + 1) * 81;
+  for (int i = lane; i < nn; i += 64) sX[i] = x[base + i];
   if (lane < 4) sCnt[lane] = sptr[e * 4 + lane + 1] - sptr[e * 4 + lane];
   __syncthreads();
   // volume, phase 1 (dimension 0)
@@ -447,10 +448,11 @@ __global__ __launch_bounds__(64) void k_elem2d(int ne, int form, const int64_t* 
     FaceRec f;
     f.nbr = -1;
     f.q = 0;
-    f.ftype = 0;
+    f.foo = f.fon = f.fnn = 0;
     f.flen = 0.0;
     f.sig = 0.0;
     if (have) f = recs[rb + fi];
+    const double flen = f.flen;
     const bool inner = have && f.nbr >= 0;
     int po = 0, no = 0;
     double ho = 1.0, ko = 0.0;
@@ -461,8 +463,6 @@ __global__ __launch_bounds__(64) void k_elem2d(int ne, int form, const int64_t* 
       ko = kk[f.nbr];
     }
     // stage this face's matrices (A_oo n*n, A_on n*no, A_nn no*no) in LDS
-    const int fsz = have ? n * n + (inner ? n * no + no * no : 0) : 0;
-    for (int t = j; t < fsz; t += 9) sF[sidx][t] = ftab[f.ftype + t];
     if (inner && j < no) {
       const int so = 1 - s;
       const int som = m == 0 ? 1 : no, sot = m == 0 ? no : 1;
@@ -474,9 +474,9 @@ __global__ __launch_bounds__(64) void k_elem2d(int ne, int form, const int64_t* 
       sDn[sidx][j] = dv / ho;
     }
     __syncthreads();
-    const double* Aoo = sF[sidx];
-    const double* Aon = sF[sidx] + n * n;
-    const double* Ann = Aon + n * no;
+    const double* Aoo = ftab + f.foo;     // face matrices (cached)
+    const double* Aon = ftab + f.fon;
+    const double* Ann = ftab + f.fnn;
     double v = 0.0, dsum = 0.0;
     if (have && j < n) {
       for (int a = 0; a < n; ++a) {
@@ -488,14 +488,14 @@ __global__ __launch_bounds__(64) void k_elem2d(int ne, int form, const int64_t* 
         dsum += ko * Aon[j * no + a] * sDn[sidx][a];
       }
       const double csym = inner ? 0.5 : 1.0;
-      G1 -= f.flen * csym * sgn * dsum;
-      G2 -= csym * k * sgn * f.flen * v;
-      if (form == 0) G1 += f.flen * f.sig * v;
+      G1 -= flen * csym * sgn * dsum;
+      G2 -= csym * k * sgn * flen * v;
+      if (form == 0) G1 += flen * f.sig * v;
       sV[sidx][j] = v;
     }
     if (form == 1) {
       const double c2 = inner ? 0.25 : 1.0;
-      const double L2 = c2 * f.sig * f.flen * f.flen;
+      const double L2 = c2 * f.sig * flen * flen;
       // own lifting: G1 += L2 s_o A_oo Minv_o v
       __syncthreads();
       if (have && j < n) {
@@ -608,6 +608,135 @@ __global__ __launch_bounds__(256) void k_dot_final(int nblocks, int nrhs, const 
     __syncthreads();
   }
   if (t < nrhs) out[t] = sm[t];
+}
+
+// CG scalars on the device, one slot per RHS (SoA, stride 256):
+struct CGScal {
+  double *rz, *pAp, *rr, *bb, *alpha, *beta, *tol2;
+  int *act, *iters, *err;
+  double *ahist, *bhist;   // [maxit * nrhs]
+  int maxit;
+};
+
+// epilogue of a dot product for RHS c with value v
+enum { EP_BB = 0, EP_RR0 = 1, EP_RZ0 = 2, EP_PAP = 3, EP_RR = 4, EP_RZ = 5, EP_TRUE = 6 };
+__device__ inline void cg_epilogue(int mode, int c, double v, CGScal S) {
+  switch (mode) {
+    case EP_BB: S.bb[c] = v; break;
+    case EP_RR0:
+      S.rr[c] = v;
+      S.iters[c] = 0;
+      S.err[c] = 0;
+      S.act[c] = (v > S.tol2[c] * S.bb[c]) ? 1 : 0;
+      break;
+    case EP_RZ0:
+      S.rz[c] = v;
+      if (S.act[c] && !(v > 0.0)) { S.err[c] = 1; S.act[c] = 0; }
+      break;
+    case EP_PAP:
+      S.pAp[c] = v;
+      if (S.act[c] && !(v > 0.0)) { S.err[c] = 1; S.act[c] = 0; }
+      S.alpha[c] = S.act[c] ? S.rz[c] / v : 0.0;
+      break;
+    case EP_RR:
+      S.rr[c] = v;
+      if (S.act[c]) {
+        int it = S.iters[c];
+        if (it < S.maxit) S.ahist[(int64_t)it * 256 + c] = S.alpha[c];
+        S.iters[c] = it + 1;
+        if (!(v > S.tol2[c] * S.bb[c])) S.act[c] = 0;
+      }
+      break;
+    case EP_RZ:
+      if (S.act[c]) {
+        if (!(v > 0.0)) { S.err[c] = 1; S.act[c] = 0; S.beta[c] = 0.0; break; }
+        double b = v / S.rz[c];
+        S.beta[c] = b;
+        S.rz[c] = v;
+        int it = S.iters[c];
+        if (it - 1 < S.maxit) S.bhist[(int64_t)(it - 1) * 256 + c] = b;
+      } else {
+        S.beta[c] = 0.0;
+      }
+      break;
+    default: S.rr[c] = v; break;   // EP_TRUE: true residual norm^2
+  }
+}
+
+// single-launch dot product a.b per RHS with a fixed-order last-block reduction
+// and a scalar epilogue. part: gridDim.x * nrhs doubles; ticket zeroed.
+__global__ __launch_bounds__(256) void k_dot_ep(int64_t n, int nrhs, const double* __restrict__ a,
+                                                const double* __restrict__ b, double* __restrict__ part,
+                                                unsigned* __restrict__ ticket, int mode, CGScal S) {
+  __shared__ double sm[256];
+  __shared__ int last;
+  const int tid = threadIdx.x;
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + tid; i < n; i += (int64_t)gridDim.x * 256) acc += a[i] * b[i];
+  sm[tid] = acc;
+  __syncthreads();
+  for (int w = 128; w >= nrhs; w >>= 1) {
+    if (tid < w) sm[tid] += sm[tid + w];
+    __syncthreads();
+  }
+  if (tid < nrhs)
+    __hip_atomic_store(&part[blockIdx.x * nrhs + tid], sm[tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) last = atomicAdd(ticket, 1u) == gridDim.x - 1;
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  const int c = tid % nrhs, g = tid / nrhs, ng = 256 / nrhs;
+  double s = 0.0;
+  for (int q = g; q < (int)gridDim.x; q += ng)
+    s += __hip_atomic_load(&part[q * nrhs + c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  sm[tid] = s;
+  __syncthreads();
+  for (int w = 128; w >= nrhs; w >>= 1) {
+    if (tid < w) sm[tid] += sm[tid + w];
+    __syncthreads();
+  }
+  if (tid < nrhs) cg_epilogue(mode, tid, sm[tid], S);
+  if (tid == 0) *ticket = 0u;
+}
+
+// final stage of a dot product (partials from k_dot_partial) with the scalar
+// epilogue; one block of 256 threads, fixed summation order
+__global__ __launch_bounds__(256) void k_dot_final_ep(int nblocks, int nrhs, const double* __restrict__ part,
+                                                      int mode, CGScal S) {
+  __shared__ double sm[256];
+  const int t = threadIdx.x;
+  const int c = t % nrhs, g = t / nrhs, ng = 256 / nrhs;
+  double s = 0.0;
+  for (int b = g; b < nblocks; b += ng) s += part[b * nrhs + c];
+  sm[t] = s;
+  __syncthreads();
+  for (int w = 128; w >= nrhs; w >>= 1) {
+    if (t < w) sm[t] += sm[t + w];
+    __syncthreads();
+  }
+  if (t < nrhs) cg_epilogue(mode, t, sm[t], S);
+}
+
+// x += alpha p ; r -= alpha Ap (alpha = 0 for converged RHS)
+__global__ void k_cg_update2(int64_t n, int nrhs, const double* __restrict__ alpha,
+                             const double* __restrict__ p, const double* __restrict__ Ap, double* __restrict__ x,
+                             double* __restrict__ r) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double al = alpha[i % nrhs];
+  x[i] += al * p[i];
+  r[i] -= al * Ap[i];
+}
+
+// p = z + beta p while active
+__global__ void k_cg_dir2(int64_t n, int nrhs, const double* __restrict__ beta, const int* __restrict__ act,
+                          const double* __restrict__ z, double* __restrict__ p) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int c = (int)(i % nrhs);
+  if (act[c]) p[i] = z[i] + beta[c] * p[i];
 }
 
 // x += alpha p ; r -= alpha Ap, alpha[r] = act ? rz/pAp : 0
@@ -759,6 +888,75 @@ __global__ __launch_bounds__(256) void k_block_gemv1(int64_t nrows, const int32_
 #pragma unroll
   for (int o = LPR / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, LPR);
   if (sub == 0) z[bdof[s0 + i]] = acc;
+}
+
+// front of B (nrhs == 1): three independent pieces in one launch, split by
+// block index: [0, nb_diag) point Jacobi z = dinv . r on all DOFs,
+// [nb_diag, nb_diag + nb_blk) V_e block solves (LPR lanes per block row),
+// the rest r_c = P^T r (binned rows as in k_spmv).
+template <typename T, int LPRB, int LPRP>
+__global__ __launch_bounds__(256) void k_front(int64_t ndof, int nb_diag, const T* __restrict__ dinv,
+                                               int64_t brows, int nb_blk, const int32_t* __restrict__ row_blk,
+                                               const int32_t* __restrict__ row_loc,
+                                               const int64_t* __restrict__ bptr, const int64_t* __restrict__ boff,
+                                               const int32_t* __restrict__ bdof, const T* __restrict__ binv,
+                                               int nlong, int nlong_blk, int nshort,
+                                               const int32_t* __restrict__ rows, const int32_t* __restrict__ ptr,
+                                               const int32_t* __restrict__ idx, const T* __restrict__ val,
+                                               const T* __restrict__ r, T* __restrict__ z, T* __restrict__ rc) {
+  int b = blockIdx.x;
+  if (b < nb_diag) {
+    // V_e DOFs carry dinv = -0.0 and are written by the block part only
+    int64_t i = (int64_t)b * 256 + threadIdx.x;
+    if (i < ndof) {
+      T d = dinv[i];
+      if (!signbit(d)) z[i] = d * r[i];
+    }
+    return;
+  }
+  b -= nb_diag;
+  if (b < nb_blk) {
+    const int64_t gt = (int64_t)b * 256 + threadIdx.x;
+    const int64_t rw = gt / LPRB;
+    const int sub = (int)(gt % LPRB);
+    if (rw >= brows) return;
+    const int bk = row_blk[rw];
+    const int i = row_loc[rw];
+    const int64_t s0 = bptr[bk];
+    const int m = (int)(bptr[bk + 1] - s0);
+    const T* row = binv + boff[bk] + (int64_t)i * m;
+    T acc = 0;
+    for (int j = sub; j < m; j += LPRB) acc += row[j] * r[bdof[s0 + j]];
+#pragma unroll
+    for (int o = LPRB / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, LPRB);
+    // V_e DOFs have dinv = 0, so the block result is the whole value there
+    if (sub == 0) z[bdof[s0 + i]] = acc;
+    return;
+  }
+  b -= nb_blk;
+  if (b < nlong_blk) {
+    const int w = b * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (w >= nlong) return;
+    const int row = rows[w];
+    T acc = 0;
+    for (int q = ptr[row] + lane; q < ptr[row + 1]; q += 64) acc += val[q] * r[idx[q]];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (lane == 0) rc[row] = acc;
+    return;
+  }
+  b -= nlong_blk;
+  const int gt = b * 256 + threadIdx.x;
+  const int rr = gt / LPRP;
+  const int sub = gt % LPRP;
+  if (rr >= nshort) return;
+  const int row = rows[nlong + rr];
+  T acc = 0;
+  for (int q = ptr[row] + sub; q < ptr[row + 1]; q += LPRP) acc += val[q] * r[idx[q]];
+#pragma unroll
+  for (int o = LPRP / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, LPRP);
+  if (sub == 0) rc[row] = acc;
 }
 
 // exact V_e solves, interleaved RHS: one thread per (block row, rhs)

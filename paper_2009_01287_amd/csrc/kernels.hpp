@@ -16,11 +16,14 @@ struct FaceRec {
   int8_t pad0;
   uint8_t oc[2];    // sub-interval code of the face inside the own side, per tangential slot
   uint8_t nc[2];    // same inside the neighbour's side
-  int32_t ftype;    // offset (doubles) of the face's 1D face-mass matrices A_oo, A_on, A_nn
+  int32_t foo;      // offsets (doubles) in the face-matrix table of the unit-length 1D
+  int32_t fon;      //   face-mass matrices A_oo (own x own), A_on (own x neighbour),
+  int32_t fnn;      //   A_nn (neighbour x neighbour)
+  int32_t pad1;
   double flen;      // physical face side length
   double sig;       // SIPG penalty sigma, or eta*k_e for BR2
 };
-static_assert(sizeof(FaceRec) == 32, "FaceRec layout");
+static_assert(sizeof(FaceRec) == 48, "FaceRec layout");
 
 // Tables of the 1D basis, all degrees, in one device buffer (doubles).
 struct TableLayout {
