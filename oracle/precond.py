@@ -330,6 +330,7 @@ def broken_stiffness(mesh):
 
 # ------------------------------------------------------------- AMG (project)
 THETA = 0.08
+THETAS = (0.08, 0.04, 0.02, 0.01, 0.0)   # retried in order when a level stalls
 TIE = 1e-10
 
 
@@ -409,8 +410,9 @@ class AMG:
     filtered matrix (rows whose filtered diagonal is at most 1e-8 a_ii, e.g. a
     structural zero from a zero row sum, are not smoothed), w = (4/3)/rho, rho = max_i sum_j |a^F_ij| / a^F_ii;
     A_{l+1} = P_l^T A_l P_l. A level that would keep more than 0.8 of its
-    rows is retried with theta halved, at most twice; if it still stalls,
-    or at n <= 256 or 12 levels, coarsening stops. Coarsest level: dense
+    rows is retried with theta = 0.04, 0.02, 0.01 and 0 (every connection
+    strong); if it still stalls, or at n <= 256 or 12 levels, coarsening
+    stops. Coarsest level: dense
     Cholesky. Smoother: l1-Jacobi (d_i = sum_j |a_ij|), one pre- and one
     post-sweep from a zero initial guess. The V(1,1) cycle is symmetric."""
 
@@ -423,12 +425,10 @@ class AMG:
             n = Al.shape[0]
             if n <= min_rows or len(self.A) >= max_levels:
                 break
-            theta = THETA
-            for _ in range(3):
+            for theta in THETAS:
                 agg, na = aggregate(Al, theta)
                 if na <= max_ratio * n:
                     break
-                theta *= 0.5
             if na > max_ratio * n:
                 break
             Ph = sp.csr_matrix((np.ones(n), (np.arange(n), agg)), shape=(n, na))

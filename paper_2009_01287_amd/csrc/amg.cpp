@@ -15,11 +15,13 @@
 //   filtered matrix (weak off-diagonals dropped and added to the diagonal;
 //   rows whose filtered diagonal is at most 1e-8 a_ii are not smoothed),
 //   w = (4/3)/rho, rho = max_i sum_j |a^F_ij| / a^F_ii; A_{l+1} = P_l^T A_l P_l
-//   a level keeping > 0.8 of its rows is retried with theta halved (twice);
+//   a level keeping > 0.8 of its rows is retried with theta = 0.04, 0.02,
+//   0.01 and 0 (every connection strong);
 //   stop at <= 256 rows, 12 levels, or a level that still stalls;
 //   the coarsest level is solved exactly (dense Cholesky, stored inverse).
 #include <algorithm>
 #include <cmath>
+#include <string>
 
 #include "internal.hpp"
 
@@ -197,11 +199,12 @@ AMGHier amg_setup(const CSR& A0, int max_levels, int64_t min_rows, double max_ra
     if (n <= min_rows || (int)H.lv.size() >= max_levels) break;
     std::vector<int64_t> agg;
     int64_t na = 0;
-    double theta = 0.08;
-    for (int tr = 0; tr < 3; ++tr) {
+    const double thetas[5] = {0.08, 0.04, 0.02, 0.01, 0.0};
+    double theta = thetas[0];
+    for (int tr = 0; tr < 5; ++tr) {
+      theta = thetas[tr];
       aggregate(A, agg, na, theta);
       if ((double)na <= max_ratio * (double)n) break;
-      theta *= 0.5;
     }
     if ((double)na > max_ratio * (double)n) break;
     std::vector<double> d = csr_diag(A);
@@ -273,6 +276,7 @@ AMGHier amg_setup(const CSR& A0, int max_levels, int64_t min_rows, double max_ra
       for (int64_t q = L.A.ptr[i]; q < L.A.ptr[i + 1]; ++q) L.l1[i] += std::fabs(L.A.val[q]);
   }
   H.nc = H.lv.back().A.nrows;
+  if (H.nc > 4096) throw Error(-6, "AMG coarsening stalled with " + std::to_string(H.nc) + " rows on the coarsest level");
   if (H.nc > 0) dense_cholesky_inverse(H.lv.back().A, H.coarse_inv);
   return H;
 }
