@@ -27,7 +27,8 @@ HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
 WORKLOADS = {1: "cfg1_uniform4x4_p2_sipg_fp64",
              2: "cfg2_random2d_32x32_q0.3_L3_p1-8_sipg_fp64",
              3: "cfg3_random3d_16^3_q0.2_L2_p1-6_br2_fp32prec",
-             4: "cfg4_cfg2mesh_64rhs_fp32prec"}
+             4: "cfg4_cfg2mesh_64rhs_fp32prec",
+             5: "cfg5_serving_stream"}
 
 
 def main():
@@ -38,6 +39,12 @@ def main():
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--apply-reps", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--requests", type=int, default=2000, help="serving (--config 5): number of requests")
+    ap.add_argument("--rate", type=float, default=0.0,
+                    help="serving: Poisson arrival rate in requests/s (0: all arrive at the start)")
+    ap.add_argument("--workers", type=int, default=12, help="serving: host setup threads")
+    ap.add_argument("--max-active", type=int, default=16, help="serving: solves in flight")
+    ap.add_argument("--serving-prec", default="mixed", choices=["mixed", "fp64", "both"])
     ap.add_argument("--apply-only", action="store_true",
                     help="only run apply_A --apply-reps times and one calibration copy of "
                          "256 MiB (for hardware-counter runs), then exit")
@@ -54,6 +61,8 @@ def main():
     import paper_2009_01287_amd as G
 
     cfg = args.config
+    if cfg == 5:
+        return serve_bench(args)
     c = H.CONFIGS[cfg]
     md = H.config_mesh(cfg)
     nrhs = c["nrhs"]
@@ -148,6 +157,55 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
+
+
+def serve_bench(args):
+    """Serving stream: seeded requests (2D or 3D random hp meshes, 1e3..2e5
+    target DOFs log-uniform, p in 1..8, SIPG or BR2), each solved to 1e-8.
+    Meshes and load vectors are generated before the clock starts (they are
+    the clients' inputs); host setup, admission, upload and solve are inside
+    the measured latency."""
+    import numpy as np
+    import torch
+
+    import hpinputs as H
+    from paper_2009_01287_amd import serving as S
+    stream = H.serving_stream(args.requests, seed=5005, rate=args.rate or None)
+    reqs = []
+    for r in stream:
+        md = H.request_mesh(r)
+        reqs.append(S.Request(id=r["id"], mesh=md, form=r["form"], f=H.gaussian_rhs(H.ndof(md), r["rhs_seed"]),
+                              t_arrive=r["t_arrive"]))
+    torch.zeros(1, device="cuda")
+    out = {}
+    precs = ["mixed", "fp64"] if args.serving_prec == "both" else [args.serving_prec]
+    for prec in precs:
+        srv = S.Server(max_active=args.max_active, workers=args.workers, prec_fp32=(prec == "mixed"),
+                       realtime=args.rate > 0)
+        t0 = time.perf_counter()
+        res = srv.run(reqs)
+        wall = time.perf_counter() - t0
+        s = S.summarize(res, wall)
+        s["max_concurrent"] = srv.max_concurrent
+        s["peak_admitted_bytes"] = srv.gate.peak
+        s["gpu_busy_s"] = float(sum(r.t_done - r.t_admit for r in res if r.status == 0))
+        out[prec] = s
+        print(json.dumps({"serving_run": prec, **s}), file=sys.stderr, flush=True)
+    main_prec = precs[0]
+    s = out[main_prec]
+    line = {
+        "metric": "DG apply GDOF/s + %HBM peak; solves/s and p50/p99 latency at 1e-8 residual",
+        "value": s["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": args.requests, "warmup": 0,
+        "ms_per_step": 1e3 / s["solves_per_s"] if s["solves_per_s"] > 0 else None,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64 (operator, CG) + f32 (preconditioner)" if main_prec == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"cfg5_serving_{args.requests}req_2d3d_1e3-2e5dof_p1-8_sipg|br2",
+                   "rate": args.rate or "all at t=0", "max_active": args.max_active, "workers": args.workers},
+        "latency_ms": {"p50": s["p50_s"] * 1e3, "p99": s["p99_s"] * 1e3},
+        "serving": out,
+    }
+    print(json.dumps(line))
 
 
 def cpu_baseline(cfg, c, gpu_iters, n_full, iters=10):

@@ -39,11 +39,13 @@ typedef enum {
   HPDG_E_HIP = -3,           /* HIP runtime error */
   HPDG_E_NOT_SPD = -4,       /* CG breakdown: p'Ap <= 0 or r'z <= 0 */
   HPDG_E_NOT_CONVERGED = -5, /* maxit reached */
-  HPDG_E_UNSUPPORTED = -6
+  HPDG_E_UNSUPPORTED = -6,
+  HPDG_E_BUSY = -7           /* batch admission: no free slot (retry later) */
 } hpdg_status;
 
 typedef struct hpdg_mesh hpdg_mesh;
 typedef struct hpdg_operator hpdg_operator;
+typedef struct hpdg_batch hpdg_batch;
 
 const char* hpdg_last_error(void);
 
@@ -83,7 +85,10 @@ typedef struct {
  * faces and penalties, diag(A) and the V_J / V_e split (Sec. 3.3), the V_e
  * blocks and their inverses, the conforming prolongation P (Sec. 3.4), the
  * LOR matrix A~_C = P^T A~ P and its AMG hierarchy. The mesh may be destroyed
- * afterwards. The operator owns all its device memory until destroy. */
+ * afterwards. The operator owns all its device memory until destroy. Uploads
+ * are synchronous; the call ends with a synchronisation of `stream` only, so
+ * setups of different operators may run in parallel host threads while other
+ * operators solve on their own streams. */
 hpdg_status hpdg_setup_operator(const hpdg_mesh* mesh, const hpdg_operator_opts* opts, void* stream,
                                 hpdg_operator** out);
 void hpdg_operator_destroy(hpdg_operator* op);
@@ -113,10 +118,50 @@ typedef struct {
 /* PCG (Sec. 4.1) on T = BA, stopping at ||r_k||_2 <= rtol ||b||_2 (per RHS).
  * x holds the initial guess on entry and the result on exit (device,
  * ndof*nrhs). Blocks the host until done. info: host array [nrhs] or NULL.
+ * The flags are read back after the first iteration and then every 4; the
+ * Lanczos estimate uses the first 2048 iterations.
  * Returns HPDG_E_NOT_SPD on a breakdown and HPDG_E_NOT_CONVERGED at maxit
  * (x then holds the last iterate and info is filled). */
 hpdg_status hpdg_pcg_solve(hpdg_operator* op, const double* b, double* x, int nrhs, double rtol, int maxit,
                            void* stream, hpdg_solve_info* info);
+
+/* Device memory of an operator. An operator set up with host_only holds only
+ * host data; hpdg_operator_upload copies it to the device (synchronous
+ * copies, then a synchronisation of `stream`) and makes it usable for every
+ * call. Idempotent. Different operators may be uploaded from different host
+ * threads at once. */
+hpdg_status hpdg_operator_upload(hpdg_operator* op, void* stream);
+
+/* Exact device bytes the operator holds once uploaded (computed by a
+ * counting pass over the upload when it is not on the device yet); the
+ * figure a server admits requests by. */
+hpdg_status hpdg_operator_device_bytes(hpdg_operator* op, int64_t* bytes);
+
+/* Batch executor for serving (continuous batching on one GPU): up to
+ * max_active (1..64) PCG solves, each on a stream of its own (default
+ * priority, non-blocking), advance together in chunks of iterations. Every
+ * reduction has a fixed order, so a solve gives bitwise the same result
+ * alone or among others. A batch is driven from one host thread.
+ *
+ * admit: start the PCG of hpdg_pcg_solve (one RHS) for an uploaded operator
+ *   with caller-owned device vectors b, x (x: initial guess) that stay
+ *   untouched by the caller until the solve is retired. b must be complete
+ *   (the caller synchronises the stream that wrote it). Returns HPDG_E_BUSY
+ *   when every slot is taken; admission by device memory is the caller's
+ *   policy, using hpdg_operator_device_bytes.
+ * step: advance every solve whose last chunk has completed (enqueue the next
+ *   chunk, the final FP64 residual, or retire it). Waits up to wait_us
+ *   microseconds for progress; never blocks on the device otherwise.
+ * poll: pop up to cap retired solves: tag, status (as hpdg_pcg_solve) and
+ *   info. A retired operator may be reused or destroyed.
+ * destroy: synchronises the batch's streams; solves still active are left
+ *   unfinished and their operators may only be destroyed afterwards. */
+hpdg_status hpdg_batch_create(int max_active, hpdg_batch** out);
+void hpdg_batch_destroy(hpdg_batch* bt);
+hpdg_status hpdg_batch_admit(hpdg_batch* bt, hpdg_operator* op, const double* b, double* x, double rtol, int maxit,
+                             int64_t tag);
+hpdg_status hpdg_batch_step(hpdg_batch* bt, int wait_us, int* n_active, int* n_done);
+hpdg_status hpdg_batch_poll(hpdg_batch* bt, int cap, int64_t* tags, int* status, hpdg_solve_info* info, int* n);
 
 /* Host copies of setup data, for tests. what:
  *  0 diag(A) [ndof] double      1 labels [ndof] int8 (0 interior, 1 V_J, 2 N)
@@ -125,8 +170,9 @@ hpdg_status hpdg_pcg_solve(hpdg_operator* op, const double* b, double* x, int nr
  *  3 A~_C as CSR (same layout)  4 V_e blocks: int64 nblocks, ptr[nb+1] int64,
  *    dofs int64                 5 DG node coordinates [ndof*dim] double
  *  6 AMG level sizes: int64 nlevels, rows[nlevels] int64
- *  7 summary: int64[9] = ndof, nconf, nblocks, max block, block entries,
- *    amg levels, nnz(A~_C), nnz(P), bytes of the face-matrix table
+ *  7 summary: int64[10] = ndof, nconf, nblocks, max block, block entries,
+ *    amg levels, nnz(A~_C), nnz(P), bytes of the face-matrix table, device
+ *    bytes held by the operator
  *  100+l  AMG level-l matrix A_l as CSR;  200+l  AMG prolongator P_l as CSR;
  *  300+l  aggregate index of every row of level l, int64
  * bytes: in: capacity of buf; out: bytes needed. buf NULL queries the size. */

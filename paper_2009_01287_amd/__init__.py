@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhpdg.so")
 
 STATUS = {0: "OK", -1: "INVALID", -2: "NOMEM", -3: "HIP", -4: "NOT_SPD", -5: "NOT_CONVERGED",
-          -6: "UNSUPPORTED"}
+          -6: "UNSUPPORTED", -7: "BUSY"}
 
 
 class HpdgError(RuntimeError):
@@ -47,7 +47,9 @@ class SolveInfo(C.Structure):
 
 SYMBOLS = ["hpdg_last_error", "hpdg_setup_mesh", "hpdg_mesh_info", "hpdg_mesh_destroy",
            "hpdg_setup_operator", "hpdg_operator_destroy", "hpdg_rhs", "hpdg_apply_A",
-           "hpdg_apply_B", "hpdg_pcg_solve", "hpdg_export"]
+           "hpdg_apply_B", "hpdg_pcg_solve", "hpdg_export", "hpdg_operator_upload",
+           "hpdg_operator_device_bytes", "hpdg_batch_create", "hpdg_batch_destroy", "hpdg_batch_admit",
+           "hpdg_batch_step", "hpdg_batch_poll"]
 
 _lib = None
 
@@ -78,6 +80,15 @@ def lib():
         getattr(L, f).argtypes = [vp, vp, vp, C.c_int, vp]
     L.hpdg_pcg_solve.argtypes = [vp, vp, vp, C.c_int, C.c_double, C.c_int, vp, C.POINTER(SolveInfo)]
     L.hpdg_export.argtypes = [vp, C.c_int, vp, C.POINTER(C.c_size_t)]
+    L.hpdg_operator_upload.argtypes = [vp, vp]
+    L.hpdg_operator_device_bytes.argtypes = [vp, C.POINTER(C.c_int64)]
+    L.hpdg_batch_create.argtypes = [C.c_int, C.POINTER(vp)]
+    L.hpdg_batch_destroy.argtypes = [vp]
+    L.hpdg_batch_destroy.restype = None
+    L.hpdg_batch_admit.argtypes = [vp, vp, vp, vp, C.c_double, C.c_int, C.c_int64]
+    L.hpdg_batch_step.argtypes = [vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+    L.hpdg_batch_poll.argtypes = [vp, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_int), C.POINTER(SolveInfo),
+                                  C.POINTER(C.c_int)]
     _lib = L
     return L
 
@@ -173,6 +184,15 @@ class Operator:
             raise HpdgError(code, lib().hpdg_last_error().decode())
         return (code, out) if not raise_on_error else out
 
+    def upload(self, stream=None):
+        """hpdg_operator_upload: device copy of a host_only operator."""
+        _check(lib().hpdg_operator_upload(self.h, _stream(stream)))
+
+    def device_bytes(self):
+        b = C.c_int64(0)
+        _check(lib().hpdg_operator_device_bytes(self.h, C.byref(b)))
+        return b.value
+
     def export(self, what):
         n = C.c_size_t(0)
         _check(lib().hpdg_export(self.h, int(what), None, C.byref(n)))
@@ -222,5 +242,44 @@ class Operator:
 
     def summary(self):
         keys = ["ndof", "nconf", "nblocks", "max_block", "block_entries", "amg_levels", "nnz_AC", "nnz_P",
-                "face_table_bytes"]
+                "face_table_bytes", "device_bytes"]
         return dict(zip(keys, (int(v) for v in self.export(7).view(np.int64))))
+
+
+class Batch:
+    """hpdg_batch_*: continuous batching of single-RHS PCG solves, each on a
+    stream of its own. Driven from one thread."""
+
+    def __init__(self, max_active=8):
+        h = C.c_void_p()
+        _check(lib().hpdg_batch_create(int(max_active), C.byref(h)))
+        self.h = h
+        self.max_active = max_active
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.hpdg_batch_destroy(self.h)
+            self.h = None
+
+    def admit(self, op: Operator, b, x, rtol=1e-8, maxit=1000, tag=0):
+        """True if admitted, False when every slot is taken."""
+        code = lib().hpdg_batch_admit(self.h, op.h, _ptr(b, "b"), _ptr(x, "x"), float(rtol), int(maxit), int(tag))
+        if code == -7:
+            return False
+        _check(code)
+        return True
+
+    def step(self, wait_us=0):
+        """Advance; returns (active, retired-not-yet-polled)."""
+        na, nd = C.c_int(), C.c_int()
+        _check(lib().hpdg_batch_step(self.h, int(wait_us), C.byref(na), C.byref(nd)))
+        return na.value, nd.value
+
+    def poll(self, cap=64):
+        """Retired solves: list of (tag, status, info dict)."""
+        tags = (C.c_int64 * cap)()
+        codes = (C.c_int * cap)()
+        info = (SolveInfo * cap)()
+        n = C.c_int()
+        _check(lib().hpdg_batch_poll(self.h, cap, tags, codes, info, C.byref(n)))
+        return [(int(tags[i]), int(codes[i]), info[i].as_dict()) for i in range(n.value)]

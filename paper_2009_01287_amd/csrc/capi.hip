@@ -7,10 +7,13 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <deque>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <array>
 #include <string>
+#include <thread>
 #include <type_traits>
 #include <vector>
 
@@ -43,6 +46,11 @@ struct hpdg_mesh {
   int dim, n_base;
 };
 
+// device bytes allocated by this thread; in a counting pass (g_dry) buffers
+// record their sizes and nothing is allocated or copied
+static thread_local int64_t g_dev_bytes = 0;
+static thread_local bool g_dry = false;
+
 namespace {
 
 struct DevBuf {
@@ -66,14 +74,16 @@ struct DevBuf {
     if (p) { (void)hipFree(p); p = nullptr; }
     bytes = b;
     if (b == 0) return;
+    if (g_dry) { g_dev_bytes += (int64_t)b; return; }
     hipError_t e = hipMalloc(&p, b);
+    if (e == hipSuccess) g_dev_bytes += (int64_t)b;
     if (e != hipSuccess)
       throw Error(HPDG_E_NOMEM, "hipMalloc of " + std::to_string(b) + " bytes failed: " + hipGetErrorString(e));
   }
   template <typename T>
   void upload(const std::vector<T>& v) {
     alloc(v.size() * sizeof(T));
-    if (!v.empty()) HIPCHK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    if (!v.empty() && !g_dry) HIPCHK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
   }
   template <typename T>
   T* as() const { return (T*)p; }
@@ -121,6 +131,28 @@ struct PrecHost {
   AMGHier amg;
 };
 
+// pinned host area the device writes the CG flags and norms into
+struct PinArea {
+  int act[256];
+  int iact[256], iters[256], err[256];
+  double tol2[256], bb[256], rr[256], trr[256];
+};
+
+// state of one PCG solve that advances in chunks of iterations
+struct PcgRun {
+  int phase = 0;               // 0 idle, 1 iterating, 2 finishing, 3 finished
+  const double* b = nullptr;
+  double* x = nullptr;
+  int nrhs = 1, maxit = 0, enq = 0, checked = 0;
+  hipStream_t s = nullptr;
+  std::chrono::steady_clock::time_point t0;
+  int code = 0;
+  std::string msg;
+  std::vector<hpdg_solve_info> info;
+};
+
+constexpr int64_t kHistCap = 2048;   // Lanczos coefficients kept per solve
+
 struct LevelDev {
   DevCSR A, P, R;
   DevBuf l1inv;          // T
@@ -150,10 +182,28 @@ struct hpdg_operator {
   DevBuf rT, zT, rc;       // T work vectors (DG and conforming sizes)
   // CG work (double)
   DevBuf r, z, pv, Ap, part, scal, iscal, ticket, act, ahist, bhist;
-  int64_t hist_cap = 0;
+  int64_t hist_cap = 0;      // Lanczos coefficients kept per RHS
   int64_t ftab_bytes = 0;
-  int* hpoll = nullptr;     // pinned host flags
-  ~hpdg_operator() { if (hpoll) (void)hipHostFree(hpoll); }
+  int64_t dev_bytes = 0;     // device memory held by this operator once uploaded
+  int uploaded = 0;
+  PinArea* pin = nullptr;    // pinned host mirror of the CG flags and norms
+  double* hist_pin = nullptr;
+  hipEvent_t ev = nullptr;   // completion of the last enqueued PCG chunk
+  PcgRun run;
+  ~hpdg_operator() {
+    if (pin) (void)hipHostFree(pin);
+    if (hist_pin) (void)hipHostFree(hist_pin);
+    if (ev) (void)hipEventDestroy(ev);
+  }
+  // host copies of the element data for the upload
+  struct {
+    std::vector<int64_t> off;
+    std::vector<int8_t> pd;
+    std::vector<double> h, k, ftab, binv;
+    std::vector<int32_t> sptr;
+    std::vector<FaceRec> recs;
+    int max_dlevel = 0;
+  } up;
   PrecHost host;           // kept for export
   std::vector<double> coords;
 };
@@ -252,15 +302,26 @@ static void build_tables(hpdg_operator* op, int max_delta) {
     }
   L.total = (int64_t)T.size();
   op->tab.upload(T);
-  // constant-memory M, K for the volume kernels
-  static double mk[9][2][81];
-  std::memset(mk, 0, sizeof(mk));
-  for (int p = 1; p <= kMaxP; ++p)
-    for (size_t i = 0; i < basis(p).M.size(); ++i) {
-      mk[p][0][i] = basis(p).M[i];
-      mk[p][1][i] = basis(p).K[i];
-    }
-  HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_MK), mk, sizeof(mk)));
+  if (g_dry) return;
+  // constant-memory M, K for the volume kernels: the same for every operator,
+  // uploaded once per device
+  static std::mutex mu;
+  static std::vector<int> done;
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(mu);
+  if ((int)done.size() <= dev) done.resize(dev + 1, 0);
+  if (!done[dev]) {
+    std::vector<double> mk(9 * 2 * 81, 0.0);
+    for (int p = 1; p <= kMaxP; ++p)
+      for (size_t i = 0; i < basis(p).M.size(); ++i) {
+        mk[(p * 2 + 0) * 81 + i] = basis(p).M[i];
+        mk[(p * 2 + 1) * 81 + i] = basis(p).K[i];
+      }
+    HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_MK), mk.data(), mk.size() * sizeof(double)));
+    HIPCHK(hipDeviceSynchronize());
+    done[dev] = 1;
+  }
 }
 
 static void spd_inverse(std::vector<double>& A, int n) {
@@ -346,9 +407,101 @@ static void upload_prec(hpdg_operator* op) {
   op->zT.alloc((size_t)op->ndof * op->max_nrhs * sizeof(T));
 }
 
+// All device buffers of an operator from its host data. In a counting pass
+// (g_dry) only the sizes are recorded. Copies are synchronous; the call ends
+// with a synchronisation of `s`.
+static void upload_device(hpdg_operator* op, hipStream_t s) {
+  auto& U = op->up;
+  const int64_t b0 = g_dev_bytes;
+  op->off.upload(U.off);
+  op->pdeg.upload(U.pd);
+  op->hh.upload(U.h);
+  op->kk.upload(U.k);
+  op->sptr.upload(U.sptr);
+  op->recs.upload(U.recs);
+  op->ftab.upload(U.ftab);
+  build_tables(op, U.max_dlevel);
+  op->dbucket.clear();
+  op->dbucket.resize(kMaxP + 1);
+  for (int p = 1; p <= kMaxP; ++p) op->dbucket[p].upload(op->bucket[p]);
+  if (op->prec32) {
+    upload_prec<float>(op);
+    std::vector<float> bi(U.binv.begin(), U.binv.end());
+    op->blk_inv.upload(bi);
+  } else {
+    upload_prec<double>(op);
+    op->blk_inv.upload(U.binv);
+  }
+  const int64_t hs = op->max_nrhs;
+  size_t nv = (size_t)op->ndof * hs * sizeof(double);
+  op->r.alloc(nv);
+  op->z.alloc(nv);
+  op->pv.alloc(nv);
+  op->Ap.alloc(nv);
+  op->part.alloc((size_t)1024 * hs * sizeof(double));
+  op->scal.alloc((size_t)16 * 256 * sizeof(double));
+  op->iscal.alloc((size_t)4 * 256 * sizeof(int));
+  op->act.alloc((size_t)256 * sizeof(int));
+  op->ticket.alloc(64 * sizeof(unsigned));
+  op->hist_cap = kHistCap;
+  op->ahist.alloc((size_t)kHistCap * hs * sizeof(double));
+  op->bhist.alloc((size_t)kHistCap * hs * sizeof(double));
+  if (g_dry) return;
+  HIPCHK(hipMemsetAsync(op->ticket.p, 0, 64 * sizeof(unsigned), s));
+  HIPCHK(hipMemsetAsync(op->iscal.p, 0, 4 * 256 * sizeof(int), s));
+  if (!op->pin) HIPCHK(hipHostMalloc((void**)&op->pin, sizeof(PinArea), hipHostMallocDefault));
+  if (!op->hist_pin)
+    HIPCHK(hipHostMalloc((void**)&op->hist_pin, (size_t)2 * kHistCap * hs * sizeof(double), hipHostMallocDefault));
+  if (!op->ev) HIPCHK(hipEventCreateWithFlags(&op->ev, hipEventDisableTiming));
+  HIPCHK(hipStreamSynchronize(s));
+  op->dev_bytes = g_dev_bytes - b0;
+  op->uploaded = 1;
+  op->host_only = 0;
+}
+
+// device bytes the operator holds once uploaded (a counting pass if it is not)
+static int64_t device_bytes(hpdg_operator* op) {
+  if (op->uploaded) return op->dev_bytes;
+  const int64_t b0 = g_dev_bytes;
+  g_dry = true;
+  try {
+    upload_device(op, nullptr);
+  } catch (...) {
+    g_dry = false;
+    g_dev_bytes = b0;
+    throw;
+  }
+  g_dry = false;
+  int64_t need = g_dev_bytes - b0;
+  g_dev_bytes = b0;
+  return need;
+}
+
+extern "C" hpdg_status hpdg_operator_upload(hpdg_operator* op, void* stream) {
+  if (!op) return fail(HPDG_E_INVALID, "null operator");
+  if (op->uploaded) return HPDG_OK;
+  try {
+    upload_device(op, (hipStream_t)stream);
+    return HPDG_OK;
+  } catch (Error& e) {
+    return fail(e.code, e.what());
+  } catch (std::bad_alloc&) {
+    return fail(HPDG_E_NOMEM, "host allocation failed");
+  }
+}
+
+extern "C" hpdg_status hpdg_operator_device_bytes(hpdg_operator* op, int64_t* bytes) {
+  if (!op || !bytes) return fail(HPDG_E_INVALID, "null argument");
+  try {
+    *bytes = device_bytes(op);
+    return HPDG_OK;
+  } catch (Error& e) {
+    return fail(e.code, e.what());
+  }
+}
+
 extern "C" hpdg_status hpdg_setup_operator(const hpdg_mesh* mh, const hpdg_operator_opts* o, void* stream,
                                           hpdg_operator** out) {
-  (void)stream;
   if (!mh || !o || !out) return fail(HPDG_E_INVALID, "null argument");
   *out = nullptr;
   if (o->form != 0 && o->form != 1) return fail(HPDG_E_INVALID, "form must be 0 (SIPG) or 1 (BR2)");
@@ -381,12 +534,11 @@ extern "C" hpdg_status hpdg_setup_operator(const hpdg_mesh* mh, const hpdg_opera
     int d = M.dim;
     // ---- element data and face records
     std::vector<int8_t> pd(M.p.begin(), M.p.end());
-    if (!o->host_only) {
-      op->off.upload(M.off);
-      op->pdeg.upload(pd);
-      op->hh.upload(M.h);
-      op->kk.upload(M.k);
-    }
+    op->up.off = M.off;
+    op->up.pd = pd;
+    op->up.h = M.h;
+    op->up.k = M.k;
+    op->up.max_dlevel = M.max_dlevel;
     std::vector<std::vector<FaceRec>> per(M.ne * 2 * d);
     // 1D face-mass matrices F[j][j'] = sum_g w_g l^a_j(x^a_g) l^b_j'(x^b_g) of the
     // face's sub-intervals in each side (unit length), deduplicated by type
@@ -470,14 +622,9 @@ extern "C" hpdg_status hpdg_setup_operator(const hpdg_mesh* mh, const hpdg_opera
     for (int e = 0; e < M.ne; ++e) op->bucket[M.p[e]].push_back(e);
     if (ftab.size() > (size_t)INT32_MAX) throw Error(HPDG_E_UNSUPPORTED, "face table too large");
     op->ftab_bytes = (int64_t)(ftab.size() * sizeof(double));
-    if (!op->host_only) {
-      op->sptr.upload(sptr);
-      op->recs.upload(recs);
-      op->ftab.upload(ftab);
-      build_tables(op.get(), M.max_dlevel);
-      op->dbucket.resize(kMaxP + 1);
-      for (int p = 1; p <= kMaxP; ++p) op->dbucket[p].upload(op->bucket[p]);
-    }
+    op->up.sptr.swap(sptr);
+    op->up.recs.swap(recs);
+    op->up.ftab.swap(ftab);
     // ---- preconditioner (host)
     const bool verbose = std::getenv("HPDG_VERBOSE") != nullptr;
     auto tlast = std::chrono::steady_clock::now();
@@ -515,7 +662,7 @@ extern "C" hpdg_status hpdg_setup_operator(const hpdg_mesh* mh, const hpdg_opera
       else if (H.lab[g] == 2) H.dinvJ[g] = -0.0;
     }
     phase("edge spaces");
-    std::vector<double> binv;
+    std::vector<double>& binv = op->up.binv;
     for (auto& B : H.blocks) {
       std::vector<double> S = dg_submatrix(M, oo, B, eta2);
       spd_inverse(S, (int)B.size());
@@ -545,33 +692,7 @@ extern "C" hpdg_status hpdg_setup_operator(const hpdg_mesh* mh, const hpdg_opera
         }
       }
     }
-    if (op->host_only) {
-      *out = op.release();
-      return HPDG_OK;
-    }
-    // ---- uploads
-    if (op->prec32) {
-      upload_prec<float>(op.get());
-      std::vector<float> bi(binv.begin(), binv.end());
-      op->blk_inv.upload(bi);
-    } else {
-      upload_prec<double>(op.get());
-      op->blk_inv.upload(binv);
-    }
-    size_t nv = (size_t)op->ndof * op->max_nrhs * sizeof(double);
-    op->r.alloc(nv);
-    op->z.alloc(nv);
-    op->pv.alloc(nv);
-    op->Ap.alloc(nv);
-    op->part.alloc((size_t)1024 * 256 * sizeof(double));
-    op->scal.alloc((size_t)16 * 256 * sizeof(double));
-    op->iscal.alloc((size_t)4 * 256 * sizeof(int));
-    op->act.alloc((size_t)256 * sizeof(int));
-    op->ticket.alloc(64 * sizeof(unsigned));
-    HIPCHK(hipMemset(op->ticket.p, 0, 64 * sizeof(unsigned)));
-    HIPCHK(hipMemset(op->iscal.p, 0, 4 * 256 * sizeof(int)));
-    HIPCHK(hipHostMalloc((void**)&op->hpoll, 256 * sizeof(int), hipHostMallocDefault));
-    HIPCHK(hipDeviceSynchronize());
+    if (!op->host_only) upload_device(op.get(), (hipStream_t)stream);
     *out = op.release();
     return HPDG_OK;
   } catch (Error& e) {
@@ -823,123 +944,322 @@ static void dot_ep(hpdg_operator* op, const double* a, const double* b, int nrhs
   hipLaunchKernelGGL(k_dot_final_ep, dim3(1), dim3(256), 0, s, nb, nrhs, op->part.as<double>(), mode, S);
 }
 
-extern "C" hpdg_status hpdg_pcg_solve(hpdg_operator* op, const double* b, double* x, int nrhs, double rtol,
-                                      int maxit, void* stream, hpdg_solve_info* info) {
+static CGScal cg_scal(hpdg_operator* op) {
+  double* D = op->scal.as<double>();
+  int* I = op->iscal.as<int>();
+  CGScal S;
+  S.rz = D; S.pAp = D + 256; S.rr = D + 512; S.bb = D + 768; S.alpha = D + 1024; S.beta = D + 1280;
+  S.tol2 = D + 1536;
+  S.act = I; S.iters = I + 256; S.err = I + 512;
+  S.ahist = op->ahist.as<double>();
+  S.bhist = op->bhist.as<double>();
+  S.maxit = (int)op->hist_cap;
+  S.hs = op->max_nrhs;
+  return S;
+}
+
+static void apply_B_any(hpdg_operator* op, const double* in, double* outv, int nrhs, hipStream_t s) {
+  if (op->prec32) apply_B_dev<float>(op, in, outv, nrhs, s);
+  else apply_B_dev<double>(op, in, outv, nrhs, s);
+}
+
+// k PCG iterations (Alg. PCG: alpha from r'z / p'Ap, residual update, B
+// application, beta, new direction), then the activity flags to the pinned
+// area and the completion event
+static void pcg_chunk(hpdg_operator* op, int k) {
+  PcgRun& R = op->run;
+  const int nrhs = R.nrhs;
+  const int64_t n = op->ndof * nrhs;
+  hipStream_t s = R.s;
+  CGScal S = cg_scal(op);
+  double *r = op->r.as<double>(), *z = op->z.as<double>(), *p = op->pv.as<double>(), *Ap = op->Ap.as<double>();
+  for (int i = 0; i < k; ++i) {
+    apply_A_dev(op, p, Ap, nrhs, s);
+    dot_ep(op, p, Ap, nrhs, EP_PAP, S, s);
+    hipLaunchKernelGGL(k_cg_update2, dim3(nblk(n)), dim3(256), 0, s, n, nrhs, S.alpha, p, Ap, R.x, r);
+    dot_ep(op, r, r, nrhs, EP_RR, S, s);
+    apply_B_any(op, r, z, nrhs, s);
+    dot_ep(op, r, z, nrhs, EP_RZ, S, s);
+    hipLaunchKernelGGL(k_cg_dir2, dim3(nblk(n)), dim3(256), 0, s, n, nrhs, S.beta, S.act, z, p);
+  }
+  R.enq += k;
+  HIPCHK(hipMemcpyAsync(op->pin->act, S.act, nrhs * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipEventRecord(op->ev, s));
+}
+
+// r = b - A x, z = B r, p = z and the initial norms; no iteration yet
+static void pcg_begin(hpdg_operator* op, const double* b, double* x, int nrhs, double rtol, int maxit,
+                      hipStream_t s) {
+  PcgRun& R = op->run;
+  R = PcgRun();
+  R.phase = 1;
+  R.b = b;
+  R.x = x;
+  R.nrhs = nrhs;
+  R.maxit = maxit;
+  R.s = s;
+  R.t0 = std::chrono::steady_clock::now();
+  const int64_t n = op->ndof * nrhs;
+  CGScal S = cg_scal(op);
+  double *r = op->r.as<double>(), *z = op->z.as<double>(), *p = op->pv.as<double>(), *Ap = op->Ap.as<double>();
+  for (int c = 0; c < nrhs; ++c) op->pin->tol2[c] = rtol * rtol;
+  HIPCHK(hipMemcpyAsync(S.tol2, op->pin->tol2, nrhs * sizeof(double), hipMemcpyHostToDevice, s));
+  apply_A_dev(op, x, Ap, nrhs, s);
+  hipLaunchKernelGGL(k_sub, dim3(nblk(n)), dim3(256), 0, s, n, b, Ap, r);
+  dot_ep(op, b, b, nrhs, EP_BB, S, s);
+  dot_ep(op, r, r, nrhs, EP_RR0, S, s);
+  apply_B_any(op, r, z, nrhs, s);
+  HIPCHK(hipMemcpyAsync(p, z, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  dot_ep(op, r, z, nrhs, EP_RZ0, S, s);
+  HIPCHK(hipMemcpyAsync(op->pin->bb, S.bb, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+  pcg_chunk(op, 0);
+}
+
+// true residual b - A x in FP64 and the per-RHS results to the pinned area
+static void pcg_finish_enqueue(hpdg_operator* op) {
+  PcgRun& R = op->run;
+  const int nrhs = R.nrhs;
+  const int64_t n = op->ndof * nrhs;
+  hipStream_t s = R.s;
+  CGScal S = cg_scal(op);
+  double *r = op->r.as<double>(), *Ap = op->Ap.as<double>();
+  PinArea* P = op->pin;
+  HIPCHK(hipMemcpyAsync(P->rr, S.rr, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+  apply_A_dev(op, R.x, Ap, nrhs, s);
+  hipLaunchKernelGGL(k_sub, dim3(nblk(n)), dim3(256), 0, s, n, R.b, Ap, r);
+  dot_ep(op, r, r, nrhs, EP_TRUE, S, s);
+  HIPCHK(hipMemcpyAsync(P->iact, S.act, nrhs * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(P->iters, S.iters, nrhs * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(P->err, S.err, nrhs * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(P->trr, S.rr, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+  const int64_t hs = op->max_nrhs;
+  const int64_t rows = std::min<int64_t>(R.enq, op->hist_cap);
+  if (rows > 0) {
+    HIPCHK(hipMemcpyAsync(op->hist_pin, S.ahist, (size_t)(rows * hs) * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(op->hist_pin + op->hist_cap * hs, S.bhist, (size_t)(rows * hs) * sizeof(double),
+                          hipMemcpyDeviceToHost, s));
+  }
+  HIPCHK(hipEventRecord(op->ev, s));
+}
+
+// per-RHS results and Lanczos extremes from the pinned area
+static void pcg_collect(hpdg_operator* op) {
+  PcgRun& R = op->run;
+  const PinArea* P = op->pin;
+  const int64_t hs = op->max_nrhs;
+  const double* ha = op->hist_pin;
+  const double* hb = op->hist_pin + op->hist_cap * hs;
+  double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - R.t0).count();
+  bool all_conv = true, breakdown = false;
+  R.info.assign(R.nrhs, hpdg_solve_info{});
+  for (int c = 0; c < R.nrhs; ++c) {
+    double bn = std::sqrt(P->bb[c]);
+    bool conv = !P->iact[c] && !P->err[c];
+    breakdown |= P->err[c] != 0;
+    all_conv &= conv;
+    hpdg_solve_info& In = R.info[c];
+    In.iters = P->iters[c];
+    In.converged = conv;
+    In.rel_res = bn > 0 ? std::sqrt(P->rr[c]) / bn : 0.0;
+    In.true_rel_res = bn > 0 ? std::sqrt(P->trr[c]) / bn : 0.0;
+    int kk = (int)std::min<int64_t>(P->iters[c], op->hist_cap);
+    std::vector<double> da(kk), db(kk > 0 ? kk - 1 : 0);
+    for (int q = 0; q < kk; ++q) {
+      double aq = ha[(size_t)q * hs + c];
+      da[q] = 1.0 / aq + (q > 0 ? hb[(size_t)(q - 1) * hs + c] / ha[(size_t)(q - 1) * hs + c] : 0.0);
+      if (q + 1 < kk) db[q] = std::sqrt(hb[(size_t)q * hs + c]) / aq;
+    }
+    tridiag_extremes(da, db, In.lambda_min, In.lambda_max);
+    In.cond_est = In.lambda_max / In.lambda_min;
+    In.t_solve_s = secs;
+  }
+  if (breakdown) { R.code = HPDG_E_NOT_SPD; R.msg = "CG breakdown: p'Ap <= 0 or r'z <= 0"; }
+  else if (!all_conv) { R.code = HPDG_E_NOT_CONVERGED; R.msg = "maximum number of iterations reached"; }
+  else R.code = HPDG_OK;
+}
+
+// one step of the state machine once the last enqueued chunk has completed:
+// check the flags, then enqueue the next chunk, the final residual, or end.
+// The flags are read after the first iteration and then every 4.
+static void pcg_advance(hpdg_operator* op) {
+  PcgRun& R = op->run;
+  if (R.phase == 1) {
+    if (!R.checked) {
+      R.checked = 1;
+      for (int c = 0; c < R.nrhs; ++c)
+        if (!std::isfinite(op->pin->bb[c])) {
+          R.code = HPDG_E_INVALID;
+          R.msg = "non-finite right-hand side";
+          R.phase = 3;
+          return;
+        }
+    }
+    bool any = false;
+    for (int c = 0; c < R.nrhs; ++c) any |= op->pin->act[c] != 0;
+    if (!any || R.enq >= R.maxit) {
+      pcg_finish_enqueue(op);
+      R.phase = 2;
+      return;
+    }
+    int k = R.enq == 0 ? 1 : R.enq < 4 ? 4 - R.enq : 4;
+    pcg_chunk(op, std::min(k, R.maxit - R.enq));
+  } else if (R.phase == 2) {
+    pcg_collect(op);
+    R.phase = 3;
+  }
+}
+
+static hpdg_status check_pcg_args(hpdg_operator* op, const double* b, double* x, int nrhs, double rtol, int maxit) {
   hpdg_status st = check_vec_args(op, b, x, nrhs);
   if (st != HPDG_OK) return st;
   if (!(rtol > 0) || maxit < 0) return fail(HPDG_E_INVALID, "bad rtol or maxit");
-  hipStream_t s = (hipStream_t)stream;
+  if (op->run.phase == 1 || op->run.phase == 2) return fail(HPDG_E_INVALID, "operator has a solve in flight");
+  return HPDG_OK;
+}
+
+extern "C" hpdg_status hpdg_pcg_solve(hpdg_operator* op, const double* b, double* x, int nrhs, double rtol,
+                                      int maxit, void* stream, hpdg_solve_info* info) {
+  hpdg_status st = check_pcg_args(op, b, x, nrhs, rtol, maxit);
+  if (st != HPDG_OK) return st;
   try {
-    auto t0 = std::chrono::steady_clock::now();
-    int64_t n = op->ndof * nrhs;
-    double* r = op->r.as<double>();
-    double* z = op->z.as<double>();
-    double* p = op->pv.as<double>();
-    double* Ap = op->Ap.as<double>();
-    if ((int64_t)maxit + 1 > op->hist_cap) {
-      op->hist_cap = std::max<int64_t>((int64_t)maxit + 1, 1024);
-      op->ahist.alloc((size_t)op->hist_cap * 256 * sizeof(double));
-      op->bhist.alloc((size_t)op->hist_cap * 256 * sizeof(double));
+    pcg_begin(op, b, x, nrhs, rtol, maxit, (hipStream_t)stream);
+    while (op->run.phase != 3) {
+      HIPCHK(hipEventSynchronize(op->ev));
+      pcg_advance(op);
     }
-    double* D = op->scal.as<double>();
-    int* I = op->iscal.as<int>();
-    CGScal S;
-    S.rz = D; S.pAp = D + 256; S.rr = D + 512; S.bb = D + 768; S.alpha = D + 1024; S.beta = D + 1280;
-    S.tol2 = D + 1536;
-    S.act = I; S.iters = I + 256; S.err = I + 512;
-    S.ahist = op->ahist.as<double>();
-    S.bhist = op->bhist.as<double>();
-    S.maxit = (int)op->hist_cap;
-    std::vector<double> tol2(nrhs, rtol * rtol);
-    HIPCHK(hipMemcpyAsync(S.tol2, tol2.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, s));
-    auto applyB = [&](const double* in, double* outv) {
-      if (op->prec32) apply_B_dev<float>(op, in, outv, nrhs, s);
-      else apply_B_dev<double>(op, in, outv, nrhs, s);
-    };
-    // r = b - A x ; z = B r ; p = z
-    apply_A_dev(op, x, Ap, nrhs, s);
-    hipLaunchKernelGGL(k_sub, dim3(nblk(n)), dim3(256), 0, s, n, b, Ap, r);
-    dot_ep(op, b, b, nrhs, EP_BB, S, s);
-    dot_ep(op, r, r, nrhs, EP_RR0, S, s);
-    applyB(r, z);
-    HIPCHK(hipMemcpyAsync(p, z, n * sizeof(double), hipMemcpyDeviceToDevice, s));
-    dot_ep(op, r, z, nrhs, EP_RZ0, S, s);
-    std::vector<double> hbb(nrhs);
-    HIPCHK(hipMemcpyAsync(hbb.data(), S.bb, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    for (int c = 0; c < nrhs; ++c)
-      if (!std::isfinite(hbb[c])) throw Error(HPDG_E_INVALID, "non-finite right-hand side");
-    int* poll = op->hpoll;   // pinned: act[nrhs]
-    int it = 0;
-    const int check_every = 4;
-    while (it < maxit) {
-      apply_A_dev(op, p, Ap, nrhs, s);
-      dot_ep(op, p, Ap, nrhs, EP_PAP, S, s);
-      hipLaunchKernelGGL(k_cg_update2, dim3(nblk(n)), dim3(256), 0, s, n, nrhs, S.alpha, p, Ap, x, r);
-      dot_ep(op, r, r, nrhs, EP_RR, S, s);
-      applyB(r, z);
-      dot_ep(op, r, z, nrhs, EP_RZ, S, s);
-      hipLaunchKernelGGL(k_cg_dir2, dim3(nblk(n)), dim3(256), 0, s, n, nrhs, S.beta, S.act, z, p);
-      ++it;
-      if (it % check_every == 0 || it == maxit || it == 1) {
-        HIPCHK(hipMemcpyAsync(poll, S.act, nrhs * sizeof(int), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        bool any = false;
-        for (int c = 0; c < nrhs; ++c) any |= poll[c] != 0;
-        if (!any) break;
-      }
+  } catch (Error& e) {
+    op->run.phase = 0;
+    return fail(e.code, e.what());
+  }
+  PcgRun& R = op->run;
+  if (info && !R.info.empty())
+    for (int c = 0; c < nrhs; ++c) info[c] = R.info[c];
+  if (R.code != HPDG_OK) return fail(R.code, R.msg);
+  return HPDG_OK;
+}
+
+// ------------------------------------------------------- batch executor
+struct hpdg_batch {
+  struct Slot {
+    hpdg_operator* op = nullptr;
+    int64_t tag = 0;
+  };
+  struct Done {
+    int64_t tag;
+    int code;
+    hpdg_solve_info info;
+  };
+  std::vector<hipStream_t> streams;
+  std::vector<Slot> slots;
+  int n_active = 0;
+  std::deque<Done> done;
+  ~hpdg_batch() {
+    for (hipStream_t s : streams) {
+      (void)hipStreamSynchronize(s);
+      (void)hipStreamDestroy(s);
     }
-    // true residual in FP64
-    apply_A_dev(op, x, Ap, nrhs, s);
-    hipLaunchKernelGGL(k_sub, dim3(nblk(n)), dim3(256), 0, s, n, b, Ap, r);
-    std::vector<double> hrr(nrhs), htr(nrhs);
-    HIPCHK(hipMemcpyAsync(hrr.data(), S.rr, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
-    dot_ep(op, r, r, nrhs, EP_TRUE, S, s);
-    std::vector<int> hact(nrhs), hit(nrhs), herr(nrhs);
-    HIPCHK(hipMemcpyAsync(hact.data(), S.act, nrhs * sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(hit.data(), S.iters, nrhs * sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(herr.data(), S.err, nrhs * sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(htr.data(), S.rr, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
-    int maxi = 0;
-    HIPCHK(hipStreamSynchronize(s));
-    for (int c = 0; c < nrhs; ++c) maxi = std::max(maxi, hit[c]);
-    std::vector<double> ha((size_t)maxi * 256), hb((size_t)maxi * 256);
-    if (maxi > 0) {
-      HIPCHK(hipMemcpyAsync(ha.data(), S.ahist, (size_t)maxi * 256 * sizeof(double), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipMemcpyAsync(hb.data(), S.bhist, (size_t)maxi * 256 * sizeof(double), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipStreamSynchronize(s));
+  }
+};
+
+extern "C" hpdg_status hpdg_batch_create(int max_active, hpdg_batch** out) {
+  if (!out) return fail(HPDG_E_INVALID, "null argument");
+  *out = nullptr;
+  if (max_active < 1 || max_active > 64) return fail(HPDG_E_INVALID, "max_active must be in 1..64");
+  auto bt = std::make_unique<hpdg_batch>();
+  try {
+    for (int i = 0; i < max_active; ++i) {
+      hipStream_t s;
+      HIPCHK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+      bt->streams.push_back(s);
     }
-    double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    bool all_conv = true, breakdown = false;
-    for (int c = 0; c < nrhs; ++c) {
-      double bn = std::sqrt(hbb[c]);
-      bool conv = !hact[c] && !herr[c];
-      breakdown |= herr[c] != 0;
-      all_conv &= conv;
-      if (info) {
-        hpdg_solve_info& In = info[c];
-        In.iters = hit[c];
-        In.converged = conv;
-        In.rel_res = bn > 0 ? std::sqrt(hrr[c]) / bn : 0.0;
-        In.true_rel_res = bn > 0 ? std::sqrt(htr[c]) / bn : 0.0;
-        int kk = hit[c];
-        std::vector<double> da(kk), db(kk > 0 ? kk - 1 : 0);
-        for (int q = 0; q < kk; ++q) {
-          double aq = ha[(size_t)q * 256 + c];
-          da[q] = 1.0 / aq + (q > 0 ? hb[(size_t)(q - 1) * 256 + c] / ha[(size_t)(q - 1) * 256 + c] : 0.0);
-          if (q + 1 < kk) db[q] = std::sqrt(hb[(size_t)q * 256 + c]) / aq;
-        }
-        tridiag_extremes(da, db, In.lambda_min, In.lambda_max);
-        In.cond_est = In.lambda_max / In.lambda_min;
-        In.t_solve_s = secs;
-      }
-    }
-    if (breakdown) return fail(HPDG_E_NOT_SPD, "CG breakdown: p'Ap <= 0 or r'z <= 0");
-    if (!all_conv) return fail(HPDG_E_NOT_CONVERGED, "maximum number of iterations reached");
-    return HPDG_OK;
   } catch (Error& e) {
     return fail(e.code, e.what());
   }
+  bt->slots.resize(max_active);
+  *out = bt.release();
+  return HPDG_OK;
+}
+
+extern "C" void hpdg_batch_destroy(hpdg_batch* bt) { delete bt; }
+
+extern "C" hpdg_status hpdg_batch_admit(hpdg_batch* bt, hpdg_operator* op, const double* b, double* x, double rtol,
+                                        int maxit, int64_t tag) {
+  if (!bt) return fail(HPDG_E_INVALID, "null batch");
+  if (op && !op->uploaded) return fail(HPDG_E_UNSUPPORTED, "operator is not on the device (hpdg_operator_upload)");
+  hpdg_status st = check_pcg_args(op, b, x, 1, rtol, maxit);
+  if (st != HPDG_OK) return st;
+  for (auto& sl : bt->slots)
+    if (sl.op == op) return fail(HPDG_E_INVALID, "operator already admitted");
+  int k = -1;
+  for (size_t i = 0; i < bt->slots.size(); ++i)
+    if (!bt->slots[i].op) { k = (int)i; break; }
+  if (k < 0) return fail(HPDG_E_BUSY, "no free slot");
+  try {
+    pcg_begin(op, b, x, 1, rtol, maxit, bt->streams[k]);
+  } catch (Error& e) {
+    op->run.phase = 0;
+    return fail(e.code, e.what());
+  }
+  bt->slots[k].op = op;
+  bt->slots[k].tag = tag;
+  ++bt->n_active;
+  return HPDG_OK;
+}
+
+extern "C" hpdg_status hpdg_batch_step(hpdg_batch* bt, int wait_us, int* n_active, int* n_done) {
+  if (!bt) return fail(HPDG_E_INVALID, "null batch");
+  auto deadline = std::chrono::steady_clock::now() + std::chrono::microseconds(std::max(wait_us, 0));
+  for (;;) {
+    int progress = 0;
+    for (auto& sl : bt->slots) {
+      if (!sl.op) continue;
+      hpdg_operator* op = sl.op;
+      hipError_t e = hipEventQuery(op->ev);
+      if (e == hipErrorNotReady) continue;
+      ++progress;
+      if (e != hipSuccess) {
+        op->run.code = HPDG_E_HIP;
+        op->run.msg = hipGetErrorString(e);
+        op->run.phase = 3;
+      } else {
+        try {
+          pcg_advance(op);
+        } catch (Error& err) {
+          op->run.code = err.code;
+          op->run.msg = err.what();
+          op->run.phase = 3;
+        }
+      }
+      if (op->run.phase == 3) {
+        hpdg_batch::Done d{sl.tag, op->run.code, hpdg_solve_info{}};
+        if (!op->run.info.empty()) d.info = op->run.info[0];
+        bt->done.push_back(d);
+        sl.op = nullptr;
+        --bt->n_active;
+      }
+    }
+    if (progress || bt->n_active == 0 || std::chrono::steady_clock::now() >= deadline) break;
+    std::this_thread::sleep_for(std::chrono::microseconds(20));
+  }
+  if (n_active) *n_active = bt->n_active;
+  if (n_done) *n_done = (int)bt->done.size();
+  return HPDG_OK;
+}
+
+extern "C" hpdg_status hpdg_batch_poll(hpdg_batch* bt, int cap, int64_t* tags, int* codes, hpdg_solve_info* info,
+                                       int* n) {
+  if (!bt || !n || cap < 0 || (cap > 0 && (!tags || !codes))) return fail(HPDG_E_INVALID, "bad argument");
+  int k = 0;
+  while (k < cap && !bt->done.empty()) {
+    const auto& d = bt->done.front();
+    tags[k] = d.tag;
+    codes[k] = d.code;
+    if (info) info[k] = d.info;
+    bt->done.pop_front();
+    ++k;
+  }
+  *n = k;
+  return HPDG_OK;
 }
 
 template <typename V>
@@ -988,7 +1308,7 @@ extern "C" hpdg_status hpdg_export(const hpdg_operator* op, int what, void* buf,
       int64_t mx = 0, ent = 0;
       for (auto& b : H.blocks) { mx = std::max<int64_t>(mx, b.size()); ent += (int64_t)b.size() * b.size(); }
       std::vector<int64_t> v{op->ndof, op->nconf, (int64_t)H.blocks.size(), mx, ent, (int64_t)H.amg.lv.size(),
-                             (int64_t)H.AC.idx.size(), (int64_t)H.P.idx.size(), op->ftab_bytes};
+                             (int64_t)H.AC.idx.size(), (int64_t)H.P.idx.size(), op->ftab_bytes, op->dev_bytes};
       return put(v.data(), v.size(), buf, bytes);
     }
     default:

@@ -614,8 +614,9 @@ __global__ __launch_bounds__(256) void k_dot_final(int nblocks, int nrhs, const 
 struct CGScal {
   double *rz, *pAp, *rr, *bb, *alpha, *beta, *tol2;
   int *act, *iters, *err;
-  double *ahist, *bhist;   // [maxit * nrhs]
-  int maxit;
+  double *ahist, *bhist;   // [maxit * hs]: alpha_k, beta_k of RHS c at k * hs + c
+  int maxit;               // capacity of the histories in iterations
+  int hs;                  // history stride (>= nrhs)
 };
 
 // epilogue of a dot product for RHS c with value v
@@ -642,7 +643,7 @@ __device__ inline void cg_epilogue(int mode, int c, double v, CGScal S) {
       S.rr[c] = v;
       if (S.act[c]) {
         int it = S.iters[c];
-        if (it < S.maxit) S.ahist[(int64_t)it * 256 + c] = S.alpha[c];
+        if (it < S.maxit) S.ahist[(int64_t)it * S.hs + c] = S.alpha[c];
         S.iters[c] = it + 1;
         if (!(v > S.tol2[c] * S.bb[c])) S.act[c] = 0;
       }
@@ -654,7 +655,7 @@ __device__ inline void cg_epilogue(int mode, int c, double v, CGScal S) {
         S.beta[c] = b;
         S.rz[c] = v;
         int it = S.iters[c];
-        if (it - 1 < S.maxit) S.bhist[(int64_t)(it - 1) * 256 + c] = b;
+        if (it - 1 < S.maxit) S.bhist[(int64_t)(it - 1) * S.hs + c] = b;
       } else {
         S.beta[c] = 0.0;
       }
