@@ -173,6 +173,8 @@ hpdg_status hpdg_batch_poll(hpdg_batch* bt, int cap, int64_t* tags, int* status,
  *  7 summary: int64[10] = ndof, nconf, nblocks, max block, block entries,
  *    amg levels, nnz(A~_C), nnz(P), bytes of the face-matrix table, device
  *    bytes held by the operator
+ *  8 inverses of the V_e blocks in FP64, row-major, concatenated in the
+ *    order of item 4
  *  100+l  AMG level-l matrix A_l as CSR;  200+l  AMG prolongator P_l as CSR;
  *  300+l  aggregate index of every row of level l, int64
  * bytes: in: capacity of buf; out: bytes needed. buf NULL queries the size. */

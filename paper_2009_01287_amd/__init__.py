@@ -233,6 +233,16 @@ class Operator:
         dofs = v[nb + 2:]
         return [dofs[ptr[i]:ptr[i + 1]].copy() for i in range(nb)]
 
+    def block_inverses(self):
+        """Inverses of the V_e blocks (FP64), in the order of blocks()."""
+        v = self.export(8).view(np.float64)
+        out, o = [], 0
+        for b in self.blocks():
+            k = len(b)
+            out.append(v[o:o + k * k].reshape(k, k).copy())
+            o += k * k
+        return out
+
     def node_coords(self):
         return self.export(5).view(np.float64).reshape(-1, self.mesh.dim)
 

@@ -25,7 +25,7 @@ static void legendre(int n, double x, double& P, double& dP, double& d2P) {
   d2P = (2.0 * x * dP - n * (n + 1.0) * P) / (1.0 - x * x);
 }
 
-void gauss_rule(int q, std::vector<double>& x, std::vector<double>& w) {
+static void gauss_rule_compute(int q, std::vector<double>& x, std::vector<double>& w) {
   x.assign(q, 0.0);
   w.assign(q, 0.0);
   for (int j = 0; j < q; ++j) {
@@ -50,6 +50,24 @@ void gauss_rule(int q, std::vector<double>& x, std::vector<double>& w) {
     w[j] = w[q - 1 - j] = b;
   }
   if (q % 2 == 1) x[q / 2] = 0.5;
+}
+
+// rules up to 32 points are computed once and copied
+void gauss_rule(int q, std::vector<double>& x, std::vector<double>& w) {
+  constexpr int kCache = 32;
+  static std::once_flag once;
+  static std::vector<std::vector<double>> cx, cw;
+  std::call_once(once, [] {
+    cx.resize(kCache + 1);
+    cw.resize(kCache + 1);
+    for (int k = 1; k <= kCache; ++k) gauss_rule_compute(k, cx[k], cw[k]);
+  });
+  if (q >= 1 && q <= kCache) {
+    x = cx[q];
+    w = cw[q];
+    return;
+  }
+  gauss_rule_compute(q, x, w);
 }
 
 void lagrange_eval(const std::vector<double>& nodes, double t, double* out) {

@@ -324,8 +324,9 @@ static void build_tables(hpdg_operator* op, int max_delta) {
   }
 }
 
+// inverse of an SPD matrix (row-major, in place) by Cholesky A = L L^T,
+// W = L^{-1}, A^{-1} = W^T W; throws if A is not positive definite
 static void spd_inverse(std::vector<double>& A, int n) {
-  // Cholesky then inverse; throws if not positive definite
   std::vector<double> L(A);
   for (int j = 0; j < n; ++j) {
     double s = L[j * n + j];
@@ -339,20 +340,31 @@ static void spd_inverse(std::vector<double>& A, int n) {
       L[i * n + j] = t / d;
     }
   }
-  std::vector<double> y(n);
-  for (int c = 0; c < n; ++c) {
-    for (int i = 0; i < n; ++i) {
-      double t = i == c ? 1.0 : 0.0;
-      for (int k = 0; k < i; ++k) t -= L[i * n + k] * y[k];
-      y[i] = t / L[i * n + i];
+  // W lower triangular, row by row: W[i][j] = (delta_ij - sum_{j<=k<i} L[i][k] W[k][j]) / L[i][i]
+  std::vector<double> W((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    const double inv = 1.0 / L[i * n + i];
+    double* wi = &W[(size_t)i * n];
+    for (int k = 0; k < i; ++k) {
+      const double lik = L[i * n + k];
+      const double* wk = &W[(size_t)k * n];
+      for (int j = 0; j <= k; ++j) wi[j] -= lik * wk[j];
     }
-    for (int i = n - 1; i >= 0; --i) {
-      double t = y[i];
-      for (int k = i + 1; k < n; ++k) t -= L[k * n + i] * y[k];
-      y[i] = t / L[i * n + i];
-    }
-    for (int i = 0; i < n; ++i) A[i * n + c] = y[i];
+    for (int j = 0; j < i; ++j) wi[j] *= inv;
+    wi[i] = inv;
   }
+  // A^{-1}[i][k] = sum_{m >= max(i,k)} W[m][i] W[m][k]
+  std::fill(A.begin(), A.end(), 0.0);
+  for (int m = 0; m < n; ++m) {
+    const double* wm = &W[(size_t)m * n];
+    for (int i = 0; i <= m; ++i) {
+      const double a = wm[i];
+      double* ai = &A[(size_t)i * n];
+      for (int k = 0; k <= i; ++k) ai[k] += a * wm[k];
+    }
+  }
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k < i; ++k) A[(size_t)k * n + i] = A[(size_t)i * n + k];
 }
 
 template <typename T>
@@ -663,11 +675,17 @@ extern "C" hpdg_status hpdg_setup_operator(const hpdg_mesh* mh, const hpdg_opera
     }
     phase("edge spaces");
     std::vector<double>& binv = op->up.binv;
+    double t_asm = 0, t_inv = 0;
     for (auto& B : H.blocks) {
+      auto ta = std::chrono::steady_clock::now();
       std::vector<double> S = dg_submatrix(M, oo, B, eta2);
+      auto tb = std::chrono::steady_clock::now();
       spd_inverse(S, (int)B.size());
+      t_asm += std::chrono::duration<double>(tb - ta).count();
+      t_inv += std::chrono::duration<double>(std::chrono::steady_clock::now() - tb).count();
       binv.insert(binv.end(), S.begin(), S.end());
     }
+    if (verbose) std::fprintf(stderr, "hpdg setup: blocks: assemble %.3f s, invert %.3f s\n", t_asm, t_inv);
     phase("blocks");
     H.P = prolongation(M);
     phase("prolongation");
@@ -1311,6 +1329,7 @@ extern "C" hpdg_status hpdg_export(const hpdg_operator* op, int what, void* buf,
                              (int64_t)H.AC.idx.size(), (int64_t)H.P.idx.size(), op->ftab_bytes, op->dev_bytes};
       return put(v.data(), v.size(), buf, bytes);
     }
+    case 8: return put(op->up.binv.data(), op->up.binv.size(), buf, bytes);
     default:
       if (what >= 100 && what < 100 + (int)H.amg.lv.size()) {
         auto v = pack_csr(H.amg.lv[what - 100].A);

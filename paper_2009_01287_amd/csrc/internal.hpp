@@ -79,6 +79,7 @@ struct Mesh {
   int64_t ndof = 0;
   std::unordered_map<EKey, int, EKeyHash> cells;   // (level, anchor) -> leaf
   std::vector<Face> faces;
+  std::vector<int> ef_ptr, ef_idx;   // faces of element e: ef_idx[ef_ptr[e] .. ef_ptr[e+1])
   int max_dlevel = 0;            // largest level jump across a face
   // entities (built on demand for the preconditioner)
   std::vector<Entity> ent;

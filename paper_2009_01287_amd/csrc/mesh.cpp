@@ -189,6 +189,19 @@ void Mesh::build_faces() {
       }
     }
   }
+  // faces of every element (CSR)
+  ef_ptr.assign(ne + 1, 0);
+  for (const Face& f : faces) {
+    ef_ptr[f.em + 1]++;
+    if (f.ep >= 0) ef_ptr[f.ep + 1]++;
+  }
+  for (int e = 0; e < ne; ++e) ef_ptr[e + 1] += ef_ptr[e];
+  ef_idx.assign(ef_ptr[ne], 0);
+  std::vector<int> fill(ef_ptr.begin(), ef_ptr.end() - 1);
+  for (int i = 0; i < (int)faces.size(); ++i) {
+    ef_idx[fill[faces[i].em]++] = i;
+    if (faces[i].ep >= 0) ef_idx[fill[faces[i].ep]++] = i;
+  }
 }
 
 EKey Mesh::sub_key(int e, const int t[3]) const {

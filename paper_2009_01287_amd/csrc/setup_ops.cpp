@@ -215,9 +215,14 @@ std::vector<double> dg_submatrix(const Mesh& M, const OpOpts& o, const std::vect
         S[ai * nb + aj] += sc * s;
       }
   }
-  for (const Face& f : M.faces) {
-    bool touch = by_elem.count(f.em) || (f.ep >= 0 && by_elem.count(f.ep));
-    if (!touch) continue;
+  // the faces of the block's elements, each once
+  std::vector<int> fl;
+  for (auto& kv : by_elem)
+    for (int q = M.ef_ptr[kv.first]; q < M.ef_ptr[kv.first + 1]; ++q) fl.push_back(M.ef_idx[q]);
+  std::sort(fl.begin(), fl.end());
+  fl.erase(std::unique(fl.begin(), fl.end()), fl.end());
+  for (int fi : fl) {
+    const Face& f = M.faces[fi];
     FaceQuad Q = face_quad(M, f);
     int nQ = 1;
     for (int j = 0; j < Q.nt; ++j) nQ *= Q.q;
@@ -255,15 +260,27 @@ std::vector<double> dg_submatrix(const Mesh& M, const OpOpts& o, const std::vect
     if (pos.empty()) continue;
     double sig = penalty_or_br2(M, o, f, eta2);
     size_t nc = pos.size();
+    // -[[u]] {k du/dn} - {k dv/dn} [[v]] (+ sigma [[u]][[v]]): the jump of a
+    // column vanishes unless its node lies on the face, so only those rows
+    // carry the consistency terms
+    std::vector<size_t> onf;
     for (size_t a = 0; a < nc; ++a)
+      for (int g = 0; g < nQ; ++g)
+        if (Ju[a][g] != 0.0) { onf.push_back(a); break; }
+    for (size_t a : onf)
       for (size_t b = 0; b < nc; ++b) {
         double s = 0;
-        for (int g = 0; g < nQ; ++g) {
-          s += W[g] * (-Ju[a][g] * Fu[b][g] - Fu[a][g] * Ju[b][g]);
-          if (o.form == 0) s += W[g] * sig * Ju[a][g] * Ju[b][g];
-        }
-        S[pos[a] * nb + pos[b]] += s;
+        for (int g = 0; g < nQ; ++g) s += W[g] * Ju[a][g] * Fu[b][g];
+        S[pos[a] * nb + pos[b]] -= s;
+        S[pos[b] * nb + pos[a]] -= s;
       }
+    if (o.form == 0)
+      for (size_t a : onf)
+        for (size_t b : onf) {
+          double s = 0;
+          for (int g = 0; g < nQ; ++g) s += W[g] * sig * Ju[a][g] * Ju[b][g];
+          S[pos[a] * nb + pos[b]] += s;
+        }
     if (o.form == 1) {
       double c2 = f.ep >= 0 ? 0.25 : 1.0;
       for (const FaceSide& K : Q.sides) {

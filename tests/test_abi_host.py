@@ -90,6 +90,10 @@ def test_host_setup_matches_oracle(name, mk, form, eta, cap):
     bo = precond.edge_spaces(m, inN)
     bg = op.blocks()
     assert len(bo) == len(bg) and all(np.array_equal(a, b) for a, b in zip(bo, bg))
+    # exact V_e solves: the stored inverses times the oracle's A[V_e, V_e]
+    for b, Binv in zip(bo, op.block_inverses()):
+        Ab = dg.submatrix(m, opts, b)
+        assert np.abs(Binv @ Ab - np.eye(len(b))).max() <= 1e-9, name
     P, nc = precond.prolongation(m)
     PG = op.prolongation()
     assert PG.shape == P.shape
