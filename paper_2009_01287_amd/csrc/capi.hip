@@ -606,6 +606,10 @@ extern "C" hpdg_status hpdg_setup_operator(const hpdg_mesh* mh, const hpdg_opera
         }
         r.flen = (double)(f.hi[tdim[0]] - f.lo[tdim[0]]) / (double)M.N;
         r.sig = sig;
+        r.pn = (int8_t)(nb >= 0 ? M.p[nb] : 0);
+        r.nbase = nb >= 0 ? (int32_t)M.off[nb] : 0;
+        r.kho = nb >= 0 ? M.k[nb] / M.h[nb] : 0.0;
+        r.hn = nb >= 0 ? M.h[nb] : 1.0;
         if (d == 2) {
           r.foo = face_mat(M.p[e], r.oc[0], M.p[e], r.oc[0]);
           if (nb >= 0) {

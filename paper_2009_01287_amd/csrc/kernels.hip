@@ -379,6 +379,11 @@ __global__ __launch_bounds__(64) void k_faces(int nitems, int nrhs, int form,
 //          BR2   sigma v -> c^2 eta k_e L [s_o A_oo Minv_o v
 //                                          + s_n A_on Minv_n (A_on^T To - A_nn Tn)]
 //          with L the face length, s = m00 / h^2 (Sec. 2; Sec. 4.4).
+//  Memory: the element's face records (up to kFChunk per pass) and all
+//  neighbour traces are fetched in two parallel rounds into LDS before any
+//  face arithmetic, so a face costs no dependent global round trip.
+constexpr int kFChunk = 16;
+
 __global__ __launch_bounds__(64) void k_elem2d(int ne, int form, const int64_t* __restrict__ off,
                                                const int8_t* __restrict__ pdeg, const double* __restrict__ hh,
                                                const double* __restrict__ kk, const int32_t* __restrict__ sptr,
@@ -386,9 +391,10 @@ __global__ __launch_bounds__(64) void k_elem2d(int ne, int form, const int64_t* 
                                                const double* __restrict__ tab, TableLayout TL,
                                                const double* __restrict__ x, double* __restrict__ y) {
   __shared__ double sX[81], sA[81], sB[81];
-  __shared__ double sTo[4][9], sDo[4][9], sTn[4][9], sDn[4][9], sV[4][9], sW[4][9];
+  __shared__ double sTo[4][9], sDo[4][9], sV[4][9], sW[4][9];
   __shared__ double sG1[4][9], sG2[4][9];
-  __shared__ int sCnt[4];
+  __shared__ double sTn[kFChunk][9], sDn[kFChunk][9];
+  __shared__ FaceRec sR[kFChunk];
   // XCD-aware order: workgroups go round-robin to the 8 XCDs, so block b
   // takes element (b % 8) * per + b / 8 and each XCD walks a contiguous range
   // of the (space-filling ordered) element list; neighbours then share its L2
@@ -399,10 +405,12 @@ __global__ __launch_bounds__(64) void k_elem2d(int ne, int form, const int64_t* 
   const int p = pdeg[e], n = p + 1, nn = n * n;
   const double h = hh[e], k = kk[e];
   const int64_t base = off[e];
+  int sp[5];
+#pragma unroll
+  for (int t = 0; t < 5; ++t) sp[t] = sptr[e * 4 + t];
   const double* sM = tab + TL.mk + (p * 2 + 0) * 81;    // 1D mass / stiffness (cached)
   const double* sK = tab + TL.mk + (p * 2 + 1) * 81;
   for (int i = lane; i < nn; i += 64) sX[i] = x[base + i];
-  if (lane < 4) sCnt[lane] = sptr[e * 4 + lane + 1] - sptr[e * 4 + lane];
   __syncthreads();
   // volume, phase 1 (dimension 0)
   for (int i = lane; i < nn; i += 64) {
@@ -438,107 +446,116 @@ __global__ __launch_bounds__(64) void k_elem2d(int ne, int form, const int64_t* 
     for (int b = 0; b < n; ++b) acc += sM[i1 * n + b] * sA[b * n + i0] + sK[i1 * n + b] * sB[b * n + i0];
     yv[c] = k * acc;
   }
-  // faces
+  // faces, in passes of up to kFChunk records
   double G1 = 0.0, G2 = 0.0;
-  const int maxf = max(max(sCnt[0], sCnt[1]), max(sCnt[2], sCnt[3]));
-  const int rb = grp ? sptr[e * 4 + sidx] : 0;
-  const int cnt = grp ? sCnt[sidx] : 0;
-  for (int fi = 0; fi < maxf; ++fi) {
-    const bool have = fi < cnt;
-    FaceRec f;
-    f.nbr = -1;
-    f.q = 0;
-    f.foo = f.fon = f.fnn = 0;
-    f.flen = 0.0;
-    f.sig = 0.0;
-    if (have) f = recs[rb + fi];
-    const double flen = f.flen;
-    const bool inner = have && f.nbr >= 0;
-    int po = 0, no = 0;
-    double ho = 1.0, ko = 0.0;
-    if (inner) {
-      po = pdeg[f.nbr];
-      no = po + 1;
-      ho = hh[f.nbr];
-      ko = kk[f.nbr];
-    }
-    // stage this face's matrices (A_oo n*n, A_on n*no, A_nn no*no) in LDS
-    if (inner && j < no) {
-      const int so = 1 - s;
-      const int som = m == 0 ? 1 : no, sot = m == 0 ? no : 1;
-      const int64_t bo = off[f.nbr];
-      const double* Dso = tab + TL.dside + (po * 2 + so) * 9;
-      double dv = 0.0;
-      for (int a = 0; a < no; ++a) dv += Dso[a] * x[bo + a * som + j * sot];
-      sTn[sidx][j] = x[bo + (so ? po : 0) * som + j * sot];
-      sDn[sidx][j] = dv / ho;
+  const int sb = grp ? sp[sidx] : 0, se = grp ? sp[sidx + 1] : 0;
+  for (int c0 = sp[0]; c0 < sp[4]; c0 += kFChunk) {
+    const int nF = min(kFChunk, sp[4] - c0);
+    // round 1: the records of this pass
+    {
+      const unsigned long long* src = reinterpret_cast<const unsigned long long*>(recs + c0);
+      unsigned long long* dst = reinterpret_cast<unsigned long long*>(sR);
+      for (int t = lane; t < nF * 8; t += 64) dst[t] = src[t];
     }
     __syncthreads();
-    const double* Aoo = ftab + f.foo;     // face matrices (cached)
-    const double* Aon = ftab + f.fon;
-    const double* Ann = ftab + f.fnn;
-    double v = 0.0, dsum = 0.0;
-    if (have && j < n) {
-      for (int a = 0; a < n; ++a) {
-        v += Aoo[j * n + a] * sTo[sidx][a];
-        dsum += k * Aoo[j * n + a] * sDo[sidx][a];
-      }
-      for (int a = 0; a < no; ++a) {
-        v -= Aon[j * no + a] * sTn[sidx][a];
-        dsum += ko * Aon[j * no + a] * sDn[sidx][a];
-      }
-      const double csym = inner ? 0.5 : 1.0;
-      G1 -= flen * csym * sgn * dsum;
-      G2 -= csym * k * sgn * flen * v;
-      if (form == 0) G1 += flen * f.sig * v;
-      sV[sidx][j] = v;
-    }
-    if (form == 1) {
-      const double c2 = inner ? 0.25 : 1.0;
-      const double L2 = c2 * f.sig * flen * flen;
-      // own lifting: G1 += L2 s_o A_oo Minv_o v
-      __syncthreads();
-      if (have && j < n) {
-        const double* Mi = tab + TL.minv + p * 81;
-        double w = 0.0;
-        for (int a = 0; a < n; ++a) w += Mi[j * n + a] * sV[sidx][a];
-        sW[sidx][j] = w;
-      }
-      __syncthreads();
-      if (have && j < n) {
-        const double* Mi = tab + TL.minv + p * 81;
-        const int sk = s ? p : 0;
-        const double so = Mi[sk * n + sk] / (h * h);
-        double acc = 0.0;
-        for (int a = 0; a < n; ++a) acc += Aoo[j * n + a] * sW[sidx][a];
-        G1 += L2 * so * acc;
-      }
-      // neighbour lifting: G1 += L2 s_n A_on Minv_n (A_on^T To - A_nn Tn)
-      __syncthreads();
-      if (inner && j < no) {
-        double vn = 0.0;
-        for (int a = 0; a < n; ++a) vn += Aon[a * no + j] * sTo[sidx][a];
-        for (int a = 0; a < no; ++a) vn -= Ann[j * no + a] * sTn[sidx][a];
-        sV[sidx][j] = vn;
-      }
-      __syncthreads();
-      if (inner && j < no) {
-        const double* Mi = tab + TL.minv + po * 81;
-        double w = 0.0;
-        for (int a = 0; a < no; ++a) w += Mi[j * no + a] * sV[sidx][a];
-        sW[sidx][j] = w;
-      }
-      __syncthreads();
-      if (inner && j < n) {
-        const double* Mi = tab + TL.minv + po * 81;
-        const int sk = (1 - s) ? po : 0;
-        const double sn = Mi[sk * no + sk] / (ho * ho);
-        double acc = 0.0;
-        for (int a = 0; a < no; ++a) acc += Aon[j * no + a] * sW[sidx][a];
-        G1 += L2 * sn * acc;
+    // round 2: neighbour trace Tn and k_n/h_n-scaled normal derivative Dn per (face, node)
+    for (int t = lane; t < nF * 9; t += 64) {
+      const int f = t / 9, jj = t - 9 * f;
+      const int nb = sR[f].nbr, po = sR[f].pn;
+      if (nb >= 0 && jj <= po) {
+        const int no = po + 1, so = 1 - sR[f].side, mm = sR[f].m;
+        const int som = mm == 0 ? 1 : no, sot = mm == 0 ? no : 1;
+        const double* Dso = tab + TL.dside + (po * 2 + so) * 9;
+        const double* xn = x + sR[f].nbase;
+        double dv = 0.0;
+        for (int a = 0; a < no; ++a) dv += Dso[a] * xn[a * som + jj * sot];
+        sTn[f][jj] = xn[(so ? po : 0) * som + jj * sot];
+        sDn[f][jj] = sR[f].kho * dv;
       }
     }
     __syncthreads();
+    // faces of each side within this pass; the count is uniform over the block
+    int maxc = 0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) maxc = max(maxc, min(sp[t + 1], c0 + nF) - max(sp[t], c0));
+    const int fb = max(sb, c0) - c0, fe = min(se, c0 + nF) - c0;
+    for (int fi = 0; fi < maxc; ++fi) {
+      const int f = fb + fi;
+      const bool have = grp && f < fe;
+      const int fr = have ? f : 0;
+      const double flen = have ? sR[fr].flen : 0.0;
+      const double sig = have ? sR[fr].sig : 0.0;
+      const bool inner = have && sR[fr].nbr >= 0;
+      const int po = inner ? (int)sR[fr].pn : 0;
+      const int no = inner ? po + 1 : 0;
+      const double* Aoo = ftab + (have ? sR[fr].foo : 0);     // face matrices (cached)
+      const double* Aon = ftab + (inner ? sR[fr].fon : 0);
+      const double* Ann = ftab + (inner ? sR[fr].fnn : 0);
+      double v = 0.0, dsum = 0.0;
+      if (have && j < n) {
+        for (int a = 0; a < n; ++a) {
+          v += Aoo[j * n + a] * sTo[sidx][a];
+          dsum += k * Aoo[j * n + a] * sDo[sidx][a];
+        }
+        for (int a = 0; a < no; ++a) {
+          v -= Aon[j * no + a] * sTn[fr][a];
+          dsum += Aon[j * no + a] * sDn[fr][a];
+        }
+        const double csym = inner ? 0.5 : 1.0;
+        G1 -= flen * csym * sgn * dsum;
+        G2 -= csym * k * sgn * flen * v;
+        if (form == 0) G1 += flen * sig * v;
+        sV[sidx][j] = v;
+      }
+      if (form == 1) {
+        const double c2 = inner ? 0.25 : 1.0;
+        const double L2 = c2 * sig * flen * flen;
+        // own lifting: G1 += L2 s_o A_oo Minv_o v
+        __syncthreads();
+        if (have && j < n) {
+          const double* Mi = tab + TL.minv + p * 81;
+          double w = 0.0;
+          for (int a = 0; a < n; ++a) w += Mi[j * n + a] * sV[sidx][a];
+          sW[sidx][j] = w;
+        }
+        __syncthreads();
+        if (have && j < n) {
+          const double* Mi = tab + TL.minv + p * 81;
+          const int sk = s ? p : 0;
+          const double so = Mi[sk * n + sk] / (h * h);
+          double acc = 0.0;
+          for (int a = 0; a < n; ++a) acc += Aoo[j * n + a] * sW[sidx][a];
+          G1 += L2 * so * acc;
+        }
+        // neighbour lifting: G1 += L2 s_n A_on Minv_n (A_on^T To - A_nn Tn)
+        __syncthreads();
+        if (inner && j < no) {
+          double vn = 0.0;
+          for (int a = 0; a < n; ++a) vn += Aon[a * no + j] * sTo[sidx][a];
+          for (int a = 0; a < no; ++a) vn -= Ann[j * no + a] * sTn[fr][a];
+          sV[sidx][j] = vn;
+        }
+        __syncthreads();
+        if (inner && j < no) {
+          const double* Mi = tab + TL.minv + po * 81;
+          double w = 0.0;
+          for (int a = 0; a < no; ++a) w += Mi[j * no + a] * sV[sidx][a];
+          sW[sidx][j] = w;
+        }
+        __syncthreads();
+        if (inner && j < n) {
+          const double* Mi = tab + TL.minv + po * 81;
+          const int sk = (1 - s) ? po : 0;
+          const double hn = sR[fr].hn;
+          const double sn = Mi[sk * no + sk] / (hn * hn);
+          double acc = 0.0;
+          for (int a = 0; a < no; ++a) acc += Aon[j * no + a] * sW[sidx][a];
+          G1 += L2 * sn * acc;
+        }
+        __syncthreads();
+      }
+    }
+    __syncthreads();   // sR, sTn, sDn are rewritten by the next pass
   }
   if (grp && j < n) {
     sG1[sidx][j] = G1;
