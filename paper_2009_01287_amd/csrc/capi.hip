@@ -174,7 +174,7 @@ struct hpdg_operator {
   // preconditioner (type T = float or double per prec32)
   DevBuf dinvJ;
   DevBuf blk_rowb, blk_rowl, blk_ptr, blk_off, blk_dof, blk_inv;
-  int64_t blk_rows = 0;
+  int64_t blk_rows = 0, nblocks = 0;
   DevCSR P, PT;
   std::vector<LevelDev> lv;
   DevBuf coarse;
@@ -384,6 +384,7 @@ static void upload_prec(hpdg_operator* op) {
     boff.push_back(boff.back() + (int64_t)m * m);
   }
   op->blk_rows = (int64_t)rowb.size();
+  op->nblocks = (int64_t)H.blocks.size();
   op->blk_rowb.upload(rowb);
   op->blk_rowl.upload(rowl);
   op->blk_ptr.upload(bptr);
@@ -450,7 +451,8 @@ static void upload_device(hpdg_operator* op, hipStream_t s) {
   op->z.alloc(nv);
   op->pv.alloc(nv);
   op->Ap.alloc(nv);
-  op->part.alloc((size_t)1024 * hs * sizeof(double));
+  // dot-product shares: 1024 blocks per RHS, or one per element / per 256 DOFs
+  op->part.alloc((size_t)std::max<int64_t>({1024 * hs, (int64_t)op->ne, (op->ndof + 255) / 256}) * sizeof(double));
   op->scal.alloc((size_t)16 * 256 * sizeof(double));
   op->iscal.alloc((size_t)4 * 256 * sizeof(int));
   op->act.alloc((size_t)256 * sizeof(int));
@@ -610,11 +612,11 @@ extern "C" hpdg_status hpdg_setup_operator(const hpdg_mesh* mh, const hpdg_opera
         r.nbase = nb >= 0 ? (int32_t)M.off[nb] : 0;
         r.kho = nb >= 0 ? M.k[nb] / M.h[nb] : 0.0;
         r.hn = nb >= 0 ? M.h[nb] : 1.0;
-        if (d == 2) {
-          r.foo = face_mat(M.p[e], r.oc[0], M.p[e], r.oc[0]);
+        for (int j = 0; j < nt; ++j) {
+          r.foo[j] = face_mat(M.p[e], r.oc[j], M.p[e], r.oc[j]);
           if (nb >= 0) {
-            r.fon = face_mat(M.p[e], r.oc[0], M.p[nb], r.nc[0]);
-            r.fnn = face_mat(M.p[nb], r.nc[0], M.p[nb], r.nc[0]);
+            r.fon[j] = face_mat(M.p[e], r.oc[j], M.p[nb], r.nc[j]);
+            r.fnn[j] = face_mat(M.p[nb], r.nc[j], M.p[nb], r.nc[j]);
           }
         }
         per[(size_t)e * 2 * d + 2 * f.m + side].push_back(r);
@@ -750,12 +752,23 @@ static void launch_vol(hpdg_operator* op, int nrhs, const double* x, double* y, 
   launch_vol_p<DIM, 8, MODE>(op, nrhs, x, y, s);
 }
 
-static void apply_A_dev(hpdg_operator* op, const double* x, double* y, int nrhs, hipStream_t s) {
+// y = A x. With pdot (one RHS) the kernel that supports it also writes
+// per-element shares of x'y there and the call returns their count; 0 when
+// the caller has to form x'y itself.
+static int apply_A_dev(hpdg_operator* op, const double* x, double* y, int nrhs, hipStream_t s,
+                       double* pdot = nullptr) {
   if (op->dim == 2 && nrhs == 1 && !op->generic_faces) {
     const unsigned grid = 8u * (unsigned)((op->ne + 7) / 8);   // k_elem2d needs a multiple of 8
     hipLaunchKernelGGL(k_elem2d, dim3(grid), dim3(64), 0, s, op->ne, op->form, op->off.as<int64_t>(),
                        op->pdeg.as<int8_t>(), op->hh.as<double>(), op->kk.as<double>(), op->sptr.as<int32_t>(),
-                       op->recs.as<FaceRec>(), op->ftab.as<double>(), op->tab.as<double>(), op->TL, x, y);
+                       op->recs.as<FaceRec>(), op->ftab.as<double>(), op->tab.as<double>(), op->TL, x, y, pdot);
+    return pdot ? op->ne : 0;
+  } else if (op->dim == 3 && nrhs == 1 && !op->generic_faces) {
+    const unsigned grid = 8u * (unsigned)((op->ne + 7) / 8);   // k_elem3d needs a multiple of 8
+    hipLaunchKernelGGL(k_elem3d, dim3(grid), dim3(256), 0, s, op->ne, op->form, op->off.as<int64_t>(),
+                       op->pdeg.as<int8_t>(), op->hh.as<double>(), op->kk.as<double>(), op->sptr.as<int32_t>(),
+                       op->recs.as<FaceRec>(), op->ftab.as<double>(), op->tab.as<double>(), op->TL, x, y, pdot);
+    return pdot ? op->ne : 0;
   } else if (op->dim == 2) {
     launch_vol<2, 0>(op, nrhs, x, y, s);
     hipLaunchKernelGGL(k_faces<2>, dim3(op->ne * nrhs), dim3(64), 0, s, op->ne * nrhs, nrhs, op->form,
@@ -767,6 +780,7 @@ static void apply_A_dev(hpdg_operator* op, const double* x, double* y, int nrhs,
                        op->off.as<int64_t>(), op->pdeg.as<int8_t>(), op->hh.as<double>(), op->kk.as<double>(),
                        op->sptr.as<int32_t>(), op->recs.as<FaceRec>(), op->tab.as<double>(), op->TL, x, y);
   }
+  return 0;
 }
 
 template <typename T, int MODE, int LPR>
@@ -823,8 +837,11 @@ static void vcycle(hpdg_operator* op, size_t l, int nrhs, hipStream_t s) {
   (void)n;
 }
 
+// z = B r. With pdot (one RHS) the last kernel also writes per-block shares
+// of r'z there; returns their count (0 without pdot).
 template <typename T>
-static void apply_B_dev(hpdg_operator* op, const double* r, double* z, int nrhs, hipStream_t s) {
+static int apply_B_dev(hpdg_operator* op, const double* r, double* z, int nrhs, hipStream_t s,
+                       double* pdot = nullptr) {
   int64_t n = op->ndof * nrhs;
   const T* rt;
   if (std::is_same<T, double>::value) rt = (const T*)r;
@@ -869,8 +886,11 @@ static void apply_B_dev(hpdg_operator* op, const double* r, double* z, int nrhs,
   vcycle<T>(op, 0, nrhs, s);
   int64_t nt = op->ndof * nrhs;
   (void)L0;
+  if (nrhs != 1) pdot = nullptr;
   hipLaunchKernelGGL(k_prolong_out<T>, dim3(nblk(nt)), dim3(256), 0, s, (int)op->ndof, nrhs,
-                     op->P.ptr.as<int32_t>(), op->P.idx.as<int32_t>(), op->P.val.as<T>(), L0.x.as<T>(), zb, z);
+                     op->P.ptr.as<int32_t>(), op->P.idx.as<int32_t>(), op->P.val.as<T>(), L0.x.as<T>(), zb, z, r,
+                     pdot);
+  return pdot ? (int)nblk(nt) : 0;
 }
 
 static hpdg_status check_vec_args(hpdg_operator* op, const void* a, const void* b, int nrhs) {
@@ -980,9 +1000,15 @@ static CGScal cg_scal(hpdg_operator* op) {
   return S;
 }
 
-static void apply_B_any(hpdg_operator* op, const double* in, double* outv, int nrhs, hipStream_t s) {
-  if (op->prec32) apply_B_dev<float>(op, in, outv, nrhs, s);
-  else apply_B_dev<double>(op, in, outv, nrhs, s);
+static int apply_B_any(hpdg_operator* op, const double* in, double* outv, int nrhs, hipStream_t s,
+                       double* pdot = nullptr) {
+  if (op->prec32) return apply_B_dev<float>(op, in, outv, nrhs, s, pdot);
+  return apply_B_dev<double>(op, in, outv, nrhs, s, pdot);
+}
+
+// final stage of a dot product whose per-block shares are already in part
+static void dot_final(hpdg_operator* op, int nparts, int mode, const CGScal& S, hipStream_t s) {
+  hipLaunchKernelGGL(k_dot_final_ep, dim3(1), dim3(256), 0, s, nparts, 1, op->part.as<double>(), mode, S);
 }
 
 // k PCG iterations (Alg. PCG: alpha from r'z / p'Ap, residual update, B
@@ -995,13 +1021,23 @@ static void pcg_chunk(hpdg_operator* op, int k) {
   hipStream_t s = R.s;
   CGScal S = cg_scal(op);
   double *r = op->r.as<double>(), *z = op->z.as<double>(), *p = op->pv.as<double>(), *Ap = op->Ap.as<double>();
+  double* part = op->part.as<double>();
   for (int i = 0; i < k; ++i) {
-    apply_A_dev(op, p, Ap, nrhs, s);
-    dot_ep(op, p, Ap, nrhs, EP_PAP, S, s);
-    hipLaunchKernelGGL(k_cg_update2, dim3(nblk(n)), dim3(256), 0, s, n, nrhs, S.alpha, p, Ap, R.x, r);
-    dot_ep(op, r, r, nrhs, EP_RR, S, s);
-    apply_B_any(op, r, z, nrhs, s);
-    dot_ep(op, r, z, nrhs, EP_RZ, S, s);
+    // with one RHS the producers of Ap, r and z also write their shares of
+    // p'Ap, r'r and r'z, and only the final reductions are separate
+    const int na = apply_A_dev(op, p, Ap, nrhs, s, nrhs == 1 ? part : nullptr);
+    if (na) dot_final(op, na, EP_PAP, S, s);
+    else dot_ep(op, p, Ap, nrhs, EP_PAP, S, s);
+    if (nrhs == 1) {
+      hipLaunchKernelGGL(k_cg_update_rr, dim3(nblk(n)), dim3(256), 0, s, n, S.alpha, p, Ap, R.x, r, part);
+      dot_final(op, (int)nblk(n), EP_RR, S, s);
+    } else {
+      hipLaunchKernelGGL(k_cg_update2, dim3(nblk(n)), dim3(256), 0, s, n, nrhs, S.alpha, p, Ap, R.x, r);
+      dot_ep(op, r, r, nrhs, EP_RR, S, s);
+    }
+    const int nb = apply_B_any(op, r, z, nrhs, s, nrhs == 1 ? part : nullptr);
+    if (nb) dot_final(op, nb, EP_RZ, S, s);
+    else dot_ep(op, r, z, nrhs, EP_RZ, S, s);
     hipLaunchKernelGGL(k_cg_dir2, dim3(nblk(n)), dim3(256), 0, s, n, nrhs, S.beta, S.act, z, p);
   }
   R.enq += k;

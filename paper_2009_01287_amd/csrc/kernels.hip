@@ -389,7 +389,8 @@ __global__ __launch_bounds__(64) void k_elem2d(int ne, int form, const int64_t* 
                                                const double* __restrict__ kk, const int32_t* __restrict__ sptr,
                                                const FaceRec* __restrict__ recs, const double* __restrict__ ftab,
                                                const double* __restrict__ tab, TableLayout TL,
-                                               const double* __restrict__ x, double* __restrict__ y) {
+                                               const double* __restrict__ x, double* __restrict__ y,
+                                               double* __restrict__ pdot) {
   __shared__ double sX[81], sA[81], sB[81];
   __shared__ double sTo[4][9], sDo[4][9], sV[4][9], sW[4][9];
   __shared__ double sG1[4][9], sG2[4][9];
@@ -453,9 +454,10 @@ __global__ __launch_bounds__(64) void k_elem2d(int ne, int form, const int64_t* 
     const int nF = min(kFChunk, sp[4] - c0);
     // round 1: the records of this pass
     {
+      constexpr int W = (int)(sizeof(FaceRec) / 8);
       const unsigned long long* src = reinterpret_cast<const unsigned long long*>(recs + c0);
       unsigned long long* dst = reinterpret_cast<unsigned long long*>(sR);
-      for (int t = lane; t < nF * 8; t += 64) dst[t] = src[t];
+      for (int t = lane; t < nF * W; t += 64) dst[t] = src[t];
     }
     __syncthreads();
     // round 2: neighbour trace Tn and k_n/h_n-scaled normal derivative Dn per (face, node)
@@ -488,9 +490,9 @@ __global__ __launch_bounds__(64) void k_elem2d(int ne, int form, const int64_t* 
       const bool inner = have && sR[fr].nbr >= 0;
       const int po = inner ? (int)sR[fr].pn : 0;
       const int no = inner ? po + 1 : 0;
-      const double* Aoo = ftab + (have ? sR[fr].foo : 0);     // face matrices (cached)
-      const double* Aon = ftab + (inner ? sR[fr].fon : 0);
-      const double* Ann = ftab + (inner ? sR[fr].fnn : 0);
+      const double* Aoo = ftab + (have ? sR[fr].foo[0] : 0);     // face matrices (cached)
+      const double* Aon = ftab + (inner ? sR[fr].fon[0] : 0);
+      const double* Ann = ftab + (inner ? sR[fr].fnn[0] : 0);
       double v = 0.0, dsum = 0.0;
       if (have && j < n) {
         for (int a = 0; a < n; ++a) {
@@ -564,6 +566,7 @@ __global__ __launch_bounds__(64) void k_elem2d(int ne, int form, const int64_t* 
   __syncthreads();
   const double* D0 = tab + TL.dside + (p * 2 + 0) * 9;
   const double* D1 = tab + TL.dside + (p * 2 + 1) * 9;
+  double xy = 0.0;
   for (int i = lane, c = 0; i < nn; i += 64, ++c) {
     const int i0 = i % n, i1 = i / n;
     double v = yv[c];
@@ -574,6 +577,13 @@ __global__ __launch_bounds__(64) void k_elem2d(int ne, int form, const int64_t* 
     if (i1 == 0) v += sG1[2][i0];
     if (i1 == p) v += sG1[3][i0];
     y[base + i] = v;
+    xy += sX[i] * v;
+  }
+  // this element's share of x'y (the block is one wavefront), fixed order
+  if (pdot) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) xy += __shfl_xor(xy, o, 64);
+    if (lane == 0) pdot[e] = xy;
   }
 }
 
@@ -748,6 +758,331 @@ __global__ void k_cg_update2(int64_t n, int nrhs, const double* __restrict__ alp
   r[i] -= al * Ap[i];
 }
 
+// ------------------------------------------------------------- 3D element
+// 3D element kernel: volume and face terms of one element per block of 256
+// threads, all degrees in one launch, y written once.
+//  volume: y_K = k h (K x M x M + M x K x M + M x M x K) x_K, three 1D
+//          contraction phases through LDS.
+//  faces:  a face of side (m, s) has tangential slots 0, 1 (the two other
+//          dimensions in increasing order); its face-mass matrices are the
+//          Kronecker products of the unit-length 1D matrices of the slots,
+//          times the area L^2. With own traces To, Do and neighbour traces
+//          Tn, Dn (Dn scaled by k_n / h_n) on the face nodes:
+//            v    = (A0oo x A1oo) To - (A0on x A1on) Tn          (jump)
+//            dsum = k (A0oo x A1oo) Do + (A0on x A1on) Dn        (2 x average)
+//          G1 += L^2 (sigma v - c sgn dsum), G2 += -c k sgn L^2 v (c = 1/2
+//          inside, 1 on the boundary) for SIPG (Sec. 2); BR2 (Sec. 4.4)
+//          replaces sigma v by the liftings
+//            c^2 eta k_e L^4 [s_o (A0oo x A1oo)(Mi x Mi) v
+//                             + s_n (A0on x A1on)(Mi_n x Mi_n) vn],
+//            vn = (A0on x A1on)^T To - (A0nn x A1nn) Tn, s = m00 / h^3.
+//          Each Kronecker product is two 1D contractions (kron2).
+//  Memory: records and neighbour traces of up to kF3 faces are fetched in
+//  two parallel rounds into LDS; faces are then applied one after another
+//  (a fixed order, so the sums per side node are deterministic).
+constexpr int kF3 = 8;
+
+// out[j0 + r0 j1] (+)= scale * sum_{a0, a1} M0(j0, a0) M1(j1, a1) in[a0 + c0 a1],
+// M(j, a) = M[j ld + a] or, transposed, M[a ld + j]. All 256 threads; two
+// barriers. tmp holds r0 * c1 values.
+__device__ inline void kron2(const double* __restrict__ M0, int ld0, bool tr0, const double* __restrict__ M1,
+                             int ld1, bool tr1, int r0, int c0, int r1, int c1, const double* in, double* tmp,
+                             double* out, double scale, bool acc) {
+  for (int t = threadIdx.x; t < r0 * c1; t += 256) {
+    const int j0 = t % r0, a1 = t / r0;
+    double s = 0.0;
+    for (int a0 = 0; a0 < c0; ++a0) s += (tr0 ? M0[a0 * ld0 + j0] : M0[j0 * ld0 + a0]) * in[a0 + c0 * a1];
+    tmp[t] = s;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < r0 * r1; t += 256) {
+    const int j0 = t % r0, j1 = t / r0;
+    double s = 0.0;
+    for (int a1 = 0; a1 < c1; ++a1) s += (tr1 ? M1[a1 * ld1 + j1] : M1[j1 * ld1 + a1]) * tmp[j0 + r0 * a1];
+    out[t] = acc ? out[t] + scale * s : scale * s;
+  }
+  __syncthreads();
+}
+
+__device__ inline void tdims3(int m, int& t0, int& t1) {
+  t0 = m == 0 ? 1 : 0;
+  t1 = m == 2 ? 1 : 2;
+}
+
+__global__ __launch_bounds__(256) void k_elem3d(int ne, int form, const int64_t* __restrict__ off,
+                                                const int8_t* __restrict__ pdeg, const double* __restrict__ hh,
+                                                const double* __restrict__ kk, const int32_t* __restrict__ sptr,
+                                                const FaceRec* __restrict__ recs, const double* __restrict__ ftab,
+                                                const double* __restrict__ tab, TableLayout TL,
+                                                const double* __restrict__ x, double* __restrict__ y,
+                                                double* __restrict__ pdot) {
+  // volume buffers, reused by the face stage once the volume is done
+  __shared__ double sV0[729], sV1[729], sV2[729], sV3[729];
+  __shared__ double sTo[6][81], sDo[6][81], sG1[6][81], sG2[6][81];
+  __shared__ FaceRec sR[kF3];
+  __shared__ double sRed[4];
+  const int per = (int)(gridDim.x >> 3);
+  const int e = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+  if (e >= ne) return;
+  const int tid = threadIdx.x;
+  const int p = pdeg[e], n = p + 1, n2 = n * n, n3 = n2 * n;
+  const double h = hh[e], k = kk[e];
+  const int64_t base = off[e];
+  int sp[7];
+#pragma unroll
+  for (int t = 0; t < 7; ++t) sp[t] = sptr[e * 6 + t];
+  const double* Mt = tab + TL.mk + (p * 2 + 0) * 81;
+  const double* Kt = tab + TL.mk + (p * 2 + 1) * 81;
+  double* sX = sV0;
+  for (int i = tid; i < n3; i += 256) sX[i] = x[base + i];
+  for (int i = tid; i < 6 * 81; i += 256) {
+    (&sG1[0][0])[i] = 0.0;
+    (&sG2[0][0])[i] = 0.0;
+  }
+  __syncthreads();
+  // phase 1 (dimension 0) and the own traces
+  double* sA = sV1;
+  double* sB = sV2;
+  for (int r = tid; r < n3; r += 256) {
+    const int i0 = r % n, i12 = r - i0;
+    double a0 = 0.0, b0 = 0.0;
+    for (int a = 0; a < n; ++a) {
+      const double xa = sX[i12 + a];
+      a0 += xa * Mt[a * n + i0];
+      b0 += xa * Kt[a * n + i0];
+    }
+    sA[r] = a0;
+    sB[r] = b0;
+  }
+  for (int t = tid; t < 6 * n2; t += 256) {
+    const int side = t / n2, q = t - side * n2;
+    const int m = side >> 1, s = side & 1;
+    int t0, t1;
+    tdims3(m, t0, t1);
+    const int st[3] = {1, n, n2};
+    const int j0 = q % n, j1 = q / n;
+    const int o = j0 * st[t0] + j1 * st[t1];
+    const double* Ds = tab + TL.dside + (p * 2 + s) * 9;
+    double dv = 0.0;
+    for (int a = 0; a < n; ++a) dv += Ds[a] * sX[o + a * st[m]];
+    sTo[side][q] = sX[o + (s ? p : 0) * st[m]];
+    sDo[side][q] = dv / h;
+  }
+  __syncthreads();
+  // phase 2 (dimension 1): C into sV0 (x is no longer needed), D into sV3
+  double* sC = sV0;
+  double* sD = sV3;
+  for (int r = tid; r < n3; r += 256) {
+    const int i0 = r % n, i1 = (r / n) % n, i2 = r / n2;
+    double aa = 0.0, ab = 0.0, ba = 0.0;
+    for (int b = 0; b < n; ++b) {
+      const double av = sA[i0 + n * b + n2 * i2], bv = sB[i0 + n * b + n2 * i2];
+      const double mb = Mt[b * n + i1], kb = Kt[b * n + i1];
+      aa += av * mb;
+      ab += av * kb;
+      ba += bv * mb;
+    }
+    sC[r] = aa;
+    sD[r] = ab + ba;
+  }
+  __syncthreads();
+  // phase 3 (dimension 2)
+  double yv[3] = {0.0, 0.0, 0.0};
+  {
+    int c = 0;
+    for (int r = tid; r < n3; r += 256, ++c) {
+      const int i01 = r % n2, i2 = r / n2;
+      double acc = 0.0;
+      for (int cc = 0; cc < n; ++cc) acc += Kt[cc * n + i2] * sC[i01 + n2 * cc] + Mt[cc * n + i2] * sD[i01 + n2 * cc];
+      yv[c] = k * h * acc;
+    }
+  }
+  __syncthreads();
+  // face stage: work arrays in the volume buffers
+  double* sTn = sV0;                 // [kF3][81]
+  double* sDn = sV3;                 // [kF3][81]
+  double* U0 = sV1;                  // contraction temporaries
+  double* U1 = sV1 + 81;
+  double* U2 = sV1 + 162;
+  double* U3 = sV1 + 243;
+  double* Tmp = sV1 + 324;
+  double* Vv = sV2;                  // jump on own face nodes
+  double* Ww = sV2 + 81;
+  double* Vn = sV2 + 162;
+  double* Wn = sV2 + 243;
+  double* Zz = sV2 + 324;
+  for (int c0 = sp[0]; c0 < sp[6]; c0 += kF3) {
+    const int nF = min(kF3, sp[6] - c0);
+    {
+      constexpr int W = (int)(sizeof(FaceRec) / 8);
+      const unsigned long long* src = reinterpret_cast<const unsigned long long*>(recs + c0);
+      unsigned long long* dst = reinterpret_cast<unsigned long long*>(sR);
+      for (int t = tid; t < nF * W; t += 256) dst[t] = src[t];
+    }
+    __syncthreads();
+    // neighbour traces
+    for (int t = tid; t < nF * 81; t += 256) {
+      const int f = t / 81, q = t - 81 * f;
+      const int nb = sR[f].nbr, po = sR[f].pn, no = po + 1;
+      if (nb < 0 || q >= no * no) continue;
+      const int mm = sR[f].m, so = 1 - sR[f].side;
+      int t0, t1;
+      tdims3(mm, t0, t1);
+      const int st[3] = {1, no, no * no};
+      const int a0 = q % no, a1 = q / no;
+      const int o = a0 * st[t0] + a1 * st[t1];
+      const double* Dso = tab + TL.dside + (po * 2 + so) * 9;
+      const double* xn = x + sR[f].nbase;
+      double dv = 0.0;
+      for (int a = 0; a < no; ++a) dv += Dso[a] * xn[o + a * st[mm]];
+      sTn[f * 81 + q] = xn[o + (so ? po : 0) * st[mm]];
+      sDn[f * 81 + q] = sR[f].kho * dv;
+    }
+    __syncthreads();
+    for (int f = 0; f < nF; ++f) {
+      const FaceRec& R = sR[f];
+      const int m = R.m, s = R.side, side = 2 * m + s;
+      const bool inner = R.nbr >= 0;
+      const int po = inner ? (int)R.pn : 0, no = po + 1;
+      const double area = R.flen * R.flen;
+      const double sgn = s ? 1.0 : -1.0;
+      const double csym = inner ? 0.5 : 1.0;
+      const double* A0oo = ftab + R.foo[0];
+      const double* A1oo = ftab + R.foo[1];
+      const double* A0on = ftab + R.fon[0];
+      const double* A1on = ftab + R.fon[1];
+      const double* Tn = sTn + f * 81;
+      const double* Dn = sDn + f * 81;
+      // stage 1: slot-0 contractions of To, Do (own) and Tn, Dn (neighbour)
+      for (int t = tid; t < 4 * 81; t += 256) {
+        const int which = t / 81, q = t - 81 * which;
+        if (which < 2) {
+          if (q >= n2) continue;
+          const int j0 = q % n, a1 = q / n;
+          const double* in = which == 0 ? sTo[side] : sDo[side];
+          double sacc = 0.0;
+          for (int a0 = 0; a0 < n; ++a0) sacc += A0oo[j0 * n + a0] * in[a0 + n * a1];
+          (which == 0 ? U0 : U1)[q] = sacc;
+        } else {
+          if (!inner || q >= n * no) continue;
+          const int j0 = q % n, a1 = q / n;
+          const double* in = which == 2 ? Tn : Dn;
+          double sacc = 0.0;
+          for (int a0 = 0; a0 < no; ++a0) sacc += A0on[j0 * no + a0] * in[a0 + no * a1];
+          (which == 2 ? U2 : U3)[q] = sacc;
+        }
+      }
+      __syncthreads();
+      // stage 2: slot-1 contractions; jump, average and the penalty
+      for (int q = tid; q < n2; q += 256) {
+        const int j0 = q % n, j1 = q / n;
+        double v = 0.0, ds = 0.0;
+        for (int a1 = 0; a1 < n; ++a1) {
+          const double w = A1oo[j1 * n + a1];
+          v += w * U0[j0 + n * a1];
+          ds += k * w * U1[j0 + n * a1];
+        }
+        if (inner)
+          for (int a1 = 0; a1 < no; ++a1) {
+            const double w = A1on[j1 * no + a1];
+            v -= w * U2[j0 + n * a1];
+            ds += w * U3[j0 + n * a1];
+          }
+        double g1 = -area * csym * sgn * ds;
+        if (form == 0) g1 += area * R.sig * v;
+        sG1[side][q] += g1;
+        sG2[side][q] -= csym * k * sgn * area * v;
+        Vv[q] = v;
+      }
+      __syncthreads();
+      if (form == 1) {
+        const double c2 = inner ? 0.25 : 1.0;
+        const double L2 = c2 * R.sig * area * area;
+        const double* Mi = tab + TL.minv + p * 81;
+        const int sk = s ? p : 0;
+        const double so = Mi[sk * n + sk] / (h * h * h);
+        // own lifting: G1 += L2 s_o (A0oo x A1oo)(Mi x Mi) v
+        kron2(Mi, n, false, Mi, n, false, n, n, n, n, Vv, Tmp, Ww, 1.0, false);
+        kron2(A0oo, n, false, A1oo, n, false, n, n, n, n, Ww, Tmp, Zz, 1.0, false);
+        for (int q = tid; q < n2; q += 256) sG1[side][q] += L2 * so * Zz[q];
+        __syncthreads();
+        if (inner) {
+          // vn = (A0on x A1on)^T To - (A0nn x A1nn) Tn on the neighbour's face nodes
+          const double* A0nn = ftab + R.fnn[0];
+          const double* A1nn = ftab + R.fnn[1];
+          const double* Min = tab + TL.minv + po * 81;
+          const int skn = (1 - s) ? po : 0;
+          const double hn = R.hn;
+          const double sn = Min[skn * no + skn] / (hn * hn * hn);
+          kron2(A0on, no, true, A1on, no, true, no, n, no, n, sTo[side], Tmp, Vn, 1.0, false);
+          kron2(A0nn, no, false, A1nn, no, false, no, no, no, no, Tn, Tmp, Vn, -1.0, true);
+          kron2(Min, no, false, Min, no, false, no, no, no, no, Vn, Tmp, Wn, 1.0, false);
+          kron2(A0on, no, false, A1on, no, false, n, no, n, no, Wn, Tmp, Zz, 1.0, false);
+          for (int q = tid; q < n2; q += 256) sG1[side][q] += L2 * sn * Zz[q];
+          __syncthreads();
+        }
+      }
+    }
+  }
+  // lift the side sums into the element: y += D_side(i_m) G2 / h + [i_m on the face] G1
+  const double* D0 = tab + TL.dside + (p * 2 + 0) * 9;
+  const double* D1 = tab + TL.dside + (p * 2 + 1) * 9;
+  double xy = 0.0;
+  {
+    int c = 0;
+    for (int r = tid; r < n3; r += 256, ++c) {
+      const int i[3] = {r % n, (r / n) % n, r / n2};
+      double v = yv[c];
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        int t0, t1;
+        tdims3(m, t0, t1);
+        const int q = i[t0] + n * i[t1];
+        v += (D0[i[m]] * sG2[2 * m][q] + D1[i[m]] * sG2[2 * m + 1][q]) / h;
+        if (i[m] == 0) v += sG1[2 * m][q];
+        if (i[m] == p) v += sG1[2 * m + 1][q];
+      }
+      y[base + r] = v;
+      xy += x[base + r] * v;
+    }
+  }
+  if (pdot) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) xy += __shfl_xor(xy, o, 64);
+    if ((tid & 63) == 0) sRed[tid >> 6] = xy;
+    __syncthreads();
+    if (tid == 0) pdot[e] = (sRed[0] + sRed[1]) + (sRed[2] + sRed[3]);
+  }
+}
+
+// sum over a block of 256 threads in a fixed order; valid in thread 0
+__device__ inline double block_sum256(double v) {
+  __shared__ double sw[4];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if ((threadIdx.x & 63) == 0) sw[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return ((sw[0] + sw[1]) + (sw[2] + sw[3]));
+}
+
+// nrhs == 1: x += alpha p ; r -= alpha Ap, and the block's share of r'r
+__global__ __launch_bounds__(256) void k_cg_update_rr(int64_t n, const double* __restrict__ alpha,
+                                                     const double* __restrict__ p, const double* __restrict__ Ap,
+                                                     double* __restrict__ x, double* __restrict__ r,
+                                                     double* __restrict__ part) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double rr = 0.0;
+  if (i < n) {
+    const double al = alpha[0];
+    x[i] += al * p[i];
+    const double ri = r[i] - al * Ap[i];
+    r[i] = ri;
+    rr = ri * ri;
+  }
+  const double s = block_sum256(rr);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
 // p = z + beta p while active
 __global__ void k_cg_dir2(int64_t n, int nrhs, const double* __restrict__ beta, const int* __restrict__ act,
                           const double* __restrict__ z, double* __restrict__ p) {
@@ -874,14 +1209,24 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_prolong_out(int nrows, int nrhs, const int32_t* __restrict__ ptr,
                                                      const int32_t* __restrict__ idx, const T* __restrict__ val,
                                                      const T* __restrict__ e, const T* __restrict__ zb,
-                                                     double* __restrict__ z) {
+                                                     double* __restrict__ z, const double* __restrict__ rdot,
+                                                     double* __restrict__ pdot) {
+  // z = z_B + P e; with pdot (nrhs == 1) also the block's share of r'z
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t row = t / nrhs;
   const int c = (int)(t - row * nrhs);
-  if (row >= nrows) return;
-  T acc = 0;
-  for (int q = ptr[row]; q < ptr[row + 1]; ++q) acc += val[q] * e[(int64_t)idx[q] * nrhs + c];
-  z[row * nrhs + c] = (double)(zb[row * nrhs + c] + acc);
+  double rz = 0.0;
+  if (row < nrows) {
+    T acc = 0;
+    for (int q = ptr[row]; q < ptr[row + 1]; ++q) acc += val[q] * e[(int64_t)idx[q] * nrhs + c];
+    const double zv = (double)(zb[row * nrhs + c] + acc);
+    z[row * nrhs + c] = zv;
+    if (pdot) rz = rdot[row] * zv;
+  }
+  if (pdot) {
+    const double s = block_sum256(rz);
+    if (threadIdx.x == 0) pdot[blockIdx.x] = s;
+  }
 }
 
 // exact V_e solves: LPR lanes per block row (coalesced row reads), nrhs == 1

@@ -7,7 +7,7 @@
 namespace hpdg {
 
 // One face as seen from one of its two elements (or the only one on the
-// boundary). 64 bytes; the neighbour's degree, first DOF and coefficient are
+// boundary). 72 bytes; the neighbour's degree, first DOF and coefficient are
 // copied in so that the element kernel needs no second lookup.
 struct FaceRec {
   int32_t nbr;      // neighbour element, -1 on the boundary
@@ -17,17 +17,16 @@ struct FaceRec {
   int8_t pn;        // neighbour degree (0 on the boundary)
   uint8_t oc[2];    // sub-interval code of the face inside the own side, per tangential slot
   uint8_t nc[2];    // same inside the neighbour's side
-  int32_t foo;      // offsets (doubles) in the face-matrix table of the unit-length 1D
-  int32_t fon;      //   face-mass matrices A_oo (own x own), A_on (own x neighbour),
-  int32_t fnn;      //   A_nn (neighbour x neighbour)
   int32_t nbase;    // first DOF of the neighbour
-  int32_t pad;
+  int32_t foo[2];   // per tangential slot: offsets (doubles) in the face-matrix table of
+  int32_t fon[2];   //   the unit-length 1D face-mass matrices A_oo (own x own),
+  int32_t fnn[2];   //   A_on (own x neighbour), A_nn (neighbour x neighbour)
   double flen;      // physical face side length
   double sig;       // SIPG penalty sigma, or eta*k_e for BR2
   double kho;       // neighbour k / h (0 on the boundary)
   double hn;        // neighbour h (1 on the boundary)
 };
-static_assert(sizeof(FaceRec) == 64, "FaceRec layout");
+static_assert(sizeof(FaceRec) == 72, "FaceRec layout");
 
 // Tables of the 1D basis, all degrees, in one device buffer (doubles).
 struct TableLayout {
