@@ -79,6 +79,10 @@ typedef struct {
   int max_nrhs;      /* >= 1 and a divisor of 256: largest nrhs accepted by the operator calls */
   int host_only;     /* 1: build only the host-side setup data (readable with hpdg_export) and
                         touch no GPU; the operator calls then fail with HPDG_E_UNSUPPORTED */
+  int no_prec;       /* 1: the DG operator only (no preconditioner setup); hpdg_apply_B and
+                        hpdg_pcg_solve then fail with HPDG_E_UNSUPPORTED */
+  int graph;         /* 1: PCG iterations are captured once per (chunk length, nrhs, x) into
+                        HIP graphs and replayed (same kernels, same results) */
 } hpdg_operator_opts;
 
 /* Builds the operator and the preconditioner (host setup, then upload):
@@ -136,6 +140,19 @@ hpdg_status hpdg_operator_upload(hpdg_operator* op, void* stream);
  * counting pass over the upload when it is not on the device yet); the
  * figure a server admits requests by. */
 hpdg_status hpdg_operator_device_bytes(hpdg_operator* op, int64_t* bytes);
+
+/* Autotuner for the one-RHS path: for P^T and every AMG level matrix A_l,
+ * R_l, P_l, times y = A x under each row binning (rows longer than 32, 64,
+ * 128 or no threshold get a wavefront each; the others 1, 2, 4, 8 or 16
+ * lanes) on `stream` and keeps the fastest. Changes the summation order and
+ * so the last bits of B r; drops captured graphs. With no_prec only the
+ * element kernel is tuned. In 2D it also picks, for the element kernel, the
+ * elements per workgroup (1 or 2) and the face records staged per pass (8,
+ * 16 or 32); the results do not depend on them. report: cap rows of 8 int64
+ * (kind 0 A / 1 R / 2 P / 3 P^T / 4 element kernel, level, rows (ndof), nnz
+ * (elements), chosen threshold (records per pass), chosen lanes (elements
+ * per workgroup), ns before, ns after); *n rows written. */
+hpdg_status hpdg_operator_tune(hpdg_operator* op, void* stream, int64_t* report, int cap, int* n);
 
 /* Batch executor for serving (continuous batching on one GPU): up to
  * max_active (1..64) PCG solves, each on a stream of its own (default

@@ -33,7 +33,8 @@ class HpdgError(RuntimeError):
 class Opts(C.Structure):
     _fields_ = [("form", C.c_int), ("penalty_rule", C.c_int), ("eta", C.c_double),
                 ("prec_fp32", C.c_int), ("remark_relax", C.c_int), ("jb_only", C.c_int),
-                ("max_block", C.c_int), ("max_nrhs", C.c_int), ("host_only", C.c_int)]
+                ("max_block", C.c_int), ("max_nrhs", C.c_int), ("host_only", C.c_int), ("no_prec", C.c_int),
+                ("graph", C.c_int)]
 
 
 class SolveInfo(C.Structure):
@@ -49,7 +50,7 @@ SYMBOLS = ["hpdg_last_error", "hpdg_setup_mesh", "hpdg_mesh_info", "hpdg_mesh_de
            "hpdg_setup_operator", "hpdg_operator_destroy", "hpdg_rhs", "hpdg_apply_A",
            "hpdg_apply_B", "hpdg_pcg_solve", "hpdg_export", "hpdg_operator_upload",
            "hpdg_operator_device_bytes", "hpdg_batch_create", "hpdg_batch_destroy", "hpdg_batch_admit",
-           "hpdg_batch_step", "hpdg_batch_poll"]
+           "hpdg_batch_step", "hpdg_batch_poll", "hpdg_operator_tune"]
 
 _lib = None
 
@@ -82,6 +83,7 @@ def lib():
     L.hpdg_export.argtypes = [vp, C.c_int, vp, C.POINTER(C.c_size_t)]
     L.hpdg_operator_upload.argtypes = [vp, vp]
     L.hpdg_operator_device_bytes.argtypes = [vp, C.POINTER(C.c_int64)]
+    L.hpdg_operator_tune.argtypes = [vp, vp, C.POINTER(C.c_int64), C.c_int, C.POINTER(C.c_int)]
     L.hpdg_batch_create.argtypes = [C.c_int, C.POINTER(vp)]
     L.hpdg_batch_destroy.argtypes = [vp]
     L.hpdg_batch_destroy.restype = None
@@ -145,14 +147,14 @@ class Operator:
 
     def __init__(self, mesh: Mesh, form="sipg", penalty_rule=0, eta=1.0, prec_fp32=False,
                  remark_relax=False, jb_only=False, max_block=0, max_nrhs=1, host_only=False,
-                 stream=None):
+                 no_prec=False, graph=False, stream=None):
         L = lib()
         self.mesh = mesh
         self.ndof = mesh.ndof
         self.max_nrhs = max_nrhs
         o = Opts(0 if form == "sipg" else 1 if form == "br2" else -1, penalty_rule, float(eta),
                  int(prec_fp32), int(remark_relax), int(jb_only), int(max_block), int(max_nrhs),
-                 int(host_only))
+                 int(host_only), int(no_prec), int(graph))
         h = C.c_void_p()
         _check(L.hpdg_setup_operator(mesh.h, C.byref(o), C.c_void_p(0) if host_only else _stream(stream),
                                      C.byref(h)))
@@ -187,6 +189,21 @@ class Operator:
     def upload(self, stream=None):
         """hpdg_operator_upload: device copy of a host_only operator."""
         _check(lib().hpdg_operator_upload(self.h, _stream(stream)))
+
+    def tune(self, stream=None):
+        """hpdg_operator_tune: per-matrix row binning picked by timing; returns
+        one dict per matrix."""
+        cap = 64
+        rep = (C.c_int64 * (8 * cap))()
+        n = C.c_int()
+        _check(lib().hpdg_operator_tune(self.h, _stream(stream), rep, cap, C.byref(n)))
+        kinds = {0: "A", 1: "R", 2: "P", 3: "PT", 4: "elem"}
+        out = []
+        for i in range(n.value):
+            r = rep[8 * i:8 * i + 8]
+            out.append({"matrix": kinds[int(r[0])], "level": int(r[1]), "rows": int(r[2]), "nnz": int(r[3]),
+                        "longrow": int(r[4]), "lanes": int(r[5]), "ns_default": int(r[6]), "ns_tuned": int(r[7])})
+        return out
 
     def device_bytes(self):
         b = C.c_int64(0)

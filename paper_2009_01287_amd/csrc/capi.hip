@@ -93,10 +93,13 @@ struct DevCSR {
   int nrows = 0, ncols = 0;
   int64_t nnz = 0;
   int lpr = 1;                 // lanes per short row
-  int nlong = 0;               // rows longer than kLongRow, one wavefront each
+  int nlong = 0;               // rows longer than longrow, one wavefront each
+  int longrow = 32;
   DevBuf ptr, idx, val, rows;  // rows: long rows first, then short rows
 };
 constexpr int kLongRow = 32;
+
+void bin_rows(const CSR& A, DevCSR& D, int longrow, int lpr);
 
 template <typename T>
 void upload_csr(const CSR& A, DevCSR& D) {
@@ -109,18 +112,26 @@ void upload_csr(const CSR& A, DevCSR& D) {
   D.ptr.upload(p32);
   D.idx.upload(A.idx);
   D.val.upload(v);
+  bin_rows(A, D, kLongRow, 0);
+}
+
+// Row binning of a CSR matrix for the one-RHS kernels: rows longer than
+// `longrow` get one wavefront each (listed first), the others `lpr` lanes
+// (0: from the average length of the short rows).
+void bin_rows(const CSR& A, DevCSR& D, int longrow, int lpr) {
   std::vector<int32_t> lr, sr;
   int64_t snnz = 0;
   for (int64_t i = 0; i < A.nrows; ++i) {
     int64_t len = A.ptr[i + 1] - A.ptr[i];
-    if (len > kLongRow) lr.push_back((int32_t)i);
+    if (len > longrow) lr.push_back((int32_t)i);
     else { sr.push_back((int32_t)i); snnz += len; }
   }
   D.nlong = (int)lr.size();
+  D.longrow = longrow;
   lr.insert(lr.end(), sr.begin(), sr.end());
   D.rows.upload(lr);
   double avg = sr.empty() ? 0.0 : (double)snnz / (double)sr.size();
-  D.lpr = avg > 12 ? 16 : avg > 6 ? 8 : avg > 2.5 ? 4 : avg > 1.5 ? 2 : 1;
+  D.lpr = lpr > 0 ? lpr : avg > 12 ? 16 : avg > 6 ? 8 : avg > 2.5 ? 4 : avg > 1.5 ? 2 : 1;
 }
 
 struct PrecHost {
@@ -186,11 +197,24 @@ struct hpdg_operator {
   int64_t ftab_bytes = 0;
   int64_t dev_bytes = 0;     // device memory held by this operator once uploaded
   int uploaded = 0;
+  int no_prec = 0;           // operator only: apply_B and PCG unsupported
+  int use_graph = 0;         // PCG chunks replayed from captured HIP graphs
+  int epb = 1;               // elements per workgroup of the 2D element kernel
+  int fchunk = 16;           // face records per pass of the 2D element kernel
+  struct GraphEntry {
+    int k, nrhs;
+    double* x;
+    hipGraphExec_t exec;
+  };
+  std::vector<GraphEntry> graphs;
+  hipStream_t cap_stream = nullptr;   // private stream the chunks are captured on
   PinArea* pin = nullptr;    // pinned host mirror of the CG flags and norms
   double* hist_pin = nullptr;
   hipEvent_t ev = nullptr;   // completion of the last enqueued PCG chunk
   PcgRun run;
   ~hpdg_operator() {
+    for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     if (pin) (void)hipHostFree(pin);
     if (hist_pin) (void)hipHostFree(hist_pin);
     if (ev) (void)hipEventDestroy(ev);
@@ -420,6 +444,11 @@ static void upload_prec(hpdg_operator* op) {
   op->zT.alloc((size_t)op->ndof * op->max_nrhs * sizeof(T));
 }
 
+// second region of the share buffer (one RHS), after the largest first region
+static int64_t part_off2(const hpdg_operator* op) {
+  return std::max<int64_t>(op->ne, (op->ndof + 255) / 256) + 64;
+}
+
 // All device buffers of an operator from its host data. In a counting pass
 // (g_dry) only the sizes are recorded. Copies are synchronous; the call ends
 // with a synchronisation of `s`.
@@ -437,7 +466,8 @@ static void upload_device(hpdg_operator* op, hipStream_t s) {
   op->dbucket.clear();
   op->dbucket.resize(kMaxP + 1);
   for (int p = 1; p <= kMaxP; ++p) op->dbucket[p].upload(op->bucket[p]);
-  if (op->prec32) {
+  if (op->no_prec) {
+  } else if (op->prec32) {
     upload_prec<float>(op);
     std::vector<float> bi(U.binv.begin(), U.binv.end());
     op->blk_inv.upload(bi);
@@ -452,7 +482,7 @@ static void upload_device(hpdg_operator* op, hipStream_t s) {
   op->pv.alloc(nv);
   op->Ap.alloc(nv);
   // dot-product shares: 1024 blocks per RHS, or one per element / per 256 DOFs
-  op->part.alloc((size_t)std::max<int64_t>({1024 * hs, (int64_t)op->ne, (op->ndof + 255) / 256}) * sizeof(double));
+  op->part.alloc((size_t)std::max<int64_t>(1024 * hs, 2 * part_off2(op)) * sizeof(double));
   op->scal.alloc((size_t)16 * 256 * sizeof(double));
   op->iscal.alloc((size_t)4 * 256 * sizeof(int));
   op->act.alloc((size_t)256 * sizeof(int));
@@ -588,6 +618,24 @@ extern "C" hpdg_status hpdg_setup_operator(const hpdg_mesh* mh, const hpdg_opera
       fmap.emplace(key, at);
       return at;
     };
+    // BR2 liftings (3D): a face-mass matrix times the inverse 1D mass matrix
+    // of its column side, L = A Minv (rows p_row+1, columns p_col+1)
+    auto lift_mat = [&](int32_t a_off, int prow, int pcol, int kind, int k0, int k1, int k2, int k3) -> int32_t {
+      std::array<int, 5> key{k0, k1, k2, k3, kind};
+      auto it = fmap.find(key);
+      if (it != fmap.end()) return it->second;
+      int32_t at = (int32_t)ftab.size();
+      const int nr = prow + 1, nc = pcol + 1;
+      const std::vector<double>& Mi = basis(pcol).Minv;
+      for (int i = 0; i < nr; ++i)
+        for (int j = 0; j < nc; ++j) {
+          double s = 0;
+          for (int l = 0; l < nc; ++l) s += ftab[a_off + i * nc + l] * Mi[l * nc + j];
+          ftab.push_back(s);
+        }
+      fmap.emplace(key, at);
+      return at;
+    };
     for (const Face& f : M.faces) {
       double sig = penalty_or_br2(M, oo, f, eta2);
       int tdim[2] = {0, 0}, nt = 0;
@@ -617,6 +665,10 @@ extern "C" hpdg_status hpdg_setup_operator(const hpdg_mesh* mh, const hpdg_opera
           if (nb >= 0) {
             r.fon[j] = face_mat(M.p[e], r.oc[j], M.p[nb], r.nc[j]);
             r.fnn[j] = face_mat(M.p[nb], r.nc[j], M.p[nb], r.nc[j]);
+          }
+          if (o->form == 1 && d == 3) {
+            r.loo[j] = lift_mat(r.foo[j], M.p[e], M.p[e], 1, M.p[e], r.oc[j], M.p[e], r.oc[j]);
+            if (nb >= 0) r.lon[j] = lift_mat(r.fon[j], M.p[e], M.p[nb], 2, M.p[e], r.oc[j], M.p[nb], r.nc[j]);
           }
         }
         per[(size_t)e * 2 * d + 2 * f.m + side].push_back(r);
@@ -652,56 +704,62 @@ extern "C" hpdg_status hpdg_setup_operator(const hpdg_mesh* mh, const hpdg_opera
       tlast = now;
     };
     phase("faces");
-    PrecHost& H = op->host;
-    H.diag = dg_diagonal(M, oo);
-    phase("diagonal");
-    H.lab = dof_labels(M, o->remark_relax);
-    phase("labels");
-    if (o->jb_only)
-      for (auto& l : H.lab)
-        if (l == 2) l = 1;
-    H.blocks = edge_spaces(M, H.lab);
-    if (o->max_block > 0) {
-      std::vector<std::vector<int64_t>> keep;
-      for (auto& b : H.blocks) {
-        if ((int)b.size() > o->max_block) {
-          for (int64_t g : b) H.lab[g] = 1;
-        } else {
-          keep.push_back(std::move(b));
+    op->no_prec = o->no_prec ? 1 : 0;
+    op->use_graph = o->graph ? 1 : 0;
+    if (const char* v = std::getenv("HPDG_ELEM2D_EPB")) op->epb = std::atoi(v) == 2 ? 2 : 1;
+    if (const char* v = std::getenv("HPDG_ELEM2D_FCHUNK")) op->fchunk = std::atoi(v) == 8 ? 8 : std::atoi(v) == 32 ? 32 : 16;
+    if (!op->no_prec) {
+      PrecHost& H = op->host;
+      H.diag = dg_diagonal(M, oo);
+      phase("diagonal");
+      H.lab = dof_labels(M, o->remark_relax);
+      phase("labels");
+      if (o->jb_only)
+        for (auto& l : H.lab)
+          if (l == 2) l = 1;
+      H.blocks = edge_spaces(M, H.lab);
+      if (o->max_block > 0) {
+        std::vector<std::vector<int64_t>> keep;
+        for (auto& b : H.blocks) {
+          if ((int)b.size() > o->max_block) {
+            for (int64_t g : b) H.lab[g] = 1;
+          } else {
+            keep.push_back(std::move(b));
+          }
         }
+        H.blocks.swap(keep);
       }
-      H.blocks.swap(keep);
+      // inverse diagonal on V_J, +0 on interior DOFs, -0 on V_e DOFs (marks
+      // the DOFs that the block solves write)
+      H.dinvJ.assign(M.ndof, 0.0);
+      for (int64_t g = 0; g < M.ndof; ++g) {
+        if (H.lab[g] == 1) H.dinvJ[g] = 1.0 / H.diag[g];
+        else if (H.lab[g] == 2) H.dinvJ[g] = -0.0;
+      }
+      phase("edge spaces");
+      std::vector<double>& binv = op->up.binv;
+      double t_asm = 0, t_inv = 0;
+      for (auto& B : H.blocks) {
+        auto ta = std::chrono::steady_clock::now();
+        std::vector<double> S = dg_submatrix(M, oo, B, eta2);
+        auto tb = std::chrono::steady_clock::now();
+        spd_inverse(S, (int)B.size());
+        t_asm += std::chrono::duration<double>(tb - ta).count();
+        t_inv += std::chrono::duration<double>(std::chrono::steady_clock::now() - tb).count();
+        binv.insert(binv.end(), S.begin(), S.end());
+      }
+      if (verbose) std::fprintf(stderr, "hpdg setup: blocks: assemble %.3f s, invert %.3f s\n", t_asm, t_inv);
+      phase("blocks");
+      H.P = prolongation(M);
+      phase("prolongation");
+      op->nconf = M.nconf;
+      H.PT = csr_transpose(H.P);
+      CSR AP = lor_times(M, H.P);
+      H.AC = csr_matmul(H.PT, AP);
+      phase("lor");
+      H.amg = amg_setup(H.AC);
+      phase("amg");
     }
-    // inverse diagonal on V_J, +0 on interior DOFs, -0 on V_e DOFs (marks
-    // the DOFs that the block solves write)
-    H.dinvJ.assign(M.ndof, 0.0);
-    for (int64_t g = 0; g < M.ndof; ++g) {
-      if (H.lab[g] == 1) H.dinvJ[g] = 1.0 / H.diag[g];
-      else if (H.lab[g] == 2) H.dinvJ[g] = -0.0;
-    }
-    phase("edge spaces");
-    std::vector<double>& binv = op->up.binv;
-    double t_asm = 0, t_inv = 0;
-    for (auto& B : H.blocks) {
-      auto ta = std::chrono::steady_clock::now();
-      std::vector<double> S = dg_submatrix(M, oo, B, eta2);
-      auto tb = std::chrono::steady_clock::now();
-      spd_inverse(S, (int)B.size());
-      t_asm += std::chrono::duration<double>(tb - ta).count();
-      t_inv += std::chrono::duration<double>(std::chrono::steady_clock::now() - tb).count();
-      binv.insert(binv.end(), S.begin(), S.end());
-    }
-    if (verbose) std::fprintf(stderr, "hpdg setup: blocks: assemble %.3f s, invert %.3f s\n", t_asm, t_inv);
-    phase("blocks");
-    H.P = prolongation(M);
-    phase("prolongation");
-    op->nconf = M.nconf;
-    H.PT = csr_transpose(H.P);
-    CSR AP = lor_times(M, H.P);
-    H.AC = csr_matmul(H.PT, AP);
-    phase("lor");
-    H.amg = amg_setup(H.AC);
-    phase("amg");
     // node coordinates (export)
     op->coords.assign(M.ndof * d, 0.0);
     for (int e = 0; e < M.ne; ++e) {
@@ -758,10 +816,26 @@ static void launch_vol(hpdg_operator* op, int nrhs, const double* x, double* y, 
 static int apply_A_dev(hpdg_operator* op, const double* x, double* y, int nrhs, hipStream_t s,
                        double* pdot = nullptr) {
   if (op->dim == 2 && nrhs == 1 && !op->generic_faces) {
-    const unsigned grid = 8u * (unsigned)((op->ne + 7) / 8);   // k_elem2d needs a multiple of 8
-    hipLaunchKernelGGL(k_elem2d, dim3(grid), dim3(64), 0, s, op->ne, op->form, op->off.as<int64_t>(),
-                       op->pdeg.as<int8_t>(), op->hh.as<double>(), op->kk.as<double>(), op->sptr.as<int32_t>(),
-                       op->recs.as<FaceRec>(), op->ftab.as<double>(), op->tab.as<double>(), op->TL, x, y, pdot);
+    auto launch = [&](auto epb_c, auto fc_c) {
+      constexpr int EPB = decltype(epb_c)::value, FC = decltype(fc_c)::value;
+      // grid a multiple of 8 workgroups of EPB elements (XCD-aware order)
+      const unsigned grid = 8u * (unsigned)((op->ne + 8 * EPB - 1) / (8 * EPB));
+      hipLaunchKernelGGL((k_elem2d<EPB, FC>), dim3(grid), dim3(64 * EPB), 0, s, op->ne, op->form,
+                         op->off.as<int64_t>(), op->pdeg.as<int8_t>(), op->hh.as<double>(), op->kk.as<double>(),
+                         op->sptr.as<int32_t>(), op->recs.as<FaceRec>(), op->ftab.as<double>(),
+                         op->tab.as<double>(), op->TL, x, y, pdot);
+    };
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    auto with_fc = [&](auto epb_c) {
+      switch (op->fchunk) {
+        case 8: launch(epb_c, std::integral_constant<int, 8>()); break;
+        case 32: launch(epb_c, std::integral_constant<int, 32>()); break;
+        default: launch(epb_c, std::integral_constant<int, 16>()); break;
+      }
+    };
+    if (op->epb == 2) with_fc(I2());
+    else with_fc(I1());
     return pdot ? op->ne : 0;
   } else if (op->dim == 3 && nrhs == 1 && !op->generic_faces) {
     const unsigned grid = 8u * (unsigned)((op->ne + 7) / 8);   // k_elem3d needs a multiple of 8
@@ -835,6 +909,142 @@ static void vcycle(hpdg_operator* op, size_t l, int nrhs, hipStream_t s) {
   spmv<T, 2>(L.P, nrhs, C.x.as<T>(), L.x.as<T>(), nullptr, nullptr, L.t.as<T>(), s);
   spmv<T, 4>(L.A, nrhs, L.t.as<T>(), L.b.as<T>(), L.l1inv.as<T>(), nullptr, L.x.as<T>(), s);
   (void)n;
+}
+
+// ------------------------------------------------------------ autotuner
+// Times y = A x for one sparse matrix of the one-RHS path under every row
+// binning (long-row threshold x lanes per short row) and keeps the fastest.
+template <typename T>
+static void tune_csr(const CSR& H, DevCSR& D, const T* x, T* y, hipStream_t s, int64_t* rep) {
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  auto time_it = [&]() {
+    for (int w = 0; w < 3; ++w) spmv<T, 0>(D, 1, x, nullptr, nullptr, nullptr, y, s);
+    HIPCHK(hipEventRecord(e0, s));
+    const int reps = 10;
+    for (int w = 0; w < reps; ++w) spmv<T, 0>(D, 1, x, nullptr, nullptr, nullptr, y, s);
+    HIPCHK(hipEventRecord(e1, s));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    return (double)ms * 1e6 / reps;
+  };
+  const int def_long = D.longrow, def_lpr = D.lpr;
+  const double t_def = time_it();
+  double best = t_def;
+  int bl = def_long, bp = def_lpr;
+  for (int longrow : {32, 64, 128, 1 << 30})
+    for (int lpr : {1, 2, 4, 8, 16}) {
+      bin_rows(H, D, longrow, lpr);
+      const double t = time_it();
+      if (t < best) { best = t; bl = longrow; bp = lpr; }
+    }
+  bin_rows(H, D, bl, bp);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  rep[0] = D.nrows; rep[1] = D.nnz; rep[2] = bl; rep[3] = bp;
+  rep[4] = (int64_t)t_def; rep[5] = (int64_t)best;
+}
+
+static int apply_A_dev(hpdg_operator* op, const double* x, double* y, int nrhs, hipStream_t s, double* pdot);
+
+// elements per workgroup of the 2D element kernel (results do not depend on it)
+static void tune_elem(hpdg_operator* op, hipStream_t s, int64_t* rep) {
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  double* x = op->pv.as<double>();
+  double* y = op->Ap.as<double>();
+  HIPCHK(hipMemsetAsync(x, 0, op->pv.bytes, s));
+  auto time_it = [&]() {
+    for (int w = 0; w < 3; ++w) apply_A_dev(op, x, y, 1, s, nullptr);
+    HIPCHK(hipEventRecord(e0, s));
+    const int reps = 20;
+    for (int w = 0; w < reps; ++w) apply_A_dev(op, x, y, 1, s, nullptr);
+    HIPCHK(hipEventRecord(e1, s));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    return (double)ms * 1e6 / reps;
+  };
+  const double t_def = time_it();
+  double best = t_def;
+  int be = op->epb, bf = op->fchunk;
+  for (int epb : {1, 2})
+    for (int fc : {8, 16, 32}) {
+      op->epb = epb;
+      op->fchunk = fc;
+      const double t = time_it();
+      if (t < best) { best = t; be = epb; bf = fc; }
+    }
+  op->epb = be;
+  op->fchunk = bf;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  rep[0] = op->ndof; rep[1] = op->ne; rep[2] = bf; rep[3] = be;
+  rep[4] = (int64_t)t_def; rep[5] = (int64_t)best;
+}
+
+template <typename T>
+static int tune_all(hpdg_operator* op, hipStream_t s, int64_t* report, int cap) {
+  PrecHost& H = op->host;
+  int k = 0;
+  auto slot = [&](int kind, int level) -> int64_t* {
+    static thread_local int64_t dummy[8];
+    if (k >= cap) return dummy;
+    int64_t* r = report + 8 * k++;
+    r[0] = kind;
+    r[1] = level;
+    return r + 2;
+  };
+  if (op->dim == 2 && !op->generic_faces) tune_elem(op, s, slot(4, 0));
+  HIPCHK(hipMemsetAsync(op->rT.p, 0, op->rT.bytes, s));
+  for (auto& L : op->lv) {
+    HIPCHK(hipMemsetAsync(L.b.p, 0, L.b.bytes, s));
+    HIPCHK(hipMemsetAsync(L.x.p, 0, L.x.bytes, s));
+    HIPCHK(hipMemsetAsync(L.r.p, 0, L.r.bytes, s));
+  }
+  tune_csr<T>(H.PT, op->PT, op->rT.as<T>(), op->lv[0].b.as<T>(), s, slot(3, 0));
+  for (size_t l = 0; l < op->lv.size(); ++l) {
+    LevelDev& L = op->lv[l];
+    tune_csr<T>(H.amg.lv[l].A, L.A, L.b.as<T>(), L.r.as<T>(), s, slot(0, (int)l));
+    if (l + 1 < op->lv.size()) {
+      LevelDev& C = op->lv[l + 1];
+      tune_csr<T>(H.amg.lv[l].R, L.R, L.r.as<T>(), C.b.as<T>(), s, slot(1, (int)l));
+      tune_csr<T>(H.amg.lv[l].P, L.P, C.x.as<T>(), L.t.as<T>(), s, slot(2, (int)l));
+    }
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  return k;
+}
+
+extern "C" hpdg_status hpdg_operator_tune(hpdg_operator* op, void* stream, int64_t* report, int cap, int* n) {
+  if (!op || (cap > 0 && !report) || cap < 0) return fail(HPDG_E_INVALID, "bad argument");
+  if (!op->uploaded) return fail(HPDG_E_UNSUPPORTED, "operator is not on the device");
+  if (op->run.phase == 1 || op->run.phase == 2) return fail(HPDG_E_INVALID, "operator has a solve in flight");
+  try {
+    for (auto& g : op->graphs) (void)hipGraphExecDestroy(g.exec);   // captured with the old binning
+    op->graphs.clear();
+    hipStream_t s = (hipStream_t)stream;
+    int k = 0;
+    if (op->no_prec) {
+      static thread_local int64_t dummy[8];
+      int64_t* r = cap > 0 ? report : dummy;
+      r[0] = 4;
+      r[1] = 0;
+      if (op->dim == 2 && !op->generic_faces) {
+        tune_elem(op, s, r + 2);
+        k = 1;
+      }
+    } else {
+      k = op->prec32 ? tune_all<float>(op, s, report, cap) : tune_all<double>(op, s, report, cap);
+    }
+    if (n) *n = std::min(k, cap);
+    return HPDG_OK;
+  } catch (Error& e) {
+    return fail(e.code, e.what());
+  }
 }
 
 // z = B r. With pdot (one RHS) the last kernel also writes per-block shares
@@ -915,6 +1125,7 @@ extern "C" hpdg_status hpdg_apply_A(hpdg_operator* op, const double* x, double* 
 extern "C" hpdg_status hpdg_apply_B(hpdg_operator* op, const double* r, double* z, int nrhs, void* stream) {
   hpdg_status st = check_vec_args(op, r, z, nrhs);
   if (st != HPDG_OK) return st;
+  if (op->no_prec) return fail(HPDG_E_UNSUPPORTED, "operator was built with no_prec");
   hipStream_t s = (hipStream_t)stream;
   if (op->prec32) apply_B_dev<float>(op, r, z, nrhs, s);
   else apply_B_dev<double>(op, r, z, nrhs, s);
@@ -1011,14 +1222,57 @@ static void dot_final(hpdg_operator* op, int nparts, int mode, const CGScal& S, 
   hipLaunchKernelGGL(k_dot_final_ep, dim3(1), dim3(256), 0, s, nparts, 1, op->part.as<double>(), mode, S);
 }
 
+
 // k PCG iterations (Alg. PCG: alpha from r'z / p'Ap, residual update, B
 // application, beta, new direction), then the activity flags to the pinned
 // area and the completion event
+static void pcg_iters(hpdg_operator* op, int k, hipStream_t s);
+
+// the HIP graph of k iterations for the current solve's x (captured once on a
+// private stream, then replayed on the solve's stream)
+static hipGraphExec_t chunk_graph(hpdg_operator* op, int k) {
+  PcgRun& R = op->run;
+  for (auto& g : op->graphs)
+    if (g.k == k && g.nrhs == R.nrhs && g.x == R.x) return g.exec;
+  if (!op->cap_stream) HIPCHK(hipStreamCreateWithFlags(&op->cap_stream, hipStreamNonBlocking));
+  if (op->graphs.size() >= 8) {
+    (void)hipGraphExecDestroy(op->graphs.front().exec);
+    op->graphs.erase(op->graphs.begin());
+  }
+  hipGraph_t g = nullptr;
+  HIPCHK(hipStreamBeginCapture(op->cap_stream, hipStreamCaptureModeThreadLocal));
+  try {
+    pcg_iters(op, k, op->cap_stream);
+  } catch (...) {
+    (void)hipStreamEndCapture(op->cap_stream, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  HIPCHK(hipStreamEndCapture(op->cap_stream, &g));
+  hipGraphExec_t ex = nullptr;
+  hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) throw Error(HPDG_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  op->graphs.push_back({k, R.nrhs, R.x, ex});
+  return ex;
+}
+
 static void pcg_chunk(hpdg_operator* op, int k) {
   PcgRun& R = op->run;
   const int nrhs = R.nrhs;
-  const int64_t n = op->ndof * nrhs;
   hipStream_t s = R.s;
+  CGScal S = cg_scal(op);
+  if (k > 0 && op->use_graph) HIPCHK(hipGraphLaunch(chunk_graph(op, k), s));
+  else if (k > 0) pcg_iters(op, k, s);
+  R.enq += k;
+  HIPCHK(hipMemcpyAsync(op->pin->act, S.act, nrhs * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipEventRecord(op->ev, s));
+}
+
+static void pcg_iters(hpdg_operator* op, int k, hipStream_t s) {
+  PcgRun& R = op->run;
+  const int nrhs = R.nrhs;
+  const int64_t n = op->ndof * nrhs;
   CGScal S = cg_scal(op);
   double *r = op->r.as<double>(), *z = op->z.as<double>(), *p = op->pv.as<double>(), *Ap = op->Ap.as<double>();
   double* part = op->part.as<double>();
@@ -1029,20 +1283,21 @@ static void pcg_chunk(hpdg_operator* op, int k) {
     if (na) dot_final(op, na, EP_PAP, S, s);
     else dot_ep(op, p, Ap, nrhs, EP_PAP, S, s);
     if (nrhs == 1) {
+      // r'r shares in the first region, r'z shares (written by the last
+      // kernel of B) in the second; one launch finishes both, r'r first
       hipLaunchKernelGGL(k_cg_update_rr, dim3(nblk(n)), dim3(256), 0, s, n, S.alpha, p, Ap, R.x, r, part);
-      dot_final(op, (int)nblk(n), EP_RR, S, s);
+      double* part2 = part + part_off2(op);
+      const int nb = apply_B_any(op, r, z, nrhs, s, part2);
+      hipLaunchKernelGGL(k_dot_final2_ep, dim3(1), dim3(256), 0, s, (int)nblk(n), part, EP_RR, nb, part2, EP_RZ, S);
     } else {
       hipLaunchKernelGGL(k_cg_update2, dim3(nblk(n)), dim3(256), 0, s, n, nrhs, S.alpha, p, Ap, R.x, r);
       dot_ep(op, r, r, nrhs, EP_RR, S, s);
+      apply_B_any(op, r, z, nrhs, s);
+      dot_ep(op, r, z, nrhs, EP_RZ, S, s);
     }
-    const int nb = apply_B_any(op, r, z, nrhs, s, nrhs == 1 ? part : nullptr);
-    if (nb) dot_final(op, nb, EP_RZ, S, s);
-    else dot_ep(op, r, z, nrhs, EP_RZ, S, s);
     hipLaunchKernelGGL(k_cg_dir2, dim3(nblk(n)), dim3(256), 0, s, n, nrhs, S.beta, S.act, z, p);
   }
-  R.enq += k;
-  HIPCHK(hipMemcpyAsync(op->pin->act, S.act, nrhs * sizeof(int), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipEventRecord(op->ev, s));
+  HIPCHK(hipGetLastError());
 }
 
 // r = b - A x, z = B r, p = z and the initial norms; no iteration yet
@@ -1170,6 +1425,7 @@ static void pcg_advance(hpdg_operator* op) {
 static hpdg_status check_pcg_args(hpdg_operator* op, const double* b, double* x, int nrhs, double rtol, int maxit) {
   hpdg_status st = check_vec_args(op, b, x, nrhs);
   if (st != HPDG_OK) return st;
+  if (op->no_prec) return fail(HPDG_E_UNSUPPORTED, "operator was built with no_prec");
   if (!(rtol > 0) || maxit < 0) return fail(HPDG_E_INVALID, "bad rtol or maxit");
   if (op->run.phase == 1 || op->run.phase == 2) return fail(HPDG_E_INVALID, "operator has a solve in flight");
   return HPDG_OK;

@@ -379,40 +379,73 @@ __global__ __launch_bounds__(64) void k_faces(int nitems, int nrhs, int form,
 //          BR2   sigma v -> c^2 eta k_e L [s_o A_oo Minv_o v
 //                                          + s_n A_on Minv_n (A_on^T To - A_nn Tn)]
 //          with L the face length, s = m00 / h^2 (Sec. 2; Sec. 4.4).
-//  Memory: the element's face records (up to kFChunk per pass) and all
+//  Faces are taken seven at a time by groups of 9 lanes; each face's
+//  contributions are summed per side node in record order afterwards.
+//  Memory: the element's face records (kFChunk per pass: 8, 16 or 32, a
+//  tuning choice between LDS use and passes) and all
 //  neighbour traces are fetched in two parallel rounds into LDS before any
 //  face arithmetic, so a face costs no dependent global round trip.
-constexpr int kFChunk = 16;
+// every element is one wavefront: LDS exchanges between its lanes need only a
+// wave-level fence, so several elements share a workgroup without barriers
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
-__global__ __launch_bounds__(64) void k_elem2d(int ne, int form, const int64_t* __restrict__ off,
+template <int EPB, int kFChunk>
+__global__ __launch_bounds__(64 * EPB) void k_elem2d(int ne, int form, const int64_t* __restrict__ off,
                                                const int8_t* __restrict__ pdeg, const double* __restrict__ hh,
                                                const double* __restrict__ kk, const int32_t* __restrict__ sptr,
                                                const FaceRec* __restrict__ recs, const double* __restrict__ ftab,
                                                const double* __restrict__ tab, TableLayout TL,
                                                const double* __restrict__ x, double* __restrict__ y,
                                                double* __restrict__ pdot) {
-  __shared__ double sX[81], sA[81], sB[81];
-  __shared__ double sTo[4][9], sDo[4][9], sV[4][9], sW[4][9];
-  __shared__ double sG1[4][9], sG2[4][9];
-  __shared__ double sTn[kFChunk][9], sDn[kFChunk][9];
-  __shared__ FaceRec sR[kFChunk];
+  // per element: x, the two volume temporaries (reused after the volume for
+  // the face sums), the 1D mass / stiffness of its degree, side traces, and
+  // one pass of face records with their neighbour traces
+  __shared__ double sXw[EPB][81], sAw[EPB][81], sBw[EPB][81], sMKw[EPB][2][81];
+  __shared__ double sTow[EPB][4][9], sDow[EPB][4][9];
+  __shared__ double sTnw[EPB][kFChunk][9], sDnw[EPB][kFChunk][9];
+  __shared__ FaceRec sRw[EPB][kFChunk];
+  const int wv = EPB == 1 ? 0 : (int)(threadIdx.x >> 6);
+  double* sX = sXw[wv];
+  double* sA = sAw[wv];
+  double* sB = sBw[wv];
+  double (*sTo)[9] = sTow[wv];
+  double (*sDo)[9] = sDow[wv];
+  // after the volume: BR2 scratch of the 7 face groups in sA, the side sums in sB
+  double (*sVg)[9] = reinterpret_cast<double (*)[9]>(sAw[wv]);        // 63 of the 81
+  double (*sWg)[9] = reinterpret_cast<double (*)[9]>(sBw[wv]);
+  double (*sG1)[9] = reinterpret_cast<double (*)[9]>(sBw[wv]);
+  double (*sG2)[9] = reinterpret_cast<double (*)[9]>(sBw[wv] + 40);
+  double (*sTn)[9] = sTnw[wv];
+  double (*sDn)[9] = sDnw[wv];
+  FaceRec* sR = sRw[wv];
   // XCD-aware order: workgroups go round-robin to the 8 XCDs, so block b
-  // takes element (b % 8) * per + b / 8 and each XCD walks a contiguous range
-  // of the (space-filling ordered) element list; neighbours then share its L2
+  // takes element group (b % 8) * per + b / 8 and each XCD walks a contiguous
+  // range of the (space-filling ordered) element list; neighbours then share
+  // its L2
   const int per = (int)(gridDim.x >> 3);
-  const int e = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+  const int e = ((int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3)) * EPB + wv;
   if (e >= ne) return;
-  const int lane = threadIdx.x;
+  const int lane = (int)(threadIdx.x & 63);
+  const int gq = lane / 9, jq = lane - 9 * (lane / 9);   // face groups of 9 lanes
   const int p = pdeg[e], n = p + 1, nn = n * n;
   const double h = hh[e], k = kk[e];
   const int64_t base = off[e];
   int sp[5];
 #pragma unroll
   for (int t = 0; t < 5; ++t) sp[t] = sptr[e * 4 + t];
-  const double* sM = tab + TL.mk + (p * 2 + 0) * 81;    // 1D mass / stiffness (cached)
-  const double* sK = tab + TL.mk + (p * 2 + 1) * 81;
-  for (int i = lane; i < nn; i += 64) sX[i] = x[base + i];
-  __syncthreads();
+  const double* gMK = tab + TL.mk + p * 2 * 81;          // 1D mass and stiffness of degree p
+  const double* sM = sMKw[wv][0];
+  const double* sK = sMKw[wv][1];
+  for (int i = lane; i < nn; i += 64) {
+    sX[i] = x[base + i];
+    sMKw[wv][0][i] = gMK[i];
+    sMKw[wv][1][i] = gMK[81 + i];
+  }
+  wave_sync();
   // volume, phase 1 (dimension 0)
   for (int i = lane; i < nn; i += 64) {
     const int i0 = i % n, i1 = i / n;
@@ -430,7 +463,6 @@ __global__ __launch_bounds__(64) void k_elem2d(int ne, int form, const int64_t* 
   const bool grp = lane < 36;
   const int m = sidx >> 1, s = sidx & 1;
   const int stm = m == 0 ? 1 : n, stt = m == 0 ? n : 1;
-  const double sgn = s ? 1.0 : -1.0;
   if (grp && j < n) {
     const double* Ds = tab + TL.dside + (p * 2 + s) * 9;
     double dv = 0.0;
@@ -438,7 +470,7 @@ __global__ __launch_bounds__(64) void k_elem2d(int ne, int form, const int64_t* 
     sTo[sidx][j] = sX[(s ? p : 0) * stm + j * stt];
     sDo[sidx][j] = dv / h;
   }
-  __syncthreads();
+  wave_sync();
   // volume, phase 2 (dimension 1)
   double yv[2] = {0.0, 0.0};
   for (int i = lane, c = 0; i < nn; i += 64, ++c) {
@@ -459,7 +491,7 @@ __global__ __launch_bounds__(64) void k_elem2d(int ne, int form, const int64_t* 
       unsigned long long* dst = reinterpret_cast<unsigned long long*>(sR);
       for (int t = lane; t < nF * W; t += 64) dst[t] = src[t];
     }
-    __syncthreads();
+    wave_sync();
     // round 2: neighbour trace Tn and k_n/h_n-scaled normal derivative Dn per (face, node)
     for (int t = lane; t < nF * 9; t += 64) {
       const int f = t / 9, jj = t - 9 * f;
@@ -475,95 +507,109 @@ __global__ __launch_bounds__(64) void k_elem2d(int ne, int form, const int64_t* 
         sDn[f][jj] = sR[f].kho * dv;
       }
     }
-    __syncthreads();
-    // faces of each side within this pass; the count is uniform over the block
-    int maxc = 0;
-#pragma unroll
-    for (int t = 0; t < 4; ++t) maxc = max(maxc, min(sp[t + 1], c0 + nF) - max(sp[t], c0));
-    const int fb = max(sb, c0) - c0, fe = min(se, c0 + nF) - c0;
-    for (int fi = 0; fi < maxc; ++fi) {
-      const int f = fb + fi;
-      const bool have = grp && f < fe;
+    wave_sync();
+    // faces of this pass in rounds of seven: lane group g (9 lanes, one per
+    // own trace node) takes face r0 + g; its contributions to the side sums
+    // go to LDS in place of the face's neighbour traces
+    for (int r0 = 0; r0 < nF; r0 += 7) {
+      const int f = r0 + gq;
+      const bool have = gq < 7 && f < nF;
       const int fr = have ? f : 0;
-      const double flen = have ? sR[fr].flen : 0.0;
-      const double sig = have ? sR[fr].sig : 0.0;
+      const int fm = sR[fr].m, fsd = sR[fr].side, fside = 2 * fm + fsd;
+      const double fsgn = fsd ? 1.0 : -1.0;
+      const double flen = sR[fr].flen, sig = sR[fr].sig;
       const bool inner = have && sR[fr].nbr >= 0;
       const int po = inner ? (int)sR[fr].pn : 0;
       const int no = inner ? po + 1 : 0;
-      const double* Aoo = ftab + (have ? sR[fr].foo[0] : 0);     // face matrices (cached)
+      const double* Aoo = ftab + sR[fr].foo[0];     // face matrices (cached)
       const double* Aon = ftab + (inner ? sR[fr].fon[0] : 0);
       const double* Ann = ftab + (inner ? sR[fr].fnn[0] : 0);
-      double v = 0.0, dsum = 0.0;
-      if (have && j < n) {
+      const double csym = inner ? 0.5 : 1.0;
+      double g1 = 0.0, g2 = 0.0, v = 0.0;
+      if (have && jq < n) {
+        double dsum = 0.0;
         for (int a = 0; a < n; ++a) {
-          v += Aoo[j * n + a] * sTo[sidx][a];
-          dsum += k * Aoo[j * n + a] * sDo[sidx][a];
+          v += Aoo[jq * n + a] * sTo[fside][a];
+          dsum += k * Aoo[jq * n + a] * sDo[fside][a];
         }
         for (int a = 0; a < no; ++a) {
-          v -= Aon[j * no + a] * sTn[fr][a];
-          dsum += Aon[j * no + a] * sDn[fr][a];
+          v -= Aon[jq * no + a] * sTn[fr][a];
+          dsum += Aon[jq * no + a] * sDn[fr][a];
         }
-        const double csym = inner ? 0.5 : 1.0;
-        G1 -= flen * csym * sgn * dsum;
-        G2 -= csym * k * sgn * flen * v;
-        if (form == 0) G1 += flen * sig * v;
-        sV[sidx][j] = v;
+        g1 = -flen * csym * fsgn * dsum;
+        g2 = -csym * k * fsgn * flen * v;
+        if (form == 0) g1 += flen * sig * v;
       }
       if (form == 1) {
         const double c2 = inner ? 0.25 : 1.0;
         const double L2 = c2 * sig * flen * flen;
-        // own lifting: G1 += L2 s_o A_oo Minv_o v
-        __syncthreads();
-        if (have && j < n) {
+        // own lifting: g1 += L2 s_o A_oo Minv_o v
+        if (have && jq < n) sVg[gq][jq] = v;
+        wave_sync();
+        if (have && jq < n) {
           const double* Mi = tab + TL.minv + p * 81;
           double w = 0.0;
-          for (int a = 0; a < n; ++a) w += Mi[j * n + a] * sV[sidx][a];
-          sW[sidx][j] = w;
+          for (int a = 0; a < n; ++a) w += Mi[jq * n + a] * sVg[gq][a];
+          sWg[gq][jq] = w;
         }
-        __syncthreads();
-        if (have && j < n) {
+        wave_sync();
+        if (have && jq < n) {
           const double* Mi = tab + TL.minv + p * 81;
-          const int sk = s ? p : 0;
+          const int sk = fsd ? p : 0;
           const double so = Mi[sk * n + sk] / (h * h);
           double acc = 0.0;
-          for (int a = 0; a < n; ++a) acc += Aoo[j * n + a] * sW[sidx][a];
-          G1 += L2 * so * acc;
+          for (int a = 0; a < n; ++a) acc += Aoo[jq * n + a] * sWg[gq][a];
+          g1 += L2 * so * acc;
         }
-        // neighbour lifting: G1 += L2 s_n A_on Minv_n (A_on^T To - A_nn Tn)
-        __syncthreads();
-        if (inner && j < no) {
+        // neighbour lifting: g1 += L2 s_n A_on Minv_n (A_on^T To - A_nn Tn)
+        wave_sync();
+        if (inner && jq < no) {
           double vn = 0.0;
-          for (int a = 0; a < n; ++a) vn += Aon[a * no + j] * sTo[sidx][a];
-          for (int a = 0; a < no; ++a) vn -= Ann[j * no + a] * sTn[fr][a];
-          sV[sidx][j] = vn;
+          for (int a = 0; a < n; ++a) vn += Aon[a * no + jq] * sTo[fside][a];
+          for (int a = 0; a < no; ++a) vn -= Ann[jq * no + a] * sTn[fr][a];
+          sVg[gq][jq] = vn;
         }
-        __syncthreads();
-        if (inner && j < no) {
+        wave_sync();
+        if (inner && jq < no) {
           const double* Mi = tab + TL.minv + po * 81;
           double w = 0.0;
-          for (int a = 0; a < no; ++a) w += Mi[j * no + a] * sV[sidx][a];
-          sW[sidx][j] = w;
+          for (int a = 0; a < no; ++a) w += Mi[jq * no + a] * sVg[gq][a];
+          sWg[gq][jq] = w;
         }
-        __syncthreads();
-        if (inner && j < n) {
+        wave_sync();
+        if (inner && jq < n) {
           const double* Mi = tab + TL.minv + po * 81;
-          const int sk = (1 - s) ? po : 0;
+          const int sk = (1 - fsd) ? po : 0;
           const double hn = sR[fr].hn;
           const double sn = Mi[sk * no + sk] / (hn * hn);
           double acc = 0.0;
-          for (int a = 0; a < no; ++a) acc += Aon[j * no + a] * sW[sidx][a];
-          G1 += L2 * sn * acc;
+          for (int a = 0; a < no; ++a) acc += Aon[jq * no + a] * sWg[gq][a];
+          g1 += L2 * sn * acc;
         }
-        __syncthreads();
+      }
+      wave_sync();
+      if (have && jq < n) {
+        sTn[fr][jq] = g1;
+        sDn[fr][jq] = g2;
       }
     }
-    __syncthreads();   // sR, sTn, sDn are rewritten by the next pass
+    wave_sync();
+    // side sums in record order (deterministic)
+    {
+      const int fb = max(sb, c0) - c0, fe = min(se, c0 + nF) - c0;
+      if (grp && j < n)
+        for (int f = fb; f < fe; ++f) {
+          G1 += sTn[f][j];
+          G2 += sDn[f][j];
+        }
+    }
+    wave_sync();   // sR, sTn, sDn are rewritten by the next pass
   }
   if (grp && j < n) {
     sG1[sidx][j] = G1;
     sG2[sidx][j] = G2 / h;
   }
-  __syncthreads();
+  wave_sync();
   const double* D0 = tab + TL.dside + (p * 2 + 0) * 9;
   const double* D1 = tab + TL.dside + (p * 2 + 1) * 9;
   double xy = 0.0;
@@ -747,6 +793,28 @@ __global__ __launch_bounds__(256) void k_dot_final_ep(int nblocks, int nrhs, con
   if (t < nrhs) cg_epilogue(mode, t, sm[t], S);
 }
 
+// two final stages (one RHS) in one launch: shares a -> epilogue ma, then
+// shares b -> epilogue mb, each summed in a fixed order
+__global__ __launch_bounds__(256) void k_dot_final2_ep(int na, const double* __restrict__ pa, int ma, int nb,
+                                                       const double* __restrict__ pb, int mb, CGScal S) {
+  __shared__ double sm[256];
+  const int t = threadIdx.x;
+  for (int pass = 0; pass < 2; ++pass) {
+    const int n = pass ? nb : na;
+    const double* part = pass ? pb : pa;
+    double s = 0.0;
+    for (int b = t; b < n; b += 256) s += part[b];
+    sm[t] = s;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+      if (t < w) sm[t] += sm[t + w];
+      __syncthreads();
+    }
+    if (t == 0) cg_epilogue(pass ? mb : ma, 0, sm[0], S);
+    __syncthreads();
+  }
+}
+
 // x += alpha p ; r -= alpha Ap (alpha = 0 for converged RHS)
 __global__ void k_cg_update2(int64_t n, int nrhs, const double* __restrict__ alpha,
                              const double* __restrict__ p, const double* __restrict__ Ap, double* __restrict__ x,
@@ -776,33 +844,13 @@ __global__ void k_cg_update2(int64_t n, int nrhs, const double* __restrict__ alp
 //            c^2 eta k_e L^4 [s_o (A0oo x A1oo)(Mi x Mi) v
 //                             + s_n (A0on x A1on)(Mi_n x Mi_n) vn],
 //            vn = (A0on x A1on)^T To - (A0nn x A1nn) Tn, s = m00 / h^3.
-//          Each Kronecker product is two 1D contractions (kron2).
+//          Each Kronecker product is two 1D contractions; the products
+//          A Minv of each slot come precomputed from the face table, so a
+//          BR2 face takes four barrier-separated stages and an SIPG face two.
 //  Memory: records and neighbour traces of up to kF3 faces are fetched in
 //  two parallel rounds into LDS; faces are then applied one after another
 //  (a fixed order, so the sums per side node are deterministic).
 constexpr int kF3 = 8;
-
-// out[j0 + r0 j1] (+)= scale * sum_{a0, a1} M0(j0, a0) M1(j1, a1) in[a0 + c0 a1],
-// M(j, a) = M[j ld + a] or, transposed, M[a ld + j]. All 256 threads; two
-// barriers. tmp holds r0 * c1 values.
-__device__ inline void kron2(const double* __restrict__ M0, int ld0, bool tr0, const double* __restrict__ M1,
-                             int ld1, bool tr1, int r0, int c0, int r1, int c1, const double* in, double* tmp,
-                             double* out, double scale, bool acc) {
-  for (int t = threadIdx.x; t < r0 * c1; t += 256) {
-    const int j0 = t % r0, a1 = t / r0;
-    double s = 0.0;
-    for (int a0 = 0; a0 < c0; ++a0) s += (tr0 ? M0[a0 * ld0 + j0] : M0[j0 * ld0 + a0]) * in[a0 + c0 * a1];
-    tmp[t] = s;
-  }
-  __syncthreads();
-  for (int t = threadIdx.x; t < r0 * r1; t += 256) {
-    const int j0 = t % r0, j1 = t / r0;
-    double s = 0.0;
-    for (int a1 = 0; a1 < c1; ++a1) s += (tr1 ? M1[a1 * ld1 + j1] : M1[j1 * ld1 + a1]) * tmp[j0 + r0 * a1];
-    out[t] = acc ? out[t] + scale * s : scale * s;
-  }
-  __syncthreads();
-}
 
 __device__ inline void tdims3(int m, int& t0, int& t1) {
   t0 = m == 0 ? 1 : 0;
@@ -905,12 +953,12 @@ __global__ __launch_bounds__(256) void k_elem3d(int ne, int form, const int64_t*
   double* U1 = sV1 + 81;
   double* U2 = sV1 + 162;
   double* U3 = sV1 + 243;
-  double* Tmp = sV1 + 324;
+  double* Y0 = sV1 + 324;
+  double* Y1 = sV1 + 405;
   double* Vv = sV2;                  // jump on own face nodes
-  double* Ww = sV2 + 81;
-  double* Vn = sV2 + 162;
-  double* Wn = sV2 + 243;
-  double* Zz = sV2 + 324;
+  double* Vn = sV2 + 81;             // jump on the neighbour's face nodes (BR2)
+  double* P0 = sV2 + 162;
+  double* Q0 = sV2 + 243;
   for (int c0 = sp[0]; c0 < sp[6]; c0 += kF3) {
     const int nF = min(kF3, sp[6] - c0);
     {
@@ -953,8 +1001,13 @@ __global__ __launch_bounds__(256) void k_elem3d(int ne, int form, const int64_t*
       const double* A1on = ftab + R.fon[1];
       const double* Tn = sTn + f * 81;
       const double* Dn = sDn + f * 81;
-      // stage 1: slot-0 contractions of To, Do (own) and Tn, Dn (neighbour)
-      for (int t = tid; t < 4 * 81; t += 256) {
+      const bool br2i = form == 1 && inner;
+      const double* A0nn = ftab + R.fnn[0];
+      const double* A1nn = ftab + R.fnn[1];
+      // stage 1: slot-0 contractions of To, Do (own) and Tn, Dn (neighbour);
+      // for BR2 also the slot-0 halves of the neighbour's jump
+      //   Y0 = A0on^T To (no x n), Y1 = A0nn Tn (no x no)
+      for (int t = tid; t < 6 * 81; t += 256) {
         const int which = t / 81, q = t - 81 * which;
         if (which < 2) {
           if (q >= n2) continue;
@@ -963,64 +1016,109 @@ __global__ __launch_bounds__(256) void k_elem3d(int ne, int form, const int64_t*
           double sacc = 0.0;
           for (int a0 = 0; a0 < n; ++a0) sacc += A0oo[j0 * n + a0] * in[a0 + n * a1];
           (which == 0 ? U0 : U1)[q] = sacc;
-        } else {
+        } else if (which < 4) {
           if (!inner || q >= n * no) continue;
           const int j0 = q % n, a1 = q / n;
           const double* in = which == 2 ? Tn : Dn;
           double sacc = 0.0;
           for (int a0 = 0; a0 < no; ++a0) sacc += A0on[j0 * no + a0] * in[a0 + no * a1];
           (which == 2 ? U2 : U3)[q] = sacc;
+        } else if (which == 4) {
+          if (!br2i || q >= no * n) continue;
+          const int a0 = q % no, a1 = q / no;      // a1 over own slot-1 nodes
+          double sacc = 0.0;
+          for (int j0 = 0; j0 < n; ++j0) sacc += A0on[j0 * no + a0] * sTo[side][j0 + n * a1];
+          Y0[q] = sacc;
+        } else {
+          if (!br2i || q >= no * no) continue;
+          const int a0 = q % no, a1 = q / no;
+          double sacc = 0.0;
+          for (int b0 = 0; b0 < no; ++b0) sacc += A0nn[a0 * no + b0] * Tn[b0 + no * a1];
+          Y1[q] = sacc;
         }
       }
       __syncthreads();
-      // stage 2: slot-1 contractions; jump, average and the penalty
-      for (int q = tid; q < n2; q += 256) {
-        const int j0 = q % n, j1 = q / n;
-        double v = 0.0, ds = 0.0;
-        for (int a1 = 0; a1 < n; ++a1) {
-          const double w = A1oo[j1 * n + a1];
-          v += w * U0[j0 + n * a1];
-          ds += k * w * U1[j0 + n * a1];
-        }
-        if (inner)
-          for (int a1 = 0; a1 < no; ++a1) {
-            const double w = A1on[j1 * no + a1];
-            v -= w * U2[j0 + n * a1];
-            ds += w * U3[j0 + n * a1];
+      // stage 2: slot-1 contractions; jump, average and the penalty; for BR2
+      // the neighbour's jump vn = (A0on x A1on)^T To - (A0nn x A1nn) Tn
+      for (int t = tid; t < 2 * 81; t += 256) {
+        if (t < 81) {
+          const int q = t;
+          if (q >= n2) continue;
+          const int j0 = q % n, j1 = q / n;
+          double v = 0.0, ds = 0.0;
+          for (int a1 = 0; a1 < n; ++a1) {
+            const double w = A1oo[j1 * n + a1];
+            v += w * U0[j0 + n * a1];
+            ds += k * w * U1[j0 + n * a1];
           }
-        double g1 = -area * csym * sgn * ds;
-        if (form == 0) g1 += area * R.sig * v;
-        sG1[side][q] += g1;
-        sG2[side][q] -= csym * k * sgn * area * v;
-        Vv[q] = v;
+          if (inner)
+            for (int a1 = 0; a1 < no; ++a1) {
+              const double w = A1on[j1 * no + a1];
+              v -= w * U2[j0 + n * a1];
+              ds += w * U3[j0 + n * a1];
+            }
+          double g1 = -area * csym * sgn * ds;
+          if (form == 0) g1 += area * R.sig * v;
+          sG1[side][q] += g1;
+          sG2[side][q] -= csym * k * sgn * area * v;
+          Vv[q] = v;
+        } else {
+          const int q = t - 81;
+          if (!br2i || q >= no * no) continue;
+          const int a0 = q % no, b1 = q / no;
+          double vn = 0.0;
+          for (int a1 = 0; a1 < n; ++a1) vn += A1on[a1 * no + b1] * Y0[a0 + no * a1];
+          for (int c1 = 0; c1 < no; ++c1) vn -= A1nn[b1 * no + c1] * Y1[a0 + no * c1];
+          Vn[q] = vn;
+        }
       }
       __syncthreads();
       if (form == 1) {
+        // liftings with the products L = A Minv of each slot:
+        //   G1 += L2 [s_o (Loo0 x Loo1) v + s_n (Lon0 x Lon1) vn]
         const double c2 = inner ? 0.25 : 1.0;
         const double L2 = c2 * R.sig * area * area;
         const double* Mi = tab + TL.minv + p * 81;
         const int sk = s ? p : 0;
         const double so = Mi[sk * n + sk] / (h * h * h);
-        // own lifting: G1 += L2 s_o (A0oo x A1oo)(Mi x Mi) v
-        kron2(Mi, n, false, Mi, n, false, n, n, n, n, Vv, Tmp, Ww, 1.0, false);
-        kron2(A0oo, n, false, A1oo, n, false, n, n, n, n, Ww, Tmp, Zz, 1.0, false);
-        for (int q = tid; q < n2; q += 256) sG1[side][q] += L2 * so * Zz[q];
-        __syncthreads();
+        double sn = 0.0;
         if (inner) {
-          // vn = (A0on x A1on)^T To - (A0nn x A1nn) Tn on the neighbour's face nodes
-          const double* A0nn = ftab + R.fnn[0];
-          const double* A1nn = ftab + R.fnn[1];
           const double* Min = tab + TL.minv + po * 81;
           const int skn = (1 - s) ? po : 0;
-          const double hn = R.hn;
-          const double sn = Min[skn * no + skn] / (hn * hn * hn);
-          kron2(A0on, no, true, A1on, no, true, no, n, no, n, sTo[side], Tmp, Vn, 1.0, false);
-          kron2(A0nn, no, false, A1nn, no, false, no, no, no, no, Tn, Tmp, Vn, -1.0, true);
-          kron2(Min, no, false, Min, no, false, no, no, no, no, Vn, Tmp, Wn, 1.0, false);
-          kron2(A0on, no, false, A1on, no, false, n, no, n, no, Wn, Tmp, Zz, 1.0, false);
-          for (int q = tid; q < n2; q += 256) sG1[side][q] += L2 * sn * Zz[q];
-          __syncthreads();
+          sn = Min[skn * no + skn] / (R.hn * R.hn * R.hn);
         }
+        const double* L0o = ftab + R.loo[0];
+        const double* L1o = ftab + R.loo[1];
+        const double* L0n = ftab + R.lon[0];
+        const double* L1n = ftab + R.lon[1];
+        // stage 3: slot 0
+        for (int t = tid; t < 2 * 81; t += 256) {
+          const int which = t / 81, q = t - 81 * which;
+          if (which == 0) {
+            if (q >= n2) continue;
+            const int j0 = q % n, a1 = q / n;
+            double sacc = 0.0;
+            for (int a0 = 0; a0 < n; ++a0) sacc += L0o[j0 * n + a0] * Vv[a0 + n * a1];
+            P0[q] = sacc;
+          } else {
+            if (!inner || q >= n * no) continue;
+            const int j0 = q % n, a1 = q / n;
+            double sacc = 0.0;
+            for (int a0 = 0; a0 < no; ++a0) sacc += L0n[j0 * no + a0] * Vn[a0 + no * a1];
+            Q0[q] = sacc;
+          }
+        }
+        __syncthreads();
+        // stage 4: slot 1 and the sum
+        for (int q = tid; q < n2; q += 256) {
+          const int j0 = q % n, j1 = q / n;
+          double so_acc = 0.0, sn_acc = 0.0;
+          for (int a1 = 0; a1 < n; ++a1) so_acc += L1o[j1 * n + a1] * P0[j0 + n * a1];
+          if (inner)
+            for (int a1 = 0; a1 < no; ++a1) sn_acc += L1n[j1 * no + a1] * Q0[j0 + n * a1];
+          sG1[side][q] += L2 * (so * so_acc + sn * sn_acc);
+        }
+        __syncthreads();
       }
     }
   }

@@ -7,7 +7,7 @@
 namespace hpdg {
 
 // One face as seen from one of its two elements (or the only one on the
-// boundary). 72 bytes; the neighbour's degree, first DOF and coefficient are
+// boundary). 88 bytes; the neighbour's degree, first DOF and coefficient are
 // copied in so that the element kernel needs no second lookup.
 struct FaceRec {
   int32_t nbr;      // neighbour element, -1 on the boundary
@@ -21,12 +21,14 @@ struct FaceRec {
   int32_t foo[2];   // per tangential slot: offsets (doubles) in the face-matrix table of
   int32_t fon[2];   //   the unit-length 1D face-mass matrices A_oo (own x own),
   int32_t fnn[2];   //   A_on (own x neighbour), A_nn (neighbour x neighbour)
+  int32_t loo[2];   // per slot: A_oo Minv_own and A_on Minv_nbr (BR2 liftings)
+  int32_t lon[2];
   double flen;      // physical face side length
   double sig;       // SIPG penalty sigma, or eta*k_e for BR2
   double kho;       // neighbour k / h (0 on the boundary)
   double hn;        // neighbour h (1 on the boundary)
 };
-static_assert(sizeof(FaceRec) == 72, "FaceRec layout");
+static_assert(sizeof(FaceRec) == 88, "FaceRec layout");
 
 // Tables of the 1D basis, all degrees, in one device buffer (doubles).
 struct TableLayout {

@@ -107,3 +107,14 @@ def test_host_setup_matches_oracle(name, mk, form, eta, cap):
         if l < len(amg.P):
             assert np.array_equal(op.export(300 + l).view(np.int64), amg.aggs[l])
             assert abs(op._csr(op.export(200 + l)) - amg.P[l]).max() <= 1e-11
+
+
+def test_no_prec_operator_host():
+    _lib_or_skip()
+    md = H.random_mesh(2, 3, 0.3, 2, 1, 5, seed=21)
+    m = G.Mesh(md)
+    full = G.Operator(m, host_only=True)
+    bare = G.Operator(m, host_only=True, no_prec=True)
+    assert bare.device_bytes() < full.device_bytes()
+    s = bare.summary()
+    assert s["ndof"] == m.ndof and s["amg_levels"] == 0 and s["nblocks"] == 0

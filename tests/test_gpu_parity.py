@@ -220,3 +220,104 @@ def test_error_paths():
         op.apply_A(b, b)
     with pytest.raises(G.HpdgError):
         op.apply_A(b, x, nrhs=3)
+
+
+@pytest.mark.gpu
+def test_no_prec_operator_matches_full():
+    import torch
+    md = H.random_mesh(2, 4, 0.3, 3, 1, 8, seed=23)
+    m = G.Mesh(md)
+    full = G.Operator(m)
+    bare = G.Operator(m, no_prec=True)
+    x = torch.from_numpy(H.gaussian_rhs(m.ndof, 24)).cuda()
+    y1, y2 = torch.empty_like(x), torch.empty_like(x)
+    full.apply_A(x, y1)
+    bare.apply_A(x, y2)
+    assert torch.equal(y1, y2)
+    with pytest.raises(G.HpdgError) as e:
+        bare.apply_B(x, y2)
+    assert e.value.code == -6
+    with pytest.raises(G.HpdgError) as e:
+        bare.pcg_solve(x, y2)
+    assert e.value.code == -6
+
+
+@pytest.mark.gpu
+def test_graph_replay_equals_eager():
+    """PCG chunks replayed from captured HIP graphs give bitwise the eager
+    result, over several solves with re-capture for a new x."""
+    import torch
+    md = H.random_mesh(2, 4, 0.3, 3, 1, 8, seed=31)
+    m = G.Mesh(md)
+    eager = G.Operator(m)
+    graph = G.Operator(m, graph=True)
+    f = torch.from_numpy(H.gaussian_rhs(m.ndof, 32)).cuda()
+    b = torch.empty_like(f)
+    eager.rhs(f, b)
+    xe = torch.zeros_like(b)
+    ie = eager.pcg_solve(b, xe, rtol=1e-8, maxit=500)
+    for rep in range(3):
+        xg = torch.zeros_like(b)            # a new x each time: new capture
+        ig = graph.pcg_solve(b, xg, rtol=1e-8, maxit=500)
+        torch.cuda.synchronize()
+        assert ig[0]["iters"] == ie[0]["iters"]
+        assert torch.equal(xg, xe), f"replay {rep} differs from the eager solve"
+        y = torch.empty_like(b)
+        eager.apply_A(xg, y)                 # eager work between replays
+    # same x again: the cached graphs are replayed
+    xg.zero_()
+    graph.pcg_solve(b, xg, rtol=1e-8, maxit=500)
+    assert torch.equal(xg, xe)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("fp32", [False, True])
+def test_autotuned_binning_same_results(fp32):
+    import torch
+    md = H.random_mesh(2, 6, 0.3, 3, 1, 8, seed=33)
+    m = G.Mesh(md)
+    ref = G.Operator(m, prec_fp32=fp32)
+    tuned = G.Operator(m, prec_fp32=fp32)
+    rep = tuned.tune()
+    assert rep and {r["matrix"] for r in rep} >= {"A", "PT"}
+    for r in rep:
+        assert r["lanes"] in (1, 2, 4, 8, 16) and r["ns_tuned"] <= r["ns_default"]
+    r = torch.from_numpy(H.gaussian_rhs(m.ndof, 34)).cuda()
+    z0, z1 = torch.empty_like(r), torch.empty_like(r)
+    ref.apply_B(r, z0)
+    tuned.apply_B(r, z1)
+    tol = 1e-5 if fp32 else 1e-12
+    assert (z0 - z1).norm() <= tol * z0.norm()
+    b = torch.empty_like(r)
+    ref.rhs(r, b)
+    x0, x1 = torch.zeros_like(b), torch.zeros_like(b)
+    i0 = ref.pcg_solve(b, x0, rtol=1e-8, maxit=1000)
+    i1 = tuned.pcg_solve(b, x1, rtol=1e-8, maxit=1000)
+    assert abs(i0[0]["iters"] - i1[0]["iters"]) <= 1
+    assert i1[0]["true_rel_res"] <= 1e-8
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("form,eta", [("sipg", 1.0), ("br2", 0.0)])
+def test_elem2d_elements_per_workgroup_bitwise(monkeypatch, form, eta):
+    """The 2D element kernel with 1 or 2 elements per workgroup and 8, 16 or
+    32 face records per pass gives bitwise the same y = A x and the same PCG
+    iterates."""
+    import torch
+    md = H.random_mesh(2, 5, 0.3, 3, 1, 8, seed=41)
+    out = []
+    for epb, fc in (("1", "16"), ("2", "8"), ("1", "32"), ("2", "16")):
+        monkeypatch.setenv("HPDG_ELEM2D_EPB", epb)
+        monkeypatch.setenv("HPDG_ELEM2D_FCHUNK", fc)
+        m = G.Mesh(md)
+        op = G.Operator(m, form=form, eta=eta)
+        x = torch.from_numpy(H.gaussian_rhs(m.ndof, 42)).cuda()
+        y = torch.empty_like(x)
+        op.apply_A(x, y)
+        b = torch.empty_like(x)
+        op.rhs(x, b)
+        xx = torch.zeros_like(b)
+        info = op.pcg_solve(b, xx, rtol=1e-8, maxit=500)
+        out.append((y, xx, info[0]["iters"]))
+    for y, xx, it in out[1:]:
+        assert torch.equal(y, out[0][0]) and torch.equal(xx, out[0][1]) and it == out[0][2]
