@@ -815,12 +815,14 @@ static void launch_vol(hpdg_operator* op, int nrhs, const double* x, double* y, 
 // the caller has to form x'y itself.
 static int apply_A_dev(hpdg_operator* op, const double* x, double* y, int nrhs, hipStream_t s,
                        double* pdot = nullptr) {
-  if (op->dim == 2 && nrhs == 1 && !op->generic_faces) {
+  if (nrhs != 1) pdot = nullptr;
+  const int64_t items = (int64_t)op->ne * nrhs;   // (element, RHS) pairs
+  if (op->dim == 2 && !op->generic_faces) {
     auto launch = [&](auto epb_c, auto fc_c) {
       constexpr int EPB = decltype(epb_c)::value, FC = decltype(fc_c)::value;
-      // grid a multiple of 8 workgroups of EPB elements (XCD-aware order)
-      const unsigned grid = 8u * (unsigned)((op->ne + 8 * EPB - 1) / (8 * EPB));
-      hipLaunchKernelGGL((k_elem2d<EPB, FC>), dim3(grid), dim3(64 * EPB), 0, s, op->ne, op->form,
+      // grid a multiple of 8 workgroups of EPB items (XCD-aware order)
+      const unsigned grid = 8u * (unsigned)((items + 8 * EPB - 1) / (8 * EPB));
+      hipLaunchKernelGGL((k_elem2d<EPB, FC>), dim3(grid), dim3(64 * EPB), 0, s, op->ne, nrhs, op->form,
                          op->off.as<int64_t>(), op->pdeg.as<int8_t>(), op->hh.as<double>(), op->kk.as<double>(),
                          op->sptr.as<int32_t>(), op->recs.as<FaceRec>(), op->ftab.as<double>(),
                          op->tab.as<double>(), op->TL, x, y, pdot);
@@ -837,9 +839,9 @@ static int apply_A_dev(hpdg_operator* op, const double* x, double* y, int nrhs, 
     if (op->epb == 2) with_fc(I2());
     else with_fc(I1());
     return pdot ? op->ne : 0;
-  } else if (op->dim == 3 && nrhs == 1 && !op->generic_faces) {
-    const unsigned grid = 8u * (unsigned)((op->ne + 7) / 8);   // k_elem3d needs a multiple of 8
-    hipLaunchKernelGGL(k_elem3d, dim3(grid), dim3(256), 0, s, op->ne, op->form, op->off.as<int64_t>(),
+  } else if (op->dim == 3 && !op->generic_faces) {
+    const unsigned grid = 8u * (unsigned)((items + 7) / 8);   // k_elem3d needs a multiple of 8
+    hipLaunchKernelGGL(k_elem3d, dim3(grid), dim3(256), 0, s, op->ne, nrhs, op->form, op->off.as<int64_t>(),
                        op->pdeg.as<int8_t>(), op->hh.as<double>(), op->kk.as<double>(), op->sptr.as<int32_t>(),
                        op->recs.as<FaceRec>(), op->ftab.as<double>(), op->tab.as<double>(), op->TL, x, y, pdot);
     return pdot ? op->ne : 0;

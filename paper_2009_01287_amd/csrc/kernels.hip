@@ -394,7 +394,7 @@ __device__ inline void wave_sync() {
 }
 
 template <int EPB, int kFChunk>
-__global__ __launch_bounds__(64 * EPB) void k_elem2d(int ne, int form, const int64_t* __restrict__ off,
+__global__ __launch_bounds__(64 * EPB) void k_elem2d(int ne, int nrhs, int form, const int64_t* __restrict__ off,
                                                const int8_t* __restrict__ pdeg, const double* __restrict__ hh,
                                                const double* __restrict__ kk, const int32_t* __restrict__ sptr,
                                                const FaceRec* __restrict__ recs, const double* __restrict__ ftab,
@@ -427,8 +427,11 @@ __global__ __launch_bounds__(64 * EPB) void k_elem2d(int ne, int form, const int
   // range of the (space-filling ordered) element list; neighbours then share
   // its L2
   const int per = (int)(gridDim.x >> 3);
-  const int e = ((int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3)) * EPB + wv;
-  if (e >= ne) return;
+  // one item per (element, right-hand side); the RHS of an element are
+  // consecutive items, so they run on one XCD and share its L2
+  const int item = ((int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3)) * EPB + wv;
+  if (item >= ne * nrhs) return;
+  const int e = item / nrhs, rhs = item - e * nrhs;
   const int lane = (int)(threadIdx.x & 63);
   const int gq = lane / 9, jq = lane - 9 * (lane / 9);   // face groups of 9 lanes
   const int p = pdeg[e], n = p + 1, nn = n * n;
@@ -441,7 +444,7 @@ __global__ __launch_bounds__(64 * EPB) void k_elem2d(int ne, int form, const int
   const double* sM = sMKw[wv][0];
   const double* sK = sMKw[wv][1];
   for (int i = lane; i < nn; i += 64) {
-    sX[i] = x[base + i];
+    sX[i] = x[(base + i) * nrhs + rhs];
     sMKw[wv][0][i] = gMK[i];
     sMKw[wv][1][i] = gMK[81 + i];
   }
@@ -500,10 +503,10 @@ __global__ __launch_bounds__(64 * EPB) void k_elem2d(int ne, int form, const int
         const int no = po + 1, so = 1 - sR[f].side, mm = sR[f].m;
         const int som = mm == 0 ? 1 : no, sot = mm == 0 ? no : 1;
         const double* Dso = tab + TL.dside + (po * 2 + so) * 9;
-        const double* xn = x + sR[f].nbase;
+        const double* xn = x + (int64_t)sR[f].nbase * nrhs + rhs;
         double dv = 0.0;
-        for (int a = 0; a < no; ++a) dv += Dso[a] * xn[a * som + jj * sot];
-        sTn[f][jj] = xn[(so ? po : 0) * som + jj * sot];
+        for (int a = 0; a < no; ++a) dv += Dso[a] * xn[(int64_t)(a * som + jj * sot) * nrhs];
+        sTn[f][jj] = xn[(int64_t)((so ? po : 0) * som + jj * sot) * nrhs];
         sDn[f][jj] = sR[f].kho * dv;
       }
     }
@@ -622,7 +625,7 @@ __global__ __launch_bounds__(64 * EPB) void k_elem2d(int ne, int form, const int
     v += D0[i1] * sG2[2][i0] + D1[i1] * sG2[3][i0];
     if (i1 == 0) v += sG1[2][i0];
     if (i1 == p) v += sG1[3][i0];
-    y[base + i] = v;
+    y[(base + i) * nrhs + rhs] = v;
     xy += sX[i] * v;
   }
   // this element's share of x'y (the block is one wavefront), fixed order
@@ -857,7 +860,7 @@ __device__ inline void tdims3(int m, int& t0, int& t1) {
   t1 = m == 2 ? 1 : 2;
 }
 
-__global__ __launch_bounds__(256) void k_elem3d(int ne, int form, const int64_t* __restrict__ off,
+__global__ __launch_bounds__(256) void k_elem3d(int ne, int nrhs, int form, const int64_t* __restrict__ off,
                                                 const int8_t* __restrict__ pdeg, const double* __restrict__ hh,
                                                 const double* __restrict__ kk, const int32_t* __restrict__ sptr,
                                                 const FaceRec* __restrict__ recs, const double* __restrict__ ftab,
@@ -870,8 +873,9 @@ __global__ __launch_bounds__(256) void k_elem3d(int ne, int form, const int64_t*
   __shared__ FaceRec sR[kF3];
   __shared__ double sRed[4];
   const int per = (int)(gridDim.x >> 3);
-  const int e = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
-  if (e >= ne) return;
+  const int item = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);   // (element, RHS)
+  if (item >= ne * nrhs) return;
+  const int e = item / nrhs, rhs = item - e * nrhs;
   const int tid = threadIdx.x;
   const int p = pdeg[e], n = p + 1, n2 = n * n, n3 = n2 * n;
   const double h = hh[e], k = kk[e];
@@ -882,7 +886,7 @@ __global__ __launch_bounds__(256) void k_elem3d(int ne, int form, const int64_t*
   const double* Mt = tab + TL.mk + (p * 2 + 0) * 81;
   const double* Kt = tab + TL.mk + (p * 2 + 1) * 81;
   double* sX = sV0;
-  for (int i = tid; i < n3; i += 256) sX[i] = x[base + i];
+  for (int i = tid; i < n3; i += 256) sX[i] = x[(base + i) * nrhs + rhs];
   for (int i = tid; i < 6 * 81; i += 256) {
     (&sG1[0][0])[i] = 0.0;
     (&sG2[0][0])[i] = 0.0;
@@ -980,10 +984,10 @@ __global__ __launch_bounds__(256) void k_elem3d(int ne, int form, const int64_t*
       const int a0 = q % no, a1 = q / no;
       const int o = a0 * st[t0] + a1 * st[t1];
       const double* Dso = tab + TL.dside + (po * 2 + so) * 9;
-      const double* xn = x + sR[f].nbase;
+      const double* xn = x + (int64_t)sR[f].nbase * nrhs + rhs;
       double dv = 0.0;
-      for (int a = 0; a < no; ++a) dv += Dso[a] * xn[o + a * st[mm]];
-      sTn[f * 81 + q] = xn[o + (so ? po : 0) * st[mm]];
+      for (int a = 0; a < no; ++a) dv += Dso[a] * xn[(int64_t)(o + a * st[mm]) * nrhs];
+      sTn[f * 81 + q] = xn[(int64_t)(o + (so ? po : 0) * st[mm]) * nrhs];
       sDn[f * 81 + q] = sR[f].kho * dv;
     }
     __syncthreads();
@@ -1140,8 +1144,8 @@ __global__ __launch_bounds__(256) void k_elem3d(int ne, int form, const int64_t*
         if (i[m] == 0) v += sG1[2 * m][q];
         if (i[m] == p) v += sG1[2 * m + 1][q];
       }
-      y[base + r] = v;
-      xy += x[base + r] * v;
+      y[(base + r) * nrhs + rhs] = v;
+      xy += x[(base + r) * nrhs + rhs] * v;
     }
   }
   if (pdot) {
