@@ -53,6 +53,7 @@ def main():
                     help="serving: Poisson arrival rate in requests/s (0: all arrive at the start)")
     ap.add_argument("--workers", type=int, default=12, help="serving: host setup threads")
     ap.add_argument("--max-active", type=int, default=16, help="serving: solves in flight")
+    ap.add_argument("--serving-graph", type=int, default=0, help="serving: 1 replays CG chunks from HIP graphs")
     ap.add_argument("--serving-prec", default="mixed", choices=["mixed", "fp64", "both"])
     ap.add_argument("--apply-only", action="store_true",
                     help="only run apply_A --apply-reps times and one calibration copy of "
@@ -240,7 +241,7 @@ def serve_bench(args):
     precs = ["mixed", "fp64"] if args.serving_prec == "both" else [args.serving_prec]
     for prec in precs:
         srv = S.Server(max_active=args.max_active, workers=args.workers, prec_fp32=(prec == "mixed"),
-                       realtime=args.rate > 0)
+                       realtime=args.rate > 0, graph=bool(args.serving_graph))
         t0 = time.perf_counter()
         res = srv.run(reqs)
         wall = time.perf_counter() - t0
@@ -260,7 +261,8 @@ def serve_bench(args):
         "dtype": "f64 (operator, CG) + f32 (preconditioner)" if main_prec == "mixed" else "f64",
         "data": "synthetic",
         "config": {"workload": f"cfg5_serving_{args.requests}req_2d3d_1e3-2e5dof_p1-8_sipg|br2",
-                   "rate": args.rate or "all at t=0", "max_active": args.max_active, "workers": args.workers},
+                   "rate": args.rate or "all at t=0", "max_active": args.max_active, "workers": args.workers,
+                   "hip_graph": bool(args.serving_graph)},
         "latency_ms": {"p50": s["p50_s"] * 1e3, "p99": s["p99_s"] * 1e3},
         "serving": out,
     }

@@ -134,10 +134,15 @@ class Server:
     keep_x       return each solution on the host
     min_batch    hold admission until this many requests are prepared (or no
                  more can be: all prepared, or a worker waits for memory)
+    graph        replay each solve's chunks of CG iterations from HIP graphs
+                 (one launch per chunk instead of one per kernel). A capture
+                 must not overlap device calls of other threads on the legacy
+                 stream (allocations, synchronous copies), so with graphs the
+                 workers' uploads and the batch steps take turns on a lock.
     """
 
     def __init__(self, max_active=16, mem_budget=64 << 30, workers=8, prec_fp32=True, max_block=256,
-                 realtime=True, keep_x=False, min_batch=1):
+                 realtime=True, keep_x=False, min_batch=1, graph=False):
         self.max_active = max_active
         self.gate = MemoryGate(mem_budget)
         self.workers = workers
@@ -146,6 +151,8 @@ class Server:
         self.realtime = realtime
         self.keep_x = keep_x
         self.min_batch = min_batch
+        self.graph = graph
+        self._dev_lock = threading.Lock() if graph else None
         self.max_concurrent = 0
 
     # -- worker side ---------------------------------------------------
@@ -157,7 +164,7 @@ class Server:
             mesh = Mesh(req.mesh)
             eta = req.eta if req.eta is not None else (1.0 if req.form == "sipg" else 0.0)
             op = Operator(mesh, form=req.form, eta=eta, prec_fp32=self.prec_fp32, host_only=True,
-                          max_block=self.max_block if mesh.dim == 3 else 0)
+                          max_block=self.max_block if mesh.dim == 3 else 0, graph=self.graph)
             res.ndof = mesh.ndof
             nbytes = op.device_bytes() + 3 * 8 * mesh.ndof
             res.device_bytes = nbytes
@@ -168,6 +175,9 @@ class Server:
             self.gate.acquire(nbytes)
             try:
                 s = streams.get()
+                lock = self._dev_lock
+                if lock:
+                    lock.acquire()
                 try:
                     with torch.cuda.stream(s):
                         op.upload(stream=s.cuda_stream)
@@ -177,6 +187,8 @@ class Server:
                         op.rhs(fd, b, stream=s.cuda_stream)
                     s.synchronize()
                 finally:
+                    if lock:
+                        lock.release()
                     streams.put(s)
             except BaseException:
                 self.gate.release(nbytes)
@@ -222,16 +234,26 @@ class Server:
                 # admit at chunk boundaries while slots are free
                 left = n - len(results) - len(inflight)
                 hold = (len(waiting) < min(self.min_batch, left) and self.gate.waiters == 0)
+                lock = self._dev_lock
                 while waiting and not hold:
                     it = waiting[0]
-                    if not batch.admit(it.op, it.b, it.x, rtol=it.req.rtol, maxit=it.req.maxit, tag=it.req.id):
+                    if lock:
+                        with lock:
+                            ok = batch.admit(it.op, it.b, it.x, rtol=it.req.rtol, maxit=it.req.maxit, tag=it.req.id)
+                    else:
+                        ok = batch.admit(it.op, it.b, it.x, rtol=it.req.rtol, maxit=it.req.maxit, tag=it.req.id)
+                    if not ok:
                         break
                     it.res.t_admit = time.perf_counter() - t0
                     inflight[it.req.id] = it
                     waiting.pop(0)
                 self.max_concurrent = max(self.max_concurrent, len(inflight))
                 if inflight:
-                    _, nd = batch.step(wait_us=200)
+                    if lock:
+                        with lock:
+                            _, nd = batch.step(wait_us=200)
+                    else:
+                        _, nd = batch.step(wait_us=200)
                     if nd:
                         for tag, code, info in batch.poll():
                             it = inflight.pop(tag)
@@ -241,7 +263,11 @@ class Server:
                             r.iters = info["iters"]
                             r.true_rel_res = info["true_rel_res"]
                             if self.keep_x:
-                                r.x = it.x.cpu().numpy()
+                                if lock:
+                                    with lock:
+                                        r.x = it.x.cpu().numpy()
+                                else:
+                                    r.x = it.x.cpu().numpy()
                             results[tag] = r
                             del it.op, it.mesh, it.f, it.b, it.x
                             self.gate.release(it.nbytes)
@@ -277,6 +303,7 @@ def summarize(results, wall):
         "iters_mean": float(np.mean([r.iters for r in ok])) if ok else float("nan"),
         "max_true_rel_res": float(max((r.true_rel_res for r in ok), default=float("nan"))),
         "host_setup_s": float(sum(r.t_setup for r in results)),
+        "errors": sorted({f"{r.status}: {r.error}" for r in results if r.status != 0})[:5],
     }
 
 

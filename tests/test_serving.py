@@ -117,9 +117,10 @@ def alone(req, prec_fp32=True):
 
 
 @pytest.mark.gpu
-def test_mix_equals_alone_bitwise():
+@pytest.mark.parametrize("graph", [False, True])
+def test_mix_equals_alone_bitwise(graph):
     reqs = small_requests(10)
-    srv = S.Server(max_active=4, workers=4, realtime=False, keep_x=True, min_batch=len(reqs))
+    srv = S.Server(max_active=4, workers=4, realtime=False, keep_x=True, min_batch=len(reqs), graph=graph)
     res = srv.run(reqs)
     assert srv.max_concurrent == 4
     for q, r in zip(reqs, res):
