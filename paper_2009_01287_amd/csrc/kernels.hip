@@ -404,7 +404,7 @@ __global__ __launch_bounds__(64 * EPB) void k_elem2d(int ne, int nrhs, int form,
   // per element: x, the two volume temporaries (reused after the volume for
   // the face sums), the 1D mass / stiffness of its degree, side traces, and
   // one pass of face records with their neighbour traces
-  __shared__ double sXw[EPB][81], sAw[EPB][81], sBw[EPB][81], sMKw[EPB][2][81];
+  __shared__ double sXw[EPB][81], sAw[EPB][81], sBw[EPB][81], sMKw[EPB][2][81], sDsw[EPB][18];
   __shared__ double sTow[EPB][4][9], sDow[EPB][4][9];
   __shared__ double sTnw[EPB][kFChunk][9], sDnw[EPB][kFChunk][9];
   __shared__ FaceRec sRw[EPB][kFChunk];
@@ -448,6 +448,8 @@ __global__ __launch_bounds__(64 * EPB) void k_elem2d(int ne, int nrhs, int form,
     sMKw[wv][0][i] = gMK[i];
     sMKw[wv][1][i] = gMK[81 + i];
   }
+  // l_i'(0), l_i'(1) of degree p
+  if (lane < 18) sDsw[wv][lane] = tab[TL.dside + p * 2 * 9 + lane];
   wave_sync();
   // volume, phase 1 (dimension 0)
   for (int i = lane; i < nn; i += 64) {
@@ -467,7 +469,7 @@ __global__ __launch_bounds__(64 * EPB) void k_elem2d(int ne, int nrhs, int form,
   const int m = sidx >> 1, s = sidx & 1;
   const int stm = m == 0 ? 1 : n, stt = m == 0 ? n : 1;
   if (grp && j < n) {
-    const double* Ds = tab + TL.dside + (p * 2 + s) * 9;
+    const double* Ds = sDsw[wv] + s * 9;
     double dv = 0.0;
     for (int a = 0; a < n; ++a) dv += Ds[a] * sX[a * stm + j * stt];
     sTo[sidx][j] = sX[(s ? p : 0) * stm + j * stt];
@@ -613,8 +615,8 @@ __global__ __launch_bounds__(64 * EPB) void k_elem2d(int ne, int nrhs, int form,
     sG2[sidx][j] = G2 / h;
   }
   wave_sync();
-  const double* D0 = tab + TL.dside + (p * 2 + 0) * 9;
-  const double* D1 = tab + TL.dside + (p * 2 + 1) * 9;
+  const double* D0 = sDsw[wv];
+  const double* D1 = sDsw[wv] + 9;
   double xy = 0.0;
   for (int i = lane, c = 0; i < nn; i += 64, ++c) {
     const int i0 = i % n, i1 = i / n;

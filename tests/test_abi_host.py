@@ -47,6 +47,11 @@ def test_mesh_validation_errors():
         G.Mesh(dict(md, degree=np.array([1, 2, 9, 1], np.int32)))
     with pytest.raises(G.HpdgError):
         G.Mesh(dict(md, kcoef=np.array([1, 1, -1, 1.0])))
+    empty = dict(md, level=md["level"][:0], anchor=md["anchor"][:0], degree=md["degree"][:0],
+                 kcoef=md["kcoef"][:0])
+    with pytest.raises(G.HpdgError) as ei:
+        G.Mesh(empty)
+    assert ei.value.code == -1
     m = G.Mesh(H.fig1_mesh(3))
     assert m.max_level_jump == 3
     assert m.nface == len(O.Mesh(H.fig1_mesh(3)).faces)
