@@ -142,6 +142,7 @@ def main():
               else "apply_A (volume kernels + face kernel)")
 
     scaled = apply_scaled(cfg, c) if cfg == 2 else None
+    versus_fp64 = fp64_reference(args, cfg, c, mesh, b, x, infos, nrhs, dt) if c["prec_fp32"] else None
     cpu = None if args.no_cpu_baseline else cpu_baseline(cfg, c, it, n)
     traffic = None
     if cfg == 2 and md["dim"] == 2 and nrhs == 1 and elem2d_digest() == ELEM2D_TRAFFIC["digest"]:
@@ -173,8 +174,39 @@ def main():
                      "us_per_launch": t_apply * 1e6},
         "cpu_baseline": cpu,
         "apply_scaled": scaled,
+        "versus_fp64": versus_fp64,
     }
     print(json.dumps(out))
+
+
+def fp64_reference(args, cfg, c, mesh, b, x_mixed, infos_mixed, nrhs, dt_mixed, steps=2):
+    """The same solves with the FP64 preconditioner on the same GPU (plain FP64
+    PCG at the same 1e-8 accuracy): its solves/s, iterations, and the
+    difference of the two solutions."""
+    import torch
+
+    import paper_2009_01287_amd as G
+    md_dim = mesh.dim
+    op = G.Operator(mesh, form=c["form"], penalty_rule=c["penalty_rule"], eta=c["eta"], prec_fp32=False,
+                    max_nrhs=nrhs, max_block=256 if md_dim == 3 else 0)
+    if not args.no_tune:
+        op.tune()
+    x = torch.zeros_like(b)
+    infos = op.pcg_solve(b, x, nrhs=nrhs, rtol=c["rtol"], maxit=5000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        x.zero_()
+        infos = op.pcg_solve(b, x, nrhs=nrhs, rtol=c["rtol"], maxit=5000)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    d = (x - x_mixed).view(-1, nrhs)
+    rel = (d.norm(dim=0) / x.view(-1, nrhs).norm(dim=0)).max().item()
+    return {"fp64_solves_per_s": nrhs / dt, "mixed_solves_per_s": nrhs / dt_mixed,
+            "speedup": dt / dt_mixed, "fp64_iters": max(i["iters"] for i in infos),
+            "mixed_iters": max(i["iters"] for i in infos_mixed),
+            "max_rel_diff_mixed_vs_fp64": rel,
+            "fp64_true_rel_res": max(i["true_rel_res"] for i in infos)}
 
 
 def apply_scaled(cfg, c, n_base=128, reps=50):
