@@ -167,6 +167,9 @@ constexpr int64_t kHistCap = 2048;   // Lanczos coefficients kept per solve
 
 struct LevelDev {
   DevCSR A, P, R;
+  DevCSR M, AP;          // fused cycle: R (I - A D) and A P
+  int fused = 0;
+  int has_fused = 0;
   DevBuf l1inv;          // T
   DevBuf b, x, r, t;     // T, nrows * max_nrhs
 };
@@ -392,6 +395,49 @@ static void spd_inverse(std::vector<double>& A, int n) {
     for (int k = 0; k < i; ++k) A[(size_t)k * n + i] = A[(size_t)i * n + k];
 }
 
+constexpr int64_t kFuseNnz = 4 << 20;   // levels the fused cycle is tried on (nonzeros of A)
+
+// host matrices of a fused V-cycle level: M = R (I - A D) with D = diag(1/l1),
+// and A P
+static void fused_mats(const AMGLevel& L, CSR& M, CSR& AP) {
+  CSR RA = csr_matmul(L.R, L.A);
+  std::vector<int64_t> r;
+  std::vector<int32_t> cc;
+  std::vector<double> v;
+  for (int64_t i = 0; i < L.R.nrows; ++i) {
+    for (int64_t q = L.R.ptr[i]; q < L.R.ptr[i + 1]; ++q) {
+      r.push_back(i);
+      cc.push_back(L.R.idx[q]);
+      v.push_back(L.R.val[q]);
+    }
+    for (int64_t q = RA.ptr[i]; q < RA.ptr[i + 1]; ++q) {
+      r.push_back(i);
+      cc.push_back(RA.idx[q]);
+      v.push_back(-RA.val[q] / L.l1[RA.idx[q]]);
+    }
+  }
+  M = csr_from_triplets(L.R.nrows, L.R.ncols, r, cc, v);
+  AP = csr_matmul(L.A, L.P);
+}
+
+template <typename T>
+static void set_fused(hpdg_operator* op, size_t l, bool on) {
+  LevelDev& D = op->lv[l];
+  if (on && !D.has_fused) {
+    CSR M, AP;
+    fused_mats(op->host.amg.lv[l], M, AP);
+    upload_csr<T>(M, D.M);
+    upload_csr<T>(AP, D.AP);
+    D.has_fused = 1;
+  }
+  if (!on && D.has_fused) {
+    D.M = DevCSR();
+    D.AP = DevCSR();
+    D.has_fused = 0;
+  }
+  D.fused = on ? 1 : 0;
+}
+
 template <typename T>
 static void upload_prec(hpdg_operator* op) {
   PrecHost& H = op->host;
@@ -441,6 +487,9 @@ static void upload_prec(hpdg_operator* op) {
   std::vector<T> ci(H.amg.coarse_inv.begin(), H.amg.coarse_inv.end());
   op->coarse.upload(ci);
   op->ncoarse = (int)H.amg.nc;
+  if (std::getenv("HPDG_FUSE_LEVELS") && !g_dry)
+    for (size_t l = 0; l + 1 < op->lv.size(); ++l)
+      if (op->lv[l].A.nnz <= kFuseNnz) set_fused<T>(op, l, true);
   op->rT.alloc((size_t)op->ndof * op->max_nrhs * sizeof(T));
   op->zT.alloc((size_t)op->ndof * op->max_nrhs * sizeof(T));
 }
@@ -888,7 +937,38 @@ static void spmv(const DevCSR& A, int nrhs, const T* x, const T* b, const T* d, 
 }
 
 template <typename T>
+static void vcycle(hpdg_operator* op, size_t l, int nrhs, hipStream_t s);
+
+template <typename T, int LPR>
+static void upleg_launch(LevelDev& L, LevelDev& C, hipStream_t s) {
+  const int n = L.A.nrows;
+  hipLaunchKernelGGL((k_upleg<T, LPR>), dim3(nblk((int64_t)n * LPR)), dim3(256), 0, s, n, L.P.ptr.as<int32_t>(),
+                     L.P.idx.as<int32_t>(), L.P.val.as<T>(), L.A.ptr.as<int32_t>(), L.A.idx.as<int32_t>(),
+                     L.A.val.as<T>(), L.AP.ptr.as<int32_t>(), L.AP.idx.as<int32_t>(), L.AP.val.as<T>(),
+                     L.l1inv.as<T>(), L.b.as<T>(), C.x.as<T>(), L.x.as<T>());
+}
+
+// fused level (one RHS): two launches instead of four, same V(1,1) steps
+template <typename T>
+static void vcycle_fused(hpdg_operator* op, size_t l, hipStream_t s) {
+  LevelDev& L = op->lv[l];
+  LevelDev& C = op->lv[l + 1];
+  spmv<T, 0>(L.M, 1, L.b.as<T>(), nullptr, nullptr, nullptr, C.b.as<T>(), s);
+  vcycle<T>(op, l + 1, 1, s);
+  switch (L.A.lpr) {
+    case 1: case 2: upleg_launch<T, 2>(L, C, s); break;
+    case 4: upleg_launch<T, 4>(L, C, s); break;
+    case 8: upleg_launch<T, 8>(L, C, s); break;
+    default: upleg_launch<T, 16>(L, C, s); break;
+  }
+}
+
+template <typename T>
 static void vcycle(hpdg_operator* op, size_t l, int nrhs, hipStream_t s) {
+  if (nrhs == 1 && l + 1 < op->lv.size() && op->lv[l].fused) {
+    vcycle_fused<T>(op, l, s);
+    return;
+  }
   LevelDev& L = op->lv[l];
   int n = L.A.nrows;
   if (l + 1 == op->lv.size()) {
@@ -1032,6 +1112,39 @@ static int tune_all(hpdg_operator* op, hipStream_t s, int64_t* report, int cap) 
       tune_csr<T>(H.amg.lv[l].P, L.P, C.x.as<T>(), L.t.as<T>(), s, slot(2, (int)l));
     }
   }
+  // fused V-cycle levels, coarsest first (the cycle below a level is settled
+  // when it is timed)
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  for (int l = (int)op->lv.size() - 2; l >= 0; --l) {
+    if (op->lv[l].A.nnz > kFuseNnz) continue;
+    auto time_cycle = [&]() {
+      for (int w = 0; w < 3; ++w) vcycle<T>(op, l, 1, s);
+      HIPCHK(hipEventRecord(e0, s));
+      for (int w = 0; w < 10; ++w) vcycle<T>(op, l, 1, s);
+      HIPCHK(hipEventRecord(e1, s));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      return (double)ms * 1e6 / 10;
+    };
+    set_fused<T>(op, l, false);
+    const double t0 = time_cycle();
+    set_fused<T>(op, l, true);
+    const double t1 = time_cycle();
+    const bool keep = t1 < kTuneMargin * t0;
+    if (!keep) set_fused<T>(op, l, false);
+    int64_t* r = slot(5, l);
+    r[0] = op->lv[l].A.nrows;
+    r[1] = op->lv[l].A.nnz;
+    r[2] = 0;
+    r[3] = keep ? 1 : 0;
+    r[4] = (int64_t)t0;
+    r[5] = (int64_t)(keep ? t1 : t0);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   HIPCHK(hipStreamSynchronize(s));
   return k;
 }

@@ -1463,6 +1463,41 @@ __global__ __launch_bounds__(256) void k_dense_gemv1(int n, const T* __restrict_
   if (lane == 0) x[row] = acc;
 }
 
+// Up-leg of a fused V(1,1) level (one RHS), with x = D b from the pre-smoother
+// and x_c from the coarser level: t = D b + P x_c and the post-smoother
+// t + D (b - A t), where A t = A D b + (A P) x_c, in one pass over the rows
+// of P, A and A P (LPR lanes per row). The down-leg b_c = R (I - A D) b is a
+// plain product with the precomputed matrix.
+template <typename T, int LPR>
+__global__ __launch_bounds__(256) void k_upleg(int n, const int32_t* __restrict__ Pp, const int32_t* __restrict__ Pi,
+                                               const T* __restrict__ Pv, const int32_t* __restrict__ Ap,
+                                               const int32_t* __restrict__ Ai, const T* __restrict__ Av,
+                                               const int32_t* __restrict__ Qp, const int32_t* __restrict__ Qi,
+                                               const T* __restrict__ Qv, const T* __restrict__ d,
+                                               const T* __restrict__ b, const T* __restrict__ xc,
+                                               T* __restrict__ x) {
+  const int gt = blockIdx.x * 256 + threadIdx.x;
+  const int row = gt / LPR, sub = gt % LPR;
+  if (row >= n) return;   // whole lane groups exit together
+  T pe = 0, s = 0;
+  for (int q = Pp[row] + sub; q < Pp[row + 1]; q += LPR) pe += Pv[q] * xc[Pi[q]];
+  for (int q = Ap[row] + sub; q < Ap[row + 1]; q += LPR) {
+    const int j = Ai[q];
+    s += Av[q] * (d[j] * b[j]);
+  }
+  for (int q = Qp[row] + sub; q < Qp[row + 1]; q += LPR) s += Qv[q] * xc[Qi[q]];
+#pragma unroll
+  for (int o = LPR / 2; o > 0; o >>= 1) {
+    pe += __shfl_xor(pe, o, LPR);
+    s += __shfl_xor(s, o, LPR);
+  }
+  if (sub == 0) {
+    const T db = d[row] * b[row];
+    const T t = db + pe;
+    x[row] = t + d[row] * (b[row] - s);
+  }
+}
+
 template <typename T>
 __global__ void k_dense_gemv(int n, int nrhs, const T* __restrict__ C, const T* __restrict__ b, T* __restrict__ x) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
