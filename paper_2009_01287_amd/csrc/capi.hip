@@ -997,6 +997,9 @@ static void vcycle(hpdg_operator* op, size_t l, int nrhs, hipStream_t s) {
 // ------------------------------------------------------------ autotuner
 // Times y = A x for one sparse matrix of the one-RHS path under every row
 // binning (long-row threshold x lanes per short row) and keeps the fastest.
+template <typename T>
+static void launch_front(hpdg_operator* op, const T* rt, T* zb, hipStream_t s);
+
 // a candidate replaces the default only when this much faster (timing noise)
 constexpr double kTuneMargin = 0.95;
 
