@@ -301,7 +301,7 @@ def serve_bench(args):
     print(json.dumps(line))
 
 
-def cpu_baseline(cfg, c, gpu_iters, n_full, iters=10):
+def cpu_baseline(cfg, c, gpu_iters, n_full, iters=30):
     """The FP64 oracle (numpy/scipy) on this host, on a bounded sample: the
     same refinement recipe with n_base/4 (1/16 of the elements), `iters`
     oracle PCG iterations (one matrix-free A apply and one B apply each, the

@@ -196,7 +196,7 @@ struct hpdg_operator {
   int ncoarse = 0;
   DevBuf rT, zT, rc;       // T work vectors (DG and conforming sizes)
   // CG work (double)
-  DevBuf r, z, pv, Ap, part, scal, iscal, ticket, act, ahist, bhist;
+  DevBuf r, z, pv, Ap, part, scal, iscal, ahist, bhist;
   int64_t hist_cap = 0;      // Lanczos coefficients kept per RHS
   int64_t ftab_bytes = 0;
   int64_t dev_bytes = 0;     // device memory held by this operator once uploaded
@@ -535,13 +535,10 @@ static void upload_device(hpdg_operator* op, hipStream_t s) {
   op->part.alloc((size_t)std::max<int64_t>(1024 * hs, 2 * part_off2(op)) * sizeof(double));
   op->scal.alloc((size_t)16 * 256 * sizeof(double));
   op->iscal.alloc((size_t)4 * 256 * sizeof(int));
-  op->act.alloc((size_t)256 * sizeof(int));
-  op->ticket.alloc(64 * sizeof(unsigned));
   op->hist_cap = kHistCap;
   op->ahist.alloc((size_t)kHistCap * hs * sizeof(double));
   op->bhist.alloc((size_t)kHistCap * hs * sizeof(double));
   if (g_dry) return;
-  HIPCHK(hipMemsetAsync(op->ticket.p, 0, 64 * sizeof(unsigned), s));
   HIPCHK(hipMemsetAsync(op->iscal.p, 0, 4 * 256 * sizeof(int), s));
   if (!op->pin) HIPCHK(hipHostMalloc((void**)&op->pin, sizeof(PinArea), hipHostMallocDefault));
   if (!op->hist_pin)
@@ -1286,13 +1283,6 @@ extern "C" hpdg_status hpdg_rhs(hpdg_operator* op, const double* f, double* b, i
   return HPDG_OK;
 }
 
-// dot products of interleaved vectors into out[nrhs] (device)
-static void dot_dev(hpdg_operator* op, const double* a, const double* b, int nrhs, double* out, hipStream_t s) {
-  int64_t n = op->ndof * nrhs;
-  int nb = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n + 255) / 256));
-  hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(256), 0, s, n, nrhs, a, b, op->part.as<double>());
-  hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, s, nb, nrhs, op->part.as<double>(), out);
-}
 
 // extreme eigenvalues of the symmetric tridiagonal Lanczos matrix by bisection
 static void tridiag_extremes(const std::vector<double>& a, const std::vector<double>& b, double& lmin, double& lmax) {

@@ -1,20 +1,23 @@
 // HIP kernels for gfx950 (MI355X): DG operator, preconditioner pieces and
 // CG vector operations.
 //
-//   k_vol<DIM,P>   volume term of the DG operator (Sec. 2) by sum
-//                  factorisation: y_K = k h^{d-2} sum_m (K in dim m, M in the
-//                  others) x_K, 1D contractions staged through LDS, one
-//                  thread per element node, elements of one degree per block.
-//   k_mass<DIM,P>  element mass matrices h^d (M x ... x M) (load vector).
-//   k_faces<DIM>   face terms (Sec. 2 SIPG, Sec. 4.4 BR2) for every face of
-//                  one element per block: own and neighbour traces and
-//                  normal derivatives interpolated to the face's Gauss
-//                  points (covers conforming, mismatched-degree and
-//                  nonconforming sub-faces), tested against the own basis.
-//   k_spmv*        CSR products for P, P^T and the AMG levels, with fused
-//                  smoother / residual / prolongation-add forms.
-//   k_block_gemv   exact solves with the V_e blocks (stored inverses).
-//   k_dot_*        deterministic two-stage reductions (fixed order).
+//   k_elem2d, k_elem3d  the DG operator (Sec. 2; BR2 Sec. 4.4): volume term by
+//                  sum factorisation and every face term of one element in
+//                  one workgroup, faces through exact 1D face-mass matrices
+//                  (conforming, mismatched-degree and nonconforming sub-faces
+//                  alike); one item per (element, right-hand side).
+//   k_vol<DIM,P>   volume term by degree bucket (mode 0) and the element mass
+//                  matrices for the load vector (mode 1).
+//   k_faces<DIM>   generic face kernel (quadrature at the face points), kept
+//                  as an alternative path for checks.
+//   k_front        B's point Jacobi, V_e block solves and P^T in one launch.
+//   k_spmv, k_spmm CSR products for P, P^T and the AMG levels, with fused
+//                  smoother / residual / prolongation-add forms; k_upleg the
+//                  up-leg of a fused V-cycle level.
+//   k_block_gemv, k_diag_scale, k_dense_gemv*  multi-RHS pieces of B and the
+//                  coarsest AMG solve.
+//   k_dot_*, k_cg_*     deterministic two-stage reductions (fixed order) with
+//                  the CG scalar updates on the device, and the vector updates.
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -670,23 +673,6 @@ __global__ __launch_bounds__(256) void k_dot_partial(int64_t n, int nrhs, const 
   if (tid < nrhs) part[blockIdx.x * nrhs + tid] = sm[tid];
 }
 
-// out[r] = sum over blocks of part; one block of 256 threads, thread t sums
-// blocks t/nrhs, t/nrhs + 256/nrhs, ... of RHS t % nrhs, then a fixed tree
-__global__ __launch_bounds__(256) void k_dot_final(int nblocks, int nrhs, const double* __restrict__ part,
-                                                   double* __restrict__ out) {
-  __shared__ double sm[256];
-  const int t = threadIdx.x;
-  const int c = t % nrhs, g = t / nrhs, ng = 256 / nrhs;
-  double s = 0.0;
-  for (int b = g; b < nblocks; b += ng) s += part[b * nrhs + c];
-  sm[t] = s;
-  __syncthreads();
-  for (int w = 128; w >= nrhs; w >>= 1) {
-    if (t < w) sm[t] += sm[t + w];
-    __syncthreads();
-  }
-  if (t < nrhs) out[t] = sm[t];
-}
 
 // CG scalars on the device, one slot per RHS (SoA, stride 256):
 struct CGScal {
@@ -742,43 +728,6 @@ __device__ inline void cg_epilogue(int mode, int c, double v, CGScal S) {
   }
 }
 
-// single-launch dot product a.b per RHS with a fixed-order last-block reduction
-// and a scalar epilogue. part: gridDim.x * nrhs doubles; ticket zeroed.
-__global__ __launch_bounds__(256) void k_dot_ep(int64_t n, int nrhs, const double* __restrict__ a,
-                                                const double* __restrict__ b, double* __restrict__ part,
-                                                unsigned* __restrict__ ticket, int mode, CGScal S) {
-  __shared__ double sm[256];
-  __shared__ int last;
-  const int tid = threadIdx.x;
-  double acc = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + tid; i < n; i += (int64_t)gridDim.x * 256) acc += a[i] * b[i];
-  sm[tid] = acc;
-  __syncthreads();
-  for (int w = 128; w >= nrhs; w >>= 1) {
-    if (tid < w) sm[tid] += sm[tid + w];
-    __syncthreads();
-  }
-  if (tid < nrhs)
-    __hip_atomic_store(&part[blockIdx.x * nrhs + tid], sm[tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) last = atomicAdd(ticket, 1u) == gridDim.x - 1;
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  const int c = tid % nrhs, g = tid / nrhs, ng = 256 / nrhs;
-  double s = 0.0;
-  for (int q = g; q < (int)gridDim.x; q += ng)
-    s += __hip_atomic_load(&part[q * nrhs + c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  sm[tid] = s;
-  __syncthreads();
-  for (int w = 128; w >= nrhs; w >>= 1) {
-    if (tid < w) sm[tid] += sm[tid + w];
-    __syncthreads();
-  }
-  if (tid < nrhs) cg_epilogue(mode, tid, sm[tid], S);
-  if (tid == 0) *ticket = 0u;
-}
 
 // final stage of a dot product (partials from k_dot_partial) with the scalar
 // epilogue; one block of 256 threads, fixed summation order
@@ -1196,26 +1145,7 @@ __global__ void k_cg_dir2(int64_t n, int nrhs, const double* __restrict__ beta, 
   if (act[c]) p[i] = z[i] + beta[c] * p[i];
 }
 
-// x += alpha p ; r -= alpha Ap, alpha[r] = act ? rz/pAp : 0
-__global__ void k_cg_update(int64_t n, int nrhs, const double* __restrict__ rz, const double* __restrict__ pAp,
-                            const int* __restrict__ act, const double* __restrict__ p,
-                            const double* __restrict__ Ap, double* __restrict__ x, double* __restrict__ r) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  int c = (int)(i % nrhs);
-  double al = act[c] ? rz[c] / pAp[c] : 0.0;
-  x[i] += al * p[i];
-  r[i] -= al * Ap[i];
-}
 
-// p = z + beta p, beta[r] = rz_new/rz_old (act) else 0
-__global__ void k_cg_dir(int64_t n, int nrhs, const double* __restrict__ beta, const int* __restrict__ act,
-                         const double* __restrict__ z, double* __restrict__ p) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  int c = (int)(i % nrhs);
-  p[i] = act[c] ? z[i] + beta[c] * p[i] : p[i];
-}
 
 __global__ void k_sub(int64_t n, const double* __restrict__ a, const double* __restrict__ b, double* __restrict__ c) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1333,29 +1263,6 @@ __global__ __launch_bounds__(256) void k_prolong_out(int nrows, int nrhs, const 
   }
 }
 
-// exact V_e solves: LPR lanes per block row (coalesced row reads), nrhs == 1
-template <typename T, int LPR>
-__global__ __launch_bounds__(256) void k_block_gemv1(int64_t nrows, const int32_t* __restrict__ row_blk,
-                                                     const int32_t* __restrict__ row_loc,
-                                                     const int64_t* __restrict__ bptr,
-                                                     const int64_t* __restrict__ boff,
-                                                     const int32_t* __restrict__ bdof, const T* __restrict__ binv,
-                                                     const T* __restrict__ r, T* __restrict__ z) {
-  const int64_t gt = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int64_t rw = gt / LPR;
-  const int sub = (int)(gt % LPR);
-  if (rw >= nrows) return;
-  const int b = row_blk[rw];
-  const int i = row_loc[rw];
-  const int64_t s0 = bptr[b];
-  const int m = (int)(bptr[b + 1] - s0);
-  const T* row = binv + boff[b] + (int64_t)i * m;
-  T acc = 0;
-  for (int j = sub; j < m; j += LPR) acc += row[j] * r[bdof[s0 + j]];
-#pragma unroll
-  for (int o = LPR / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, LPR);
-  if (sub == 0) z[bdof[s0 + i]] = acc;
-}
 
 // front of B (nrhs == 1): three independent pieces in one launch, split by
 // block index: [0, nb_diag) point Jacobi z = dinv . r on all DOFs,
