@@ -29,11 +29,11 @@ HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
 # for a 256 MiB copy: 2.0 and 1.0), valid for the kernel source with this
 # digest; reported as null once the source differs
 ELEM2D_TRAFFIC = {"digest": "1e5076b93a68abb7", "fetch_bytes": 5630331.0, "write_bytes": 1241952.0}
-WORKLOADS = {1: "cfg1_uniform4x4_p2_sipg_fp64",
-             2: "cfg2_random2d_32x32_q0.3_L3_p1-8_sipg_fp64",
-             3: "cfg3_random3d_16^3_q0.2_L2_p1-6_br2_fp32prec",
-             4: "cfg4_cfg2mesh_64rhs_fp32prec",
-             5: "cfg5_serving_stream"}
+WORKLOADS = {1: "uniform2d_4x4_p2_sipg_fp64",
+             2: "random2d_32x32_q0.3_L3_p1-8_sipg_fp64",
+             3: "random3d_16^3_q0.2_L2_p1-6_br2_fp32prec",
+             4: "random2d_32x32_q0.3_L3_p1-8_64rhs_fp32prec",
+             5: "serving_stream"}
 
 
 def main():
@@ -60,7 +60,7 @@ def main():
                          "256 MiB (for hardware-counter runs), then exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU; --gpus must be 1 (no multi-GPU path here)",
+        print("bench.py: runs on one GPU only; --gpus must be 1 (no multi-GPU path)",
               file=sys.stderr)
         sys.exit(2)
 
@@ -292,7 +292,7 @@ def serve_bench(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64 (operator, CG) + f32 (preconditioner)" if main_prec == "mixed" else "f64",
         "data": "synthetic",
-        "config": {"workload": f"cfg5_serving_{args.requests}req_2d3d_1e3-2e5dof_p1-8_sipg|br2",
+        "config": {"workload": f"serving_{args.requests}req_2d3d_1e3-2e5dof_p1-8_sipg|br2",
                    "rate": args.rate or "all at t=0", "max_active": args.max_active, "workers": args.workers,
                    "hip_graph": bool(args.serving_graph)},
         "latency_ms": {"p50": s["p50_s"] * 1e3, "p99": s["p99_s"] * 1e3},

@@ -168,15 +168,15 @@ def gaussian_rhs(n, seed, nrhs=1):
 
 # Named workloads. Sizes are the expected values of the generator.
 CONFIGS = {
-    1: dict(name="cfg1_uniform4x4_p2", dim=2, form="sipg", penalty_rule=0,
+    1: dict(name="uniform2d_4x4_p2", dim=2, form="sipg", penalty_rule=0,
             eta=1.0, rtol=1e-10, prec_fp32=0, nrhs=1),
-    2: dict(name="cfg2_random2d_32x32_q0.3_L3_p1-8", dim=2, form="sipg",
+    2: dict(name="random2d_32x32_q0.3_L3_p1-8", dim=2, form="sipg",
             penalty_rule=0, eta=1.0, rtol=1e-8, prec_fp32=0, nrhs=1,
             mesh_seed=1002, rhs_seed=2002),
-    3: dict(name="cfg3_random3d_16^3_q0.2_L2_p1-6_br2", dim=3, form="br2",
+    3: dict(name="random3d_16^3_q0.2_L2_p1-6_br2", dim=3, form="br2",
             penalty_rule=0, eta=0.0, rtol=1e-8, prec_fp32=1, nrhs=1,
             mesh_seed=1003, rhs_seed=2003, k_seed=3003),
-    4: dict(name="cfg4_random2d_32x32_64rhs", dim=2, form="sipg",
+    4: dict(name="random2d_32x32_64rhs", dim=2, form="sipg",
             penalty_rule=0, eta=1.0, rtol=1e-8, prec_fp32=1, nrhs=64,
             mesh_seed=1002, rhs_seed=2004),
 }

@@ -15,8 +15,8 @@ Modules
   precond  V_J/V_e labels, conforming prolongation, LOR, AMG, B (Sec. 3)
   pcg      PCG with Lanczos condition estimate (Sec. 3.1, Sec. 4.1)
 
-Parity status of each function is recorded in the design doc; every function is
-pinned by a test under tests/ that does not re-use the oracle's own code.
+Every function is pinned by a test under tests/ that does not re-use the
+oracle's own code.
 """
 from . import gl, mesh, dg, precond, pcg  # noqa: F401
 from .mesh import Mesh  # noqa: F401

@@ -492,7 +492,7 @@ __global__ __launch_bounds__(64 * EPB) void k_elem2d(int ne, int nrhs, int form,
   const int sb = grp ? sp[sidx] : 0, se = grp ? sp[sidx + 1] : 0;
   for (int c0 = sp[0]; c0 < sp[4]; c0 += kFChunk) {
     const int nF = min(kFChunk, sp[4] - c0);
-    // round 1: the records of this pass
+    // first fetch: the records of this pass
     {
       constexpr int W = (int)(sizeof(FaceRec) / 8);
       const unsigned long long* src = reinterpret_cast<const unsigned long long*>(recs + c0);
@@ -500,7 +500,7 @@ __global__ __launch_bounds__(64 * EPB) void k_elem2d(int ne, int nrhs, int form,
       for (int t = lane; t < nF * W; t += 64) dst[t] = src[t];
     }
     wave_sync();
-    // round 2: neighbour trace Tn and k_n/h_n-scaled normal derivative Dn per (face, node)
+    // second fetch: neighbour trace Tn and k_n/h_n-scaled normal derivative Dn per (face, node)
     for (int t = lane; t < nF * 9; t += 64) {
       const int f = t / 9, jj = t - 9 * f;
       const int nb = sR[f].nbr, po = sR[f].pn;

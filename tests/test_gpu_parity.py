@@ -105,7 +105,7 @@ def test_pcg_matches_oracle(name, form):
     assert abs(info["cond_est"] / io["cond"] - 1) < 1e-3
 
 
-def test_cfg1_solve():
+def test_uniform_manufactured_solve():
     md = H.config_mesh(1)
     m = O.Mesh(md)
     op = G.Operator(G.Mesh(md))
@@ -125,8 +125,8 @@ def test_cfg1_solve():
     assert np.abs(_host(x) - u).max() < 1e-2
 
 
-def test_cfg2_full_size():
-    """cfg2 at its full size (155k DOFs), autotuned as bench.py runs it:
+def test_random2d_full_size():
+    """The 2D random hp mesh at its full size (155k DOFs), autotuned as bench.py runs it:
     apply_A on sampled elements against the oracle, B symmetric, PCG to 1e-8
     with the FP64 true residual."""
     md = H.config_mesh(2)
@@ -358,8 +358,8 @@ def test_single_element_meshes(dim, p, form):
     assert info["converged"] and _rel(_host(xs), xo) <= 1e-8
 
 
-def test_cfg3_full_size_sampled():
-    """cfg3 at its full size (3D, 2.57M DOFs, BR2, k contrast 1e4, FP32
+def test_random3d_br2_full_size_sampled():
+    """The 3D random hp mesh at its full size (2.57M DOFs, BR2, k contrast 1e4, FP32
     preconditioner): apply_A on 30 sampled elements against the oracle, and
     the PCG solve to 1e-8 with the FP64 true residual."""
     md = H.config_mesh(3)
@@ -379,12 +379,12 @@ def test_cfg3_full_size_sampled():
     op.rhs(_dev(H.config_rhs(3, m.ndof)), b)
     xs = torch.zeros_like(y)
     info = op.pcg_solve(b, xs, rtol=1e-8, maxit=3000)[0]
-    print(f"cfg3: {info['iters']} iterations, true residual {info['true_rel_res']:.2e}", flush=True)
+    print(f"random3d br2: {info['iters']} iterations, true residual {info['true_rel_res']:.2e}", flush=True)
     assert info["converged"] and info["true_rel_res"] <= 1e-8
 
 
-def test_cfg4_full_size():
-    """cfg4 at its full size (155k DOFs x 64 RHS, FP32 preconditioner): the
+def test_random2d_64rhs_full_size():
+    """64 right-hand sides on the 2D random mesh at full size (155k DOFs x 64 RHS, FP32 preconditioner): the
     batched apply equals the single-RHS apply bitwise on sampled columns, and
     every column of the batched solve reaches 1e-8 like its single solve."""
     md = H.config_mesh(4)

@@ -86,8 +86,8 @@ def test_symmetric_spd_and_polynomial_reproduction(dim, form):
     assert np.abs(x - u).max() < 1e-11
 
 
-def test_manufactured_rate_cfg1():
-    """cfg1 family: u = sin(pi x) sin(pi y), p=2, SIPG with (p+1)^2/h:
+def test_manufactured_rate_uniform_p2():
+    """Uniform p = 2 meshes: u = sin(pi x) sin(pi y), p=2, SIPG with (p+1)^2/h:
     L2 nodal-error decreases at about the rate p+1 = 3."""
     errs = []
     for n in (4, 8, 16):
