@@ -83,6 +83,8 @@ typedef struct {
                         hpdg_pcg_solve then fail with HPDG_E_UNSUPPORTED */
   int graph;         /* 1: PCG iterations are captured once per (chunk length, nrhs, x) into
                         HIP graphs and replayed (same kernels, same results) */
+  int setup_threads; /* host threads for the setup's sparse products (0: all hardware
+                        threads, 1: serial); results do not depend on it */
 } hpdg_operator_opts;
 
 /* Builds the operator and the preconditioner (host setup, then upload):

@@ -23,6 +23,8 @@
 #include <cmath>
 #include <string>
 
+#include <thread>
+
 #include "internal.hpp"
 
 namespace hpdg {
@@ -46,35 +48,80 @@ CSR csr_transpose(const CSR& A) {
   return T;
 }
 
-CSR csr_matmul(const CSR& A, const CSR& B) {
-  CSR C;
-  C.nrows = A.nrows;
-  C.ncols = B.ncols;
-  C.ptr.assign(1, 0);
-  std::vector<double> acc(B.ncols, 0.0);
-  std::vector<char> used(B.ncols, 0);
-  std::vector<int32_t> cols;
-  for (int64_t i = 0; i < A.nrows; ++i) {
-    cols.clear();
-    for (int64_t q = A.ptr[i]; q < A.ptr[i + 1]; ++q) {
-      int32_t k = A.idx[q];
-      double a = A.val[q];
-      for (int64_t r = B.ptr[k]; r < B.ptr[k + 1]; ++r) {
-        int32_t j = B.idx[r];
-        if (!used[j]) { used[j] = 1; acc[j] = 0.0; cols.push_back(j); }
-        acc[j] += a * B.val[r];
-      }
-    }
-    std::sort(cols.begin(), cols.end());
-    for (int32_t j : cols) {
-      used[j] = 0;
-      if (acc[j] == 0.0) continue;
-      C.idx.push_back(j);
-      C.val.push_back(acc[j]);
-    }
-    C.ptr.push_back((int64_t)C.idx.size());
+static thread_local int g_threads = 1;
+void set_setup_threads(int n) { g_threads = std::max(1, n); }
+int setup_threads() { return g_threads; }
+
+void parallel_chunks(int64_t n, const std::function<void(int64_t, int64_t, int)>& f, int64_t min_chunk) {
+  int T = (int)std::min<int64_t>(g_threads, std::max<int64_t>(1, n / std::max<int64_t>(1, min_chunk)));
+  if (T <= 1) {
+    f(0, n, 0);
+    return;
   }
-  return C;
+  std::vector<std::thread> th;
+  for (int t = 0; t < T; ++t) {
+    const int64_t b = n * t / T, e = n * (t + 1) / T;
+    th.emplace_back([&f, b, e, t]() { f(b, e, t); });
+  }
+  for (auto& x : th) x.join();
+}
+
+// Rows of a product or other row-wise result computed in chunks by several
+// threads and joined in row order.
+struct RowPieces {
+  std::vector<std::vector<int64_t>> len;
+  std::vector<std::vector<int32_t>> idx;
+  std::vector<std::vector<double>> val;
+  explicit RowPieces(int T) : len(T), idx(T), val(T) {}
+  CSR join(int64_t nrows, int64_t ncols) {
+    CSR C;
+    C.nrows = nrows;
+    C.ncols = ncols;
+    C.ptr.assign(1, 0);
+    size_t tot = 0;
+    for (auto& v : idx) tot += v.size();
+    C.idx.reserve(tot);
+    C.val.reserve(tot);
+    for (size_t t = 0; t < len.size(); ++t) {
+      for (int64_t l : len[t]) C.ptr.push_back(C.ptr.back() + l);
+      C.idx.insert(C.idx.end(), idx[t].begin(), idx[t].end());
+      C.val.insert(C.val.end(), val[t].begin(), val[t].end());
+    }
+    return C;
+  }
+};
+
+CSR csr_matmul(const CSR& A, const CSR& B) {
+  const int T = std::max(1, setup_threads());
+  RowPieces pc(T);
+  parallel_chunks(A.nrows, [&](int64_t b, int64_t e, int t) {
+    std::vector<double> acc(B.ncols, 0.0);
+    std::vector<char> used(B.ncols, 0);
+    std::vector<int32_t> cols;
+    for (int64_t i = b; i < e; ++i) {
+      cols.clear();
+      for (int64_t q = A.ptr[i]; q < A.ptr[i + 1]; ++q) {
+        int32_t k = A.idx[q];
+        double a = A.val[q];
+        for (int64_t r = B.ptr[k]; r < B.ptr[k + 1]; ++r) {
+          int32_t j = B.idx[r];
+          if (!used[j]) { used[j] = 1; acc[j] = 0.0; cols.push_back(j); }
+          acc[j] += a * B.val[r];
+        }
+      }
+      std::sort(cols.begin(), cols.end());
+      int64_t l = 0;
+      for (int32_t j : cols) {
+        used[j] = 0;
+        if (acc[j] == 0.0) continue;
+        pc.idx[t].push_back(j);
+        pc.val[t].push_back(acc[j]);
+        ++l;
+      }
+      pc.len[t].push_back(l);
+    }
+  });
+  return pc.join(A.nrows, B.ncols);
 }
 
 CSR csr_from_triplets(int64_t nr, int64_t nc, std::vector<int64_t>& r, std::vector<int32_t>& c,

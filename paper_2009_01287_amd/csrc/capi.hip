@@ -601,6 +601,11 @@ extern "C" hpdg_status hpdg_setup_operator(const hpdg_mesh* mh, const hpdg_opera
     return fail(HPDG_E_INVALID, "max_nrhs must divide 256");
   if (o->penalty_rule != 0 && o->penalty_rule != 1) return fail(HPDG_E_INVALID, "penalty_rule must be 0 or 1");
   auto op = std::make_unique<hpdg_operator>();
+  {
+    int nt = o->setup_threads;
+    if (nt <= 0) nt = (int)std::max(1u, std::thread::hardware_concurrency());
+    set_setup_threads(std::min(nt, 64));
+  }
   try {
     // a private copy of the mesh: entity tables are built lazily
     std::unique_ptr<Mesh> Mp(make_mesh(mh->dim, mh->n_base, (int64_t)mh->level.size(), mh->level.data(),
@@ -1247,6 +1252,8 @@ static hpdg_status check_vec_args(hpdg_operator* op, const void* a, const void* 
   if (!a || !b) return fail(HPDG_E_INVALID, "null vector");
   if (a == b) return fail(HPDG_E_INVALID, "input and output must not alias");
   if (nrhs < 1 || nrhs > op->max_nrhs || 256 % nrhs != 0) return fail(HPDG_E_INVALID, "bad nrhs");
+  if ((int64_t)op->ne * nrhs > (int64_t)INT32_MAX || op->ndof * nrhs > (int64_t)INT32_MAX)
+    return fail(HPDG_E_UNSUPPORTED, "elements x right-hand sides or DOFs x right-hand sides exceed 2^31");
   return HPDG_OK;
 }
 

@@ -3,6 +3,7 @@
 
 #include <cstdint>
 #include <cstring>
+#include <functional>
 #include <stdexcept>
 #include <string>
 #include <unordered_map>
@@ -100,6 +101,14 @@ struct Mesh {
 
 Mesh* make_mesh(int dim, int n_base, int64_t n, const int32_t* level, const int32_t* anchor,
                 const int32_t* degree, const double* kcoef);
+
+// ------------------------------------------------------ host threading
+// Host threads for the setup's row-parallel products (set per calling
+// thread; 1 = serial). Results do not depend on it.
+void set_setup_threads(int n);
+int setup_threads();
+// f(begin, end) over consecutive chunks of [0, n), one per thread
+void parallel_chunks(int64_t n, const std::function<void(int64_t, int64_t, int)>& f, int64_t min_chunk = 256);
 
 // --------------------------------------------------------------- CSR (host)
 struct CSR {

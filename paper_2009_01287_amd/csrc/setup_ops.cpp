@@ -638,33 +638,45 @@ static void lor_elem(const Mesh& M, int e, std::vector<double>& A) {
 }
 
 CSR lor_times(const Mesh& M, const CSR& P) {
+  // element ranges in parallel; each range yields consecutive rows
+  const int T = std::max(1, setup_threads());
+  std::vector<std::vector<int64_t>> len(T);
+  std::vector<std::vector<int32_t>> idx(T);
+  std::vector<std::vector<double>> val(T);
+  parallel_chunks(M.ne, [&](int64_t e0, int64_t e1, int t) {
+    std::vector<double> acc(P.ncols, 0.0);
+    std::vector<char> used(P.ncols, 0);
+    std::vector<int32_t> cols;
+    std::vector<double> A;
+    for (int64_t e = e0; e < e1; ++e) {
+      lor_elem(M, (int)e, A);
+      int64_t nd = M.off[e + 1] - M.off[e];
+      for (int64_t r = 0; r < nd; ++r) {
+        cols.clear();
+        for (int64_t c = 0; c < nd; ++c) {
+          double a = A[(size_t)r * nd + c];
+          if (a == 0.0) continue;
+          int64_t row = M.off[e] + c;
+          for (int64_t q = P.ptr[row]; q < P.ptr[row + 1]; ++q) {
+            int32_t j = P.idx[q];
+            if (!used[j]) { used[j] = 1; cols.push_back(j); acc[j] = 0.0; }
+            acc[j] += a * P.val[q];
+          }
+        }
+        std::sort(cols.begin(), cols.end());
+        for (int32_t j : cols) { idx[t].push_back(j); val[t].push_back(acc[j]); used[j] = 0; }
+        len[t].push_back((int64_t)cols.size());
+      }
+    }
+  }, 16);
   CSR R;
   R.nrows = M.ndof;
   R.ncols = P.ncols;
   R.ptr.assign(1, 0);
-  std::vector<double> acc(P.ncols, 0.0);
-  std::vector<char> used(P.ncols, 0);
-  std::vector<int32_t> cols;
-  std::vector<double> A;
-  for (int e = 0; e < M.ne; ++e) {
-    lor_elem(M, e, A);
-    int64_t nd = M.off[e + 1] - M.off[e];
-    for (int64_t r = 0; r < nd; ++r) {
-      cols.clear();
-      for (int64_t c = 0; c < nd; ++c) {
-        double a = A[(size_t)r * nd + c];
-        if (a == 0.0) continue;
-        int64_t row = M.off[e] + c;
-        for (int64_t q = P.ptr[row]; q < P.ptr[row + 1]; ++q) {
-          int32_t j = P.idx[q];
-          if (!used[j]) { used[j] = 1; cols.push_back(j); acc[j] = 0.0; }
-          acc[j] += a * P.val[q];
-        }
-      }
-      std::sort(cols.begin(), cols.end());
-      for (int32_t j : cols) { R.idx.push_back(j); R.val.push_back(acc[j]); used[j] = 0; }
-      R.ptr.push_back((int64_t)R.idx.size());
-    }
+  for (int t = 0; t < T; ++t) {
+    for (int64_t l : len[t]) R.ptr.push_back(R.ptr.back() + l);
+    R.idx.insert(R.idx.end(), idx[t].begin(), idx[t].end());
+    R.val.insert(R.val.end(), val[t].begin(), val[t].end());
   }
   return R;
 }

@@ -164,7 +164,8 @@ class Server:
             mesh = Mesh(req.mesh)
             eta = req.eta if req.eta is not None else (1.0 if req.form == "sipg" else 0.0)
             op = Operator(mesh, form=req.form, eta=eta, prec_fp32=self.prec_fp32, host_only=True,
-                          max_block=self.max_block if mesh.dim == 3 else 0, graph=self.graph)
+                          max_block=self.max_block if mesh.dim == 3 else 0, graph=self.graph,
+                          setup_threads=1)     # the workers already run setups in parallel
             res.ndof = mesh.ndof
             nbytes = op.device_bytes() + 3 * 8 * mesh.ndof
             res.device_bytes = nbytes
