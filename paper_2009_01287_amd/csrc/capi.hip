@@ -205,6 +205,7 @@ struct hpdg_operator {
   int use_graph = 0;         // PCG chunks replayed from captured HIP graphs
   int epb = 1;               // elements per workgroup of the 2D element kernel
   int fchunk = 16;           // face records per pass of the 2D element kernel
+  int rhs_group = 1;         // right-hand sides per item of the 2D element kernel
   struct GraphEntry {
     int k, nrhs;
     double* x;
@@ -760,6 +761,7 @@ extern "C" hpdg_status hpdg_setup_operator(const hpdg_mesh* mh, const hpdg_opera
     op->use_graph = o->graph ? 1 : 0;
     if (const char* v = std::getenv("HPDG_ELEM2D_EPB")) op->epb = std::atoi(v) == 2 ? 2 : 1;
     if (const char* v = std::getenv("HPDG_ELEM2D_FCHUNK")) op->fchunk = std::atoi(v) == 8 ? 8 : std::atoi(v) == 32 ? 32 : 16;
+    if (const char* v = std::getenv("HPDG_ELEM2D_RHSGROUP")) op->rhs_group = std::max(1, std::atoi(v));
     if (!op->no_prec) {
       PrecHost& H = op->host;
       H.diag = dg_diagonal(M, oo);
@@ -870,11 +872,14 @@ static int apply_A_dev(hpdg_operator* op, const double* x, double* y, int nrhs, 
   if (nrhs != 1) pdot = nullptr;
   const int64_t items = (int64_t)op->ne * nrhs;   // (element, RHS) pairs
   if (op->dim == 2 && !op->generic_faces) {
+    const int rg = std::max(1, std::min(nrhs, op->rhs_group));
+    const int64_t items2 = (int64_t)op->ne * ((nrhs + rg - 1) / rg);   // (element, RHS group) pairs
     auto launch = [&](auto epb_c, auto fc_c) {
       constexpr int EPB = decltype(epb_c)::value, FC = decltype(fc_c)::value;
       // grid a multiple of 8 workgroups of EPB items (XCD-aware order)
-      const unsigned grid = 8u * (unsigned)((items + 8 * EPB - 1) / (8 * EPB));
-      hipLaunchKernelGGL((k_elem2d<EPB, FC>), dim3(grid), dim3(64 * EPB), 0, s, op->ne, nrhs, op->form,
+      const unsigned grid = 8u * (unsigned)((items2 + 8 * EPB - 1) / (8 * EPB));
+      auto kern = rg > 1 ? k_elem2d<EPB, FC, true> : k_elem2d<EPB, FC, false>;
+      hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * EPB), 0, s, op->ne, nrhs, rg, op->form,
                          op->off.as<int64_t>(), op->pdeg.as<int8_t>(), op->hh.as<double>(), op->kk.as<double>(),
                          op->sptr.as<int32_t>(), op->recs.as<FaceRec>(), op->ftab.as<double>(),
                          op->tab.as<double>(), op->TL, x, y, pdot);
@@ -1085,6 +1090,45 @@ static void tune_elem(hpdg_operator* op, hipStream_t s, int64_t* rep) {
   rep[4] = (int64_t)t_def; rep[5] = (int64_t)best;
 }
 
+// right-hand sides per item of the 2D element kernel at the operator's
+// largest nrhs (results do not depend on it)
+static void tune_rhs_group(hpdg_operator* op, hipStream_t s, int64_t* rep) {
+  const int nr = op->max_nrhs;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  double* x = op->pv.as<double>();
+  double* y = op->Ap.as<double>();
+  HIPCHK(hipMemsetAsync(x, 0, op->pv.bytes, s));
+  auto time_it = [&]() {
+    for (int w = 0; w < 2; ++w) apply_A_dev(op, x, y, nr, s, nullptr);
+    HIPCHK(hipEventRecord(e0, s));
+    const int reps = 5;
+    for (int w = 0; w < reps; ++w) apply_A_dev(op, x, y, nr, s, nullptr);
+    HIPCHK(hipEventRecord(e1, s));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    return (double)ms * 1e6 / reps;
+  };
+  const int def = op->rhs_group;
+  const double t_def = time_it();
+  double best = t_def * kTuneMargin;
+  int bg = def;
+  for (int g : {1, 2, 4, 8, 16, 32, 64}) {
+    if (g > nr) break;
+    op->rhs_group = g;
+    const double t = time_it();
+    if (t < best) { best = t; bg = g; }
+  }
+  if (bg == def) best = t_def;
+  op->rhs_group = bg;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  rep[0] = op->ndof; rep[1] = op->ne; rep[2] = nr; rep[3] = bg;
+  rep[4] = (int64_t)t_def; rep[5] = (int64_t)best;
+}
+
 template <typename T>
 static int tune_all(hpdg_operator* op, hipStream_t s, int64_t* report, int cap) {
   PrecHost& H = op->host;
@@ -1097,7 +1141,10 @@ static int tune_all(hpdg_operator* op, hipStream_t s, int64_t* report, int cap) 
     r[1] = level;
     return r + 2;
   };
-  if (op->dim == 2 && !op->generic_faces) tune_elem(op, s, slot(4, 0));
+  if (op->dim == 2 && !op->generic_faces) {
+    tune_elem(op, s, slot(4, 0));
+    if (op->max_nrhs > 1) tune_rhs_group(op, s, slot(6, 0));
+  }
   HIPCHK(hipMemsetAsync(op->rT.p, 0, op->rT.bytes, s));
   for (auto& L : op->lv) {
     HIPCHK(hipMemsetAsync(L.b.p, 0, L.b.bytes, s));

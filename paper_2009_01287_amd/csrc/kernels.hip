@@ -396,8 +396,8 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int EPB, int kFChunk>
-__global__ __launch_bounds__(64 * EPB) void k_elem2d(int ne, int nrhs, int form, const int64_t* __restrict__ off,
+template <int EPB, int kFChunk, bool GROUPED>
+__global__ __launch_bounds__(64 * EPB) void k_elem2d(int ne, int nrhs, int rg, int form, const int64_t* __restrict__ off,
                                                const int8_t* __restrict__ pdeg, const double* __restrict__ hh,
                                                const double* __restrict__ kk, const int32_t* __restrict__ sptr,
                                                const FaceRec* __restrict__ recs, const double* __restrict__ ftab,
@@ -430,11 +430,15 @@ __global__ __launch_bounds__(64 * EPB) void k_elem2d(int ne, int nrhs, int form,
   // range of the (space-filling ordered) element list; neighbours then share
   // its L2
   const int per = (int)(gridDim.x >> 3);
-  // one item per (element, right-hand side); the RHS of an element are
-  // consecutive items, so they run on one XCD and share its L2
+  // one item per (element, group of rg right-hand sides), the RHS of a group
+  // taken one after another (metadata, tables and records stay hot); the
+  // groups of an element are consecutive items, on one XCD
+  // (without GROUPED: one right-hand side per item)
+  const int rgc = GROUPED ? rg : 1;
+  const int ngrp = (nrhs + rgc - 1) / rgc;
   const int item = ((int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3)) * EPB + wv;
-  if (item >= ne * nrhs) return;
-  const int e = item / nrhs, rhs = item - e * nrhs;
+  if (item >= ne * ngrp) return;
+  const int e = item / ngrp, r0 = (item - e * ngrp) * rgc, r1 = GROUPED ? min(nrhs, r0 + rgc) : r0 + 1;
   const int lane = (int)(threadIdx.x & 63);
   const int gq = lane / 9, jq = lane - 9 * (lane / 9);   // face groups of 9 lanes
   const int p = pdeg[e], n = p + 1, nn = n * n;
@@ -447,12 +451,13 @@ __global__ __launch_bounds__(64 * EPB) void k_elem2d(int ne, int nrhs, int form,
   const double* sM = sMKw[wv][0];
   const double* sK = sMKw[wv][1];
   for (int i = lane; i < nn; i += 64) {
-    sX[i] = x[(base + i) * nrhs + rhs];
     sMKw[wv][0][i] = gMK[i];
     sMKw[wv][1][i] = gMK[81 + i];
   }
   // l_i'(0), l_i'(1) of degree p
   if (lane < 18) sDsw[wv][lane] = tab[TL.dside + p * 2 * 9 + lane];
+  for (int rhs = r0; rhs < r1; ++rhs) {
+  for (int i = lane; i < nn; i += 64) sX[i] = x[(base + i) * nrhs + rhs];
   wave_sync();
   // volume, phase 1 (dimension 0)
   for (int i = lane; i < nn; i += 64) {
@@ -638,6 +643,8 @@ __global__ __launch_bounds__(64 * EPB) void k_elem2d(int ne, int nrhs, int form,
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) xy += __shfl_xor(xy, o, 64);
     if (lane == 0) pdot[e] = xy;
+  }
+  if (GROUPED) wave_sync();   // the next right-hand side rewrites the LDS
   }
 }
 

@@ -286,6 +286,8 @@ def test_autotuned_binning_same_results(fp32):
         assert r["ns_tuned"] <= r["ns_default"]
         if r["matrix"] == "vcycle_fused":
             assert r["lanes"] in (0, 1)
+        elif r["matrix"] == "elem_rhs_group":
+            assert r["lanes"] in (1, 2, 4, 8, 16, 32, 64)
         else:
             assert r["lanes"] in (1, 2, 4, 8, 16)
     r = torch.from_numpy(H.gaussian_rhs(m.ndof, 34)).cuda()
@@ -434,3 +436,20 @@ def test_fused_vcycle_levels(monkeypatch, name, fp32):
     x = torch.zeros_like(b)
     info = op.pcg_solve(b, x, rtol=1e-8, maxit=1000)[0]
     assert info["converged"] and info["true_rel_res"] <= 1e-8
+
+
+@pytest.mark.parametrize("group", ["1", "4", "64"])
+def test_elem2d_rhs_groups_bitwise(monkeypatch, group):
+    """The 2D element kernel with groups of right-hand sides per item gives
+    bitwise the same multi-RHS apply as one RHS per item."""
+    md = H.random_mesh(2, 4, 0.3, 3, 1, 8, seed=43)
+    nr = 64
+    x = _dev(H.gaussian_rhs(H.ndof(md), 44, nrhs=nr).reshape(-1))
+    outs = []
+    for g in ("1", group):
+        monkeypatch.setenv("HPDG_ELEM2D_RHSGROUP", g)
+        op = G.Operator(G.Mesh(md), max_nrhs=nr)
+        y = torch.empty_like(x)
+        op.apply_A(x, y, nrhs=nr)
+        outs.append(y)
+    assert torch.equal(outs[0], outs[1])
