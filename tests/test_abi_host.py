@@ -123,3 +123,17 @@ def test_no_prec_operator_host():
     assert bare.device_bytes() < full.device_bytes()
     s = bare.summary()
     assert s["ndof"] == m.ndof and s["amg_levels"] == 0 and s["nblocks"] == 0
+
+
+def test_setup_threads_do_not_change_results():
+    """The row-parallel setup products give bitwise the same host data with
+    one thread and with several."""
+    _lib_or_skip()
+    md = H.random_mesh(3, 2, 0.4, 2, 1, 4, seed=5, k_logrange=(-2, 2))
+    m = G.Mesh(md)
+    a = G.Operator(m, form="br2", eta=0.0, host_only=True, max_block=128, setup_threads=1)
+    b = G.Operator(m, form="br2", eta=0.0, host_only=True, max_block=128, setup_threads=4)
+    for what in (0, 1, 2, 3, 4, 6, 8):
+        assert np.array_equal(a.export(what), b.export(what)), what
+    for l in range(len(a.amg_levels())):
+        assert np.array_equal(a.export(100 + l), b.export(100 + l))
