@@ -190,6 +190,7 @@ struct hpdg_operator {
   DevBuf dinvJ;
   DevBuf blk_rowb, blk_rowl, blk_ptr, blk_off, blk_dof, blk_inv;
   int64_t blk_rows = 0, nblocks = 0;
+  int max_blk = 0;           // largest V_e block
   DevCSR P, PT;
   std::vector<LevelDev> lv;
   DevBuf coarse;
@@ -457,6 +458,8 @@ static void upload_prec(hpdg_operator* op) {
   }
   op->blk_rows = (int64_t)rowb.size();
   op->nblocks = (int64_t)H.blocks.size();
+  op->max_blk = 0;
+  for (auto& B : H.blocks) op->max_blk = std::max(op->max_blk, (int)B.size());
   op->blk_rowb.upload(rowb);
   op->blk_rowl.upload(rowl);
   op->blk_ptr.upload(bptr);
@@ -985,8 +988,8 @@ static void vcycle(hpdg_operator* op, size_t l, int nrhs, hipStream_t s) {
       hipLaunchKernelGGL(k_dense_gemv1<T>, dim3((op->ncoarse + 3) / 4), dim3(256), 0, s, op->ncoarse,
                          op->coarse.as<T>(), L.b.as<T>(), L.x.as<T>());
     else
-      hipLaunchKernelGGL(k_dense_gemv<T>, dim3(nblk(nt)), dim3(256), 0, s, op->ncoarse, nrhs, op->coarse.as<T>(),
-                         L.b.as<T>(), L.x.as<T>());
+      hipLaunchKernelGGL(k_dense_gemm<T>, dim3(op->ncoarse), dim3(256), 0, s, op->ncoarse, nrhs,
+                         op->coarse.as<T>(), L.b.as<T>(), L.x.as<T>());
     return;
   }
   LevelDev& C = op->lv[l + 1];
@@ -1277,9 +1280,15 @@ static int apply_B_dev(hpdg_operator* op, const double* r, double* z, int nrhs, 
     hipLaunchKernelGGL(k_diag_scale<T>, dim3(nblk(n)), dim3(256), 0, s, n, nrhs, op->dinvJ.as<T>(), rt, zb);
     if (op->blk_rows > 0) {
       int64_t nt = op->blk_rows * nrhs;
-      hipLaunchKernelGGL(k_block_gemv<T>, dim3(nblk(nt)), dim3(256), 0, s, op->blk_rows, nrhs,
-                         op->blk_rowb.as<int32_t>(), op->blk_rowl.as<int32_t>(), op->blk_ptr.as<int64_t>(),
-                         op->blk_off.as<int64_t>(), op->blk_dof.as<int32_t>(), op->blk_inv.as<T>(), rt, zb);
+      const size_t shm = (size_t)op->max_blk * nrhs * sizeof(T);
+      if (shm <= 48 * 1024)
+        hipLaunchKernelGGL(k_block_gemm<T>, dim3((unsigned)op->nblocks), dim3(256), shm, s, (int)op->nblocks, nrhs,
+                           op->blk_ptr.as<int64_t>(), op->blk_off.as<int64_t>(), op->blk_dof.as<int32_t>(),
+                           op->blk_inv.as<T>(), rt, zb);
+      else
+        hipLaunchKernelGGL(k_block_gemv<T>, dim3(nblk(nt)), dim3(256), 0, s, op->blk_rows, nrhs,
+                           op->blk_rowb.as<int32_t>(), op->blk_rowl.as<int32_t>(), op->blk_ptr.as<int64_t>(),
+                           op->blk_off.as<int64_t>(), op->blk_dof.as<int32_t>(), op->blk_inv.as<T>(), rt, zb);
     }
     spmv<T, 0>(op->PT, nrhs, rt, nullptr, nullptr, nullptr, L0.b.as<T>(), s);
   }
@@ -1379,7 +1388,10 @@ static void dot_ep(hpdg_operator* op, const double* a, const double* b, int nrhs
   int64_t n = op->ndof * nrhs;
   int nb = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n + 1023) / 1024));
   hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(256), 0, s, n, nrhs, a, b, op->part.as<double>());
-  hipLaunchKernelGGL(k_dot_final_ep, dim3(1), dim3(256), 0, s, nb, nrhs, op->part.as<double>(), mode, S);
+  if (nrhs == 1)
+    hipLaunchKernelGGL(k_dot_final_ep, dim3(1), dim3(256), 0, s, nb, nrhs, op->part.as<double>(), mode, S);
+  else
+    hipLaunchKernelGGL(k_dot_final_rhs, dim3(nrhs), dim3(256), 0, s, nb, nrhs, op->part.as<double>(), mode, S);
 }
 
 static CGScal cg_scal(hpdg_operator* op) {

@@ -1362,6 +1362,71 @@ __global__ __launch_bounds__(256) void k_block_gemv(int64_t nrows, int nrhs, con
   z[(int64_t)bdof[s0 + i] * nrhs + c] = acc;
 }
 
+// exact V_e solves, interleaved RHS: one workgroup per block; the block's
+// r values (m x nrhs) are staged in LDS once and every (row, rhs) pair of the
+// block reads them from there (dynamic LDS: m_max * nrhs values)
+template <typename T>
+__global__ __launch_bounds__(256) void k_block_gemm(int nblocks, int nrhs, const int64_t* __restrict__ bptr,
+                                                    const int64_t* __restrict__ boff,
+                                                    const int32_t* __restrict__ bdof, const T* __restrict__ binv,
+                                                    const T* __restrict__ r, T* __restrict__ z) {
+  extern __shared__ unsigned char blk_lds[];
+  T* rl = reinterpret_cast<T*>(blk_lds);
+  const int b = blockIdx.x;
+  if (b >= nblocks) return;
+  const int64_t s0 = bptr[b];
+  const int m = (int)(bptr[b + 1] - s0);
+  for (int t = threadIdx.x; t < m * nrhs; t += 256) {
+    const int j = t / nrhs, c = t - j * nrhs;
+    rl[t] = r[(int64_t)bdof[s0 + j] * nrhs + c];
+  }
+  __syncthreads();
+  const T* B = binv + boff[b];
+  for (int t = threadIdx.x; t < m * nrhs; t += 256) {
+    const int i = t / nrhs, c = t - i * nrhs;
+    T acc = 0;
+    for (int j = 0; j < m; ++j) acc += B[(int64_t)i * m + j] * rl[j * nrhs + c];
+    z[(int64_t)bdof[s0 + i] * nrhs + c] = acc;
+  }
+}
+
+// coarsest level, interleaved RHS: a workgroup per row, its 256 / nrhs lane
+// groups split the row and add their parts in a fixed order
+template <typename T>
+__global__ __launch_bounds__(256) void k_dense_gemm(int n, int nrhs, const T* __restrict__ C,
+                                                    const T* __restrict__ b, T* __restrict__ x) {
+  __shared__ T part[256];
+  const int row = blockIdx.x;
+  const int c = threadIdx.x % nrhs, g = threadIdx.x / nrhs, ng = 256 / nrhs;
+  T acc = 0;
+  for (int j = g; j < n; j += ng) acc += C[(int64_t)row * n + j] * b[(int64_t)j * nrhs + c];
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  if (g == 0) {
+    T s = part[c];
+    for (int q = 1; q < ng; ++q) s += part[q * nrhs + c];
+    x[(int64_t)row * nrhs + c] = s;
+  }
+}
+
+// final stage of a dot product for many RHS: one workgroup per RHS, fixed
+// summation order, then the scalar epilogue
+__global__ __launch_bounds__(256) void k_dot_final_rhs(int nblocks, int nrhs, const double* __restrict__ part,
+                                                       int mode, CGScal S) {
+  __shared__ double sm[256];
+  const int c = blockIdx.x;
+  const int t = threadIdx.x;
+  double s = 0.0;
+  for (int bb = t; bb < nblocks; bb += 256) s += part[(int64_t)bb * nrhs + c];
+  sm[t] = s;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if (t < w) sm[t] += sm[t + w];
+    __syncthreads();
+  }
+  if (t == 0) cg_epilogue(mode, c, sm[0], S);
+}
+
 // coarsest level: x = C b (dense inverse). nrhs == 1: one wavefront per row
 // (coalesced row reads); otherwise one thread per (row, rhs)
 template <typename T>
