@@ -158,7 +158,8 @@ hpdg_status hpdg_operator_device_bytes(hpdg_operator* op, int64_t* bytes);
  * ns after); *n rows written. A fused level (one RHS, at most 4M nonzeros)
  * runs the V(1,1) steps of that level in two launches with the precomputed
  * products R (I - A D) and A P instead of four; it is kept only where it
- * measures faster, and its matrices add device memory. */
+ * measures faster, and its matrices add device memory. Its row holds the
+ * lanes per row of the fused up-leg in the threshold column. */
 hpdg_status hpdg_operator_tune(hpdg_operator* op, void* stream, int64_t* report, int cap, int* n);
 
 /* Batch executor for serving (continuous batching on one GPU): up to

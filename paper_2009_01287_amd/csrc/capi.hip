@@ -167,7 +167,8 @@ constexpr int64_t kHistCap = 2048;   // Lanczos coefficients kept per solve
 
 struct LevelDev {
   DevCSR A, P, R;
-  DevCSR M, AP;          // fused cycle: R (I - A D) and A P
+  DevCSR M, U;           // fused cycle: R (I - A D) and [2D - D A D, P - D A P]
+  CSR hM, hU;            // host copies of M and U (row binning by the tuner)
   int fused = 0;
   int has_fused = 0;
   DevBuf l1inv;          // T
@@ -399,9 +400,12 @@ static void spd_inverse(std::vector<double>& A, int n) {
 
 constexpr int64_t kFuseNnz = 4 << 20;   // levels the fused cycle is tried on (nonzeros of A)
 
-// host matrices of a fused V-cycle level: M = R (I - A D) with D = diag(1/l1),
-// and A P
-static void fused_mats(const AMGLevel& L, CSR& M, CSR& AP) {
+// host matrices of a fused V-cycle level, with D = diag(1/l1):
+//   M = R (I - A D)                       (down-leg: b_c = M b)
+//   U = [2D - D A D | P - D A P]          (up-leg: x = U [b; x_c])
+// The up-leg is the V(1,1) post-steps t = D b + P x_c, x = t + D (b - A t)
+// written as one product over the concatenated vector [b; x_c].
+static void fused_mats(const AMGLevel& L, CSR& M, CSR& U) {
   CSR RA = csr_matmul(L.R, L.A);
   std::vector<int64_t> r;
   std::vector<int32_t> cc;
@@ -419,22 +423,47 @@ static void fused_mats(const AMGLevel& L, CSR& M, CSR& AP) {
     }
   }
   M = csr_from_triplets(L.R.nrows, L.R.ncols, r, cc, v);
-  AP = csr_matmul(L.A, L.P);
+  const CSR AP = csr_matmul(L.A, L.P);
+  const int64_t n = L.A.nrows;
+  U = CSR();
+  U.nrows = n;
+  U.ncols = n + L.P.ncols;
+  U.ptr.assign(n + 1, 0);
+  std::vector<std::pair<int32_t, double>> row;
+  for (int64_t i = 0; i < n; ++i) {
+    const double di = 1.0 / L.l1[i];
+    row.clear();
+    row.push_back({(int32_t)i, 2.0 * di});
+    for (int64_t q = L.A.ptr[i]; q < L.A.ptr[i + 1]; ++q) {
+      const int32_t j = L.A.idx[q];
+      row.push_back({j, -di * L.A.val[q] / L.l1[j]});
+    }
+    for (int64_t q = L.P.ptr[i]; q < L.P.ptr[i + 1]; ++q) row.push_back({(int32_t)(n + L.P.idx[q]), L.P.val[q]});
+    for (int64_t q = AP.ptr[i]; q < AP.ptr[i + 1]; ++q) row.push_back({(int32_t)(n + AP.idx[q]), -di * AP.val[q]});
+    std::sort(row.begin(), row.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
+    for (size_t t = 0; t < row.size(); ++t) {
+      if (t > 0 && row[t].first == row[t - 1].first) { U.val.back() += row[t].second; continue; }
+      U.idx.push_back(row[t].first);
+      U.val.push_back(row[t].second);
+    }
+    U.ptr[i + 1] = (int64_t)U.idx.size();
+  }
 }
 
 template <typename T>
 static void set_fused(hpdg_operator* op, size_t l, bool on) {
   LevelDev& D = op->lv[l];
   if (on && !D.has_fused) {
-    CSR M, AP;
-    fused_mats(op->host.amg.lv[l], M, AP);
-    upload_csr<T>(M, D.M);
-    upload_csr<T>(AP, D.AP);
+    fused_mats(op->host.amg.lv[l], D.hM, D.hU);
+    upload_csr<T>(D.hM, D.M);
+    upload_csr<T>(D.hU, D.U);
     D.has_fused = 1;
   }
   if (!on && D.has_fused) {
     D.M = DevCSR();
-    D.AP = DevCSR();
+    D.U = DevCSR();
+    D.hM = CSR();
+    D.hU = CSR();
     D.has_fused = 0;
   }
   D.fused = on ? 1 : 0;
@@ -924,7 +953,8 @@ static void spmv_launch(const DevCSR& A, const T* x, const T* b, const T* d, T* 
   int nshort = A.nrows - A.nlong;
   int nlb = (A.nlong + 3) / 4;
   unsigned grid = (unsigned)(nlb + nblk((int64_t)nshort * LPR));
-  hipLaunchKernelGGL((k_spmv<T, MODE, LPR>), dim3(grid), dim3(256), 0, s, A.nlong, nlb, nshort,
+  // MODE 5: the first nrows columns read x, the others b
+  hipLaunchKernelGGL((k_spmv<T, MODE, LPR>), dim3(grid), dim3(256), 0, s, A.nlong, nlb, nshort, A.nrows,
                      A.rows.as<int32_t>(), A.ptr.as<int32_t>(), A.idx.as<int32_t>(), A.val.as<T>(), x, b, d, xo, y);
 }
 
@@ -939,6 +969,8 @@ static void spmv(const DevCSR& A, int nrhs, const T* x, const T* b, const T* d, 
       case 8: spmv_launch<T, MODE, 8>(A, x, b, d, xo, y, s); break;
       default: spmv_launch<T, MODE, 16>(A, x, b, d, xo, y, s); break;
     }
+  } else if constexpr (MODE == 5) {
+    throw Error(HPDG_E_UNSUPPORTED, "two-vector product with several right-hand sides");
   } else {
     int64_t nt = (int64_t)A.nrows * nrhs;
     hipLaunchKernelGGL((k_spmm<T, MODE>), dim3(nblk(nt)), dim3(256), 0, s, A.nrows, nrhs, A.ptr.as<int32_t>(),
@@ -949,15 +981,6 @@ static void spmv(const DevCSR& A, int nrhs, const T* x, const T* b, const T* d, 
 template <typename T>
 static void vcycle(hpdg_operator* op, size_t l, int nrhs, hipStream_t s);
 
-template <typename T, int LPR>
-static void upleg_launch(LevelDev& L, LevelDev& C, hipStream_t s) {
-  const int n = L.A.nrows;
-  hipLaunchKernelGGL((k_upleg<T, LPR>), dim3(nblk((int64_t)n * LPR)), dim3(256), 0, s, n, L.P.ptr.as<int32_t>(),
-                     L.P.idx.as<int32_t>(), L.P.val.as<T>(), L.A.ptr.as<int32_t>(), L.A.idx.as<int32_t>(),
-                     L.A.val.as<T>(), L.AP.ptr.as<int32_t>(), L.AP.idx.as<int32_t>(), L.AP.val.as<T>(),
-                     L.l1inv.as<T>(), L.b.as<T>(), C.x.as<T>(), L.x.as<T>());
-}
-
 // fused level (one RHS): two launches instead of four, same V(1,1) steps
 template <typename T>
 static void vcycle_fused(hpdg_operator* op, size_t l, hipStream_t s) {
@@ -965,12 +988,7 @@ static void vcycle_fused(hpdg_operator* op, size_t l, hipStream_t s) {
   LevelDev& C = op->lv[l + 1];
   spmv<T, 0>(L.M, 1, L.b.as<T>(), nullptr, nullptr, nullptr, C.b.as<T>(), s);
   vcycle<T>(op, l + 1, 1, s);
-  switch (L.A.lpr) {
-    case 1: case 2: upleg_launch<T, 2>(L, C, s); break;
-    case 4: upleg_launch<T, 4>(L, C, s); break;
-    case 8: upleg_launch<T, 8>(L, C, s); break;
-    default: upleg_launch<T, 16>(L, C, s); break;
-  }
+  spmv<T, 5>(L.U, 1, L.b.as<T>(), C.x.as<T>(), nullptr, nullptr, L.x.as<T>(), s);
 }
 
 template <typename T>
@@ -1187,13 +1205,20 @@ static int tune_all(hpdg_operator* op, hipStream_t s, int64_t* report, int cap) 
     set_fused<T>(op, l, false);
     const double t0 = time_cycle();
     set_fused<T>(op, l, true);
+    // row binning of the two fused products, then the fused cycle
+    LevelDev& F = op->lv[l];
+    LevelDev& FC = op->lv[l + 1];
+    int64_t um[6], uu[6];
+    tune_csr<T>(F.hM, F.M, F.b.as<T>(), FC.b.as<T>(), s, um);
+    tune_csr<T>(F.hU, F.U, F.b.as<T>(), F.x.as<T>(), s, uu,
+                [&]() { spmv<T, 5>(F.U, 1, F.b.as<T>(), FC.x.as<T>(), nullptr, nullptr, F.x.as<T>(), s); });
     const double t1 = time_cycle();
     const bool keep = t1 < kTuneMargin * t0;
     if (!keep) set_fused<T>(op, l, false);
     int64_t* r = slot(5, l);
     r[0] = op->lv[l].A.nrows;
     r[1] = op->lv[l].A.nnz;
-    r[2] = 0;
+    r[2] = keep ? uu[3] : 0;
     r[3] = keep ? 1 : 0;
     r[4] = (int64_t)t0;
     r[5] = (int64_t)(keep ? t1 : t0);

@@ -1162,7 +1162,8 @@ __global__ void k_sub(int64_t n, const double* __restrict__ a, const double* __r
 // ------------------------------------------------------------------- CSR
 // modes: 0 y = A x; 1 y = b - A x; 2 y = b + A x;
 //        3 (pre-smoother from zero) xo = d.b, y = b - A (d.b);
-//        4 (post-smoother) y = x + d.(b - A x)
+//        4 (post-smoother) y = x + d.(b - A x);
+//        5 y = A [x; b] (columns below nsplit read x, the others b)
 // Rows are binned at setup: the first nlong_blk blocks take the long rows
 // (one wavefront per row, 4 per block), the others the short rows (LPR
 // lanes per row). rows[] lists long rows first, then short rows.
@@ -1175,13 +1176,28 @@ __device__ inline void spmv_row_out(int row, T acc, const T* __restrict__ x, con
   else if (MODE == 3) {
     xo[row] = d[row] * x[row];
     y[row] = x[row] - acc;
-  } else {
+  } else if (MODE == 4) {
     y[row] = x[row] + d[row] * (b[row] - acc);
+  } else {
+    y[row] = acc;
   }
 }
 
+// operand of one nonzero: MODE 3 scales by d; MODE 5 reads from two vectors,
+// columns below nsplit from x and the others from b (shifted by nsplit)
+template <typename T, int MODE>
+__device__ inline T spmv_src(int j, int nsplit, const T* __restrict__ x, const T* __restrict__ b,
+                             const T* __restrict__ d) {
+  if (MODE == 3) return d[j] * x[j];
+  if (MODE == 5) {
+    const T* src = j < nsplit ? x + j : b + (j - nsplit);
+    return *src;
+  }
+  return x[j];
+}
+
 template <typename T, int MODE, int LPR>
-__global__ __launch_bounds__(256) void k_spmv(int nlong, int nlong_blk, int nshort,
+__global__ __launch_bounds__(256) void k_spmv(int nlong, int nlong_blk, int nshort, int nsplit,
                                               const int32_t* __restrict__ rows,
                                               const int32_t* __restrict__ ptr,
                                               const int32_t* __restrict__ idx, const T* __restrict__ val,
@@ -1194,8 +1210,7 @@ __global__ __launch_bounds__(256) void k_spmv(int nlong, int nlong_blk, int nsho
     const int row = rows[w];
     T acc = 0;
     for (int q = ptr[row] + lane; q < ptr[row + 1]; q += 64) {
-      int j = idx[q];
-      acc += val[q] * (MODE == 3 ? d[j] * x[j] : x[j]);
+      acc += val[q] * spmv_src<T, MODE>(idx[q], nsplit, x, b, d);
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
@@ -1209,8 +1224,7 @@ __global__ __launch_bounds__(256) void k_spmv(int nlong, int nlong_blk, int nsho
   const int row = rows[nlong + r];
   T acc = 0;
   for (int q = ptr[row] + sub; q < ptr[row + 1]; q += LPR) {
-    int j = idx[q];
-    acc += val[q] * (MODE == 3 ? d[j] * x[j] : x[j]);
+    acc += val[q] * spmv_src<T, MODE>(idx[q], nsplit, x, b, d);
   }
 #pragma unroll
   for (int o = LPR / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, LPR);
@@ -1440,41 +1454,6 @@ __global__ __launch_bounds__(256) void k_dense_gemv1(int n, const T* __restrict_
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
   if (lane == 0) x[row] = acc;
-}
-
-// Up-leg of a fused V(1,1) level (one RHS), with x = D b from the pre-smoother
-// and x_c from the coarser level: t = D b + P x_c and the post-smoother
-// t + D (b - A t), where A t = A D b + (A P) x_c, in one pass over the rows
-// of P, A and A P (LPR lanes per row). The down-leg b_c = R (I - A D) b is a
-// plain product with the precomputed matrix.
-template <typename T, int LPR>
-__global__ __launch_bounds__(256) void k_upleg(int n, const int32_t* __restrict__ Pp, const int32_t* __restrict__ Pi,
-                                               const T* __restrict__ Pv, const int32_t* __restrict__ Ap,
-                                               const int32_t* __restrict__ Ai, const T* __restrict__ Av,
-                                               const int32_t* __restrict__ Qp, const int32_t* __restrict__ Qi,
-                                               const T* __restrict__ Qv, const T* __restrict__ d,
-                                               const T* __restrict__ b, const T* __restrict__ xc,
-                                               T* __restrict__ x) {
-  const int gt = blockIdx.x * 256 + threadIdx.x;
-  const int row = gt / LPR, sub = gt % LPR;
-  if (row >= n) return;   // whole lane groups exit together
-  T pe = 0, s = 0;
-  for (int q = Pp[row] + sub; q < Pp[row + 1]; q += LPR) pe += Pv[q] * xc[Pi[q]];
-  for (int q = Ap[row] + sub; q < Ap[row + 1]; q += LPR) {
-    const int j = Ai[q];
-    s += Av[q] * (d[j] * b[j]);
-  }
-  for (int q = Qp[row] + sub; q < Qp[row + 1]; q += LPR) s += Qv[q] * xc[Qi[q]];
-#pragma unroll
-  for (int o = LPR / 2; o > 0; o >>= 1) {
-    pe += __shfl_xor(pe, o, LPR);
-    s += __shfl_xor(s, o, LPR);
-  }
-  if (sub == 0) {
-    const T db = d[row] * b[row];
-    const T t = db + pe;
-    x[row] = t + d[row] * (b[row] - s);
-  }
 }
 
 template <typename T>

@@ -417,8 +417,9 @@ def test_random2d_64rhs_full_size():
 @pytest.mark.parametrize("name", ["rand2", "rand3"])
 @pytest.mark.parametrize("fp32", [False, True])
 def test_fused_vcycle_levels(monkeypatch, name, fp32):
-    """Every AMG level in the fused form (two launches with R (I - A D) and
-    A P): B against the oracle's V(1,1) cycle and the solve."""
+    """Every AMG level in the fused form (two launches: b_c = R (I - A D) b
+    down, x = [2D - D A D | P - D A P] [b; x_c] up): B against the oracle's
+    V(1,1) cycle and the solve."""
     monkeypatch.setenv("HPDG_FUSE_LEVELS", "1")
     md = MESHES[name]()
     m = O.Mesh(md)
