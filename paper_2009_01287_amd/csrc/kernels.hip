@@ -450,14 +450,47 @@ __global__ __launch_bounds__(64 * EPB) void k_elem2d(int ne, int nrhs, int rg, i
   const double* gMK = tab + TL.mk + p * 2 * 81;          // 1D mass and stiffness of degree p
   const double* sM = sMKw[wv][0];
   const double* sK = sMKw[wv][1];
-  for (int i = lane; i < nn; i += 64) {
-    sMKw[wv][0][i] = gMK[i];
-    sMKw[wv][1][i] = gMK[81 + i];
+  {
+    // nn <= 81: at most two entries per lane, loads issued together
+    const int i0 = min(lane, nn - 1), i1 = min(lane + 64, nn - 1);
+    const double m0 = gMK[i0], k0 = gMK[81 + i0], m1 = gMK[i1], k1 = gMK[81 + i1];
+    if (lane < nn) {
+      sMKw[wv][0][lane] = m0;
+      sMKw[wv][1][lane] = k0;
+    }
+    if (lane + 64 < nn) {
+      sMKw[wv][0][lane + 64] = m1;
+      sMKw[wv][1][lane + 64] = k1;
+    }
   }
   // l_i'(0), l_i'(1) of degree p
   if (lane < 18) sDsw[wv][lane] = tab[TL.dside + p * 2 * 9 + lane];
+  auto fetch_records = [&](int c0, int nF) {
+    constexpr int W = (int)(sizeof(FaceRec) / 8);
+    constexpr int NT = (kFChunk * W + 63) / 64;   // words per lane
+    const unsigned long long* src = reinterpret_cast<const unsigned long long*>(recs + c0);
+    unsigned long long* dst = reinterpret_cast<unsigned long long*>(sR);
+    const int nw = nF * W;
+    if (nw <= 0) return;
+    unsigned long long w[NT];
+#pragma unroll
+    for (int u = 0; u < NT; ++u) w[u] = src[min(lane + 64 * u, nw - 1)];
+#pragma unroll
+    for (int u = 0; u < NT; ++u)
+      if (lane + 64 * u < nw) dst[lane + 64 * u] = w[u];
+  };
+  // an element whose face records fit one pass (nearly all) fetches them
+  // here, beside its other loads, instead of after the volume; the pass never
+  // rewrites them, so they serve every right-hand side of the item
+  const bool onepass = sp[4] - sp[0] <= kFChunk;
+  if (onepass) fetch_records(sp[0], sp[4] - sp[0]);
   for (int rhs = r0; rhs < r1; ++rhs) {
-  for (int i = lane; i < nn; i += 64) sX[i] = x[(base + i) * nrhs + rhs];
+  {
+    const double x0 = x[(base + min(lane, nn - 1)) * nrhs + rhs];
+    const double x1 = x[(base + min(lane + 64, nn - 1)) * nrhs + rhs];
+    if (lane < nn) sX[lane] = x0;
+    if (lane + 64 < nn) sX[lane + 64] = x1;
+  }
   wave_sync();
   // volume, phase 1 (dimension 0)
   for (int i = lane; i < nn; i += 64) {
@@ -497,14 +530,11 @@ __global__ __launch_bounds__(64 * EPB) void k_elem2d(int ne, int nrhs, int rg, i
   const int sb = grp ? sp[sidx] : 0, se = grp ? sp[sidx + 1] : 0;
   for (int c0 = sp[0]; c0 < sp[4]; c0 += kFChunk) {
     const int nF = min(kFChunk, sp[4] - c0);
-    // first fetch: the records of this pass
-    {
-      constexpr int W = (int)(sizeof(FaceRec) / 8);
-      const unsigned long long* src = reinterpret_cast<const unsigned long long*>(recs + c0);
-      unsigned long long* dst = reinterpret_cast<unsigned long long*>(sR);
-      for (int t = lane; t < nF * W; t += 64) dst[t] = src[t];
+    // first fetch: the records of this pass (already there for one pass)
+    if (!onepass) {
+      fetch_records(c0, nF);
+      wave_sync();
     }
-    wave_sync();
     // second fetch: neighbour trace Tn and k_n/h_n-scaled normal derivative Dn per (face, node)
     for (int t = lane; t < nF * 9; t += 64) {
       const int f = t / 9, jj = t - 9 * f;
@@ -515,6 +545,7 @@ __global__ __launch_bounds__(64 * EPB) void k_elem2d(int ne, int nrhs, int rg, i
         const double* Dso = tab + TL.dside + (po * 2 + so) * 9;
         const double* xn = x + (int64_t)sR[f].nbase * nrhs + rhs;
         double dv = 0.0;
+#pragma unroll 4
         for (int a = 0; a < no; ++a) dv += Dso[a] * xn[(int64_t)(a * som + jj * sot) * nrhs];
         sTn[f][jj] = xn[(int64_t)((so ? po : 0) * som + jj * sot) * nrhs];
         sDn[f][jj] = sR[f].kho * dv;
@@ -541,10 +572,13 @@ __global__ __launch_bounds__(64 * EPB) void k_elem2d(int ne, int nrhs, int rg, i
       double g1 = 0.0, g2 = 0.0, v = 0.0;
       if (have && jq < n) {
         double dsum = 0.0;
+        // (unrolled so that several face-matrix loads are in flight at once)
+#pragma unroll 4
         for (int a = 0; a < n; ++a) {
           v += Aoo[jq * n + a] * sTo[fside][a];
           dsum += k * Aoo[jq * n + a] * sDo[fside][a];
         }
+#pragma unroll 4
         for (int a = 0; a < no; ++a) {
           v -= Aon[jq * no + a] * sTn[fr][a];
           dsum += Aon[jq * no + a] * sDn[fr][a];
@@ -736,6 +770,25 @@ __device__ inline void cg_epilogue(int mode, int c, double v, CGScal S) {
 }
 
 
+// sum of p[b * m + c] for b = b0, b0 + bs, ... < n, added in that order; the
+// loads are issued four at a time (same result as the plain loop)
+__device__ inline double ordered_sum(const double* __restrict__ p, int b0, int bs, int n, int m, int c) {
+  double s = 0.0;
+  int b = b0;
+  for (; b + 3 * bs < n; b += 4 * bs) {
+    const double v0 = p[(int64_t)b * m + c];
+    const double v1 = p[(int64_t)(b + bs) * m + c];
+    const double v2 = p[(int64_t)(b + 2 * bs) * m + c];
+    const double v3 = p[(int64_t)(b + 3 * bs) * m + c];
+    s += v0;
+    s += v1;
+    s += v2;
+    s += v3;
+  }
+  for (; b < n; b += bs) s += p[(int64_t)b * m + c];
+  return s;
+}
+
 // final stage of a dot product (partials from k_dot_partial) with the scalar
 // epilogue; one block of 256 threads, fixed summation order
 __global__ __launch_bounds__(256) void k_dot_final_ep(int nblocks, int nrhs, const double* __restrict__ part,
@@ -743,8 +796,7 @@ __global__ __launch_bounds__(256) void k_dot_final_ep(int nblocks, int nrhs, con
   __shared__ double sm[256];
   const int t = threadIdx.x;
   const int c = t % nrhs, g = t / nrhs, ng = 256 / nrhs;
-  double s = 0.0;
-  for (int b = g; b < nblocks; b += ng) s += part[b * nrhs + c];
+  double s = ordered_sum(part, g, ng, nblocks, nrhs, c);
   sm[t] = s;
   __syncthreads();
   for (int w = 128; w >= nrhs; w >>= 1) {
@@ -763,8 +815,7 @@ __global__ __launch_bounds__(256) void k_dot_final2_ep(int na, const double* __r
   for (int pass = 0; pass < 2; ++pass) {
     const int n = pass ? nb : na;
     const double* part = pass ? pb : pa;
-    double s = 0.0;
-    for (int b = t; b < n; b += 256) s += part[b];
+    double s = ordered_sum(part, t, 256, n, 1, 0);
     sm[t] = s;
     __syncthreads();
     for (int w = 128; w >= 1; w >>= 1) {
@@ -1148,8 +1199,10 @@ __global__ void k_cg_dir2(int64_t n, int nrhs, const double* __restrict__ beta, 
                           const double* __restrict__ z, double* __restrict__ p) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  int c = (int)(i % nrhs);
-  if (act[c]) p[i] = z[i] + beta[c] * p[i];
+  const int c = (int)(i % nrhs);
+  // all loads issued together; the store depends on the flag only
+  const double zi = z[i], pi = p[i], bc = beta[c];
+  if (act[c]) p[i] = zi + bc * pi;
 }
 
 
@@ -1209,6 +1262,7 @@ __global__ __launch_bounds__(256) void k_spmv(int nlong, int nlong_blk, int nsho
     if (w >= nlong) return;
     const int row = rows[w];
     T acc = 0;
+#pragma unroll 4
     for (int q = ptr[row] + lane; q < ptr[row + 1]; q += 64) {
       acc += val[q] * spmv_src<T, MODE>(idx[q], nsplit, x, b, d);
     }
@@ -1223,6 +1277,7 @@ __global__ __launch_bounds__(256) void k_spmv(int nlong, int nlong_blk, int nsho
   if (r >= nshort) return;
   const int row = rows[nlong + r];
   T acc = 0;
+#pragma unroll 4
   for (int q = ptr[row] + sub; q < ptr[row + 1]; q += LPR) {
     acc += val[q] * spmv_src<T, MODE>(idx[q], nsplit, x, b, d);
   }
@@ -1321,6 +1376,7 @@ __global__ __launch_bounds__(256) void k_front(int64_t ndof, int nb_diag, const 
     const int m = (int)(bptr[bk + 1] - s0);
     const T* row = binv + boff[bk] + (int64_t)i * m;
     T acc = 0;
+#pragma unroll 4
     for (int j = sub; j < m; j += LPRB) acc += row[j] * r[bdof[s0 + j]];
 #pragma unroll
     for (int o = LPRB / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, LPRB);
@@ -1335,6 +1391,7 @@ __global__ __launch_bounds__(256) void k_front(int64_t ndof, int nb_diag, const 
     if (w >= nlong) return;
     const int row = rows[w];
     T acc = 0;
+#pragma unroll 4
     for (int q = ptr[row] + lane; q < ptr[row + 1]; q += 64) acc += val[q] * r[idx[q]];
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
@@ -1348,6 +1405,7 @@ __global__ __launch_bounds__(256) void k_front(int64_t ndof, int nb_diag, const 
   if (rr >= nshort) return;
   const int row = rows[nlong + rr];
   T acc = 0;
+#pragma unroll 4
   for (int q = ptr[row] + sub; q < ptr[row + 1]; q += LPRP) acc += val[q] * r[idx[q]];
 #pragma unroll
   for (int o = LPRP / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, LPRP);
@@ -1430,8 +1488,7 @@ __global__ __launch_bounds__(256) void k_dot_final_rhs(int nblocks, int nrhs, co
   __shared__ double sm[256];
   const int c = blockIdx.x;
   const int t = threadIdx.x;
-  double s = 0.0;
-  for (int bb = t; bb < nblocks; bb += 256) s += part[(int64_t)bb * nrhs + c];
+  double s = ordered_sum(part, t, 256, nblocks, nrhs, c);
   sm[t] = s;
   __syncthreads();
   for (int w = 128; w >= 1; w >>= 1) {
