@@ -596,6 +596,7 @@ __global__ __launch_bounds__(64 * EPB) void k_elem2d(int ne, int nrhs, int rg, i
         if (have && jq < n) {
           const double* Mi = tab + TL.minv + p * 81;
           double w = 0.0;
+          #pragma unroll 4
           for (int a = 0; a < n; ++a) w += Mi[jq * n + a] * sVg[gq][a];
           sWg[gq][jq] = w;
         }
@@ -605,6 +606,7 @@ __global__ __launch_bounds__(64 * EPB) void k_elem2d(int ne, int nrhs, int rg, i
           const int sk = fsd ? p : 0;
           const double so = Mi[sk * n + sk] / (h * h);
           double acc = 0.0;
+          #pragma unroll 4
           for (int a = 0; a < n; ++a) acc += Aoo[jq * n + a] * sWg[gq][a];
           g1 += L2 * so * acc;
         }
@@ -612,7 +614,9 @@ __global__ __launch_bounds__(64 * EPB) void k_elem2d(int ne, int nrhs, int rg, i
         wave_sync();
         if (inner && jq < no) {
           double vn = 0.0;
+          #pragma unroll 4
           for (int a = 0; a < n; ++a) vn += Aon[a * no + jq] * sTo[fside][a];
+          #pragma unroll 4
           for (int a = 0; a < no; ++a) vn -= Ann[jq * no + a] * sTn[fr][a];
           sVg[gq][jq] = vn;
         }
@@ -620,6 +624,7 @@ __global__ __launch_bounds__(64 * EPB) void k_elem2d(int ne, int nrhs, int rg, i
         if (inner && jq < no) {
           const double* Mi = tab + TL.minv + po * 81;
           double w = 0.0;
+          #pragma unroll 4
           for (int a = 0; a < no; ++a) w += Mi[jq * no + a] * sVg[gq][a];
           sWg[gq][jq] = w;
         }
@@ -630,6 +635,7 @@ __global__ __launch_bounds__(64 * EPB) void k_elem2d(int ne, int nrhs, int rg, i
           const double hn = sR[fr].hn;
           const double sn = Mi[sk * no + sk] / (hn * hn);
           double acc = 0.0;
+          #pragma unroll 4
           for (int a = 0; a < no; ++a) acc += Aon[jq * no + a] * sWg[gq][a];
           g1 += L2 * sn * acc;
         }
@@ -907,6 +913,7 @@ __global__ __launch_bounds__(256) void k_elem3d(int ne, int nrhs, int form, cons
   for (int r = tid; r < n3; r += 256) {
     const int i0 = r % n, i12 = r - i0;
     double a0 = 0.0, b0 = 0.0;
+    #pragma unroll 4
     for (int a = 0; a < n; ++a) {
       const double xa = sX[i12 + a];
       a0 += xa * Mt[a * n + i0];
@@ -925,6 +932,7 @@ __global__ __launch_bounds__(256) void k_elem3d(int ne, int nrhs, int form, cons
     const int o = j0 * st[t0] + j1 * st[t1];
     const double* Ds = tab + TL.dside + (p * 2 + s) * 9;
     double dv = 0.0;
+    #pragma unroll 4
     for (int a = 0; a < n; ++a) dv += Ds[a] * sX[o + a * st[m]];
     sTo[side][q] = sX[o + (s ? p : 0) * st[m]];
     sDo[side][q] = dv / h;
@@ -936,6 +944,7 @@ __global__ __launch_bounds__(256) void k_elem3d(int ne, int nrhs, int form, cons
   for (int r = tid; r < n3; r += 256) {
     const int i0 = r % n, i1 = (r / n) % n, i2 = r / n2;
     double aa = 0.0, ab = 0.0, ba = 0.0;
+    #pragma unroll 4
     for (int b = 0; b < n; ++b) {
       const double av = sA[i0 + n * b + n2 * i2], bv = sB[i0 + n * b + n2 * i2];
       const double mb = Mt[b * n + i1], kb = Kt[b * n + i1];
@@ -954,6 +963,7 @@ __global__ __launch_bounds__(256) void k_elem3d(int ne, int nrhs, int form, cons
     for (int r = tid; r < n3; r += 256, ++c) {
       const int i01 = r % n2, i2 = r / n2;
       double acc = 0.0;
+      #pragma unroll 4
       for (int cc = 0; cc < n; ++cc) acc += Kt[cc * n + i2] * sC[i01 + n2 * cc] + Mt[cc * n + i2] * sD[i01 + n2 * cc];
       yv[c] = k * h * acc;
     }
@@ -995,6 +1005,7 @@ __global__ __launch_bounds__(256) void k_elem3d(int ne, int nrhs, int form, cons
       const double* Dso = tab + TL.dside + (po * 2 + so) * 9;
       const double* xn = x + (int64_t)sR[f].nbase * nrhs + rhs;
       double dv = 0.0;
+      #pragma unroll 4
       for (int a = 0; a < no; ++a) dv += Dso[a] * xn[(int64_t)(o + a * st[mm]) * nrhs];
       sTn[f * 81 + q] = xn[(int64_t)(o + (so ? po : 0) * st[mm]) * nrhs];
       sDn[f * 81 + q] = sR[f].kho * dv;
@@ -1027,6 +1038,7 @@ __global__ __launch_bounds__(256) void k_elem3d(int ne, int nrhs, int form, cons
           const int j0 = q % n, a1 = q / n;
           const double* in = which == 0 ? sTo[side] : sDo[side];
           double sacc = 0.0;
+          #pragma unroll 4
           for (int a0 = 0; a0 < n; ++a0) sacc += A0oo[j0 * n + a0] * in[a0 + n * a1];
           (which == 0 ? U0 : U1)[q] = sacc;
         } else if (which < 4) {
@@ -1034,18 +1046,21 @@ __global__ __launch_bounds__(256) void k_elem3d(int ne, int nrhs, int form, cons
           const int j0 = q % n, a1 = q / n;
           const double* in = which == 2 ? Tn : Dn;
           double sacc = 0.0;
+          #pragma unroll 4
           for (int a0 = 0; a0 < no; ++a0) sacc += A0on[j0 * no + a0] * in[a0 + no * a1];
           (which == 2 ? U2 : U3)[q] = sacc;
         } else if (which == 4) {
           if (!br2i || q >= no * n) continue;
           const int a0 = q % no, a1 = q / no;      // a1 over own slot-1 nodes
           double sacc = 0.0;
+          #pragma unroll 4
           for (int j0 = 0; j0 < n; ++j0) sacc += A0on[j0 * no + a0] * sTo[side][j0 + n * a1];
           Y0[q] = sacc;
         } else {
           if (!br2i || q >= no * no) continue;
           const int a0 = q % no, a1 = q / no;
           double sacc = 0.0;
+          #pragma unroll 4
           for (int b0 = 0; b0 < no; ++b0) sacc += A0nn[a0 * no + b0] * Tn[b0 + no * a1];
           Y1[q] = sacc;
         }
@@ -1059,12 +1074,14 @@ __global__ __launch_bounds__(256) void k_elem3d(int ne, int nrhs, int form, cons
           if (q >= n2) continue;
           const int j0 = q % n, j1 = q / n;
           double v = 0.0, ds = 0.0;
+          #pragma unroll 4
           for (int a1 = 0; a1 < n; ++a1) {
             const double w = A1oo[j1 * n + a1];
             v += w * U0[j0 + n * a1];
             ds += k * w * U1[j0 + n * a1];
           }
           if (inner)
+            #pragma unroll 4
             for (int a1 = 0; a1 < no; ++a1) {
               const double w = A1on[j1 * no + a1];
               v -= w * U2[j0 + n * a1];
@@ -1080,7 +1097,9 @@ __global__ __launch_bounds__(256) void k_elem3d(int ne, int nrhs, int form, cons
           if (!br2i || q >= no * no) continue;
           const int a0 = q % no, b1 = q / no;
           double vn = 0.0;
+          #pragma unroll 4
           for (int a1 = 0; a1 < n; ++a1) vn += A1on[a1 * no + b1] * Y0[a0 + no * a1];
+          #pragma unroll 4
           for (int c1 = 0; c1 < no; ++c1) vn -= A1nn[b1 * no + c1] * Y1[a0 + no * c1];
           Vn[q] = vn;
         }
@@ -1111,12 +1130,14 @@ __global__ __launch_bounds__(256) void k_elem3d(int ne, int nrhs, int form, cons
             if (q >= n2) continue;
             const int j0 = q % n, a1 = q / n;
             double sacc = 0.0;
+            #pragma unroll 4
             for (int a0 = 0; a0 < n; ++a0) sacc += L0o[j0 * n + a0] * Vv[a0 + n * a1];
             P0[q] = sacc;
           } else {
             if (!inner || q >= n * no) continue;
             const int j0 = q % n, a1 = q / n;
             double sacc = 0.0;
+            #pragma unroll 4
             for (int a0 = 0; a0 < no; ++a0) sacc += L0n[j0 * no + a0] * Vn[a0 + no * a1];
             Q0[q] = sacc;
           }
@@ -1126,8 +1147,10 @@ __global__ __launch_bounds__(256) void k_elem3d(int ne, int nrhs, int form, cons
         for (int q = tid; q < n2; q += 256) {
           const int j0 = q % n, j1 = q / n;
           double so_acc = 0.0, sn_acc = 0.0;
+          #pragma unroll 4
           for (int a1 = 0; a1 < n; ++a1) so_acc += L1o[j1 * n + a1] * P0[j0 + n * a1];
           if (inner)
+            #pragma unroll 4
             for (int a1 = 0; a1 < no; ++a1) sn_acc += L1n[j1 * no + a1] * Q0[j0 + n * a1];
           sG1[side][q] += L2 * (so * so_acc + sn * sn_acc);
         }
@@ -1297,6 +1320,7 @@ __global__ __launch_bounds__(256) void k_spmm(int nrows, int nrhs, const int32_t
   const int c = (int)(t - row * nrhs);
   if (row >= nrows) return;
   T acc = 0;
+#pragma unroll 4
   for (int q = ptr[row]; q < ptr[row + 1]; ++q) {
     int64_t j = idx[q];
     T xv = MODE == 3 ? d[j] * x[j * nrhs + c] : x[j * nrhs + c];
@@ -1328,6 +1352,7 @@ __global__ __launch_bounds__(256) void k_prolong_out(int nrows, int nrhs, const 
   double rz = 0.0;
   if (row < nrows) {
     T acc = 0;
+#pragma unroll 4
     for (int q = ptr[row]; q < ptr[row + 1]; ++q) acc += val[q] * e[(int64_t)idx[q] * nrhs + c];
     const double zv = (double)(zb[row * nrhs + c] + acc);
     z[row * nrhs + c] = zv;
@@ -1430,6 +1455,7 @@ __global__ __launch_bounds__(256) void k_block_gemv(int64_t nrows, int nrhs, con
   const int m = (int)(bptr[b + 1] - s0);
   const T* row = binv + boff[b] + (int64_t)i * m;
   T acc = 0;
+#pragma unroll 4
   for (int j = 0; j < m; ++j) acc += row[j] * r[(int64_t)bdof[s0 + j] * nrhs + c];
   z[(int64_t)bdof[s0 + i] * nrhs + c] = acc;
 }
