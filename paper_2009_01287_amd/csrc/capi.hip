@@ -192,6 +192,7 @@ struct hpdg_operator {
   DevBuf blk_rowb, blk_rowl, blk_ptr, blk_off, blk_dof, blk_inv;
   int64_t blk_rows = 0, nblocks = 0;
   int max_blk = 0;           // largest V_e block
+  int lprb = 16;             // lanes per V_e block row in the B front (one RHS)
   DevCSR P, PT;
   std::vector<LevelDev> lv;
   DevBuf coarse;
@@ -1176,6 +1177,39 @@ static int tune_all(hpdg_operator* op, hipStream_t s, int64_t* report, int cap) 
   T* zb = op->zT.as<T>();
   tune_csr<T>(H.PT, op->PT, op->rT.as<T>(), op->lv[0].b.as<T>(), s, slot(3, 0),
               [&]() { launch_front<T>(op, op->rT.as<T>(), zb, s); });
+  // then the lanes per V_e block row of the same kernel
+  if (op->blk_rows > 0) {
+    hipEvent_t f0, f1;
+    HIPCHK(hipEventCreate(&f0));
+    HIPCHK(hipEventCreate(&f1));
+    auto time_front = [&]() {
+      for (int w = 0; w < 3; ++w) launch_front<T>(op, op->rT.as<T>(), zb, s);
+      HIPCHK(hipEventRecord(f0, s));
+      for (int w = 0; w < 10; ++w) launch_front<T>(op, op->rT.as<T>(), zb, s);
+      HIPCHK(hipEventRecord(f1, s));
+      HIPCHK(hipEventSynchronize(f1));
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, f0, f1));
+      return (double)ms * 1e6 / 10;
+    };
+    const int def = op->lprb;
+    const double t_def = time_front();
+    double best = t_def * kTuneMargin;
+    int bb = def;
+    for (int lb : {1, 2, 4, 8, 16, 32}) {
+      if (lb == def) continue;
+      op->lprb = lb;
+      const double t = time_front();
+      if (t < best) { best = t; bb = lb; }
+    }
+    if (bb == def) best = t_def;
+    op->lprb = bb;
+    (void)hipEventDestroy(f0);
+    (void)hipEventDestroy(f1);
+    int64_t* r = slot(7, 0);
+    r[0] = op->blk_rows; r[1] = op->nblocks; r[2] = 0; r[3] = bb;
+    r[4] = (int64_t)t_def; r[5] = (int64_t)best;
+  }
   for (size_t l = 0; l < op->lv.size(); ++l) {
     LevelDev& L = op->lv[l];
     tune_csr<T>(H.amg.lv[l].A, L.A, L.b.as<T>(), L.r.as<T>(), s, slot(0, (int)l));
@@ -1262,27 +1296,37 @@ extern "C" hpdg_status hpdg_operator_tune(hpdg_operator* op, void* stream, int64
 template <typename T>
 static void launch_front(hpdg_operator* op, const T* rt, T* zb, hipStream_t s) {
   LevelDev& L0 = op->lv[0];
-    const DevCSR& A = op->PT;
-    int nb_diag = (int)nblk(op->ndof);
-    int nb_blk = (int)nblk(op->blk_rows * 16);
-    int nlb = (A.nlong + 3) / 4;
-    int nshort = A.nrows - A.nlong;
-    auto launch = [&](auto lprp) {
-      constexpr int LP = decltype(lprp)::value;
-      unsigned grid = (unsigned)(nb_diag + nb_blk + nlb + (int)nblk((int64_t)nshort * LP));
-      hipLaunchKernelGGL((k_front<T, 16, LP>), dim3(grid), dim3(256), 0, s, op->ndof, nb_diag, op->dinvJ.as<T>(),
-                         op->blk_rows, nb_blk, op->blk_rowb.as<int32_t>(), op->blk_rowl.as<int32_t>(),
-                         op->blk_ptr.as<int64_t>(), op->blk_off.as<int64_t>(), op->blk_dof.as<int32_t>(),
-                         op->blk_inv.as<T>(), A.nlong, nlb, nshort, A.rows.as<int32_t>(), A.ptr.as<int32_t>(),
-                         A.idx.as<int32_t>(), A.val.as<T>(), rt, zb, L0.b.as<T>());
-    };
+  const DevCSR& A = op->PT;
+  const int nb_diag = (int)nblk(op->ndof);
+  const int nlb = (A.nlong + 3) / 4;
+  const int nshort = A.nrows - A.nlong;
+  auto launch = [&](auto lprb, auto lprp) {
+    constexpr int LB = decltype(lprb)::value, LP = decltype(lprp)::value;
+    const int nb_blk = (int)nblk(op->blk_rows * LB);
+    unsigned grid = (unsigned)(nb_diag + nb_blk + nlb + (int)nblk((int64_t)nshort * LP));
+    hipLaunchKernelGGL((k_front<T, LB, LP>), dim3(grid), dim3(256), 0, s, op->ndof, nb_diag, op->dinvJ.as<T>(),
+                       op->blk_rows, nb_blk, op->blk_rowb.as<int32_t>(), op->blk_rowl.as<int32_t>(),
+                       op->blk_ptr.as<int64_t>(), op->blk_off.as<int64_t>(), op->blk_dof.as<int32_t>(),
+                       op->blk_inv.as<T>(), A.nlong, nlb, nshort, A.rows.as<int32_t>(), A.ptr.as<int32_t>(),
+                       A.idx.as<int32_t>(), A.val.as<T>(), rt, zb, L0.b.as<T>());
+  };
+  auto with_lprp = [&](auto lprb) {
     switch (A.lpr) {
-      case 1: launch(std::integral_constant<int, 1>()); break;
-      case 2: launch(std::integral_constant<int, 2>()); break;
-      case 4: launch(std::integral_constant<int, 4>()); break;
-      case 8: launch(std::integral_constant<int, 8>()); break;
-      default: launch(std::integral_constant<int, 16>()); break;
+      case 1: launch(lprb, std::integral_constant<int, 1>()); break;
+      case 2: launch(lprb, std::integral_constant<int, 2>()); break;
+      case 4: launch(lprb, std::integral_constant<int, 4>()); break;
+      case 8: launch(lprb, std::integral_constant<int, 8>()); break;
+      default: launch(lprb, std::integral_constant<int, 16>()); break;
     }
+  };
+  switch (op->lprb) {
+    case 1: with_lprp(std::integral_constant<int, 1>()); break;
+    case 2: with_lprp(std::integral_constant<int, 2>()); break;
+    case 4: with_lprp(std::integral_constant<int, 4>()); break;
+    case 8: with_lprp(std::integral_constant<int, 8>()); break;
+    case 32: with_lprp(std::integral_constant<int, 32>()); break;
+    default: with_lprp(std::integral_constant<int, 16>()); break;
+  }
 }
 
 // z = B r. With pdot (one RHS) the last kernel also writes per-block shares
