@@ -171,6 +171,8 @@ struct LevelDev {
   CSR hM, hU;            // host copies of M and U (row binning by the tuner)
   int fused = 0;
   int has_fused = 0;
+  DevBuf tail;           // T, n x n: the whole cycle from this level down (see set_tail)
+  int use_tail = 0;
   DevBuf l1inv;          // T
   DevBuf b, x, r, t;     // T, nrows * max_nrhs
 };
@@ -400,6 +402,9 @@ static void spd_inverse(std::vector<double>& A, int n) {
 }
 
 constexpr int64_t kFuseNnz = 4 << 20;   // levels the fused cycle is tried on (nonzeros of A)
+constexpr int kTailMax = 2048;          // largest level the dense tail is tried on (rows)
+template <typename T>
+static void set_tail(hpdg_operator* op, size_t l, bool on);
 
 // host matrices of a fused V-cycle level, with D = diag(1/l1):
 //   M = R (I - A D)                       (down-leg: b_c = M b)
@@ -524,6 +529,10 @@ static void upload_prec(hpdg_operator* op) {
   if (std::getenv("HPDG_FUSE_LEVELS") && !g_dry)
     for (size_t l = 0; l + 1 < op->lv.size(); ++l)
       if (op->lv[l].A.nnz <= kFuseNnz) set_fused<T>(op, l, true);
+  // HPDG_DENSE_TAIL=1: the dense tail on the level above the coarsest
+  if (std::getenv("HPDG_DENSE_TAIL") && !g_dry && op->lv.size() >= 2 && op->ncoarse > 0 &&
+      op->lv[op->lv.size() - 2].A.nrows <= kTailMax)
+    set_tail<T>(op, op->lv.size() - 2, true);
   op->rT.alloc((size_t)op->ndof * op->max_nrhs * sizeof(T));
   op->zT.alloc((size_t)op->ndof * op->max_nrhs * sizeof(T));
 }
@@ -982,6 +991,54 @@ static void spmv(const DevCSR& A, int nrhs, const T* x, const T* b, const T* d, 
 template <typename T>
 static void vcycle(hpdg_operator* op, size_t l, int nrhs, hipStream_t s);
 
+// Dense tail of the V-cycle: on the level just above the coarsest, one
+// V(1,1) cycle is a fixed linear map of that level's right-hand side,
+//   x = G b + W C M b,  with U = [G | W] and M the fused up- and down-leg
+// matrices and C the dense coarsest inverse. For a small level the map is
+// stored as a dense n x n matrix and the cycle is one dense product (same
+// operator, other rounding). The autotuner turns it on where it is faster.
+
+template <typename T>
+static void set_tail(hpdg_operator* op, size_t l, bool on) {
+  LevelDev& D = op->lv[l];
+  if (!on) {
+    D.tail = DevBuf();
+    D.use_tail = 0;
+    return;
+  }
+  if (D.use_tail) return;
+  const AMGLevel& L = op->host.amg.lv[l];
+  const int64_t n = L.A.nrows, nc = op->ncoarse;
+  const std::vector<double>& Cinv = op->host.amg.coarse_inv;
+  CSR M, U;
+  fused_mats(L, M, U);
+  // CM = C M  (nc x n, dense)
+  std::vector<double> CM((size_t)nc * n, 0.0);
+  for (int64_t i = 0; i < nc; ++i)
+    for (int64_t k = 0; k < nc; ++k) {
+      const double c = Cinv[(size_t)i * nc + k];
+      if (c == 0.0) continue;
+      for (int64_t q = M.ptr[k]; q < M.ptr[k + 1]; ++q) CM[(size_t)i * n + M.idx[q]] += c * M.val[q];
+    }
+  // tail = G + W (C M)
+  std::vector<double> Tl((size_t)n * n, 0.0);
+  for (int64_t i = 0; i < n; ++i) {
+    double* ti = &Tl[(size_t)i * n];
+    for (int64_t q = U.ptr[i]; q < U.ptr[i + 1]; ++q) {
+      const int64_t j = U.idx[q];
+      if (j < n) ti[j] += U.val[q];
+      else {
+        const double w = U.val[q];
+        const double* cm = &CM[(size_t)(j - n) * n];
+        for (int64_t t = 0; t < n; ++t) ti[t] += w * cm[t];
+      }
+    }
+  }
+  std::vector<T> tv(Tl.begin(), Tl.end());
+  D.tail.upload(tv);
+  D.use_tail = 1;
+}
+
 // fused level (one RHS): two launches instead of four, same V(1,1) steps
 template <typename T>
 static void vcycle_fused(hpdg_operator* op, size_t l, hipStream_t s) {
@@ -994,6 +1051,17 @@ static void vcycle_fused(hpdg_operator* op, size_t l, hipStream_t s) {
 
 template <typename T>
 static void vcycle(hpdg_operator* op, size_t l, int nrhs, hipStream_t s) {
+  if (op->lv[l].use_tail) {
+    LevelDev& L = op->lv[l];
+    const int n = L.A.nrows;
+    if (nrhs == 1)
+      hipLaunchKernelGGL(k_dense_gemv1<T>, dim3((n + 3) / 4), dim3(256), 0, s, n, L.tail.as<T>(), L.b.as<T>(),
+                         L.x.as<T>());
+    else
+      hipLaunchKernelGGL(k_dense_gemm<T>, dim3(n), dim3(256), 0, s, n, nrhs, L.tail.as<T>(), L.b.as<T>(),
+                         L.x.as<T>());
+    return;
+  }
   if (nrhs == 1 && l + 1 < op->lv.size() && op->lv[l].fused) {
     vcycle_fused<T>(op, l, s);
     return;
@@ -1225,7 +1293,6 @@ static int tune_all(hpdg_operator* op, hipStream_t s, int64_t* report, int cap) 
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
   for (int l = (int)op->lv.size() - 2; l >= 0; --l) {
-    if (op->lv[l].A.nnz > kFuseNnz) continue;
     auto time_cycle = [&]() {
       for (int w = 0; w < 3; ++w) vcycle<T>(op, l, 1, s);
       HIPCHK(hipEventRecord(e0, s));
@@ -1236,6 +1303,8 @@ static int tune_all(hpdg_operator* op, hipStream_t s, int64_t* report, int cap) 
       HIPCHK(hipEventElapsedTime(&ms, e0, e1));
       return (double)ms * 1e6 / 10;
     };
+    if (l == (int)op->lv.size() - 2) set_tail<T>(op, l, false);
+    if (op->lv[l].A.nnz > kFuseNnz) continue;
     set_fused<T>(op, l, false);
     const double t0 = time_cycle();
     set_fused<T>(op, l, true);
@@ -1256,6 +1325,22 @@ static int tune_all(hpdg_operator* op, hipStream_t s, int64_t* report, int cap) 
     r[3] = keep ? 1 : 0;
     r[4] = (int64_t)t0;
     r[5] = (int64_t)(keep ? t1 : t0);
+    // the dense tail on the level above the coarsest, against the best above
+    if (l == (int)op->lv.size() - 2 && op->lv[l].A.nrows <= kTailMax && op->ncoarse > 0) {
+      const double tb = keep ? t1 : t0;
+      set_tail<T>(op, l, true);
+      const double tt = time_cycle();
+      const bool kt = tt < kTuneMargin * tb;
+      if (!kt) set_tail<T>(op, l, false);
+      else if (keep) set_fused<T>(op, l, false);   // the tail replaces the fused level
+      int64_t* q = slot(8, l);
+      q[0] = op->lv[l].A.nrows;
+      q[1] = (int64_t)op->lv[l].A.nrows * op->lv[l].A.nrows;
+      q[2] = 0;
+      q[3] = kt ? 1 : 0;
+      q[4] = (int64_t)tb;
+      q[5] = (int64_t)(kt ? tt : tb);
+    }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

@@ -1497,6 +1497,7 @@ __global__ __launch_bounds__(256) void k_dense_gemm(int n, int nrhs, const T* __
   const int row = blockIdx.x;
   const int c = threadIdx.x % nrhs, g = threadIdx.x / nrhs, ng = 256 / nrhs;
   T acc = 0;
+#pragma unroll 4
   for (int j = g; j < n; j += ng) acc += C[(int64_t)row * n + j] * b[(int64_t)j * nrhs + c];
   part[threadIdx.x] = acc;
   __syncthreads();
@@ -1533,6 +1534,7 @@ __global__ __launch_bounds__(256) void k_dense_gemv1(int n, const T* __restrict_
   const int lane = threadIdx.x & 63;
   if (row >= n) return;
   T acc = 0;
+#pragma unroll 4
   for (int j = lane; j < n; j += 64) acc += C[(int64_t)row * n + j] * b[j];
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);

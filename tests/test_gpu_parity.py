@@ -284,7 +284,7 @@ def test_autotuned_binning_same_results(fp32):
     assert rep and {r["matrix"] for r in rep} >= {"A", "PT"}
     for r in rep:
         assert r["ns_tuned"] <= r["ns_default"]
-        if r["matrix"] == "vcycle_fused":
+        if r["matrix"] in ("vcycle_fused", "vcycle_dense_tail"):
             assert r["lanes"] in (0, 1)
         elif r["matrix"] == "elem_rhs_group":
             assert r["lanes"] in (1, 2, 4, 8, 16, 32, 64)
@@ -436,6 +436,39 @@ def test_fused_vcycle_levels(monkeypatch, name, fp32):
     assert _rel(_host(z), pc.apply(r)) <= (1e-5 if fp32 else 1e-12)
     b = torch.empty_like(z)
     op.rhs(_dev(r), b)
+    x = torch.zeros_like(b)
+    info = op.pcg_solve(b, x, rtol=1e-8, maxit=1000)[0]
+    assert info["converged"] and info["true_rel_res"] <= 1e-8
+
+
+@pytest.mark.parametrize("name", ["rand2", "rand3"])
+@pytest.mark.parametrize("fp32", [False, True])
+def test_dense_vcycle_tail(monkeypatch, name, fp32):
+    """The V(1,1) cycle from the level above the coarsest stored as one dense
+    matrix (the same linear map G + W C M): B against the oracle's cycle for
+    one and for four right-hand sides, and the solve."""
+    monkeypatch.setenv("HPDG_DENSE_TAIL", "1")
+    md = MESHES[name]()
+    m = O.Mesh(md)
+    opts = O.Opts("sipg", 0, 1.0)
+    cap = 128 if m.dim == 3 else 0
+    nr = 4
+    op = G.Operator(G.Mesh(md), prec_fp32=fp32, max_block=cap, max_nrhs=nr)
+    lv = op.amg_levels()
+    assert len(lv) >= 2 and lv[-2] <= 2048          # the tail is in use
+    pc = precond.Preconditioner(m, opts, max_block=cap)
+    R = np.random.default_rng(71).standard_normal((m.ndof, nr))
+    tol = 1e-5 if fp32 else 1e-12
+    z = torch.empty(m.ndof, dtype=torch.float64, device="cuda")
+    op.apply_B(_dev(np.ascontiguousarray(R[:, 0])), z)
+    assert _rel(_host(z), pc.apply(R[:, 0])) <= tol
+    Z = torch.empty(m.ndof * nr, dtype=torch.float64, device="cuda")
+    op.apply_B(_dev(R.reshape(-1)), Z, nrhs=nr)
+    Zh = _host(Z).reshape(m.ndof, nr)
+    for c in range(nr):
+        assert _rel(Zh[:, c], pc.apply(R[:, c])) <= tol
+    b = torch.empty_like(z)
+    op.rhs(_dev(np.ascontiguousarray(R[:, 0])), b)
     x = torch.zeros_like(b)
     info = op.pcg_solve(b, x, rtol=1e-8, maxit=1000)[0]
     assert info["converged"] and info["true_rel_res"] <= 1e-8
