@@ -28,7 +28,7 @@ HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
 # rocprofv3 FETCH_SIZE and WRITE_SIZE (each scaled by what the counter reads
 # for a 256 MiB copy: 2.0 and 1.0), valid for the kernel source with this
 # digest; reported as null once the source differs
-ELEM2D_TRAFFIC = {"digest": "5b30c287a640228c", "fetch_bytes": 5631299.2, "write_bytes": 1241952.0}
+ELEM2D_TRAFFIC = {"digest": "7c863440eab2e8be", "fetch_bytes": 5669344.3, "write_bytes": 1241952.0}
 WORKLOADS = {1: "uniform2d_4x4_p2_sipg_fp64",
              2: "random2d_32x32_q0.3_L3_p1-8_sipg_fp64",
              3: "random3d_16^3_q0.2_L2_p1-6_br2_fp32prec",
