@@ -195,6 +195,7 @@ struct hpdg_operator {
   int64_t blk_rows = 0, nblocks = 0;
   int max_blk = 0;           // largest V_e block
   int lprb = 16;             // lanes per V_e block row in the B front (one RHS)
+  int no_mfma = 0;           // HPDG_NO_MFMA=1: V_e block solves for many RHS without the matrix cores
   DevCSR P, PT;
   std::vector<LevelDev> lv;
   DevBuf coarse;
@@ -804,6 +805,7 @@ extern "C" hpdg_status hpdg_setup_operator(const hpdg_mesh* mh, const hpdg_opera
     if (const char* v = std::getenv("HPDG_ELEM2D_EPB")) op->epb = std::atoi(v) == 2 ? 2 : 1;
     if (const char* v = std::getenv("HPDG_ELEM2D_FCHUNK")) op->fchunk = std::atoi(v) == 8 ? 8 : std::atoi(v) == 32 ? 32 : 16;
     if (const char* v = std::getenv("HPDG_ELEM2D_RHSGROUP")) op->rhs_group = std::max(1, std::atoi(v));
+    if (const char* v = std::getenv("HPDG_NO_MFMA")) op->no_mfma = std::atoi(v) != 0;
     if (!op->no_prec) {
       PrecHost& H = op->host;
       H.diag = dg_diagonal(M, oo);
@@ -1435,7 +1437,12 @@ static int apply_B_dev(hpdg_operator* op, const double* r, double* z, int nrhs, 
     if (op->blk_rows > 0) {
       int64_t nt = op->blk_rows * nrhs;
       const size_t shm = (size_t)op->max_blk * nrhs * sizeof(T);
-      if (shm <= 48 * 1024)
+      if (nrhs % 16 == 0 && (size_t)op->max_blk * sizeof(int32_t) <= 48 * 1024 && !op->no_mfma)
+        hipLaunchKernelGGL(k_block_mfma<T>, dim3((unsigned)op->nblocks), dim3(256),
+                           (size_t)op->max_blk * sizeof(int32_t), s, (int)op->nblocks, nrhs,
+                           op->blk_ptr.as<int64_t>(), op->blk_off.as<int64_t>(), op->blk_dof.as<int32_t>(),
+                           op->blk_inv.as<T>(), rt, zb);
+      else if (shm <= 48 * 1024)
         hipLaunchKernelGGL(k_block_gemm<T>, dim3((unsigned)op->nblocks), dim3(256), shm, s, (int)op->nblocks, nrhs,
                            op->blk_ptr.as<int64_t>(), op->blk_off.as<int64_t>(), op->blk_dof.as<int32_t>(),
                            op->blk_inv.as<T>(), rt, zb);

@@ -1488,6 +1488,80 @@ __global__ __launch_bounds__(256) void k_block_gemm(int nblocks, int nrhs, const
   }
 }
 
+// exact V_e solves for many RHS (nrhs a multiple of 16) on the matrix cores:
+// Z_b = B_b R_b per block in 16 x 16 output tiles (block rows x right-hand
+// sides), each a chain of 16x16x4 MFMA steps over the block's columns. The
+// stored inverse B_b is exactly symmetric, so the A operand B_b[i][k] is read
+// as B_b[k][i]: 16 consecutive entries of a row per lane group. Operand
+// layout of the 16x16x4 steps on gfx950 (one 64-lane wavefront, checked by a
+// lane probe): lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]; its
+// accumulator entry v holds D[row][l % 16] with row = 4 (l / 16) + v for FP32
+// and row = l / 16 + 4 v for FP64. One workgroup (4 wavefronts) per block;
+// the block's DOF list is staged in LDS (dynamic, m int32).
+template <typename T>
+struct Mfma16;
+template <>
+struct Mfma16<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ inline v4 step(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ inline int row(int lk, int v) { return 4 * lk + v; }
+};
+template <>
+struct Mfma16<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ inline v4 step(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ inline int row(int lk, int v) { return lk + 4 * v; }
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_block_mfma(int nblocks, int nrhs, const int64_t* __restrict__ bptr,
+                                                    const int64_t* __restrict__ boff,
+                                                    const int32_t* __restrict__ bdof, const T* __restrict__ binv,
+                                                    const T* __restrict__ r, T* __restrict__ z) {
+  extern __shared__ unsigned char blk_lds[];
+  int32_t* sdof = reinterpret_cast<int32_t*>(blk_lds);
+  const int b = blockIdx.x;
+  if (b >= nblocks) return;
+  const int64_t s0 = bptr[b];
+  const int m = (int)(bptr[b + 1] - s0);
+  for (int t = threadIdx.x; t < m; t += 256) sdof[t] = bdof[s0 + t];
+  __syncthreads();
+  const T* B = binv + boff[b];
+  const int lane = (int)(threadIdx.x & 63), wv = (int)(threadIdx.x >> 6);
+  const int li = lane & 15, lk = lane >> 4;
+  const int nti = (m + 15) >> 4, ntj = nrhs >> 4;
+  for (int tile = wv; tile < nti * ntj; tile += 4) {
+    const int i0 = (tile % nti) * 16, j0 = (tile / nti) * 16;
+    const int i = i0 + li;
+    typename Mfma16<T>::v4 acc = {0, 0, 0, 0};
+    // four k-steps per pass: their eight operand loads in flight together
+    for (int k0 = 0; k0 < m; k0 += 16) {
+      T a[4], bv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int k = k0 + 4 * u + lk;
+        a[u] = 0;
+        bv[u] = 0;
+        if (k < m) {
+          if (i < m) a[u] = B[(int64_t)k * m + i];
+          bv[u] = r[(int64_t)sdof[k] * nrhs + j0 + li];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc = Mfma16<T>::step(a[u], bv[u], acc);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = i0 + Mfma16<T>::row(lk, v);
+      if (row < m) z[(int64_t)sdof[row] * nrhs + j0 + li] = acc[v];
+    }
+  }
+}
+
 // coarsest level, interleaved RHS: a workgroup per row, its 256 / nrhs lane
 // groups split the row and add their parts in a fixed order
 template <typename T>
