@@ -245,6 +245,9 @@ struct hpdg_operator {
 
 // ---------------------------------------------------------------- helpers
 static inline unsigned nblk(int64_t n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
+// blocks of the dot-product kernels (grid-stride loops; a multiple of nrhs
+// threads per block): at most 1024, about 1024 elements per block
+static inline int dot_grid(int64_t n) { return (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n + 1023) / 1024)); }
 
 extern "C" hpdg_status hpdg_setup_mesh(int dim, int n_base, int64_t n_elem, const int32_t* level,
                                        const int32_t* anchor, const int32_t* degree, const double* kcoef,
@@ -1547,7 +1550,7 @@ static void tridiag_extremes(const std::vector<double>& a, const std::vector<dou
 static void dot_ep(hpdg_operator* op, const double* a, const double* b, int nrhs, int mode, const CGScal& S,
                    hipStream_t s) {
   int64_t n = op->ndof * nrhs;
-  int nb = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n + 1023) / 1024));
+  const int nb = dot_grid(n);
   hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(256), 0, s, n, nrhs, a, b, op->part.as<double>());
   if (nrhs == 1)
     hipLaunchKernelGGL(k_dot_final_ep, dim3(1), dim3(256), 0, s, nb, nrhs, op->part.as<double>(), mode, S);
@@ -1649,8 +1652,11 @@ static void pcg_iters(hpdg_operator* op, int k, hipStream_t s) {
       const int nb = apply_B_any(op, r, z, nrhs, s, part2);
       hipLaunchKernelGGL(k_dot_final2_ep, dim3(1), dim3(256), 0, s, (int)nblk(n), part, EP_RR, nb, part2, EP_RZ, S);
     } else {
-      hipLaunchKernelGGL(k_cg_update2, dim3(nblk(n)), dim3(256), 0, s, n, nrhs, S.alpha, p, Ap, R.x, r);
-      dot_ep(op, r, r, nrhs, EP_RR, S, s);
+      // the update writes the per-RHS shares of r'r (on the grid of the dot
+      // kernels, so they are bitwise those of a separate pass)
+      const int g = dot_grid(n);
+      hipLaunchKernelGGL(k_cg_update2, dim3(g), dim3(256), 0, s, n, nrhs, S.alpha, p, Ap, R.x, r, part);
+      hipLaunchKernelGGL(k_dot_final_rhs, dim3(nrhs), dim3(256), 0, s, g, nrhs, part, EP_RR, S);
       apply_B_any(op, r, z, nrhs, s);
       dot_ep(op, r, z, nrhs, EP_RZ, S, s);
     }

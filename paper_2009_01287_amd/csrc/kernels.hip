@@ -833,15 +833,31 @@ __global__ __launch_bounds__(256) void k_dot_final2_ep(int na, const double* __r
   }
 }
 
-// x += alpha p ; r -= alpha Ap (alpha = 0 for converged RHS)
-__global__ void k_cg_update2(int64_t n, int nrhs, const double* __restrict__ alpha,
-                             const double* __restrict__ p, const double* __restrict__ Ap, double* __restrict__ x,
-                             double* __restrict__ r) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double al = alpha[i % nrhs];
-  x[i] += al * p[i];
-  r[i] -= al * Ap[i];
+// x += alpha p ; r -= alpha Ap (alpha = 0 for converged RHS), interleaved
+// RHS, with the per-RHS shares of r'r: the grid-stride loop and the
+// reduction are those of k_dot_partial (same grid), so the shares are bitwise
+// the ones a separate pass over r would give
+__global__ __launch_bounds__(256) void k_cg_update2(int64_t n, int nrhs, const double* __restrict__ alpha,
+                                                   const double* __restrict__ p, const double* __restrict__ Ap,
+                                                   double* __restrict__ x, double* __restrict__ r,
+                                                   double* __restrict__ part) {
+  __shared__ double sm[256];
+  const int tid = threadIdx.x;
+  const double al = alpha[tid % nrhs];   // the grid stride is a multiple of nrhs
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + tid; i < n; i += (int64_t)gridDim.x * 256) {
+    x[i] += al * p[i];
+    const double ri = r[i] - al * Ap[i];
+    r[i] = ri;
+    acc += ri * ri;
+  }
+  sm[tid] = acc;
+  __syncthreads();
+  for (int w = 128; w >= nrhs; w >>= 1) {
+    if (tid < w) sm[tid] += sm[tid + w];
+    __syncthreads();
+  }
+  if (tid < nrhs) part[blockIdx.x * nrhs + tid] = sm[tid];
 }
 
 // ------------------------------------------------------------- 3D element
