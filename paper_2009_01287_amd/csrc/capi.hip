@@ -1054,6 +1054,17 @@ static void vcycle_fused(hpdg_operator* op, size_t l, hipStream_t s) {
   spmv<T, 5>(L.U, 1, L.b.as<T>(), C.x.as<T>(), nullptr, nullptr, L.x.as<T>(), s);
 }
 
+// x = C b for a dense n x n matrix and nrhs > 1 interleaved right-hand sides:
+// on the matrix cores when nrhs is a multiple of 16, else a workgroup per row
+template <typename T>
+static void dense_many(hpdg_operator* op, int n, int nrhs, const T* C, const T* b, T* x, hipStream_t s) {
+  if (nrhs % 16 == 0 && !op->no_mfma)
+    hipLaunchKernelGGL(k_dense_mfma<T>, dim3((unsigned)((n + 15) / 16), (unsigned)(nrhs / 16)), dim3(256), 0, s, n,
+                       nrhs, C, b, x);
+  else
+    hipLaunchKernelGGL(k_dense_gemm<T>, dim3(n), dim3(256), 0, s, n, nrhs, C, b, x);
+}
+
 template <typename T>
 static void vcycle(hpdg_operator* op, size_t l, int nrhs, hipStream_t s) {
   if (op->lv[l].use_tail) {
@@ -1063,8 +1074,7 @@ static void vcycle(hpdg_operator* op, size_t l, int nrhs, hipStream_t s) {
       hipLaunchKernelGGL(k_dense_gemv1<T>, dim3((n + 3) / 4), dim3(256), 0, s, n, L.tail.as<T>(), L.b.as<T>(),
                          L.x.as<T>());
     else
-      hipLaunchKernelGGL(k_dense_gemm<T>, dim3(n), dim3(256), 0, s, n, nrhs, L.tail.as<T>(), L.b.as<T>(),
-                         L.x.as<T>());
+      dense_many<T>(op, n, nrhs, L.tail.as<T>(), L.b.as<T>(), L.x.as<T>(), s);
     return;
   }
   if (nrhs == 1 && l + 1 < op->lv.size() && op->lv[l].fused) {
@@ -1080,8 +1090,7 @@ static void vcycle(hpdg_operator* op, size_t l, int nrhs, hipStream_t s) {
       hipLaunchKernelGGL(k_dense_gemv1<T>, dim3((op->ncoarse + 3) / 4), dim3(256), 0, s, op->ncoarse,
                          op->coarse.as<T>(), L.b.as<T>(), L.x.as<T>());
     else
-      hipLaunchKernelGGL(k_dense_gemm<T>, dim3(op->ncoarse), dim3(256), 0, s, op->ncoarse, nrhs,
-                         op->coarse.as<T>(), L.b.as<T>(), L.x.as<T>());
+      dense_many<T>(op, op->ncoarse, nrhs, op->coarse.as<T>(), L.b.as<T>(), L.x.as<T>(), s);
     return;
   }
   LevelDev& C = op->lv[l + 1];

@@ -1578,6 +1578,49 @@ __global__ __launch_bounds__(256) void k_block_mfma(int nblocks, int nrhs, const
   }
 }
 
+// dense x = C b for many RHS (nrhs a multiple of 16) on the matrix cores: one
+// workgroup per 16 x 16 output tile (rows x right-hand sides); its four
+// wavefronts take a quarter of the columns of C each (16x16x4 MFMA steps, four
+// per pass) and their partial tiles are added in wavefront order through LDS.
+template <typename T>
+__global__ __launch_bounds__(256) void k_dense_mfma(int n, int nrhs, const T* __restrict__ C,
+                                                    const T* __restrict__ b, T* __restrict__ x) {
+  __shared__ T red[4][64][4];
+  const int lane = (int)(threadIdx.x & 63), wv = (int)(threadIdx.x >> 6);
+  const int li = lane & 15, lk = lane >> 4;
+  const int i0 = blockIdx.x * 16, j0 = blockIdx.y * 16;
+  const int i = i0 + li;
+  const int kq = (((n + 3) / 4 + 15) / 16) * 16;   // columns per wavefront, a multiple of 16
+  const int ka = wv * kq, kb = min(n, ka + kq);
+  typename Mfma16<T>::v4 acc = {0, 0, 0, 0};
+  for (int k0 = ka; k0 < kb; k0 += 16) {
+    T a[4], bv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = k0 + 4 * u + lk;
+      a[u] = 0;
+      bv[u] = 0;
+      if (k < kb) {
+        if (i < n) a[u] = C[(int64_t)i * n + k];
+        bv[u] = b[(int64_t)k * nrhs + j0 + li];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc = Mfma16<T>::step(a[u], bv[u], acc);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) red[wv][lane][v] = acc[v];
+  __syncthreads();
+  if (wv == 0) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const T sum = ((red[0][lane][v] + red[1][lane][v]) + red[2][lane][v]) + red[3][lane][v];
+      const int row = i0 + Mfma16<T>::row(lk, v);
+      if (row < n) x[(int64_t)row * nrhs + j0 + li] = sum;
+    }
+  }
+}
+
 // coarsest level, interleaved RHS: a workgroup per row, its 256 / nrhs lane
 // groups split the row and add their parts in a fixed order
 template <typename T>

@@ -443,16 +443,17 @@ def test_fused_vcycle_levels(monkeypatch, name, fp32):
 
 @pytest.mark.parametrize("name", ["rand2", "rand3"])
 @pytest.mark.parametrize("fp32", [False, True])
-def test_dense_vcycle_tail(monkeypatch, name, fp32):
+@pytest.mark.parametrize("nr", [4, 16])
+def test_dense_vcycle_tail(monkeypatch, name, fp32, nr):
     """The V(1,1) cycle from the level above the coarsest stored as one dense
     matrix (the same linear map G + W C M): B against the oracle's cycle for
-    one and for four right-hand sides, and the solve."""
+    one and for nr right-hand sides (16: dense products on the matrix cores),
+    and the solve."""
     monkeypatch.setenv("HPDG_DENSE_TAIL", "1")
     md = MESHES[name]()
     m = O.Mesh(md)
     opts = O.Opts("sipg", 0, 1.0)
     cap = 128 if m.dim == 3 else 0
-    nr = 4
     op = G.Operator(G.Mesh(md), prec_fp32=fp32, max_block=cap, max_nrhs=nr)
     lv = op.amg_levels()
     assert len(lv) >= 2 and lv[-2] <= 2048          # the tail is in use
