@@ -210,6 +210,7 @@ struct hpdg_operator {
   int no_prec = 0;           // operator only: apply_B and PCG unsupported
   int use_graph = 0;         // PCG chunks replayed from captured HIP graphs
   int epb = 1;               // elements per workgroup of the 2D element kernel
+  int nm3 = 9;               // LDS size class of the 3D element kernel: largest n = p + 1 (7 or 9)
   int fchunk = 16;           // face records per pass of the 2D element kernel
   int rhs_group = 1;         // right-hand sides per item of the 2D element kernel
   struct GraphEntry {
@@ -554,6 +555,11 @@ static void upload_device(hpdg_operator* op, hipStream_t s) {
   const int64_t b0 = g_dev_bytes;
   op->off.upload(U.off);
   op->pdeg.upload(U.pd);
+  {
+    int pm = 0;
+    for (int8_t v : U.pd) pm = std::max(pm, (int)v);
+    op->nm3 = pm <= 6 ? 7 : 9;   // degree <= 6: LDS for 7 nodes per direction
+  }
   op->hh.upload(U.h);
   op->kk.upload(U.k);
   op->sptr.upload(U.sptr);
@@ -945,7 +951,8 @@ static int apply_A_dev(hpdg_operator* op, const double* x, double* y, int nrhs, 
     return pdot ? op->ne : 0;
   } else if (op->dim == 3 && !op->generic_faces) {
     const unsigned grid = 8u * (unsigned)((items + 7) / 8);   // k_elem3d needs a multiple of 8
-    hipLaunchKernelGGL(k_elem3d, dim3(grid), dim3(256), 0, s, op->ne, nrhs, op->form, op->off.as<int64_t>(),
+    auto kern = op->nm3 == 7 ? k_elem3d<7> : k_elem3d<9>;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, s, op->ne, nrhs, op->form, op->off.as<int64_t>(),
                        op->pdeg.as<int8_t>(), op->hh.as<double>(), op->kk.as<double>(), op->sptr.as<int32_t>(),
                        op->recs.as<FaceRec>(), op->ftab.as<double>(), op->tab.as<double>(), op->TL, x, y, pdot);
     return pdot ? op->ne : 0;

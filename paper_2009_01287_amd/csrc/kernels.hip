@@ -881,27 +881,30 @@ __global__ __launch_bounds__(256) void k_cg_update2(int64_t n, int nrhs, const d
 //          Each Kronecker product is two 1D contractions; the products
 //          A Minv of each slot come precomputed from the face table, so a
 //          BR2 face takes four barrier-separated stages and an SIPG face two.
-//  Memory: records and neighbour traces of up to kF3 faces are fetched in
+//  Memory: records and neighbour traces of up to NM faces are fetched in
 //  two parallel rounds into LDS; faces are then applied one after another
 //  (a fixed order, so the sums per side node are deterministic).
-constexpr int kF3 = 8;
-
 __device__ inline void tdims3(int m, int& t0, int& t1) {
   t0 = m == 0 ? 1 : 0;
   t1 = m == 2 ? 1 : 2;
 }
 
-__global__ __launch_bounds__(256) void k_elem3d(int ne, int nrhs, int form, const int64_t* __restrict__ off,
+template <int NM>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NM == 7 ? 7 : 4))) void k_elem3d(int ne, int nrhs, int form, const int64_t* __restrict__ off,
                                                 const int8_t* __restrict__ pdeg, const double* __restrict__ hh,
                                                 const double* __restrict__ kk, const int32_t* __restrict__ sptr,
                                                 const FaceRec* __restrict__ recs, const double* __restrict__ ftab,
                                                 const double* __restrict__ tab, TableLayout TL,
                                                 const double* __restrict__ x, double* __restrict__ y,
                                                 double* __restrict__ pdot) {
-  // volume buffers, reused by the face stage once the volume is done
-  __shared__ double sV0[729], sV1[729], sV2[729], sV3[729];
-  __shared__ double sTo[6][81], sDo[6][81], sG1[6][81], sG2[6][81];
-  __shared__ FaceRec sR[kF3];
+  // LDS sized for degree <= NM - 1: volume buffers of NM^3 (reused by the
+  // face stage once the volume is done), face slots of F2 = NM^2, KF = NM
+  // face records per pass (KF slots of F2 fill a volume buffer)
+  constexpr int F2 = NM * NM, V3 = NM * NM * NM, KF = NM;
+  static_assert(6 * F2 <= V3, "six face slots must fit a volume buffer");
+  __shared__ double sV0[V3], sV1[V3], sV2[V3], sV3[V3];
+  __shared__ double sTo[6][F2], sDo[6][F2], sG1[6][F2], sG2[6][F2];
+  __shared__ FaceRec sR[KF];
   __shared__ double sRed[4];
   const int per = (int)(gridDim.x >> 3);
   const int item = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);   // (element, RHS)
@@ -918,7 +921,7 @@ __global__ __launch_bounds__(256) void k_elem3d(int ne, int nrhs, int form, cons
   const double* Kt = tab + TL.mk + (p * 2 + 1) * 81;
   double* sX = sV0;
   for (int i = tid; i < n3; i += 256) sX[i] = x[(base + i) * nrhs + rhs];
-  for (int i = tid; i < 6 * 81; i += 256) {
+  for (int i = tid; i < 6 * F2; i += 256) {
     (&sG1[0][0])[i] = 0.0;
     (&sG2[0][0])[i] = 0.0;
   }
@@ -986,20 +989,20 @@ __global__ __launch_bounds__(256) void k_elem3d(int ne, int nrhs, int form, cons
   }
   __syncthreads();
   // face stage: work arrays in the volume buffers
-  double* sTn = sV0;                 // [kF3][81]
-  double* sDn = sV3;                 // [kF3][81]
+  double* sTn = sV0;                 // [KF][F2]
+  double* sDn = sV3;                 // [KF][F2]
   double* U0 = sV1;                  // contraction temporaries
-  double* U1 = sV1 + 81;
-  double* U2 = sV1 + 162;
-  double* U3 = sV1 + 243;
-  double* Y0 = sV1 + 324;
-  double* Y1 = sV1 + 405;
+  double* U1 = sV1 + F2;
+  double* U2 = sV1 + 2 * F2;
+  double* U3 = sV1 + 3 * F2;
+  double* Y0 = sV1 + 4 * F2;
+  double* Y1 = sV1 + 5 * F2;
   double* Vv = sV2;                  // jump on own face nodes
-  double* Vn = sV2 + 81;             // jump on the neighbour's face nodes (BR2)
-  double* P0 = sV2 + 162;
-  double* Q0 = sV2 + 243;
-  for (int c0 = sp[0]; c0 < sp[6]; c0 += kF3) {
-    const int nF = min(kF3, sp[6] - c0);
+  double* Vn = sV2 + F2;             // jump on the neighbour's face nodes (BR2)
+  double* P0 = sV2 + 2 * F2;
+  double* Q0 = sV2 + 3 * F2;
+  for (int c0 = sp[0]; c0 < sp[6]; c0 += KF) {
+    const int nF = min(KF, sp[6] - c0);
     {
       constexpr int W = (int)(sizeof(FaceRec) / 8);
       const unsigned long long* src = reinterpret_cast<const unsigned long long*>(recs + c0);
@@ -1008,8 +1011,8 @@ __global__ __launch_bounds__(256) void k_elem3d(int ne, int nrhs, int form, cons
     }
     __syncthreads();
     // neighbour traces
-    for (int t = tid; t < nF * 81; t += 256) {
-      const int f = t / 81, q = t - 81 * f;
+    for (int t = tid; t < nF * F2; t += 256) {
+      const int f = t / F2, q = t - F2 * f;
       const int nb = sR[f].nbr, po = sR[f].pn, no = po + 1;
       if (nb < 0 || q >= no * no) continue;
       const int mm = sR[f].m, so = 1 - sR[f].side;
@@ -1023,8 +1026,8 @@ __global__ __launch_bounds__(256) void k_elem3d(int ne, int nrhs, int form, cons
       double dv = 0.0;
       #pragma unroll 4
       for (int a = 0; a < no; ++a) dv += Dso[a] * xn[(int64_t)(o + a * st[mm]) * nrhs];
-      sTn[f * 81 + q] = xn[(int64_t)(o + (so ? po : 0) * st[mm]) * nrhs];
-      sDn[f * 81 + q] = sR[f].kho * dv;
+      sTn[f * F2 + q] = xn[(int64_t)(o + (so ? po : 0) * st[mm]) * nrhs];
+      sDn[f * F2 + q] = sR[f].kho * dv;
     }
     __syncthreads();
     for (int f = 0; f < nF; ++f) {
@@ -1039,16 +1042,16 @@ __global__ __launch_bounds__(256) void k_elem3d(int ne, int nrhs, int form, cons
       const double* A1oo = ftab + R.foo[1];
       const double* A0on = ftab + R.fon[0];
       const double* A1on = ftab + R.fon[1];
-      const double* Tn = sTn + f * 81;
-      const double* Dn = sDn + f * 81;
+      const double* Tn = sTn + f * F2;
+      const double* Dn = sDn + f * F2;
       const bool br2i = form == 1 && inner;
       const double* A0nn = ftab + R.fnn[0];
       const double* A1nn = ftab + R.fnn[1];
       // stage 1: slot-0 contractions of To, Do (own) and Tn, Dn (neighbour);
       // for BR2 also the slot-0 halves of the neighbour's jump
       //   Y0 = A0on^T To (no x n), Y1 = A0nn Tn (no x no)
-      for (int t = tid; t < 6 * 81; t += 256) {
-        const int which = t / 81, q = t - 81 * which;
+      for (int t = tid; t < 6 * F2; t += 256) {
+        const int which = t / F2, q = t - F2 * which;
         if (which < 2) {
           if (q >= n2) continue;
           const int j0 = q % n, a1 = q / n;
@@ -1084,8 +1087,8 @@ __global__ __launch_bounds__(256) void k_elem3d(int ne, int nrhs, int form, cons
       __syncthreads();
       // stage 2: slot-1 contractions; jump, average and the penalty; for BR2
       // the neighbour's jump vn = (A0on x A1on)^T To - (A0nn x A1nn) Tn
-      for (int t = tid; t < 2 * 81; t += 256) {
-        if (t < 81) {
+      for (int t = tid; t < 2 * F2; t += 256) {
+        if (t < F2) {
           const int q = t;
           if (q >= n2) continue;
           const int j0 = q % n, j1 = q / n;
@@ -1109,7 +1112,7 @@ __global__ __launch_bounds__(256) void k_elem3d(int ne, int nrhs, int form, cons
           sG2[side][q] -= csym * k * sgn * area * v;
           Vv[q] = v;
         } else {
-          const int q = t - 81;
+          const int q = t - F2;
           if (!br2i || q >= no * no) continue;
           const int a0 = q % no, b1 = q / no;
           double vn = 0.0;
@@ -1140,8 +1143,8 @@ __global__ __launch_bounds__(256) void k_elem3d(int ne, int nrhs, int form, cons
         const double* L0n = ftab + R.lon[0];
         const double* L1n = ftab + R.lon[1];
         // stage 3: slot 0
-        for (int t = tid; t < 2 * 81; t += 256) {
-          const int which = t / 81, q = t - 81 * which;
+        for (int t = tid; t < 2 * F2; t += 256) {
+          const int which = t / F2, q = t - F2 * which;
           if (which == 0) {
             if (q >= n2) continue;
             const int j0 = q % n, a1 = q / n;
