@@ -55,6 +55,9 @@ def main():
     ap.add_argument("--max-active", type=int, default=16, help="serving: solves in flight")
     ap.add_argument("--serving-graph", type=int, default=0, help="serving: 1 replays CG chunks from HIP graphs")
     ap.add_argument("--serving-prec", default="mixed", choices=["mixed", "fp64", "both"])
+    ap.add_argument("--study", choices=["eta"], default=None,
+                    help="eta: penalty-dependence study (SIPG and BR2, eta = 10..1e4, full B against the "
+                         "simplified B with point Jacobi on all of V_B); one JSON line per solve, then a summary")
     ap.add_argument("--apply-only", action="store_true",
                     help="only run apply_A --apply-reps times and one calibration copy of "
                          "256 MiB (for hardware-counter runs), then exit")
@@ -71,6 +74,8 @@ def main():
     import paper_2009_01287_amd as G
 
     cfg = args.config
+    if args.study == "eta":
+        return eta_study(args)
     if cfg == 5:
         return serve_bench(args)
     c = H.CONFIGS[cfg]
@@ -277,6 +282,46 @@ def elem2d_digest():
     hdr = open(os.path.join(ROOT, "paper_2009_01287_amd", "csrc", "kernels.hpp")).read()
     code = "\n".join(l.split("//")[0].rstrip() for l in (src[a:b] + hdr).splitlines())   # comments do not count
     return hashlib.sha256(code.encode()).hexdigest()[:16]
+
+
+def eta_study(args):
+    """Penalty dependence (paper Sec. 4.4, Fig. 4): iterations and Lanczos
+    condition estimates of PCG to 1e-8 on one randomly refined 2D mesh with
+    degrees 5..8 and coefficient 1 or 20, for SIPG (sigma = eta k p_e^2 / h_e)
+    and BR2 (eta times the lifting term), eta = 10, 100, 1e3, 1e4, with the
+    full preconditioner B = B_J + B_E + B_C and with the simplified one (point
+    Jacobi on all of V_B plus B_C). FP64 throughout."""
+    import numpy as np
+    import torch
+
+    import hpinputs as H
+    import paper_2009_01287_amd as G
+    md = H.penalty_study_mesh()
+    mesh = G.Mesh(md)
+    f = torch.from_numpy(H.gaussian_rhs(mesh.ndof, 1263)).cuda()
+    rows = []
+    for form in ("sipg", "br2"):
+        for eta in (10.0, 100.0, 1000.0, 10000.0):
+            for variant in ("full", "simplified"):
+                t0 = time.perf_counter()
+                op = G.Operator(mesh, form=form, penalty_rule=1, eta=eta, jb_only=(variant == "simplified"))
+                t_setup = time.perf_counter() - t0
+                b = torch.empty_like(f)
+                op.rhs(f, b)
+                x = torch.zeros_like(b)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                code, info = op.pcg_solve(b, x, rtol=1e-8, maxit=20000, raise_on_error=False)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t1
+                i0 = info[0]
+                row = {"form": form, "eta": eta, "preconditioner": variant, "status": int(code),
+                       "iters": int(i0["iters"]), "cond_est": float(i0["cond_est"]),
+                       "true_rel_res": float(i0["true_rel_res"]), "solve_ms": dt * 1e3, "setup_s": t_setup}
+                rows.append(row)
+                print(json.dumps(row), flush=True)
+    print(json.dumps({"study": "penalty dependence", "ndof": mesh.ndof, "elements": int(len(md["level"])),
+                      "degrees": "5..8", "coefficient": "1 or 20 by base cell", "rtol": 1e-8, "rows": rows}))
 
 
 def serve_bench(args):

@@ -182,6 +182,19 @@ CONFIGS = {
 }
 
 
+def penalty_study_mesh(n_base=16, seed=1262, pmin=5, pmax=8):
+    """Mesh of the penalty-dependence study: one sweep of random refinement
+    (each base cell split with probability 0.5), degrees drawn uniformly in
+    {pmin..pmax}, and a piecewise constant coefficient k in {1, 20} set by the
+    parity of the base cell's index (a numbering of the initial coarse mesh),
+    inherited by its children."""
+    m = random_mesh(2, n_base, 0.5, 1, pmin, pmax, seed)
+    base = m["anchor"] >> m["level"][:, None]          # base cell of every leaf
+    idx = base[:, 0] + n_base * base[:, 1]
+    m["kcoef"] = np.where(idx % 2 == 0, 1.0, 20.0)
+    return m
+
+
 def config_mesh(cfg: int, scale: int = 1):
     """Mesh of a named workload. scale > 1 divides n_base (small variants of
     the same recipe for tests)."""

@@ -475,6 +475,27 @@ def test_dense_vcycle_tail(monkeypatch, name, fp32, nr):
     assert info["converged"] and info["true_rel_res"] <= 1e-8
 
 
+@pytest.mark.parametrize("form", ["sipg", "br2"])
+def test_simplified_preconditioner(form):
+    """jb_only (point Jacobi on all of V_B plus B_C, the simplified
+    preconditioner): B against the oracle's 'jb' variant, and the solve."""
+    md = MESHES["rand2"]()
+    m = O.Mesh(md)
+    eta = 1.0 if form == "sipg" else 0.0
+    opts = O.Opts(form, 0, eta)
+    op = G.Operator(G.Mesh(md), form=form, eta=eta, jb_only=True)
+    pc = precond.Preconditioner(m, opts, variant="jb")
+    r = np.random.default_rng(91).standard_normal(m.ndof)
+    z = torch.empty(m.ndof, dtype=torch.float64, device="cuda")
+    op.apply_B(_dev(r), z)
+    assert _rel(_host(z), pc.apply(r)) <= 1e-12
+    b = torch.empty_like(z)
+    op.rhs(_dev(r), b)
+    x = torch.zeros_like(b)
+    info = op.pcg_solve(b, x, rtol=1e-8, maxit=3000)[0]
+    assert info["converged"] and info["true_rel_res"] <= 1e-8
+
+
 @pytest.mark.parametrize("nr", [16, 64])
 @pytest.mark.parametrize("fp32", [False, True])
 def test_block_solves_mfma(monkeypatch, nr, fp32):
