@@ -137,3 +137,19 @@ def test_setup_threads_do_not_change_results():
         assert np.array_equal(a.export(what), b.export(what)), what
     for l in range(len(a.amg_levels())):
         assert np.array_equal(a.export(100 + l), b.export(100 + l))
+
+
+def test_penalty_study_mesh():
+    """The penalty-study mesh: one refinement sweep, degrees 5..8, the
+    coefficient 1 or 20 by the parity of the base cell's number (inherited)."""
+    import hpinputs as H
+    m = H.penalty_study_mesh()
+    assert set(np.unique(m["level"])) <= {0, 1}
+    assert m["degree"].min() >= 5 and m["degree"].max() <= 8
+    base = m["anchor"] >> m["level"][:, None]
+    idx = base[:, 0] + 16 * base[:, 1]
+    assert np.array_equal(m["kcoef"], np.where(idx % 2 == 0, 1.0, 20.0))
+    # every base cell is covered once: 1 leaf at level 0 or 4 at level 1
+    area = np.where(m["level"] == 0, 4, 1)
+    assert area.sum() == 4 * 16 * 16
+    assert np.array_equal(H.penalty_study_mesh()["degree"], m["degree"])   # seeded
