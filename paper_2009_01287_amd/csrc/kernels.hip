@@ -12,10 +12,13 @@
 //                  as an alternative path for checks.
 //   k_front        B's point Jacobi, V_e block solves and P^T in one launch.
 //   k_spmv, k_spmm CSR products for P, P^T and the AMG levels, with fused
-//                  smoother / residual / prolongation-add forms; k_upleg the
-//                  up-leg of a fused V-cycle level.
-//   k_block_gemv, k_diag_scale, k_dense_gemv*  multi-RHS pieces of B and the
-//                  coarsest AMG solve.
+//                  smoother / residual / prolongation-add forms and the
+//                  two-vector product of a fused V-cycle level's up-leg.
+//   k_block_mfma, k_block_gemm, k_block_gemv, k_diag_scale  multi-RHS pieces
+//                  of B (V_e block solves on the matrix cores for nrhs a
+//                  multiple of 16).
+//   k_dense_gemv1, k_dense_mfma, k_dense_gemm  dense products of the V-cycle
+//                  (coarsest solve, dense tail) for one and for many RHS.
 //   k_dot_*, k_cg_*     deterministic two-stage reductions (fixed order) with
 //                  the CG scalar updates on the device, and the vector updates.
 #include <hip/hip_runtime.h>
@@ -1677,14 +1680,5 @@ __global__ __launch_bounds__(256) void k_dense_gemv1(int n, const T* __restrict_
   if (lane == 0) x[row] = acc;
 }
 
-template <typename T>
-__global__ void k_dense_gemv(int n, int nrhs, const T* __restrict__ C, const T* __restrict__ b, T* __restrict__ x) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  const int row = t / nrhs, c = t % nrhs;
-  if (row >= n) return;
-  T acc = 0;
-  for (int j = 0; j < n; ++j) acc += C[(int64_t)row * n + j] * b[(int64_t)j * nrhs + c];
-  x[(int64_t)row * nrhs + c] = acc;
-}
 
 }  // namespace hpdg
