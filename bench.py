@@ -54,6 +54,8 @@ def main():
     ap.add_argument("--workers", type=int, default=12, help="serving: host setup threads")
     ap.add_argument("--max-active", type=int, default=16, help="serving: solves in flight")
     ap.add_argument("--serving-graph", type=int, default=0, help="serving: 1 replays CG chunks from HIP graphs")
+    ap.add_argument("--serving-auto-cycle", type=int, default=1,
+                    help="serving: 1 builds fused V-cycle levels and a small dense tail without timing")
     ap.add_argument("--serving-prec", default="mixed", choices=["mixed", "fp64", "both"])
     ap.add_argument("--study", choices=["eta"], default=None,
                     help="eta: penalty-dependence study (SIPG and BR2, eta = 10..1e4, full B against the "
@@ -346,7 +348,8 @@ def serve_bench(args):
     precs = ["mixed", "fp64"] if args.serving_prec == "both" else [args.serving_prec]
     for prec in precs:
         srv = S.Server(max_active=args.max_active, workers=args.workers, prec_fp32=(prec == "mixed"),
-                       realtime=args.rate > 0, graph=bool(args.serving_graph))
+                       realtime=args.rate > 0, graph=bool(args.serving_graph),
+                       auto_cycle=bool(args.serving_auto_cycle))
         t0 = time.perf_counter()
         res = srv.run(reqs)
         wall = time.perf_counter() - t0

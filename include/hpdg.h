@@ -85,6 +85,11 @@ typedef struct {
                         HIP graphs and replayed (same kernels, same results) */
   int setup_threads; /* host threads for the setup's sparse products (0: all hardware
                         threads, 1: serial); results do not depend on it */
+  int auto_cycle;    /* 1: at upload, without timing, every AMG level with at most 256K
+                        nonzeros in the fused form and the dense tail on the level above
+                        the coarsest when it has at most 512 rows (see hpdg_operator_tune):
+                        fewer launches per V-cycle, for callers that do not run the
+                        autotuner (many small solves); the same operator, other rounding */
 } hpdg_operator_opts;
 
 /* Builds the operator and the preconditioner (host setup, then upload):

@@ -34,7 +34,7 @@ class Opts(C.Structure):
     _fields_ = [("form", C.c_int), ("penalty_rule", C.c_int), ("eta", C.c_double),
                 ("prec_fp32", C.c_int), ("remark_relax", C.c_int), ("jb_only", C.c_int),
                 ("max_block", C.c_int), ("max_nrhs", C.c_int), ("host_only", C.c_int), ("no_prec", C.c_int),
-                ("graph", C.c_int), ("setup_threads", C.c_int)]
+                ("graph", C.c_int), ("setup_threads", C.c_int), ("auto_cycle", C.c_int)]
 
 
 class SolveInfo(C.Structure):
@@ -147,14 +147,14 @@ class Operator:
 
     def __init__(self, mesh: Mesh, form="sipg", penalty_rule=0, eta=1.0, prec_fp32=False,
                  remark_relax=False, jb_only=False, max_block=0, max_nrhs=1, host_only=False,
-                 no_prec=False, graph=False, setup_threads=0, stream=None):
+                 no_prec=False, graph=False, setup_threads=0, auto_cycle=False, stream=None):
         L = lib()
         self.mesh = mesh
         self.ndof = mesh.ndof
         self.max_nrhs = max_nrhs
         o = Opts(0 if form == "sipg" else 1 if form == "br2" else -1, penalty_rule, float(eta),
                  int(prec_fp32), int(remark_relax), int(jb_only), int(max_block), int(max_nrhs),
-                 int(host_only), int(no_prec), int(graph), int(setup_threads))
+                 int(host_only), int(no_prec), int(graph), int(setup_threads), int(auto_cycle))
         h = C.c_void_p()
         _check(L.hpdg_setup_operator(mesh.h, C.byref(o), C.c_void_p(0) if host_only else _stream(stream),
                                      C.byref(h)))

@@ -211,6 +211,14 @@ struct hpdg_operator {
   int use_graph = 0;         // PCG chunks replayed from captured HIP graphs
   int epb = 1;               // elements per workgroup of the 2D element kernel
   int nm3 = 9;               // LDS size class of the 3D element kernel: largest n = p + 1 (7 or 9)
+  // host matrices of the fused levels and dense tails, built once and kept
+  // across uploads (the counting pass and the upload share them)
+  struct HostCycle {
+    bool fused = false, tail = false;
+    CSR M, U;
+    std::vector<double> T;
+  };
+  std::vector<HostCycle> hcyc;
   int fchunk = 16;           // face records per pass of the 2D element kernel
   int rhs_group = 1;         // right-hand sides per item of the 2D element kernel
   struct GraphEntry {
@@ -408,6 +416,9 @@ static void spd_inverse(std::vector<double>& A, int n) {
 
 constexpr int64_t kFuseNnz = 4 << 20;   // levels the fused cycle is tried on (nonzeros of A)
 constexpr int kTailMax = 2048;          // largest level the dense tail is tried on (rows)
+constexpr int kAutoTail = 512;          // largest level auto_cycle gives the dense tail (rows)
+constexpr int64_t kAutoFuse = 256 << 10; // largest level auto_cycle fuses (nonzeros of A): small,
+                                         // launch-bound levels whose products are cheap to form
 template <typename T>
 static void set_tail(hpdg_operator* op, size_t l, bool on);
 
@@ -465,7 +476,14 @@ template <typename T>
 static void set_fused(hpdg_operator* op, size_t l, bool on) {
   LevelDev& D = op->lv[l];
   if (on && !D.has_fused) {
-    fused_mats(op->host.amg.lv[l], D.hM, D.hU);
+    if (op->hcyc.size() < op->lv.size()) op->hcyc.resize(op->lv.size());
+    auto& hc = op->hcyc[l];
+    if (!hc.fused) {
+      fused_mats(op->host.amg.lv[l], hc.M, hc.U);
+      hc.fused = true;
+    }
+    D.hM = hc.M;
+    D.hU = hc.U;
     upload_csr<T>(D.hM, D.M);
     upload_csr<T>(D.hU, D.U);
     D.has_fused = 1;
@@ -538,6 +556,15 @@ static void upload_prec(hpdg_operator* op) {
   if (std::getenv("HPDG_DENSE_TAIL") && !g_dry && op->lv.size() >= 2 && op->ncoarse > 0 &&
       op->lv[op->lv.size() - 2].A.nrows <= kTailMax)
     set_tail<T>(op, op->lv.size() - 2, true);
+  // auto_cycle: fused levels and a small dense tail without timing (also in
+  // the counting pass, so their bytes are counted; the levels are rebuilt at
+  // every upload)
+  if (op->opts.auto_cycle && op->lv.size() >= 2) {
+    const size_t nl = op->lv.size();
+    if (op->ncoarse > 0 && op->lv[nl - 2].A.nrows <= kAutoTail) set_tail<T>(op, nl - 2, true);
+    for (size_t l = 0; l + 1 < nl; ++l)
+      if (!op->lv[l].use_tail && op->lv[l].A.nnz <= kAutoFuse) set_fused<T>(op, l, true);
+  }
   op->rT.alloc((size_t)op->ndof * op->max_nrhs * sizeof(T));
   op->zT.alloc((size_t)op->ndof * op->max_nrhs * sizeof(T));
 }
@@ -1019,11 +1046,23 @@ static void set_tail(hpdg_operator* op, size_t l, bool on) {
     return;
   }
   if (D.use_tail) return;
+  if (op->hcyc.size() < op->lv.size()) op->hcyc.resize(op->lv.size());
+  auto& hc = op->hcyc[l];
+  if (hc.tail) {
+    std::vector<T> tv(hc.T.begin(), hc.T.end());
+    D.tail.upload(tv);
+    D.use_tail = 1;
+    return;
+  }
   const AMGLevel& L = op->host.amg.lv[l];
   const int64_t n = L.A.nrows, nc = op->ncoarse;
   const std::vector<double>& Cinv = op->host.amg.coarse_inv;
-  CSR M, U;
-  fused_mats(L, M, U);
+  if (!hc.fused) {
+    fused_mats(L, hc.M, hc.U);
+    hc.fused = true;
+  }
+  const CSR& M = hc.M;
+  const CSR& U = hc.U;
   // CM = C M  (nc x n, dense)
   std::vector<double> CM((size_t)nc * n, 0.0);
   for (int64_t i = 0; i < nc; ++i)
@@ -1049,6 +1088,8 @@ static void set_tail(hpdg_operator* op, size_t l, bool on) {
   std::vector<T> tv(Tl.begin(), Tl.end());
   D.tail.upload(tv);
   D.use_tail = 1;
+  hc.T.swap(Tl);
+  hc.tail = true;
 }
 
 // fused level (one RHS): two launches instead of four, same V(1,1) steps

@@ -134,6 +134,9 @@ class Server:
     keep_x       return each solution on the host
     min_batch    hold admission until this many requests are prepared (or no
                  more can be: all prepared, or a worker waits for memory)
+    auto_cycle   fused V-cycle levels and a small dense tail without timing
+                 (fewer launches per iteration; the solves are small and
+                 launch bound)
     graph        replay each solve's chunks of CG iterations from HIP graphs
                  (one launch per chunk instead of one per kernel). A capture
                  must not overlap device calls of other threads on the legacy
@@ -142,7 +145,7 @@ class Server:
     """
 
     def __init__(self, max_active=16, mem_budget=64 << 30, workers=8, prec_fp32=True, max_block=256,
-                 realtime=True, keep_x=False, min_batch=1, graph=False):
+                 realtime=True, keep_x=False, min_batch=1, graph=False, auto_cycle=True):
         self.max_active = max_active
         self.gate = MemoryGate(mem_budget)
         self.workers = workers
@@ -152,6 +155,7 @@ class Server:
         self.keep_x = keep_x
         self.min_batch = min_batch
         self.graph = graph
+        self.auto_cycle = auto_cycle
         self._dev_lock = threading.Lock() if graph else None
         self.max_concurrent = 0
 
@@ -165,6 +169,7 @@ class Server:
             eta = req.eta if req.eta is not None else (1.0 if req.form == "sipg" else 0.0)
             op = Operator(mesh, form=req.form, eta=eta, prec_fp32=self.prec_fp32, host_only=True,
                           max_block=self.max_block if mesh.dim == 3 else 0, graph=self.graph,
+                          auto_cycle=self.auto_cycle,
                           setup_threads=1)     # the workers already run setups in parallel
             res.ndof = mesh.ndof
             nbytes = op.device_bytes() + 3 * 8 * mesh.ndof

@@ -475,6 +475,29 @@ def test_dense_vcycle_tail(monkeypatch, name, fp32, nr):
     assert info["converged"] and info["true_rel_res"] <= 1e-8
 
 
+@pytest.mark.parametrize("name", ["rand2", "rand3"])
+@pytest.mark.parametrize("fp32", [False, True])
+def test_auto_cycle(name, fp32):
+    """auto_cycle (fused levels and the dense tail chosen without timing, as
+    the server builds its operators): B against the oracle's cycle, and the
+    solve."""
+    md = MESHES[name]()
+    m = O.Mesh(md)
+    opts = O.Opts("sipg", 0, 1.0)
+    cap = 128 if m.dim == 3 else 0
+    op = G.Operator(G.Mesh(md), prec_fp32=fp32, max_block=cap, auto_cycle=True)
+    pc = precond.Preconditioner(m, opts, max_block=cap)
+    r = np.random.default_rng(93).standard_normal(m.ndof)
+    z = torch.empty(m.ndof, dtype=torch.float64, device="cuda")
+    op.apply_B(_dev(r), z)
+    assert _rel(_host(z), pc.apply(r)) <= (1e-5 if fp32 else 1e-12)
+    b = torch.empty_like(z)
+    op.rhs(_dev(r), b)
+    x = torch.zeros_like(b)
+    info = op.pcg_solve(b, x, rtol=1e-8, maxit=1000)[0]
+    assert info["converged"] and info["true_rel_res"] <= 1e-8
+
+
 @pytest.mark.parametrize("form", ["sipg", "br2"])
 def test_simplified_preconditioner(form):
     """jb_only (point Jacobi on all of V_B plus B_C, the simplified

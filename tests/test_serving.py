@@ -91,6 +91,9 @@ def test_device_bytes_counting_pass():
     assert o4.device_bytes() > b64
     # still host-only: operator calls are refused without device work
     assert o64.summary()["device_bytes"] == 0
+    # fused levels and the dense tail add their matrices to the count
+    oa = G.Operator(m, host_only=True, auto_cycle=True)
+    assert oa.device_bytes() > b64
 
 
 def test_summarize():
@@ -104,10 +107,12 @@ def test_summarize():
 
 # ------------------------------------------------------------------ GPU
 def alone(req, prec_fp32=True):
+    """The blocking solve of a request with the server's operator options."""
     import torch
     m = G.Mesh(req.mesh)
     eta = 1.0 if req.form == "sipg" else 0.0
-    op = G.Operator(m, form=req.form, eta=eta, prec_fp32=prec_fp32, max_block=256 if m.dim == 3 else 0)
+    op = G.Operator(m, form=req.form, eta=eta, prec_fp32=prec_fp32, max_block=256 if m.dim == 3 else 0,
+                    auto_cycle=True)
     f = torch.from_numpy(np.ascontiguousarray(req.f)).cuda()
     b = torch.empty_like(f)
     op.rhs(f, b)
