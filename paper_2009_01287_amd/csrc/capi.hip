@@ -1370,14 +1370,23 @@ static int tune_all(hpdg_operator* op, hipStream_t s, int64_t* report, int cap) 
     set_fused<T>(op, l, false);
     const double t0 = time_cycle();
     set_fused<T>(op, l, true);
-    // row binning of the two fused products, then the fused cycle
+    // row binning of the two fused products, each timed alone; then the
+    // fused cycle, which keeps the default binning unless the tuned one is
+    // faster there too (a product timed alone runs from a hot cache)
     LevelDev& F = op->lv[l];
     LevelDev& FC = op->lv[l + 1];
+    const double t_fd = time_cycle();
     int64_t um[6], uu[6];
     tune_csr<T>(F.hM, F.M, F.b.as<T>(), FC.b.as<T>(), s, um);
     tune_csr<T>(F.hU, F.U, F.b.as<T>(), F.x.as<T>(), s, uu,
                 [&]() { spmv<T, 5>(F.U, 1, F.b.as<T>(), FC.x.as<T>(), nullptr, nullptr, F.x.as<T>(), s); });
-    const double t1 = time_cycle();
+    double t1 = time_cycle();
+    if (!(t1 < t_fd)) {
+      bin_rows(F.hM, F.M, kLongRow, 0);
+      bin_rows(F.hU, F.U, kLongRow, 0);
+      uu[3] = F.U.lpr;
+      t1 = t_fd;
+    }
     const bool keep = t1 < kTuneMargin * t0;
     if (!keep) set_fused<T>(op, l, false);
     int64_t* r = slot(5, l);
@@ -1637,7 +1646,10 @@ static int apply_B_any(hpdg_operator* op, const double* in, double* outv, int nr
 
 // final stage of a dot product whose per-block shares are already in part
 static void dot_final(hpdg_operator* op, int nparts, int mode, const CGScal& S, hipStream_t s) {
-  hipLaunchKernelGGL(k_dot_final_ep, dim3(1), dim3(256), 0, s, nparts, 1, op->part.as<double>(), mode, S);
+  if (mode == EP_PAP)
+    hipLaunchKernelGGL(k_dot_final_pap, dim3(1), dim3(256), 0, s, nparts, op->part.as<double>(), S);
+  else
+    hipLaunchKernelGGL(k_dot_final_ep, dim3(1), dim3(256), 0, s, nparts, 1, op->part.as<double>(), mode, S);
 }
 
 
@@ -1707,7 +1719,7 @@ static void pcg_iters(hpdg_operator* op, int k, hipStream_t s) {
       hipLaunchKernelGGL(k_cg_update_rr, dim3(nblk(n)), dim3(256), 0, s, n, S.alpha, p, Ap, R.x, r, part);
       double* part2 = part + part_off2(op);
       const int nb = apply_B_any(op, r, z, nrhs, s, part2);
-      hipLaunchKernelGGL(k_dot_final2_ep, dim3(1), dim3(256), 0, s, (int)nblk(n), part, EP_RR, nb, part2, EP_RZ, S);
+      hipLaunchKernelGGL(k_dot_final_rr_rz, dim3(1), dim3(256), 0, s, (int)nblk(n), part, nb, part2, S);
     } else {
       // the update writes the per-RHS shares of r'r (on the grid of the dot
       // kernels, so they are bitwise those of a separate pass)

@@ -815,24 +815,83 @@ __global__ __launch_bounds__(256) void k_dot_final_ep(int nblocks, int nrhs, con
   if (t < nrhs) cg_epilogue(mode, t, sm[t], S);
 }
 
-// two final stages (one RHS) in one launch: shares a -> epilogue ma, then
-// shares b -> epilogue mb, each summed in a fixed order
-__global__ __launch_bounds__(256) void k_dot_final2_ep(int na, const double* __restrict__ pa, int ma, int nb,
-                                                       const double* __restrict__ pb, int mb, CGScal S) {
+// The two final stages of every CG iteration (one RHS) with their epilogues
+// specialised: the scalars an epilogue reads are loaded at the start, beside
+// the share loads, instead of after the reduction (the generic epilogue
+// reloads them after its own stores, as the scalar arrays may alias). The
+// sums and the updates are those of k_dot_final_ep with cg_epilogue.
+//
+// p'Ap -> pAp, the breakdown flags, alpha = rz / p'Ap while active
+__global__ __launch_bounds__(256) void k_dot_final_pap(int nblocks, const double* __restrict__ part, CGScal S) {
   __shared__ double sm[256];
   const int t = threadIdx.x;
+  const int act0 = S.act[0];
+  const double rz = S.rz[0];
+  sm[t] = ordered_sum(part, t, 256, nblocks, 1, 0);
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if (t < w) sm[t] += sm[t + w];
+    __syncthreads();
+  }
+  if (t == 0) {
+    const double v = sm[0];
+    int act = act0;
+    S.pAp[0] = v;
+    if (act && !(v > 0.0)) {
+      S.err[0] = 1;
+      S.act[0] = 0;
+      act = 0;
+    }
+    S.alpha[0] = act ? rz / v : 0.0;
+  }
+}
+
+// r'r (shares pa) then r'z (shares pb): the residual norm, the iteration
+// count and alpha's history, the convergence test, then beta, rz and beta's
+// history while active
+__global__ __launch_bounds__(256) void k_dot_final_rr_rz(int na, const double* __restrict__ pa, int nb,
+                                                         const double* __restrict__ pb, CGScal S) {
+  __shared__ double sm[256];
+  const int t = threadIdx.x;
+  const int act0 = S.act[0], it0 = S.iters[0];
+  const double tol2 = S.tol2[0], bb = S.bb[0], rz = S.rz[0], alpha = S.alpha[0];
+  double v[2];
   for (int pass = 0; pass < 2; ++pass) {
-    const int n = pass ? nb : na;
-    const double* part = pass ? pb : pa;
-    double s = ordered_sum(part, t, 256, n, 1, 0);
-    sm[t] = s;
+    sm[t] = ordered_sum(pass ? pb : pa, t, 256, pass ? nb : na, 1, 0);
     __syncthreads();
     for (int w = 128; w >= 1; w >>= 1) {
       if (t < w) sm[t] += sm[t + w];
       __syncthreads();
     }
-    if (t == 0) cg_epilogue(pass ? mb : ma, 0, sm[0], S);
+    v[pass] = sm[0];
     __syncthreads();
+  }
+  if (t == 0) {
+    int act = act0, it = it0;
+    S.rr[0] = v[0];
+    if (act) {
+      if (it < S.maxit) S.ahist[(int64_t)it * S.hs] = alpha;
+      it = it + 1;
+      S.iters[0] = it;
+      if (!(v[0] > tol2 * bb)) {
+        S.act[0] = 0;
+        act = 0;
+      }
+    }
+    if (act) {
+      if (!(v[1] > 0.0)) {
+        S.err[0] = 1;
+        S.act[0] = 0;
+        S.beta[0] = 0.0;
+      } else {
+        const double b = v[1] / rz;
+        S.beta[0] = b;
+        S.rz[0] = v[1];
+        if (it - 1 < S.maxit) S.bhist[(int64_t)(it - 1) * S.hs] = b;
+      }
+    } else {
+      S.beta[0] = 0.0;
+    }
   }
 }
 
