@@ -196,6 +196,7 @@ struct hpdg_operator {
   int max_blk = 0;           // largest V_e block
   int lprb = 16;             // lanes per V_e block row in the B front (one RHS)
   int no_mfma = 0;           // HPDG_NO_MFMA=1: V_e block solves for many RHS without the matrix cores
+  int no_fused_multi = 0;    // HPDG_NO_FUSED_MULTI=1: fused V-cycle levels for one RHS only
   DevCSR P, PT;
   std::vector<LevelDev> lv;
   DevBuf coarse;
@@ -842,6 +843,7 @@ extern "C" hpdg_status hpdg_setup_operator(const hpdg_mesh* mh, const hpdg_opera
     if (const char* v = std::getenv("HPDG_ELEM2D_FCHUNK")) op->fchunk = std::atoi(v) == 8 ? 8 : std::atoi(v) == 32 ? 32 : 16;
     if (const char* v = std::getenv("HPDG_ELEM2D_RHSGROUP")) op->rhs_group = std::max(1, std::atoi(v));
     if (const char* v = std::getenv("HPDG_NO_MFMA")) op->no_mfma = std::atoi(v) != 0;
+    if (const char* v = std::getenv("HPDG_NO_FUSED_MULTI")) op->no_fused_multi = std::atoi(v) != 0;
     if (!op->no_prec) {
       PrecHost& H = op->host;
       H.diag = dg_diagonal(M, oo);
@@ -1018,11 +1020,10 @@ static void spmv(const DevCSR& A, int nrhs, const T* x, const T* b, const T* d, 
       case 8: spmv_launch<T, MODE, 8>(A, x, b, d, xo, y, s); break;
       default: spmv_launch<T, MODE, 16>(A, x, b, d, xo, y, s); break;
     }
-  } else if constexpr (MODE == 5) {
-    throw Error(HPDG_E_UNSUPPORTED, "two-vector product with several right-hand sides");
   } else {
+    // MODE 5: the first nrows columns read x, the others b
     int64_t nt = (int64_t)A.nrows * nrhs;
-    hipLaunchKernelGGL((k_spmm<T, MODE>), dim3(nblk(nt)), dim3(256), 0, s, A.nrows, nrhs, A.ptr.as<int32_t>(),
+    hipLaunchKernelGGL((k_spmm<T, MODE>), dim3(nblk(nt)), dim3(256), 0, s, A.nrows, nrhs, A.nrows, A.ptr.as<int32_t>(),
                        A.idx.as<int32_t>(), A.val.as<T>(), x, b, d, xo, y);
   }
 }
@@ -1094,12 +1095,12 @@ static void set_tail(hpdg_operator* op, size_t l, bool on) {
 
 // fused level (one RHS): two launches instead of four, same V(1,1) steps
 template <typename T>
-static void vcycle_fused(hpdg_operator* op, size_t l, hipStream_t s) {
+static void vcycle_fused(hpdg_operator* op, size_t l, int nrhs, hipStream_t s) {
   LevelDev& L = op->lv[l];
   LevelDev& C = op->lv[l + 1];
-  spmv<T, 0>(L.M, 1, L.b.as<T>(), nullptr, nullptr, nullptr, C.b.as<T>(), s);
-  vcycle<T>(op, l + 1, 1, s);
-  spmv<T, 5>(L.U, 1, L.b.as<T>(), C.x.as<T>(), nullptr, nullptr, L.x.as<T>(), s);
+  spmv<T, 0>(L.M, nrhs, L.b.as<T>(), nullptr, nullptr, nullptr, C.b.as<T>(), s);
+  vcycle<T>(op, l + 1, nrhs, s);
+  spmv<T, 5>(L.U, nrhs, L.b.as<T>(), C.x.as<T>(), nullptr, nullptr, L.x.as<T>(), s);
 }
 
 // x = C b for a dense n x n matrix and nrhs > 1 interleaved right-hand sides:
@@ -1125,8 +1126,8 @@ static void vcycle(hpdg_operator* op, size_t l, int nrhs, hipStream_t s) {
       dense_many<T>(op, n, nrhs, L.tail.as<T>(), L.b.as<T>(), L.x.as<T>(), s);
     return;
   }
-  if (nrhs == 1 && l + 1 < op->lv.size() && op->lv[l].fused) {
-    vcycle_fused<T>(op, l, s);
+  if (l + 1 < op->lv.size() && op->lv[l].fused && (nrhs == 1 || !op->no_fused_multi)) {
+    vcycle_fused<T>(op, l, nrhs, s);
     return;
   }
   LevelDev& L = op->lv[l];

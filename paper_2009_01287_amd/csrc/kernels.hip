@@ -1392,7 +1392,7 @@ __global__ __launch_bounds__(256) void k_spmv(int nlong, int nlong_blk, int nsho
 
 // same with nrhs interleaved columns: one thread per (row, rhs)
 template <typename T, int MODE>
-__global__ __launch_bounds__(256) void k_spmm(int nrows, int nrhs, const int32_t* __restrict__ ptr,
+__global__ __launch_bounds__(256) void k_spmm(int nrows, int nrhs, int nsplit, const int32_t* __restrict__ ptr,
                                               const int32_t* __restrict__ idx, const T* __restrict__ val,
                                               const T* __restrict__ x, const T* __restrict__ b,
                                               const T* __restrict__ d, T* __restrict__ xo, T* __restrict__ y) {
@@ -1403,12 +1403,15 @@ __global__ __launch_bounds__(256) void k_spmm(int nrows, int nrhs, const int32_t
   T acc = 0;
 #pragma unroll 4
   for (int q = ptr[row]; q < ptr[row + 1]; ++q) {
-    int64_t j = idx[q];
-    T xv = MODE == 3 ? d[j] * x[j * nrhs + c] : x[j * nrhs + c];
+    const int64_t j = idx[q];
+    T xv;
+    if (MODE == 3) xv = d[j] * x[j * nrhs + c];
+    else if (MODE == 5) xv = *(j < nsplit ? x + j * nrhs + c : b + (j - nsplit) * nrhs + c);
+    else xv = x[j * nrhs + c];
     acc += val[q] * xv;
   }
   const int64_t o = row * nrhs + c;
-  if (MODE == 0) y[o] = acc;
+  if (MODE == 0 || MODE == 5) y[o] = acc;
   else if (MODE == 1) y[o] = b[o] - acc;
   else if (MODE == 2) y[o] = b[o] + acc;
   else if (MODE == 3) {

@@ -427,13 +427,20 @@ def test_fused_vcycle_levels(monkeypatch, name, fp32):
     m = O.Mesh(md)
     opts = O.Opts("sipg", 0, 1.0)
     cap = 128 if m.dim == 3 else 0
-    op = G.Operator(G.Mesh(md), prec_fp32=fp32, max_block=cap)
+    op = G.Operator(G.Mesh(md), prec_fp32=fp32, max_block=cap, max_nrhs=4)
     assert len(op.amg_levels()) >= 2
     r = np.random.default_rng(61).standard_normal(m.ndof)
     z = torch.empty(m.ndof, dtype=torch.float64, device="cuda")
     op.apply_B(_dev(r), z)
     pc = precond.Preconditioner(m, opts, max_block=cap)
     assert _rel(_host(z), pc.apply(r)) <= (1e-5 if fp32 else 1e-12)
+    # the same fused levels for four interleaved right-hand sides
+    R4 = np.random.default_rng(62).standard_normal((m.ndof, 4))
+    Z4 = torch.empty(m.ndof * 4, dtype=torch.float64, device="cuda")
+    op.apply_B(_dev(R4.reshape(-1)), Z4, nrhs=4)
+    Z4h = _host(Z4).reshape(m.ndof, 4)
+    for c in range(4):
+        assert _rel(Z4h[:, c], pc.apply(R4[:, c])) <= (1e-5 if fp32 else 1e-12)
     b = torch.empty_like(z)
     op.rhs(_dev(r), b)
     x = torch.zeros_like(b)
