@@ -57,9 +57,11 @@ def main():
     ap.add_argument("--serving-auto-cycle", type=int, default=1,
                     help="serving: 1 builds fused V-cycle levels and a small dense tail without timing")
     ap.add_argument("--serving-prec", default="mixed", choices=["mixed", "fp64", "both"])
-    ap.add_argument("--study", choices=["eta"], default=None,
+    ap.add_argument("--study", choices=["eta", "random"], default=None,
                     help="eta: penalty-dependence study (SIPG and BR2, eta = 10..1e4, full B against the "
-                         "simplified B with point Jacobi on all of V_B); one JSON line per solve, then a summary")
+                         "simplified B with point Jacobi on all of V_B); random: random and uniform "
+                         "refinement, unlimited and 1-irregular meshes; one JSON line per mesh and "
+                         "preconditioner, then a summary")
     ap.add_argument("--apply-only", action="store_true",
                     help="only run apply_A --apply-reps times and one calibration copy of "
                          "256 MiB (for hardware-counter runs), then exit")
@@ -78,6 +80,8 @@ def main():
     cfg = args.config
     if args.study == "eta":
         return eta_study(args)
+    if args.study == "random":
+        return random_study(args)
     if cfg == 5:
         return serve_bench(args)
     c = H.CONFIGS[cfg]
@@ -324,6 +328,46 @@ def eta_study(args):
                 print(json.dumps(row), flush=True)
     print(json.dumps({"study": "penalty dependence", "ndof": mesh.ndof, "elements": int(len(md["level"])),
                       "degrees": "5..8", "coefficient": "1 or 20 by base cell", "rtol": 1e-8, "rows": rows}))
+
+
+def random_study(args):
+    """Random refinement (paper Sec. 4.3, Table 3): one to three rounds of
+    random refinement (each leaf split with probability 0.5) with and without
+    the 1-irregular limit, and one round followed by uniform refinements, on
+    an 8 x 8 base mesh with degrees 2..6 and coefficient 1 or 20; SIPG with
+    eta = 100 (sigma = eta k p_e^2 / h_e), PCG to 1e-8 in FP64 with the full
+    and with the simplified preconditioner. Reports DOFs, iterations, Lanczos
+    condition estimates, the number of spaces V_e and the largest of them."""
+    import torch
+
+    import hpinputs as H
+    import paper_2009_01287_amd as G
+    cases = [("initial mesh", 0, 0, False), ("1 random", 1, 0, False), ("1 random, 1 uniform", 1, 1, False),
+             ("1 random, 2 uniform", 1, 2, False), ("2 random", 2, 0, False), ("2 random (1-irregular)", 2, 0, True),
+             ("3 random", 3, 0, False), ("3 random (1-irregular)", 3, 0, True)]
+    rows = []
+    for name, rounds, uniform, one in cases:
+        md = H.random_refinement_mesh(8, rounds, uniform=uniform, one_irregular=one)
+        mesh = G.Mesh(md)
+        f = torch.from_numpy(H.gaussian_rhs(mesh.ndof, 1199)).cuda()
+        row = {"refinement": name, "ndof": mesh.ndof, "elements": int(len(md["level"])),
+               "max_level_jump": mesh.max_level_jump}
+        for variant in ("full", "simplified"):
+            op = G.Operator(mesh, form="sipg", penalty_rule=1, eta=100.0, jb_only=(variant == "simplified"))
+            if variant == "full":
+                sm = op.summary()
+                row["n_Ve"], row["max_dim_Ve"] = sm["nblocks"], sm["max_block"]
+            b = torch.empty_like(f)
+            op.rhs(f, b)
+            x = torch.zeros_like(b)
+            code, info = op.pcg_solve(b, x, rtol=1e-8, maxit=20000, raise_on_error=False)
+            row[variant + "_iters"] = int(info[0]["iters"])
+            row[variant + "_cond_est"] = float(info[0]["cond_est"])
+            row[variant + "_status"] = int(code)
+        rows.append(row)
+        print(json.dumps(row), flush=True)
+    print(json.dumps({"study": "random refinement", "base": "8 x 8", "degrees": "2..6",
+                      "coefficient": "1 or 20 by base cell", "eta": 100.0, "rtol": 1e-8, "rows": rows}))
 
 
 def serve_bench(args):

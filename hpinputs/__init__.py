@@ -195,6 +195,70 @@ def penalty_study_mesh(n_base=16, seed=1262, pmin=5, pmax=8):
     return m
 
 
+def _balance_1irregular(cells, dim):
+    """Refine leaves until any two leaves sharing a face (a piece of positive
+    measure) differ by at most one level (a 1-irregular mesh). Leaves are
+    (level, anchor); refinement only ever splits the coarser leaf of a
+    violating pair, so the result contains every refinement of the input."""
+    while True:
+        n = len(cells)
+        lev = np.array([c[0] for c in cells], dtype=np.int64)
+        anc = np.array([c[1] for c in cells], dtype=np.int64).reshape(n, dim)
+        fine = int(lev.max())
+        size = np.left_shift(1, fine - lev)                 # cell size at the finest level
+        lo = anc * size[:, None]
+        hi = lo + size[:, None]
+        split = np.zeros(n, dtype=bool)
+        for m in range(dim):
+            # pairs (i, j) with hi_i == lo_j in direction m and overlapping
+            # (positive measure) in the other directions
+            touch = hi[:, m][:, None] == lo[:, m][None, :]
+            for t in range(dim):
+                if t == m:
+                    continue
+                touch &= (lo[:, t][:, None] < hi[:, t][None, :]) & (lo[:, t][None, :] < hi[:, t][:, None])
+            ii, jj = np.nonzero(touch)
+            d = lev[ii] - lev[jj]
+            split[jj[d > 1]] = True                         # j coarser by more than one level
+            split[ii[d < -1]] = True
+        if not split.any():
+            return cells
+        nxt = []
+        for c, sp in zip(cells, split):
+            if sp:
+                nxt.extend((cl, ca, c[2]) for cl, ca in _children(c[0], c[1], dim))
+            else:
+                nxt.append(c)
+        cells = nxt
+
+
+def random_refinement_mesh(n_base, rounds, uniform=0, q=0.5, one_irregular=False, seed=1198,
+                           pmin=2, pmax=6, dim=2):
+    """Mesh of the random-refinement study: `rounds` rounds in which every
+    current leaf is split with probability q (optionally followed by the
+    refinements that make the mesh 1-irregular), then `uniform` uniform
+    refinements, then degrees drawn uniformly in {pmin..pmax}; coefficient 1
+    or 20 by the parity of the base cell's number, inherited by the children."""
+    rng = _rng(seed)
+    cells = [(c[0], c[1], i) for i, c in enumerate(_base_cells(dim, n_base))]
+    for _ in range(rounds):
+        u = rng.random(len(cells))
+        nxt = []
+        for (lev, a, b), ui in zip(cells, u):
+            if ui < q:
+                nxt.extend((cl, ca, b) for cl, ca in _children(lev, a, dim))
+            else:
+                nxt.append((lev, a, b))
+        cells = nxt
+        if one_irregular:
+            cells = _balance_1irregular(cells, dim)
+    for _ in range(uniform):
+        cells = [(cl, ca, c[2]) for c in cells for cl, ca in _children(c[0], c[1], dim)]
+    degree = rng.integers(pmin, pmax + 1, size=len(cells))
+    kcoef = np.array([1.0 if c[2] % 2 == 0 else 20.0 for c in cells])
+    return _pack(dim, n_base, [(c[0], c[1]) for c in cells], degree, kcoef)
+
+
 def config_mesh(cfg: int, scale: int = 1):
     """Mesh of a named workload. scale > 1 divides n_base (small variants of
     the same recipe for tests)."""

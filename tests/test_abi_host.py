@@ -153,3 +153,47 @@ def test_penalty_study_mesh():
     area = np.where(m["level"] == 0, 4, 1)
     assert area.sum() == 4 * 16 * 16
     assert np.array_equal(H.penalty_study_mesh()["degree"], m["degree"])   # seeded
+
+
+def _faces_touch(a, b, dim):
+    """Leaves a, b = (level, anchor) share a face piece of positive measure
+    (exact rational arithmetic on the unit cube)."""
+    from fractions import Fraction as F
+    la, aa = a
+    lb, ab = b
+    for m in range(dim):
+        a0, a1 = F(aa[m], 2 ** la), F(aa[m] + 1, 2 ** la)
+        b0, b1 = F(ab[m], 2 ** lb), F(ab[m] + 1, 2 ** lb)
+        if a1 == b0 or b1 == a0:
+            ok = True
+            for t in range(dim):
+                if t == m:
+                    continue
+                c0, c1 = F(aa[t], 2 ** la), F(aa[t] + 1, 2 ** la)
+                d0, d1 = F(ab[t], 2 ** lb), F(ab[t] + 1, 2 ** lb)
+                ok &= max(c0, d0) < min(c1, d1)
+            if ok:
+                return True
+    return False
+
+
+def test_random_refinement_one_irregular():
+    """The 1-irregular limit: no two face neighbours differ by more than one
+    level (brute force over all pairs), the leaves tile the domain, and the
+    unlimited mesh of the same recipe does have larger jumps."""
+    import hpinputs as H
+    for one in (True, False):
+        m = H.random_refinement_mesh(3, 3, one_irregular=one, seed=7)
+        leaves = [(int(l), tuple(int(v) for v in a)) for l, a in zip(m["level"], m["anchor"])]
+        assert sum(4.0 ** -l for l, _ in leaves) == pytest.approx(9.0)     # 3 x 3 base cells
+        jump = 0
+        for i in range(len(leaves)):
+            for j in range(i + 1, len(leaves)):
+                if _faces_touch(leaves[i], leaves[j], 2):
+                    jump = max(jump, abs(leaves[i][0] - leaves[j][0]))
+        if one:
+            assert jump <= 1
+        else:
+            assert jump >= 2
+    g = G.Mesh(H.random_refinement_mesh(3, 3, one_irregular=True, seed=7))
+    assert g.max_level_jump <= 1
