@@ -979,14 +979,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NM == 7 ? 7
   int sp[7];
 #pragma unroll
   for (int t = 0; t < 7; ++t) sp[t] = sptr[e * 6 + t];
-  const double* Mt = tab + TL.mk + (p * 2 + 0) * 81;
-  const double* Kt = tab + TL.mk + (p * 2 + 1) * 81;
+  // the 1D mass and stiffness of the element's degree, staged in the side-sum
+  // arrays, which the volume stage does not use (they are cleared after it)
+  {
+    const double* gMt = tab + TL.mk + (p * 2 + 0) * 81;
+    const double* gKt = tab + TL.mk + (p * 2 + 1) * 81;
+    for (int i = tid; i < n2; i += 256) {
+      (&sG1[0][0])[i] = gMt[i];
+      (&sG2[0][0])[i] = gKt[i];
+    }
+  }
+  const double* Mt = &sG1[0][0];
+  const double* Kt = &sG2[0][0];
   double* sX = sV0;
   for (int i = tid; i < n3; i += 256) sX[i] = x[(base + i) * nrhs + rhs];
-  for (int i = tid; i < 6 * F2; i += 256) {
-    (&sG1[0][0])[i] = 0.0;
-    (&sG2[0][0])[i] = 0.0;
-  }
   __syncthreads();
   // phase 1 (dimension 0) and the own traces
   double* sA = sV1;
@@ -1050,6 +1056,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NM == 7 ? 7
     }
   }
   __syncthreads();
+  // the side sums start at zero (the face stage's first barrier orders this
+  // before their first use)
+  for (int i = tid; i < 6 * F2; i += 256) {
+    (&sG1[0][0])[i] = 0.0;
+    (&sG2[0][0])[i] = 0.0;
+  }
   // face stage: work arrays in the volume buffers
   double* sTn = sV0;                 // [KF][F2]
   double* sDn = sV3;                 // [KF][F2]
