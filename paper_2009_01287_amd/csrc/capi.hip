@@ -891,8 +891,9 @@ extern "C" hpdg_status hpdg_setup_operator(const hpdg_mesh* mh, const hpdg_opera
       op->nconf = M.nconf;
       H.PT = csr_transpose(H.P);
       CSR AP = lor_times(M, H.P);
+      phase("lor A P");
       H.AC = csr_matmul(H.PT, AP);
-      phase("lor");
+      phase("lor P'(AP)");
       H.amg = amg_setup(H.AC);
       phase("amg");
     }

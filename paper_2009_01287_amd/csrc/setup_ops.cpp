@@ -363,13 +363,28 @@ struct ConfBuilder {
       double r = ((double)(pt.base[m] - lo) + (double)pt.scale[m] * pt.x[m]) / (double)S;
       lagrange_eval(basis(deg).x, r, L[j]);
     }
+    // only the entity nodes whose 1D factors are all nonzero contribute (a
+    // point on the entity's own nodes has one); visited in increasing node
+    // order, so the sums are formed in the same order as a full sweep
+    int nz[3][kMaxN], nnz[3] = {1, 1, 1}, total = 1;
+    for (int j = 0; j < k; ++j) {
+      nnz[j] = 0;
+      for (int i = 0; i < n; ++i)
+        if (L[j][i] != 0.0) nz[j][nnz[j]++] = i;
+      total *= nnz[j];
+    }
     SRow acc;
-    int ng = 1;
-    for (int j = 0; j < k; ++j) ng *= n;
-    for (int g = 0; g < ng; ++g) {
+    for (int t = 0; t < total; ++t) {
       double c = 1.0;
-      int gg = g;
-      for (int j = 0; j < k; ++j) { c *= L[j][gg % n]; gg /= n; }
+      int tt = t, g = 0, stride = 1;
+      for (int j = 0; j < k; ++j) {
+        const int a = nz[j][tt % nnz[j]];
+        tt /= nnz[j];
+        c *= L[j][a];
+        g += a * stride;
+        stride *= n;
+      }
+      if (total == 1 && c == 1.0) return C[g];   // rows in C are already compact
       merge(acc, C[g], c);
     }
     compact(acc);
@@ -598,12 +613,15 @@ std::vector<std::vector<int64_t>> edge_spaces(const Mesh& M, const std::vector<i
 // A~_K: Q1 stiffness on the Cartesian sub-grid of the GL nodes of K, times
 // k_K (Sec. 3.4). Each sub-cell box with sides D_m contributes
 // sum_m (prod_{j!=m} D_j / D_m) (k1 in dim m, m1 in the other dims).
+// LOR element matrix as a 3^d stencil per node: A[r * 3^d + s] couples node r
+// with node r + delta(s), delta_m = (s / 3^m) % 3 - 1 (the Q1 sub-cells only
+// couple nodes that differ by at most one in each index)
 static void lor_elem(const Mesh& M, int e, std::vector<double>& A) {
   int d = M.dim, p = M.p[e], n = p + 1;
   const Basis1D& B = basis(p);
-  int nd = 1;
-  for (int m = 0; m < d; ++m) nd *= n;
-  A.assign((size_t)nd * nd, 0.0);
+  int nd = 1, ns = 1;
+  for (int m = 0; m < d; ++m) { nd *= n; ns *= 3; }
+  A.assign((size_t)nd * ns, 0.0);
   const double k1[2][2] = {{1, -1}, {-1, 1}};
   const double m1[2][2] = {{1.0 / 3, 1.0 / 6}, {1.0 / 6, 1.0 / 3}};
   int ncell = 1;
@@ -620,19 +638,24 @@ static void lor_elem(const Mesh& M, int e, std::vector<double>& A) {
       for (int m = 0; m < d; ++m) { g += (ci[m] + ((v >> m) & 1)) * mul; mul *= n; }
       gidx[v] = g;
     }
+    double coef[3];   // product of the other extents over this one
+    for (int m = 0; m < d; ++m) {
+      coef[m] = 1.0;
+      for (int j = 0; j < d; ++j)
+        if (j != m) coef[m] *= D[j];
+      coef[m] /= D[m];
+    }
     for (int a = 0; a < nv; ++a)
       for (int b = 0; b < nv; ++b) {
         double s = 0;
         for (int m = 0; m < d; ++m) {
-          double coef = 1.0;
-          for (int j = 0; j < d; ++j)
-            if (j != m) coef *= D[j];
-          coef /= D[m];
-          double t = coef;
+          double t = coef[m];
           for (int j = 0; j < d; ++j) t *= (j == m ? k1 : m1)[(a >> j) & 1][(b >> j) & 1];
           s += t;
         }
-        A[(size_t)gidx[a] * nd + gidx[b]] += M.k[e] * s;
+        int st = 0, mul = 1;
+        for (int m = 0; m < d; ++m) { st += (((b >> m) & 1) - ((a >> m) & 1) + 1) * mul; mul *= 3; }
+        A[(size_t)gidx[a] * ns + st] += M.k[e] * s;
       }
   }
 }
@@ -650,12 +673,18 @@ CSR lor_times(const Mesh& M, const CSR& P) {
     std::vector<double> A;
     for (int64_t e = e0; e < e1; ++e) {
       lor_elem(M, (int)e, A);
-      int64_t nd = M.off[e + 1] - M.off[e];
+      const int64_t nd = M.off[e + 1] - M.off[e];
+      const int n = M.p[e] + 1, ns = M.dim == 3 ? 27 : 9;
+      const int64_t str[3] = {1, n, (int64_t)n * n};
       for (int64_t r = 0; r < nd; ++r) {
         cols.clear();
-        for (int64_t c = 0; c < nd; ++c) {
-          double a = A[(size_t)r * nd + c];
+        // stencil entries in increasing column order; those off the element
+        // are never written and stay zero
+        for (int st = 0; st < ns; ++st) {
+          double a = A[(size_t)r * ns + st];
           if (a == 0.0) continue;
+          int64_t c = r;
+          for (int m = 0, q = st; m < M.dim; ++m, q /= 3) c += (q % 3 - 1) * str[m];
           int64_t row = M.off[e] + c;
           for (int64_t q = P.ptr[row]; q < P.ptr[row + 1]; ++q) {
             int32_t j = P.idx[q];
