@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <exception>
 #include <map>
 #include <numeric>
 
@@ -329,9 +330,9 @@ using SRow = std::vector<std::pair<int32_t, double>>;
 struct Pt { int64_t base[3], scale[3]; double x[3]; };
 
 struct ConfBuilder {
-  Mesh& M;
+  const Mesh& M;
   std::unordered_map<int, std::vector<SRow>> memo;
-  explicit ConfBuilder(Mesh& m) : M(m) {}
+  explicit ConfBuilder(const Mesh& m) : M(m) {}
 
   static void merge(SRow& acc, const SRow& r, double c) {
     if (c == 0.0) return;
@@ -445,31 +446,55 @@ struct ConfBuilder {
 
 CSR prolongation(Mesh& M) {
   M.build_entities();
-  ConfBuilder cb(M);
+  // element ranges in parallel, each with its own memo of entity rows (a
+  // row does not depend on what the memo already holds); ranges yield
+  // consecutive rows
+  const int T = std::max(1, setup_threads());
+  std::vector<std::vector<int64_t>> len(T);
+  std::vector<std::vector<int32_t>> idx(T);
+  std::vector<std::vector<double>> val(T);
+  std::vector<std::exception_ptr> err(T);
+  const Mesh& CM = M;
+  const int d = M.dim;
+  parallel_chunks(M.ne, [&](int64_t e0, int64_t e1, int t) {
+    try {
+      ConfBuilder cb(CM);
+      for (int64_t e = e0; e < e1; ++e) {
+        int p = CM.p[e], n = p + 1;
+        const Basis1D& B = basis(p);
+        int64_t nd = CM.off[e + 1] - CM.off[e];
+        for (int64_t r = 0; r < nd; ++r) {
+          int i[3] = {1, 1, 1};
+          multi_index(r, n, d, i);
+          int ti = 0, mul = 1;
+          for (int m = 0; m < d; ++m) {
+            const int tm = i[m] == 0 ? 0 : (i[m] == p ? 2 : 1);
+            ti += tm * mul;
+            mul *= 3;
+          }
+          int id = CM.resolve(CM.sub[(size_t)e * 27 + ti]);
+          Pt pt;
+          for (int m = 0; m < 3; ++m) { pt.base[m] = 0; pt.scale[m] = 0; pt.x[m] = 0; }
+          for (int m = 0; m < d; ++m) { pt.base[m] = CM.lo[3 * e + m]; pt.scale[m] = CM.sz[e]; pt.x[m] = B.x[i[m]]; }
+          SRow row = cb.eval(id, pt);
+          for (auto& [j, v] : row) { idx[t].push_back(j); val[t].push_back(v); }
+          len[t].push_back((int64_t)row.size());
+        }
+      }
+    } catch (...) {
+      err[t] = std::current_exception();
+    }
+  }, 64);
+  for (auto& x : err)
+    if (x) std::rethrow_exception(x);
   CSR P;
   P.nrows = M.ndof;
   P.ncols = M.nconf;
   P.ptr.assign(1, 0);
-  int d = M.dim;
-  for (int e = 0; e < M.ne; ++e) {
-    int p = M.p[e], n = p + 1;
-    const Basis1D& B = basis(p);
-    int64_t nd = M.off[e + 1] - M.off[e];
-    for (int64_t r = 0; r < nd; ++r) {
-      int i[3] = {1, 1, 1};
-      multi_index(r, n, d, i);
-      int t[3] = {1, 1, 1};
-      for (int m = 0; m < d; ++m) t[m] = i[m] == 0 ? 0 : (i[m] == p ? 2 : 1);
-      int ti = 0, mul = 1;
-      for (int m = 0; m < d; ++m) { ti += t[m] * mul; mul *= 3; }
-      int id = M.resolve(M.sub[(size_t)e * 27 + ti]);
-      Pt pt;
-      for (int m = 0; m < 3; ++m) { pt.base[m] = 0; pt.scale[m] = 0; pt.x[m] = 0; }
-      for (int m = 0; m < d; ++m) { pt.base[m] = M.lo[3 * e + m]; pt.scale[m] = M.sz[e]; pt.x[m] = B.x[i[m]]; }
-      SRow row = cb.eval(id, pt);
-      for (auto& [j, v] : row) { P.idx.push_back(j); P.val.push_back(v); }
-      P.ptr.push_back((int64_t)P.idx.size());
-    }
+  for (int t = 0; t < T; ++t) {
+    for (int64_t l : len[t]) P.ptr.push_back(P.ptr.back() + l);
+    P.idx.insert(P.idx.end(), idx[t].begin(), idx[t].end());
+    P.val.insert(P.val.end(), val[t].begin(), val[t].end());
   }
   return P;
 }
