@@ -159,7 +159,9 @@ hpdg_status hpdg_operator_device_bytes(hpdg_operator* op, int64_t* bytes);
  * (kind 0 A / 1 R / 2 P / 3 P^T / 4 element kernel / 5 fused V-cycle level /
  * 6 right-hand sides per element-kernel item, at the largest nrhs /
  * 7 lanes per V_e block row in the B front (one RHS) / 8 dense tail of the
- * V-cycle on the level above the coarsest (chosen lanes 1 if kept),
+ * V-cycle on the level above the coarsest (chosen lanes 1 if kept) / 10 3D
+ * element kernel dispatched by decreasing element cost (chosen lanes 1 if
+ * kept; the threshold column holds the ns of that order),
  * level, rows (ndof), nnz (elements), chosen threshold (records per pass),
  * chosen lanes (elements per workgroup; 1 if the level is fused), ns before,
  * ns after); *n rows written. A fused level (one RHS, at most 4M nonzeros)

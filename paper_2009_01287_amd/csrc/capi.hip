@@ -12,6 +12,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <numeric>
 #include <array>
 #include <string>
 #include <thread>
@@ -212,6 +213,8 @@ struct hpdg_operator {
   int use_graph = 0;         // PCG chunks replayed from captured HIP graphs
   int epb = 1;               // elements per workgroup of the 2D element kernel
   int nm3 = 9;               // LDS size class of the 3D element kernel: largest n = p + 1 (7 or 9)
+  DevBuf elem_perm;          // 3D elements by decreasing estimated cost
+  int use_perm = 0;          // 3D element kernel dispatched in that order (autotuned)
   // host matrices of the fused levels and dense tails, built once and kept
   // across uploads (the counting pass and the upload share them)
   struct HostCycle {
@@ -591,6 +594,19 @@ static void upload_device(hpdg_operator* op, hipStream_t s) {
   op->hh.upload(U.h);
   op->kk.upload(U.k);
   op->sptr.upload(U.sptr);
+  if (op->dim == 3) {
+    // cost estimate: (p+1)^4 for the volume, (p+1)^3 per face record
+    const int64_t ne = (int64_t)U.pd.size();
+    std::vector<int64_t> cost(ne);
+    for (int64_t e = 0; e < ne; ++e) {
+      const int64_t n = U.pd[e] + 1;
+      cost[e] = n * n * n * n + (int64_t)(U.sptr[e * 6 + 6] - U.sptr[e * 6]) * n * n * n;
+    }
+    std::vector<int32_t> perm(ne);
+    std::iota(perm.begin(), perm.end(), 0);
+    std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
+    op->elem_perm.upload(perm);
+  }
   op->recs.upload(U.recs);
   op->ftab.upload(U.ftab);
   build_tables(op, U.max_dlevel);
@@ -844,6 +860,7 @@ extern "C" hpdg_status hpdg_setup_operator(const hpdg_mesh* mh, const hpdg_opera
     if (const char* v = std::getenv("HPDG_ELEM2D_RHSGROUP")) op->rhs_group = std::max(1, std::atoi(v));
     if (const char* v = std::getenv("HPDG_NO_MFMA")) op->no_mfma = std::atoi(v) != 0;
     if (const char* v = std::getenv("HPDG_NO_FUSED_MULTI")) op->no_fused_multi = std::atoi(v) != 0;
+    if (const char* v = std::getenv("HPDG_ELEM3D_COST_ORDER")) op->use_perm = std::atoi(v) != 0;
     if (!op->no_prec) {
       PrecHost& H = op->host;
       H.diag = dg_diagonal(M, oo);
@@ -984,7 +1001,8 @@ static int apply_A_dev(hpdg_operator* op, const double* x, double* y, int nrhs, 
     auto kern = op->nm3 == 7 ? k_elem3d<7> : k_elem3d<9>;
     hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, s, op->ne, nrhs, op->form, op->off.as<int64_t>(),
                        op->pdeg.as<int8_t>(), op->hh.as<double>(), op->kk.as<double>(), op->sptr.as<int32_t>(),
-                       op->recs.as<FaceRec>(), op->ftab.as<double>(), op->tab.as<double>(), op->TL, x, y, pdot);
+                       op->recs.as<FaceRec>(), op->ftab.as<double>(), op->tab.as<double>(), op->TL, x, y, pdot,
+                       op->use_perm ? op->elem_perm.as<int32_t>() : nullptr);
     return pdot ? op->ne : 0;
   } else if (op->dim == 2) {
     launch_vol<2, 0>(op, nrhs, x, y, s);
@@ -1244,6 +1262,39 @@ static void tune_elem(hpdg_operator* op, hipStream_t s, int64_t* rep) {
   rep[4] = (int64_t)t_def; rep[5] = (int64_t)best;
 }
 
+// dispatch order of the 3D element kernel: mesh order with the XCD-aware
+// mapping, or the elements by decreasing estimated cost (results do not
+// depend on it)
+static void tune_elem_order(hpdg_operator* op, hipStream_t s, int64_t* rep) {
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  double* x = op->pv.as<double>();
+  double* y = op->Ap.as<double>();
+  HIPCHK(hipMemsetAsync(x, 0, op->pv.bytes, s));
+  auto time_it = [&]() {
+    for (int w = 0; w < 2; ++w) apply_A_dev(op, x, y, 1, s, nullptr);
+    HIPCHK(hipEventRecord(e0, s));
+    const int reps = 6;
+    for (int w = 0; w < reps; ++w) apply_A_dev(op, x, y, 1, s, nullptr);
+    HIPCHK(hipEventRecord(e1, s));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    return (double)ms * 1e6 / reps;
+  };
+  op->use_perm = 0;
+  const double t0 = time_it();
+  op->use_perm = 1;
+  const double t1 = time_it();
+  const bool keep = t1 < kTuneMargin * t0;
+  op->use_perm = keep ? 1 : 0;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  rep[0] = op->ndof; rep[1] = op->ne; rep[2] = (int64_t)t1; rep[3] = keep ? 1 : 0;
+  rep[4] = (int64_t)t0; rep[5] = (int64_t)(keep ? t1 : t0);
+}
+
 // right-hand sides per item of the 2D element kernel at the operator's
 // largest nrhs (results do not depend on it)
 static void tune_rhs_group(hpdg_operator* op, hipStream_t s, int64_t* rep) {
@@ -1299,6 +1350,7 @@ static int tune_all(hpdg_operator* op, hipStream_t s, int64_t* report, int cap) 
     tune_elem(op, s, slot(4, 0));
     if (op->max_nrhs > 1) tune_rhs_group(op, s, slot(6, 0));
   }
+  if (op->dim == 3 && !op->generic_faces) tune_elem_order(op, s, slot(10, 0));
   HIPCHK(hipMemsetAsync(op->rT.p, 0, op->rT.bytes, s));
   for (auto& L : op->lv) {
     HIPCHK(hipMemsetAsync(L.b.p, 0, L.b.bytes, s));

@@ -958,7 +958,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NM == 7 ? 7
                                                 const FaceRec* __restrict__ recs, const double* __restrict__ ftab,
                                                 const double* __restrict__ tab, TableLayout TL,
                                                 const double* __restrict__ x, double* __restrict__ y,
-                                                double* __restrict__ pdot) {
+                                                double* __restrict__ pdot, const int32_t* __restrict__ perm) {
   // LDS sized for degree <= NM - 1: volume buffers of NM^3 (reused by the
   // face stage once the volume is done), face slots of F2 = NM^2, KF = NM
   // face records per pass (KF slots of F2 fill a volume buffer)
@@ -969,9 +969,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NM == 7 ? 7
   __shared__ FaceRec sR[KF];
   __shared__ double sRed[4];
   const int per = (int)(gridDim.x >> 3);
-  const int item = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);   // (element, RHS)
+  // (element, RHS) items: XCD-aware mesh order, or with perm in dispatch
+  // order, element perm[i] for the i-th (heaviest first, so that the last
+  // workgroups to start are the short ones)
+  const int item = perm ? (int)blockIdx.x : (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
   if (item >= ne * nrhs) return;
-  const int e = item / nrhs, rhs = item - e * nrhs;
+  const int ei = item / nrhs, rhs = item - ei * nrhs;
+  const int e = perm ? perm[ei] : ei;
   const int tid = threadIdx.x;
   const int p = pdeg[e], n = p + 1, n2 = n * n, n3 = n2 * n;
   const double h = hh[e], k = kk[e];

@@ -284,7 +284,7 @@ def test_autotuned_binning_same_results(fp32):
     assert rep and {r["matrix"] for r in rep} >= {"A", "PT"}
     for r in rep:
         assert r["ns_tuned"] <= r["ns_default"]
-        if r["matrix"] in ("vcycle_fused", "vcycle_dense_tail"):
+        if r["matrix"] in ("vcycle_fused", "vcycle_dense_tail", "elem_order"):
             assert r["lanes"] in (0, 1)
         elif r["matrix"] == "elem_rhs_group":
             assert r["lanes"] in (1, 2, 4, 8, 16, 32, 64)
@@ -331,6 +331,36 @@ def test_elem2d_elements_per_workgroup_bitwise(monkeypatch, form, eta):
         out.append((y, xx, info[0]["iters"]))
     for y, xx, it in out[1:]:
         assert torch.equal(y, out[0][0]) and torch.equal(xx, out[0][1]) and it == out[0][2]
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("form,eta", [("sipg", 1.0), ("br2", 0.0)])
+def test_elem3d_cost_order_bitwise(monkeypatch, form, eta):
+    """The 3D element kernel with its elements dispatched by decreasing cost
+    gives bitwise the same y = A x, the same r'r shares and the same PCG
+    iterates as in mesh order, and the autotuner's choice of order too."""
+    import torch
+    md = H.random_mesh(3, 3, 0.3, 2, 1, 6, seed=43)
+    out = []
+    for flag in ("0", "1"):
+        monkeypatch.setenv("HPDG_ELEM3D_COST_ORDER", flag)
+        m = G.Mesh(md)
+        op = G.Operator(m, form=form, eta=eta, max_block=256)
+        x = torch.from_numpy(H.gaussian_rhs(m.ndof, 44)).cuda()
+        y = torch.empty_like(x)
+        op.apply_A(x, y)
+        b = torch.empty_like(x)
+        op.rhs(x, b)
+        xx = torch.zeros_like(b)
+        info = op.pcg_solve(b, xx, rtol=1e-8, maxit=500)
+        out.append((y, xx, info[0]["iters"]))
+        if flag == "1":
+            rep = [r for r in op.tune() if r["matrix"] == "elem_order"]
+            assert len(rep) == 1 and rep[0]["lanes"] in (0, 1)
+            y2 = torch.empty_like(x)
+            op.apply_A(x, y2)
+            assert torch.equal(y2, y)
+    assert torch.equal(out[1][0], out[0][0]) and torch.equal(out[1][1], out[0][1]) and out[1][2] == out[0][2]
 
 
 @pytest.mark.parametrize("dim,p", [(2, 1), (2, 8), (3, 1), (3, 8)])
