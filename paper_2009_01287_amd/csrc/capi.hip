@@ -214,7 +214,7 @@ struct hpdg_operator {
   int epb = 1;               // elements per workgroup of the 2D element kernel
   int nm3 = 9;               // LDS size class of the 3D element kernel: largest n = p + 1 (7 or 9)
   DevBuf elem_perm;          // 3D elements by decreasing estimated cost
-  int use_perm = 0;          // 3D element kernel dispatched in that order (autotuned)
+  int use_perm = 1;          // 3D element kernel dispatched in that order (autotuned)
   // host matrices of the fused levels and dense tails, built once and kept
   // across uploads (the counting pass and the upload share them)
   struct HostCycle {
