@@ -213,7 +213,7 @@ struct hpdg_operator {
   int use_graph = 0;         // PCG chunks replayed from captured HIP graphs
   int epb = 1;               // elements per workgroup of the 2D element kernel
   int nm3 = 9;               // LDS size class of the 3D element kernel: largest n = p + 1 (7 or 9)
-  DevBuf elem_perm;          // 3D elements by decreasing estimated cost
+  DevBuf elem_perm;          // 3D elements by decreasing cost within each XCD's share
   int use_perm = 1;          // 3D element kernel dispatched in that order (autotuned)
   // host matrices of the fused levels and dense tails, built once and kept
   // across uploads (the counting pass and the upload share them)
@@ -602,9 +602,16 @@ static void upload_device(hpdg_operator* op, hipStream_t s) {
       const int64_t n = U.pd[e] + 1;
       cost[e] = n * n * n * n + (int64_t)(U.sptr[e * 6 + 6] - U.sptr[e * 6]) * n * n * n;
     }
+    // the element kernel gives each XCD a contiguous eighth of the element
+    // positions and starts its workgroups in order: within each eighth the
+    // elements (a contiguous piece of the mesh) are put in decreasing cost,
+    // so the heavy ones start first and the last to start are short
     std::vector<int32_t> perm(ne);
     std::iota(perm.begin(), perm.end(), 0);
-    std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
+    const int64_t chunk = (ne + 7) / 8;
+    for (int64_t c0 = 0; c0 < ne; c0 += chunk)
+      std::stable_sort(perm.begin() + c0, perm.begin() + std::min(ne, c0 + chunk),
+                       [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
     op->elem_perm.upload(perm);
   }
   op->recs.upload(U.recs);
@@ -1262,9 +1269,8 @@ static void tune_elem(hpdg_operator* op, hipStream_t s, int64_t* rep) {
   rep[4] = (int64_t)t_def; rep[5] = (int64_t)best;
 }
 
-// dispatch order of the 3D element kernel: mesh order with the XCD-aware
-// mapping, or the elements by decreasing estimated cost (results do not
-// depend on it)
+// element order of the 3D element kernel: mesh order, or by decreasing
+// estimated cost within each XCD's share (results do not depend on it)
 static void tune_elem_order(hpdg_operator* op, hipStream_t s, int64_t* rep) {
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));

@@ -969,10 +969,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NM == 7 ? 7
   __shared__ FaceRec sR[KF];
   __shared__ double sRed[4];
   const int per = (int)(gridDim.x >> 3);
-  // (element, RHS) items: XCD-aware mesh order, or with perm in dispatch
-  // order, element perm[i] for the i-th (heaviest first, so that the last
-  // workgroups to start are the short ones)
-  const int item = perm ? (int)blockIdx.x : (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+  // (element, RHS) items in XCD-aware order; with perm the i-th element
+  // position holds element perm[i]
+  const int item = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
   if (item >= ne * nrhs) return;
   const int ei = item / nrhs, rhs = item - ei * nrhs;
   const int e = perm ? perm[ei] : ei;

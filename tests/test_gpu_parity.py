@@ -336,8 +336,8 @@ def test_elem2d_elements_per_workgroup_bitwise(monkeypatch, form, eta):
 @pytest.mark.gpu
 @pytest.mark.parametrize("form,eta", [("sipg", 1.0), ("br2", 0.0)])
 def test_elem3d_cost_order_bitwise(monkeypatch, form, eta):
-    """The 3D element kernel with its elements dispatched by decreasing cost
-    gives bitwise the same y = A x, the same r'r shares and the same PCG
+    """The 3D element kernel with its elements taken by decreasing cost
+    within each XCD's share gives bitwise the same y = A x, the same r'r shares and the same PCG
     iterates as in mesh order, and the autotuner's choice of order too."""
     import torch
     md = H.random_mesh(3, 3, 0.3, 2, 1, 6, seed=43)
@@ -598,3 +598,4 @@ def test_elem2d_rhs_groups_bitwise(monkeypatch, group):
         op.apply_A(x, y, nrhs=nr)
         outs.append(y)
     assert torch.equal(outs[0], outs[1])
+
