@@ -215,6 +215,7 @@ struct hpdg_operator {
   int nm3 = 9;               // LDS size class of the 3D element kernel: largest n = p + 1 (7 or 9)
   DevBuf elem_perm;          // 3D elements by decreasing cost within each XCD's share
   int use_perm = 1;          // 3D element kernel dispatched in that order (autotuned)
+  int cg_separate = 0;       // one RHS: CG final reductions as kernels of their own
   // host matrices of the fused levels and dense tails, built once and kept
   // across uploads (the counting pass and the upload share them)
   struct HostCycle {
@@ -636,7 +637,7 @@ static void upload_device(hpdg_operator* op, hipStream_t s) {
   op->pv.alloc(nv);
   op->Ap.alloc(nv);
   // dot-product shares: 1024 blocks per RHS, or one per element / per 256 DOFs
-  op->part.alloc((size_t)std::max<int64_t>(1024 * hs, 2 * part_off2(op)) * sizeof(double));
+  op->part.alloc((size_t)std::max<int64_t>(1024 * hs, 3 * part_off2(op)) * sizeof(double));
   op->scal.alloc((size_t)16 * 256 * sizeof(double));
   op->iscal.alloc((size_t)4 * 256 * sizeof(int));
   op->hist_cap = kHistCap;
@@ -868,6 +869,7 @@ extern "C" hpdg_status hpdg_setup_operator(const hpdg_mesh* mh, const hpdg_opera
     if (const char* v = std::getenv("HPDG_NO_MFMA")) op->no_mfma = std::atoi(v) != 0;
     if (const char* v = std::getenv("HPDG_NO_FUSED_MULTI")) op->no_fused_multi = std::atoi(v) != 0;
     if (const char* v = std::getenv("HPDG_ELEM3D_COST_ORDER")) op->use_perm = std::atoi(v) != 0;
+    if (const char* v = std::getenv("HPDG_CG_SEPARATE_FINALS")) op->cg_separate = std::atoi(v) != 0;
     if (!op->no_prec) {
       PrecHost& H = op->host;
       H.diag = dg_diagonal(M, oo);
@@ -1188,6 +1190,7 @@ static void launch_front(hpdg_operator* op, const T* rt, T* zb, hipStream_t s);
 
 // a candidate replaces the default only when this much faster (timing noise)
 constexpr double kTuneMargin = 0.95;
+constexpr int64_t kCgFoldReads = 8 << 20;
 
 template <typename T>
 static void tune_csr(const CSR& H, DevCSR& D, const T* x, T* y, hipStream_t s, int64_t* rep,
@@ -1690,6 +1693,7 @@ static CGScal cg_scal(hpdg_operator* op) {
   CGScal S;
   S.rz = D; S.pAp = D + 256; S.rr = D + 512; S.bb = D + 768; S.alpha = D + 1024; S.beta = D + 1280;
   S.tol2 = D + 1536;
+  S.rzn = D + 1792;
   S.act = I; S.iters = I + 256; S.err = I + 512;
   S.ahist = op->ahist.as<double>();
   S.bhist = op->bhist.as<double>();
@@ -1768,27 +1772,48 @@ static void pcg_iters(hpdg_operator* op, int k, hipStream_t s) {
   double *r = op->r.as<double>(), *z = op->z.as<double>(), *p = op->pv.as<double>(), *Ap = op->Ap.as<double>();
   double* part = op->part.as<double>();
   for (int i = 0; i < k; ++i) {
-    // with one RHS the producers of Ap, r and z also write their shares of
-    // p'Ap, r'r and r'z, and only the final reductions are separate
-    const int na = apply_A_dev(op, p, Ap, nrhs, s, nrhs == 1 ? part : nullptr);
-    if (na) dot_final(op, na, EP_PAP, S, s);
-    else dot_ep(op, p, Ap, nrhs, EP_PAP, S, s);
-    if (nrhs == 1) {
-      // r'r shares in the first region, r'z shares (written by the last
-      // kernel of B) in the second; one launch finishes both, r'r first
+    // every block of the folded kernels re-reads all shares: kept for
+    // systems where that stays small (up to 8M share reads per kernel)
+    const int64_t nbk = (int64_t)nblk(n);
+    const bool fold = !op->cg_separate && nbk * std::max<int64_t>(op->ne, 2 * nbk) <= kCgFoldReads;
+    if (nrhs == 1 && !fold) {
+      // the same with the final reductions as one-block kernels of their own
+      const int na = apply_A_dev(op, p, Ap, 1, s, part);
+      if (na) dot_final(op, na, EP_PAP, S, s);
+      else dot_ep(op, p, Ap, 1, EP_PAP, S, s);
       hipLaunchKernelGGL(k_cg_update_rr, dim3(nblk(n)), dim3(256), 0, s, n, S.alpha, p, Ap, R.x, r, part);
       double* part2 = part + part_off2(op);
-      const int nb = apply_B_any(op, r, z, nrhs, s, part2);
+      const int nb = apply_B_any(op, r, z, 1, s, part2);
       hipLaunchKernelGGL(k_dot_final_rr_rz, dim3(1), dim3(256), 0, s, (int)nblk(n), part, nb, part2, S);
-    } else {
-      // the update writes the per-RHS shares of r'r (on the grid of the dot
-      // kernels, so they are bitwise those of a separate pass)
-      const int g = dot_grid(n);
-      hipLaunchKernelGGL(k_cg_update2, dim3(g), dim3(256), 0, s, n, nrhs, S.alpha, p, Ap, R.x, r, part);
-      hipLaunchKernelGGL(k_dot_final_rhs, dim3(nrhs), dim3(256), 0, s, g, nrhs, part, EP_RR, S);
-      apply_B_any(op, r, z, nrhs, s);
-      dot_ep(op, r, z, nrhs, EP_RZ, S, s);
+      hipLaunchKernelGGL(k_cg_dir2, dim3(nblk(n)), dim3(256), 0, s, n, 1, S.beta, S.act, z, p);
+      continue;
     }
+    if (nrhs == 1) {
+      // the producers of Ap, r and z write their shares of p'Ap (first
+      // region), r'r (third) and r'z (second, by the last kernel of B); the
+      // final reductions run inside the update and direction kernels
+      int na = apply_A_dev(op, p, Ap, 1, s, part);
+      if (!na) {
+        na = dot_grid(n);
+        hipLaunchKernelGGL(k_dot_partial, dim3(na), dim3(256), 0, s, n, 1, p, Ap, part);
+      }
+      double* part2 = part + part_off2(op);
+      double* part3 = part + 2 * part_off2(op);
+      hipLaunchKernelGGL(k_cg_update_pap, dim3(nblk(n)), dim3(256), 0, s, n, na, part, S, p, Ap, R.x, r, part3);
+      const int nb = apply_B_any(op, r, z, 1, s, part2);
+      hipLaunchKernelGGL(k_cg_dir_rr_rz, dim3(nblk(n)), dim3(256), 0, s, n, (int)nblk(n), part3, nb, part2, S,
+                         z, p);
+      continue;
+    }
+    apply_A_dev(op, p, Ap, nrhs, s, nullptr);
+    dot_ep(op, p, Ap, nrhs, EP_PAP, S, s);
+    // the update writes the per-RHS shares of r'r (on the grid of the dot
+    // kernels, so they are bitwise those of a separate pass)
+    const int g = dot_grid(n);
+    hipLaunchKernelGGL(k_cg_update2, dim3(g), dim3(256), 0, s, n, nrhs, S.alpha, p, Ap, R.x, r, part);
+    hipLaunchKernelGGL(k_dot_final_rhs, dim3(nrhs), dim3(256), 0, s, g, nrhs, part, EP_RR, S);
+    apply_B_any(op, r, z, nrhs, s);
+    dot_ep(op, r, z, nrhs, EP_RZ, S, s);
     hipLaunchKernelGGL(k_cg_dir2, dim3(nblk(n)), dim3(256), 0, s, n, nrhs, S.beta, S.act, z, p);
   }
   HIPCHK(hipGetLastError());

@@ -727,6 +727,7 @@ __global__ __launch_bounds__(256) void k_dot_partial(int64_t n, int nrhs, const 
 // CG scalars on the device, one slot per RHS (SoA, stride 256):
 struct CGScal {
   double *rz, *pAp, *rr, *bb, *alpha, *beta, *tol2;
+  double* rzn;             // one RHS: the latest r'z (rz holds the one before)
   int *act, *iters, *err;
   double *ahist, *bhist;   // [maxit * hs]: alpha_k, beta_k of RHS c at k * hs + c
   int maxit;               // capacity of the histories in iterations
@@ -746,6 +747,7 @@ __device__ inline void cg_epilogue(int mode, int c, double v, CGScal S) {
       break;
     case EP_RZ0:
       S.rz[c] = v;
+      S.rzn[c] = v;
       if (S.act[c] && !(v > 0.0)) { S.err[c] = 1; S.act[c] = 0; }
       break;
     case EP_PAP:
@@ -1311,6 +1313,110 @@ __global__ __launch_bounds__(256) void k_cg_update_rr(int64_t n, const double* _
   }
   const double s = block_sum256(rr);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// Sum of n shares in the order of the one-block final stages k_dot_final_pap
+// and k_dot_final_rr_rz (each thread's ordered_sum with stride 256, then the
+// halving tree): every block that calls it gets the same value, bitwise that
+// of those stages.
+__device__ inline double shares_sum(const double* __restrict__ part, int n, double* sm) {
+  const int t = threadIdx.x;
+  sm[t] = ordered_sum(part, t, 256, n, 1, 0);
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if (t < w) sm[t] += sm[t + w];
+    __syncthreads();
+  }
+  const double v = sm[0];
+  __syncthreads();
+  return v;
+}
+
+// One RHS, the final stages folded into the vector kernels that follow them
+// (one launch fewer each): every block repeats the final reduction of the
+// shares and takes the same scalar decisions; block 0 stores the scalars.
+// No block reads a scalar that another block of the same launch writes,
+// except the activity and breakdown flags, which only go from set to
+// cleared (activity) or from clear to set (breakdown): a block that already
+// sees block 0's store takes the branch block 0 took.
+//
+// p'Ap from its nsh shares, alpha = r'z / p'Ap while active (r'z from rzn,
+// copied to rz), then x += alpha p, r -= alpha Ap and the block's share of
+// r'r (as k_cg_update_rr). A breakdown sets err here; the activity flag is
+// cleared by k_cg_dir_rr_rz.
+__global__ __launch_bounds__(256) void k_cg_update_pap(int64_t n, int nsh, const double* __restrict__ sh, CGScal S,
+                                                       const double* __restrict__ p, const double* __restrict__ Ap,
+                                                       double* __restrict__ x, double* __restrict__ r,
+                                                       double* __restrict__ part) {
+  __shared__ double sm[256];
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int act0 = S.act[0];
+  const double rz = S.rzn[0];
+  double pi = 0.0, api = 0.0, xi = 0.0, ri = 0.0;
+  if (i < n) {
+    pi = p[i];
+    api = Ap[i];
+    xi = x[i];
+    ri = r[i];
+  }
+  const double v = shares_sum(sh, nsh, sm);
+  const bool ok = act0 && v > 0.0;
+  const double al = ok ? rz / v : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    S.pAp[0] = v;
+    S.alpha[0] = al;
+    S.rz[0] = rz;
+    if (act0 && !(v > 0.0)) S.err[0] = 1;
+  }
+  double rr = 0.0;
+  if (i < n) {
+    x[i] = xi + al * pi;
+    const double rn = ri - al * api;
+    r[i] = rn;
+    rr = rn * rn;
+  }
+  const double s = block_sum256(rr);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// r'r (na shares pa) and r'z (nb shares pb) as in k_dot_final_rr_rz, then
+// p = z + beta p while active. Block 0 stores r'r, alpha's and beta's
+// histories, the iteration count, the new r'z (in rzn), beta and the flags
+// (including the activity flag after a breakdown in k_cg_update_pap).
+__global__ __launch_bounds__(256) void k_cg_dir_rr_rz(int64_t n, int na, const double* __restrict__ pa, int nb,
+                                                      const double* __restrict__ pb, CGScal S,
+                                                      const double* __restrict__ z, double* __restrict__ p) {
+  __shared__ double sm[256];
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int act0 = S.act[0], err0 = S.err[0], it0 = S.iters[0];
+  const double tol2 = S.tol2[0], bb = S.bb[0], rz = S.rz[0];
+  double zi = 0.0, pi = 0.0;
+  if (i < n) {
+    zi = z[i];
+    pi = p[i];
+  }
+  const double v0 = shares_sum(pa, na, sm);
+  const double v1 = shares_sum(pb, nb, sm);
+  const bool run = act0 && !err0;   // active through this iteration's update
+  bool act = run && v0 > tol2 * bb;
+  const bool brk = act && !(v1 > 0.0);
+  act = act && !brk;
+  const double beta = act ? v1 / rz : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    S.rr[0] = v0;
+    if (run) {
+      if (it0 < S.maxit) S.ahist[(int64_t)it0 * S.hs] = S.alpha[0];
+      S.iters[0] = it0 + 1;
+    }
+    if (act0 && !act) S.act[0] = 0;
+    if (brk) S.err[0] = 1;
+    S.beta[0] = beta;
+    if (act) {
+      S.rzn[0] = v1;
+      if (it0 < S.maxit) S.bhist[(int64_t)it0 * S.hs] = beta;
+    }
+  }
+  if (i < n && act) p[i] = zi + beta * pi;
 }
 
 // p = z + beta p while active

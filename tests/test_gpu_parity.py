@@ -363,6 +363,33 @@ def test_elem3d_cost_order_bitwise(monkeypatch, form, eta):
     assert torch.equal(out[1][0], out[0][0]) and torch.equal(out[1][1], out[0][1]) and out[1][2] == out[0][2]
 
 
+@pytest.mark.gpu
+@pytest.mark.parametrize("dim,fp32", [(2, False), (3, True)])
+def test_cg_final_stages_bitwise(monkeypatch, dim, fp32):
+    """One RHS: the CG iteration with the final reductions folded into the
+    update and direction kernels gives bitwise the same iterates, iteration
+    count and alpha/beta histories as with one-block final kernels, in
+    blocking solves and in HIP-graph replays."""
+    import torch
+    md = H.random_mesh(2, 6, 0.3, 3, 1, 8, seed=51) if dim == 2 else H.random_mesh(3, 3, 0.3, 2, 1, 5, seed=52)
+    out = []
+    for flag in ("1", "0"):
+        monkeypatch.setenv("HPDG_CG_SEPARATE_FINALS", flag)
+        m = G.Mesh(md)
+        for graph in (False, True):
+            op = G.Operator(m, prec_fp32=fp32, graph=graph, max_block=256 if dim == 3 else 0)
+            f = torch.from_numpy(H.gaussian_rhs(m.ndof, 53)).cuda()
+            b = torch.empty_like(f)
+            op.rhs(f, b)
+            x = torch.zeros_like(b)
+            info = op.pcg_solve(b, x, rtol=1e-8, maxit=800)
+            i0 = info[0]
+            out.append((x, (i0["iters"], i0["rel_res"], i0["true_rel_res"], i0["lambda_min"], i0["lambda_max"])))
+    for x, scal in out[1:]:
+        assert torch.equal(x, out[0][0])
+        assert np.array_equal(np.array(scal), np.array(out[0][1]), equal_nan=True)
+
+
 @pytest.mark.parametrize("dim,p", [(2, 1), (2, 8), (3, 1), (3, 8)])
 @pytest.mark.parametrize("form", ["sipg", "br2"])
 def test_single_element_meshes(dim, p, form):
