@@ -515,10 +515,18 @@ static void upload_prec(hpdg_operator* op) {
   for (size_t b = 0; b < H.blocks.size(); ++b) {
     const auto& B = H.blocks[b];
     int m = (int)B.size();
-    for (int i = 0; i < m; ++i) { rowb.push_back((int32_t)b); rowl.push_back(i); bdof.push_back((int32_t)B[i]); }
+    for (int i = 0; i < m; ++i) bdof.push_back((int32_t)B[i]);
     bptr.push_back(bptr.back() + m);
     boff.push_back(boff.back() + (int64_t)m * m);
   }
+  // the row list of the row-parallel block solves: largest blocks first (their
+  // rows take longest), the rows of a block together
+  std::vector<int32_t> border(H.blocks.size());
+  std::iota(border.begin(), border.end(), 0);
+  std::stable_sort(border.begin(), border.end(),
+                   [&](int32_t a, int32_t b) { return H.blocks[a].size() > H.blocks[b].size(); });
+  for (int32_t b : border)
+    for (int i = 0; i < (int)H.blocks[b].size(); ++i) { rowb.push_back(b); rowl.push_back(i); }
   op->blk_rows = (int64_t)rowb.size();
   op->nblocks = (int64_t)H.blocks.size();
   op->max_blk = 0;
