@@ -180,6 +180,8 @@ struct LevelDev {
 
 }  // namespace
 
+constexpr int64_t kPreSplitNnz = 4 << 20;   // pre-smoother in two launches above this many nonzeros
+
 struct hpdg_operator {
   int dim = 2, ne = 0, max_nrhs = 1, form = 0, prec32 = 0, host_only = 0;
   int generic_faces = 0;   // HPDG_GENERIC_FACES=1: use the one-block-per-element face kernel
@@ -216,6 +218,7 @@ struct hpdg_operator {
   DevBuf elem_perm;          // 3D elements by decreasing cost within each XCD's share
   int use_perm = 1;          // 3D element kernel dispatched in that order (autotuned)
   int cg_separate = 0;       // one RHS: CG final reductions as kernels of their own
+  int64_t presplit_nnz = kPreSplitNnz;   // pre-smoother in two launches above this
   // host matrices of the fused levels and dense tails, built once and kept
   // across uploads (the counting pass and the upload share them)
   struct HostCycle {
@@ -878,6 +881,7 @@ extern "C" hpdg_status hpdg_setup_operator(const hpdg_mesh* mh, const hpdg_opera
     if (const char* v = std::getenv("HPDG_NO_FUSED_MULTI")) op->no_fused_multi = std::atoi(v) != 0;
     if (const char* v = std::getenv("HPDG_ELEM3D_COST_ORDER")) op->use_perm = std::atoi(v) != 0;
     if (const char* v = std::getenv("HPDG_CG_SEPARATE_FINALS")) op->cg_separate = std::atoi(v) != 0;
+    if (const char* v = std::getenv("HPDG_PRESPLIT_NNZ")) op->presplit_nnz = std::max<int64_t>(-1, std::atoll(v));
     if (!op->no_prec) {
       PrecHost& H = op->host;
       H.diag = dg_diagonal(M, oo);
@@ -1179,8 +1183,15 @@ static void vcycle(hpdg_operator* op, size_t l, int nrhs, hipStream_t s) {
     return;
   }
   LevelDev& C = op->lv[l + 1];
-  // pre-smoothing from zero and residual: x = D b, r = b - A D b
-  spmv<T, 3>(L.A, nrhs, L.b.as<T>(), nullptr, L.l1inv.as<T>(), L.x.as<T>(), L.r.as<T>(), s);
+  // pre-smoothing from zero and residual: x = D b, r = b - A D b; on large
+  // levels x is formed first, so that the product gathers one vector
+  // instead of two (the same values: x is rounded as in the fused form)
+  if (nrhs == 1 && L.A.nnz > op->presplit_nnz) {
+    hipLaunchKernelGGL(k_dscale<T>, dim3(nblk(n)), dim3(256), 0, s, n, L.l1inv.as<T>(), L.b.as<T>(), L.x.as<T>());
+    spmv<T, 1>(L.A, 1, L.x.as<T>(), L.b.as<T>(), nullptr, nullptr, L.r.as<T>(), s);
+  } else {
+    spmv<T, 3>(L.A, nrhs, L.b.as<T>(), nullptr, L.l1inv.as<T>(), L.x.as<T>(), L.r.as<T>(), s);
+  }
   // restriction b_c = P^T r
   spmv<T, 0>(L.R, nrhs, L.r.as<T>(), nullptr, nullptr, nullptr, C.b.as<T>(), s);
   vcycle<T>(op, l + 1, nrhs, s);

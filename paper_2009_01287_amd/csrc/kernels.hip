@@ -1432,6 +1432,14 @@ __global__ void k_cg_dir2(int64_t n, int nrhs, const double* __restrict__ beta, 
 
 
 
+// x = d . b (pre-smoothing from zero)
+template <typename T>
+__global__ __launch_bounds__(256) void k_dscale(int n, const T* __restrict__ d, const T* __restrict__ b,
+                                                T* __restrict__ x) {
+  const int i = (int)blockIdx.x * 256 + (int)threadIdx.x;
+  if (i < n) x[i] = d[i] * b[i];
+}
+
 __global__ void k_sub(int64_t n, const double* __restrict__ a, const double* __restrict__ b, double* __restrict__ c) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) c[i] = a[i] - b[i];

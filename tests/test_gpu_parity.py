@@ -364,6 +364,25 @@ def test_elem3d_cost_order_bitwise(monkeypatch, form, eta):
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("fp32", [False, True])
+def test_presmoother_split_bitwise(monkeypatch, fp32):
+    """The pre-smoothing step on large levels as x = D b followed by
+    r = b - A x (two launches) gives bitwise the same B r as the one-launch
+    form; forced here on every level."""
+    import torch
+    md = H.random_mesh(3, 3, 0.3, 2, 1, 5, seed=54)
+    out = []
+    for thr in ("-1", str(1 << 40)):
+        monkeypatch.setenv("HPDG_PRESPLIT_NNZ", thr)
+        op = G.Operator(G.Mesh(md), prec_fp32=fp32, max_block=256)
+        r = torch.from_numpy(H.gaussian_rhs(H.ndof(md), 55)).cuda()
+        z = torch.empty_like(r)
+        op.apply_B(r, z)
+        out.append(z)
+    assert torch.equal(out[0], out[1])
+
+
+@pytest.mark.gpu
 @pytest.mark.parametrize("dim,fp32", [(2, False), (3, True)])
 def test_cg_final_stages_bitwise(monkeypatch, dim, fp32):
     """One RHS: the CG iteration with the final reductions folded into the
