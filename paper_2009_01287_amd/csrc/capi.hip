@@ -1574,17 +1574,24 @@ static int apply_B_dev(hpdg_operator* op, const double* r, double* z, int nrhs, 
                        double* pdot = nullptr) {
   int64_t n = op->ndof * nrhs;
   const T* rt;
-  if (std::is_same<T, double>::value) rt = (const T*)r;
-  else {
+  T* zb = op->zT.as<T>();
+  const bool lowp = !std::is_same<T, double>::value;
+  if (!lowp) rt = (const T*)r;
+  else if (nrhs == 1) {
     hipLaunchKernelGGL((k_cast<double, T>), dim3(nblk(n)), dim3(256), 0, s, n, r, op->rT.as<T>());
     rt = op->rT.as<T>();
+  } else {
+    // the cast and the point Jacobi part in one pass
+    hipLaunchKernelGGL(k_cast_diag_scale<T>, dim3(nblk(n)), dim3(256), 0, s, n, nrhs, op->dinvJ.as<T>(), r,
+                       op->rT.as<T>(), zb);
+    rt = op->rT.as<T>();
   }
-  T* zb = op->zT.as<T>();
   LevelDev& L0 = op->lv[0];
   if (nrhs == 1) {
     launch_front<T>(op, rt, zb, s);
   } else {
-    hipLaunchKernelGGL(k_diag_scale<T>, dim3(nblk(n)), dim3(256), 0, s, n, nrhs, op->dinvJ.as<T>(), rt, zb);
+    if (!lowp)
+      hipLaunchKernelGGL(k_diag_scale<T>, dim3(nblk(n)), dim3(256), 0, s, n, nrhs, op->dinvJ.as<T>(), rt, zb);
     if (op->blk_rows > 0) {
       int64_t nt = op->blk_rows * nrhs;
       const size_t shm = (size_t)op->max_blk * nrhs * sizeof(T);

@@ -706,6 +706,19 @@ __global__ void k_diag_scale(int64_t n, int nrhs, const T* __restrict__ d, const
   if (i < n) z[i] = d[i / nrhs] * r[i];
 }
 
+// rt[i] = (T) r[i], z[i] = d[i / nrhs] * rt[i]
+template <typename T>
+__global__ __launch_bounds__(256) void k_cast_diag_scale(int64_t n, int nrhs, const T* __restrict__ d,
+                                                         const double* __restrict__ r, T* __restrict__ rt,
+                                                         T* __restrict__ z) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) {
+    const T v = (T)r[i];
+    rt[i] = v;
+    z[i] = d[i / nrhs] * v;
+  }
+}
+
 // partial dot products per block and per RHS (rhs = index % nrhs); nrhs
 // divides 256. part[block * nrhs + r]
 __global__ __launch_bounds__(256) void k_dot_partial(int64_t n, int nrhs, const double* __restrict__ a,
