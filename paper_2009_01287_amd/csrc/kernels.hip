@@ -795,10 +795,17 @@ __device__ inline void cg_epilogue(int mode, int c, double v, CGScal S) {
 
 
 // sum of p[b * m + c] for b = b0, b0 + bs, ... < n, added in that order; the
-// loads are issued four at a time (same result as the plain loop)
+// loads are issued eight, then four at a time (same result as the plain loop)
 __device__ inline double ordered_sum(const double* __restrict__ p, int b0, int bs, int n, int m, int c) {
   double s = 0.0;
   int b = b0;
+  for (; b + 7 * bs < n; b += 8 * bs) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = p[(int64_t)(b + u * bs) * m + c];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
+  }
   for (; b + 3 * bs < n; b += 4 * bs) {
     const double v0 = p[(int64_t)b * m + c];
     const double v1 = p[(int64_t)(b + bs) * m + c];
