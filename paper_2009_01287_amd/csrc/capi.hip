@@ -1571,13 +1571,15 @@ static void launch_front(hpdg_operator* op, const T* rt, T* zb, hipStream_t s) {
 // of r'z there; returns their count (0 without pdot).
 template <typename T>
 static int apply_B_dev(hpdg_operator* op, const double* r, double* z, int nrhs, hipStream_t s,
-                       double* pdot = nullptr) {
+                       double* pdot = nullptr, bool r_cast = false) {
   int64_t n = op->ndof * nrhs;
   const T* rt;
   T* zb = op->zT.as<T>();
   const bool lowp = !std::is_same<T, double>::value;
   if (!lowp) rt = (const T*)r;
-  else if (nrhs == 1) {
+  else if (nrhs == 1 && r_cast) {
+    rt = op->rT.as<T>();   // written by the CG update together with r
+  } else if (nrhs == 1) {
     hipLaunchKernelGGL((k_cast<double, T>), dim3(nblk(n)), dim3(256), 0, s, n, r, op->rT.as<T>());
     rt = op->rT.as<T>();
   } else {
@@ -1728,9 +1730,10 @@ static CGScal cg_scal(hpdg_operator* op) {
   return S;
 }
 
+// r_cast: the FP32 copy of in is already in rT (one RHS)
 static int apply_B_any(hpdg_operator* op, const double* in, double* outv, int nrhs, hipStream_t s,
-                       double* pdot = nullptr) {
-  if (op->prec32) return apply_B_dev<float>(op, in, outv, nrhs, s, pdot);
+                       double* pdot = nullptr, bool r_cast = false) {
+  if (op->prec32) return apply_B_dev<float>(op, in, outv, nrhs, s, pdot, r_cast);
   return apply_B_dev<double>(op, in, outv, nrhs, s, pdot);
 }
 
@@ -1797,6 +1800,8 @@ static void pcg_iters(hpdg_operator* op, int k, hipStream_t s) {
   CGScal S = cg_scal(op);
   double *r = op->r.as<double>(), *z = op->z.as<double>(), *p = op->pv.as<double>(), *Ap = op->Ap.as<double>();
   double* part = op->part.as<double>();
+  // one RHS, FP32 B: the update writes B's single-precision copy of r
+  float* rt32 = (nrhs == 1 && op->prec32 && !op->no_prec) ? op->rT.as<float>() : nullptr;
   for (int i = 0; i < k; ++i) {
     // every block of the folded kernels re-reads all shares: kept for
     // systems where that stays small (up to 8M share reads per kernel)
@@ -1807,9 +1812,9 @@ static void pcg_iters(hpdg_operator* op, int k, hipStream_t s) {
       const int na = apply_A_dev(op, p, Ap, 1, s, part);
       if (na) dot_final(op, na, EP_PAP, S, s);
       else dot_ep(op, p, Ap, 1, EP_PAP, S, s);
-      hipLaunchKernelGGL(k_cg_update_rr, dim3(nblk(n)), dim3(256), 0, s, n, S.alpha, p, Ap, R.x, r, part);
+      hipLaunchKernelGGL(k_cg_update_rr, dim3(nblk(n)), dim3(256), 0, s, n, S.alpha, p, Ap, R.x, r, part, rt32);
       double* part2 = part + part_off2(op);
-      const int nb = apply_B_any(op, r, z, 1, s, part2);
+      const int nb = apply_B_any(op, r, z, 1, s, part2, rt32 != nullptr);
       hipLaunchKernelGGL(k_dot_final_rr_rz, dim3(1), dim3(256), 0, s, (int)nblk(n), part, nb, part2, S);
       hipLaunchKernelGGL(k_cg_dir2, dim3(nblk(n)), dim3(256), 0, s, n, 1, S.beta, S.act, z, p);
       continue;
@@ -1825,8 +1830,9 @@ static void pcg_iters(hpdg_operator* op, int k, hipStream_t s) {
       }
       double* part2 = part + part_off2(op);
       double* part3 = part + 2 * part_off2(op);
-      hipLaunchKernelGGL(k_cg_update_pap, dim3(nblk(n)), dim3(256), 0, s, n, na, part, S, p, Ap, R.x, r, part3);
-      const int nb = apply_B_any(op, r, z, 1, s, part2);
+      hipLaunchKernelGGL(k_cg_update_pap, dim3(nblk(n)), dim3(256), 0, s, n, na, part, S, p, Ap, R.x, r, part3,
+                         rt32);
+      const int nb = apply_B_any(op, r, z, 1, s, part2, rt32 != nullptr);
       hipLaunchKernelGGL(k_cg_dir_rr_rz, dim3(nblk(n)), dim3(256), 0, s, n, (int)nblk(n), part3, nb, part2, S,
                          z, p);
       continue;

@@ -1317,11 +1317,12 @@ __device__ inline double block_sum256(double v) {
   return ((sw[0] + sw[1]) + (sw[2] + sw[3]));
 }
 
-// nrhs == 1: x += alpha p ; r -= alpha Ap, and the block's share of r'r
+// nrhs == 1: x += alpha p ; r -= alpha Ap, and the block's share of r'r;
+// with rt also the single-precision copy of r that an FP32 B reads
 __global__ __launch_bounds__(256) void k_cg_update_rr(int64_t n, const double* __restrict__ alpha,
                                                      const double* __restrict__ p, const double* __restrict__ Ap,
                                                      double* __restrict__ x, double* __restrict__ r,
-                                                     double* __restrict__ part) {
+                                                     double* __restrict__ part, float* __restrict__ rt) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   double rr = 0.0;
   if (i < n) {
@@ -1329,6 +1330,7 @@ __global__ __launch_bounds__(256) void k_cg_update_rr(int64_t n, const double* _
     x[i] += al * p[i];
     const double ri = r[i] - al * Ap[i];
     r[i] = ri;
+    if (rt) rt[i] = (float)ri;
     rr = ri * ri;
   }
   const double s = block_sum256(rr);
@@ -1362,12 +1364,13 @@ __device__ inline double shares_sum(const double* __restrict__ part, int n, doub
 //
 // p'Ap from its nsh shares, alpha = r'z / p'Ap while active (r'z from rzn,
 // copied to rz), then x += alpha p, r -= alpha Ap and the block's share of
-// r'r (as k_cg_update_rr). A breakdown sets err here; the activity flag is
+// r'r (and the FP32 copy of r) as k_cg_update_rr. A breakdown sets err here;
+// the activity flag is
 // cleared by k_cg_dir_rr_rz.
 __global__ __launch_bounds__(256) void k_cg_update_pap(int64_t n, int nsh, const double* __restrict__ sh, CGScal S,
                                                        const double* __restrict__ p, const double* __restrict__ Ap,
                                                        double* __restrict__ x, double* __restrict__ r,
-                                                       double* __restrict__ part) {
+                                                       double* __restrict__ part, float* __restrict__ rt) {
   __shared__ double sm[256];
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int act0 = S.act[0];
@@ -1393,6 +1396,7 @@ __global__ __launch_bounds__(256) void k_cg_update_pap(int64_t n, int nsh, const
     x[i] = xi + al * pi;
     const double rn = ri - al * api;
     r[i] = rn;
+    if (rt) rt[i] = (float)rn;
     rr = rn * rn;
   }
   const double s = block_sum256(rr);
