@@ -125,12 +125,17 @@ def test_no_prec_operator_host():
     assert s["ndof"] == m.ndof and s["amg_levels"] == 0 and s["nblocks"] == 0
 
 
-def test_setup_threads_do_not_change_results():
-    """The row-parallel setup products give bitwise the same host data with
-    one thread and with several."""
+@pytest.mark.parametrize("dim,nb", [(3, 2), (3, 4), (2, 12)])
+def test_setup_threads_do_not_change_results(dim, nb):
+    """The row-parallel setup products and the prolongation built on element
+    ranges (each with its own memo of entity rows) give bitwise the same host
+    data with one thread and with several; the larger meshes have enough
+    elements for several ranges."""
     _lib_or_skip()
-    md = H.random_mesh(3, 2, 0.4, 2, 1, 4, seed=5, k_logrange=(-2, 2))
+    md = H.random_mesh(dim, nb, 0.4, 2, 1, 4, seed=5, k_logrange=(-2, 2))
     m = G.Mesh(md)
+    if nb > 2:
+        assert len(md["degree"]) >= 256
     a = G.Operator(m, form="br2", eta=0.0, host_only=True, max_block=128, setup_threads=1)
     b = G.Operator(m, form="br2", eta=0.0, host_only=True, max_block=128, setup_threads=4)
     for what in (0, 1, 2, 3, 4, 6, 8):
