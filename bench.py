@@ -92,7 +92,7 @@ def main():
     use_graph = (nrhs > 1) if args.graph < 0 else bool(args.graph)
     op = G.Operator(mesh, form=c["form"], penalty_rule=c["penalty_rule"], eta=c["eta"],
                     prec_fp32=bool(c["prec_fp32"]), max_nrhs=nrhs,
-                    max_block=256 if md["dim"] == 3 else 0, graph=use_graph)
+                    max_block=0, graph=use_graph)
     t_setup = time.time() - t0
     tuned = None if args.no_tune else op.tune()
     n = mesh.ndof
@@ -225,7 +225,7 @@ def fp64_reference(args, cfg, c, mesh, b, x_mixed, infos_mixed, nrhs, dt_mixed, 
     import paper_2009_01287_amd as G
     md_dim = mesh.dim
     op = G.Operator(mesh, form=c["form"], penalty_rule=c["penalty_rule"], eta=c["eta"], prec_fp32=False,
-                    max_nrhs=nrhs, max_block=256 if md_dim == 3 else 0)
+                    max_nrhs=nrhs, max_block=0)
     if not args.no_tune:
         op.tune()
     x = torch.zeros_like(b)

@@ -187,7 +187,11 @@ hpdg_status hpdg_operator_tune(hpdg_operator* op, void* stream, int64_t* report,
  *   chunk, the final FP64 residual, or retire it). Waits up to wait_us
  *   microseconds for progress; never blocks on the device otherwise.
  * poll: pop up to cap retired solves: tag, status (as hpdg_pcg_solve) and
- *   info. A retired operator may be reused or destroyed.
+ *   info. A retired operator may be reused or destroyed. Until then the
+ *   operator, b and x must stay alive: destroying an admitted operator or
+ *   freeing its vectors is invalid, and hpdg_pcg_solve and hpdg_apply_B on it
+ *   return HPDG_E_INVALID (they would overwrite the work vectors of the
+ *   solve in flight).
  * destroy: synchronises the batch's streams; solves still active are left
  *   unfinished and their operators may only be destroyed afterwards. */
 hpdg_status hpdg_batch_create(int max_active, hpdg_batch** out);

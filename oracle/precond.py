@@ -15,7 +15,9 @@ Readings of the paper used here (each is stated where it is used):
     the minimum rule of Sec. 3.2.1 generalised to every entity dimension.
   * V_J rules J1-J4 (Sec. 3.3, Lemmas regular-vertex, conf-edge, no-hp and
     Remark cases), with "edge" = element side mapped to its master.
-  * V_e = connected components of the seed-and-grow relation of Sec. 3.3.
+  * V_e = connected components of the seed-and-grow relation of Sec. 3.3
+    (2D); in 3D the growth stays inside the seed's master face, so the
+    spaces are face-sized and may overlap (face_spaces).
   * The multigrid method is a project-defined smoothed-aggregation AMG
     (the paper uses BoomerAMG without stating its settings).
 """
@@ -253,10 +255,10 @@ def labels(mesh, remark_relax=False):
 
 
 def edge_spaces(mesh, inN):
-    """V_e (Sec. 3.3): two N-DOFs are related when both have a nonzero trace
-    on a common face (so [[phi]].[[psi]] is not identically zero there); the
-    V_e are the connected components. Returned as sorted DOF arrays, ordered
-    by their smallest DOF."""
+    """V_e (Sec. 3.3), 2D: two N-DOFs are related when both have a nonzero
+    trace on a common face (so [[phi]].[[psi]] is not identically zero
+    there); the V_e are the connected components. Returned as sorted DOF
+    arrays, ordered by their smallest DOF."""
     parent = {}
 
     def find(a):
@@ -267,16 +269,7 @@ def edge_spaces(mesh, inN):
 
     for g in np.nonzero(inN)[0]:
         parent[int(g)] = int(g)
-    for f in mesh.faces:
-        m = f["m"]
-        sides = [(f["em"], 1), (f["ep"], 0)] if f["ep"] >= 0 else [(f["em"], f["side"])]
-        members = []
-        for e, upper in sides:
-            p = int(mesh.p[e])
-            ni = mesh.node_index(e)
-            sel = ni[:, m] == (p if upper else 0)
-            g = mesh.dofs(e)[sel]
-            members.extend(int(x) for x in g if inN[x])
+    for members in _face_members(mesh, inN):
         for a in members[1:]:
             ra, rb = find(a), find(members[0])
             if ra != rb:
@@ -287,6 +280,51 @@ def edge_spaces(mesh, inN):
     out = [np.array(sorted(v), dtype=np.int64) for v in comps.values()]
     out.sort(key=lambda a: a[0])
     return out
+
+
+def _face_members(mesh, inN):
+    """Per face of the skeleton: the N-DOFs of its two sides (one on the
+    boundary) whose basis function has a nonzero trace there, i.e. whose node
+    lies on the element's side that contains the face."""
+    out = []
+    for f in mesh.faces:
+        m = f["m"]
+        sides = [(f["em"], 1), (f["ep"], 0)] if f["ep"] >= 0 else [(f["em"], f["side"])]
+        members = []
+        for e, upper in sides:
+            p = int(mesh.p[e])
+            ni = mesh.node_index(e)
+            sel = ni[:, m] == (p if upper else 0)
+            g = mesh.dofs(e)[sel]
+            members.extend(int(x) for x in g if inN[x])
+        out.append(members)
+    return out
+
+
+def face_spaces(mesh, inN):
+    """V_e in 3D (the paper treats 2D only): the seed-and-grow process of
+    Sec. 3.3 with growth kept inside the seed's master face. The seed of a
+    face piece e holds the N-DOFs whose node lies on e; a function joins when
+    its jump meets the jump of a member on a face piece of the same master
+    face (the full side of the coarser of the two leaves, or the common side
+    of two equal leaves, or a boundary side). The fixed point is the set of
+    N-DOFs with a nonzero trace on any piece of that master face, from every
+    leaf on either side of it. Spaces of different master faces overlap on
+    shared element edges and vertices; B_E sums their exact block solves.
+    (Unrestricted growth joins about two thirds of V_B into one space on
+    random 3D hp meshes.) Returned as sorted DOF arrays, duplicates removed,
+    ordered lexicographically."""
+    groups = {}
+    for f, members in zip(mesh.faces, _face_members(mesh, inN)):
+        m = f["m"]
+        if f["ep"] >= 0:
+            em, ep = f["em"], f["ep"]
+            key = (em, m, 1) if mesh.size[em] >= mesh.size[ep] else (ep, m, 0)
+        else:
+            key = (f["em"], m, f["side"])
+        groups.setdefault(key, set()).update(members)
+    out = sorted({tuple(sorted(v)) for v in groups.values() if v})
+    return [np.array(b, dtype=np.int64) for b in out]
 
 
 # --------------------------------------------------------------------- LOR
@@ -474,15 +512,17 @@ class Preconditioner:
         if variant == "jb":
             self.inJ = self.inJ | self.inN
             self.inN = np.zeros_like(self.inN)
-        self.blocks = edge_spaces(mesh, self.inN)
+        self.blocks = (edge_spaces if mesh.dim == 2 else face_spaces)(mesh, self.inN)
         if max_block > 0:
-            # project rule (3D): a component larger than max_block is handled
-            # by point Jacobi instead of an exact block solve
-            for b in self.blocks:
-                if len(b) > max_block:
-                    self.inJ[b] = True
-                    self.inN[b] = False
+            # project option: a space larger than max_block gets no block
+            # solve; N-DOFs left in no block are handled by point Jacobi
             self.blocks = [b for b in self.blocks if len(b) <= max_block]
+            covered = np.zeros(mesh.ndof, dtype=bool)
+            for b in self.blocks:
+                covered[b] = True
+            moved = self.inN & ~covered
+            self.inJ |= moved
+            self.inN &= ~moved
         self.dinvJ = np.where(self.inJ, 1.0 / self.diag, 0.0)
         self.binv = [np.linalg.inv(dg.submatrix(mesh, opts, b)) for b in self.blocks]
         self.P, self.nc = prolongation(mesh)

@@ -282,18 +282,27 @@ class Batch:
         _check(lib().hpdg_batch_create(int(max_active), C.byref(h)))
         self.h = h
         self.max_active = max_active
+        # (operator, b, x) of every admitted solve until poll returns its tag:
+        # the native batch holds raw pointers to them
+        self._held = {}
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
-            _lib.hpdg_batch_destroy(self.h)
+            _lib.hpdg_batch_destroy(self.h)   # synchronises; active solves stay unfinished
             self.h = None
+        self._held = {}
 
     def admit(self, op: Operator, b, x, rtol=1e-8, maxit=1000, tag=0):
-        """True if admitted, False when every slot is taken."""
+        """True if admitted, False when every slot is taken. The batch keeps
+        op, b and x alive until poll() returns the solve's tag; tags of
+        solves in flight must be distinct."""
+        if int(tag) in self._held:
+            raise ValueError(f"tag {tag} already has a solve in flight")
         code = lib().hpdg_batch_admit(self.h, op.h, _ptr(b, "b"), _ptr(x, "x"), float(rtol), int(maxit), int(tag))
         if code == -7:
             return False
         _check(code)
+        self._held[int(tag)] = (op, b, x)
         return True
 
     def step(self, wait_us=0):
@@ -309,4 +318,7 @@ class Batch:
         info = (SolveInfo * cap)()
         n = C.c_int()
         _check(lib().hpdg_batch_poll(self.h, cap, tags, codes, info, C.byref(n)))
-        return [(int(tags[i]), int(codes[i]), info[i].as_dict()) for i in range(n.value)]
+        out = [(int(tags[i]), int(codes[i]), info[i].as_dict()) for i in range(n.value)]
+        for t, _, _ in out:
+            self._held.pop(t, None)
+        return out

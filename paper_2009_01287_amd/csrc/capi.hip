@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -178,6 +179,21 @@ struct LevelDev {
   DevBuf b, x, r, t;     // T, nrows * max_nrhs
 };
 
+// Work vectors of one application of B in the preconditioner's precision:
+// the copies of r and z, and per AMG level the right-hand side b, the
+// iterate x, the residual r and the temporary t of the V-cycle (passed as
+// a descriptor, so that the same code can run on other work buffers than
+// the operator's).
+constexpr int kMaxLevels = 16;
+struct BWork {
+  void* rT = nullptr;
+  void* zT = nullptr;
+  void* b[kMaxLevels] = {};
+  void* x[kMaxLevels] = {};
+  void* r[kMaxLevels] = {};
+  void* t[kMaxLevels] = {};
+};
+
 }  // namespace
 
 constexpr int64_t kPreSplitNnz = 4 << 20;   // pre-smoother in two launches above this many nonzeros
@@ -196,6 +212,11 @@ struct hpdg_operator {
   DevBuf dinvJ;
   DevBuf blk_rowb, blk_rowl, blk_ptr, blk_off, blk_dof, blk_inv;
   int64_t blk_rows = 0, nblocks = 0;
+  // overlapping V_e (3D face spaces): the block solves write slot ndof + row
+  // (blk_out) and each N-DOF sums its slots (g_dof, g_ptr, g_slot)
+  int blk_overlap = 0;
+  DevBuf blk_out, g_dof, g_ptr, g_slot;
+  int64_t g_n = 0;
   int max_blk = 0;           // largest V_e block
   int lprb = 16;             // lanes per V_e block row in the B front (one RHS)
   int no_mfma = 0;           // HPDG_NO_MFMA=1: V_e block solves for many RHS without the matrix cores
@@ -506,6 +527,10 @@ static void set_fused(hpdg_operator* op, size_t l, bool on) {
   D.fused = on ? 1 : 0;
 }
 
+// rows of B's z work vector: the DG vector, plus one slot per block row when
+// the V_e overlap
+static int64_t zt_rows(const hpdg_operator* op) { return op->ndof + (op->blk_overlap ? op->blk_rows : 0); }
+
 template <typename T>
 static void upload_prec(hpdg_operator* op) {
   PrecHost& H = op->host;
@@ -539,10 +564,46 @@ static void upload_prec(hpdg_operator* op) {
   op->blk_ptr.upload(bptr);
   op->blk_off.upload(boff);
   op->blk_dof.upload(bdof);
+  // overlapping spaces: output slots past the DG vector and, per N-DOF, the
+  // slots to sum (in block order)
+  {
+    std::vector<int32_t> cnt(op->ndof, 0);
+    bool overlap = false;
+    for (int32_t g : bdof) overlap |= ++cnt[g] > 1;
+    op->blk_overlap = overlap ? 1 : 0;
+    op->blk_out = DevBuf();
+    op->g_dof = DevBuf();
+    op->g_ptr = DevBuf();
+    op->g_slot = DevBuf();
+    op->g_n = 0;
+    if (overlap) {
+      if (op->ndof + (int64_t)bdof.size() > (int64_t)INT32_MAX)
+        throw Error(HPDG_E_UNSUPPORTED, "DOFs plus block rows exceed 2^31");
+      std::vector<int32_t> out(bdof.size());
+      for (size_t q = 0; q < bdof.size(); ++q) out[q] = (int32_t)(op->ndof + (int64_t)q);
+      std::vector<int32_t> gdof, gptr{0}, gslot;
+      std::vector<int32_t> first(op->ndof + 1, 0);
+      for (int64_t g = 0; g < op->ndof; ++g) first[g + 1] = first[g] + cnt[g];
+      std::vector<int32_t> fill(first.begin(), first.end() - 1), slots(bdof.size());
+      for (size_t q = 0; q < bdof.size(); ++q) slots[fill[bdof[q]]++] = out[q];   // block order
+      for (int64_t g = 0; g < op->ndof; ++g) {
+        if (cnt[g] == 0) continue;
+        gdof.push_back((int32_t)g);
+        for (int32_t q = first[g]; q < first[g + 1]; ++q) gslot.push_back(slots[q]);
+        gptr.push_back((int32_t)gslot.size());
+      }
+      op->blk_out.upload(out);
+      op->g_dof.upload(gdof);
+      op->g_ptr.upload(gptr);
+      op->g_slot.upload(gslot);
+      op->g_n = (int64_t)gdof.size();
+    }
+  }
   // block inverses were computed in FP64 (binv64) during setup
   op->blk_inv.alloc(0);
   upload_csr<T>(H.P, op->P);
   upload_csr<T>(H.PT, op->PT);
+  if (H.amg.lv.size() > (size_t)kMaxLevels) throw Error(HPDG_E_UNSUPPORTED, "too many AMG levels");
   op->lv.clear();
   op->lv.resize(H.amg.lv.size());
   for (size_t l = 0; l < H.amg.lv.size(); ++l) {
@@ -582,7 +643,7 @@ static void upload_prec(hpdg_operator* op) {
       if (!op->lv[l].use_tail && op->lv[l].A.nnz <= kAutoFuse) set_fused<T>(op, l, true);
   }
   op->rT.alloc((size_t)op->ndof * op->max_nrhs * sizeof(T));
-  op->zT.alloc((size_t)op->ndof * op->max_nrhs * sizeof(T));
+  op->zT.alloc((size_t)zt_rows(op) * op->max_nrhs * sizeof(T));
 }
 
 // second region of the share buffer (one RHS), after the largest first region
@@ -891,16 +952,19 @@ extern "C" hpdg_status hpdg_setup_operator(const hpdg_mesh* mh, const hpdg_opera
       if (o->jb_only)
         for (auto& l : H.lab)
           if (l == 2) l = 1;
-      H.blocks = edge_spaces(M, H.lab);
+      H.blocks = M.dim == 2 ? edge_spaces(M, H.lab) : face_spaces(M, H.lab);
       if (o->max_block > 0) {
+        // a space larger than max_block gets no block solve; N-DOFs left in
+        // no block are handled by point Jacobi
         std::vector<std::vector<int64_t>> keep;
-        for (auto& b : H.blocks) {
-          if ((int)b.size() > o->max_block) {
-            for (int64_t g : b) H.lab[g] = 1;
-          } else {
+        std::vector<char> covered(M.ndof, 0);
+        for (auto& b : H.blocks)
+          if ((int)b.size() <= o->max_block) {
+            for (int64_t g : b) covered[g] = 1;
             keep.push_back(std::move(b));
           }
-        }
+        for (int64_t g = 0; g < M.ndof; ++g)
+          if (H.lab[g] == 2 && !covered[g]) H.lab[g] = 1;
         H.blocks.swap(keep);
       }
       // inverse diagonal on V_J, +0 on interior DOFs, -0 on V_e DOFs (marks
@@ -911,18 +975,43 @@ extern "C" hpdg_status hpdg_setup_operator(const hpdg_mesh* mh, const hpdg_opera
         else if (H.lab[g] == 2) H.dinvJ[g] = -0.0;
       }
       phase("edge spaces");
+      // the blocks are independent: assembled and inverted on the setup
+      // threads, each into its own slice of binv (results do not depend on
+      // the thread count)
       std::vector<double>& binv = op->up.binv;
-      double t_asm = 0, t_inv = 0;
-      for (auto& B : H.blocks) {
-        auto ta = std::chrono::steady_clock::now();
-        std::vector<double> S = dg_submatrix(M, oo, B, eta2);
-        auto tb = std::chrono::steady_clock::now();
-        spd_inverse(S, (int)B.size());
-        t_asm += std::chrono::duration<double>(tb - ta).count();
-        t_inv += std::chrono::duration<double>(std::chrono::steady_clock::now() - tb).count();
-        binv.insert(binv.end(), S.begin(), S.end());
+      std::vector<int64_t> boff(H.blocks.size() + 1, 0);
+      for (size_t b = 0; b < H.blocks.size(); ++b)
+        boff[b + 1] = boff[b] + (int64_t)H.blocks[b].size() * (int64_t)H.blocks[b].size();
+      binv.assign((size_t)boff.back(), 0.0);
+      {
+        const int64_t nbk = (int64_t)H.blocks.size();
+        std::atomic<int64_t> next{0};
+        std::mutex emu;
+        int ecode = 0;
+        std::string emsg;
+        parallel_chunks(std::min<int64_t>(setup_threads(), std::max<int64_t>(1, nbk)),
+                        [&](int64_t, int64_t, int) {
+                          for (;;) {
+                            const int64_t b = next.fetch_add(1);
+                            if (b >= nbk) break;
+                            try {
+                              std::vector<double> S = dg_submatrix(M, oo, H.blocks[b], eta2);
+                              spd_inverse(S, (int)H.blocks[b].size());
+                              std::copy(S.begin(), S.end(), binv.begin() + boff[b]);
+                            } catch (Error& e) {
+                              std::lock_guard<std::mutex> lk(emu);
+                              if (!ecode) { ecode = e.code; emsg = e.what(); }
+                              next.store(nbk);
+                            } catch (std::bad_alloc&) {
+                              std::lock_guard<std::mutex> lk(emu);
+                              if (!ecode) { ecode = HPDG_E_NOMEM; emsg = "host allocation failed"; }
+                              next.store(nbk);
+                            }
+                          }
+                        },
+                        1);
+        if (ecode) throw Error(ecode, emsg);
       }
-      if (verbose) std::fprintf(stderr, "hpdg setup: blocks: assemble %.3f s, invert %.3f s\n", t_asm, t_inv);
       phase("blocks");
       H.P = prolongation(M);
       phase("prolongation");
@@ -1069,7 +1158,7 @@ static void spmv(const DevCSR& A, int nrhs, const T* x, const T* b, const T* d, 
 }
 
 template <typename T>
-static void vcycle(hpdg_operator* op, size_t l, int nrhs, hipStream_t s);
+static void vcycle(hpdg_operator* op, const BWork& W, size_t l, int nrhs, hipStream_t s);
 
 // Dense tail of the V-cycle: on the level just above the coarsest, one
 // V(1,1) cycle is a fixed linear map of that level's right-hand side,
@@ -1135,12 +1224,12 @@ static void set_tail(hpdg_operator* op, size_t l, bool on) {
 
 // fused level (one RHS): two launches instead of four, same V(1,1) steps
 template <typename T>
-static void vcycle_fused(hpdg_operator* op, size_t l, int nrhs, hipStream_t s) {
+static void vcycle_fused(hpdg_operator* op, const BWork& W, size_t l, int nrhs, hipStream_t s) {
   LevelDev& L = op->lv[l];
-  LevelDev& C = op->lv[l + 1];
-  spmv<T, 0>(L.M, nrhs, L.b.as<T>(), nullptr, nullptr, nullptr, C.b.as<T>(), s);
-  vcycle<T>(op, l + 1, nrhs, s);
-  spmv<T, 5>(L.U, nrhs, L.b.as<T>(), C.x.as<T>(), nullptr, nullptr, L.x.as<T>(), s);
+  T *b = (T*)W.b[l], *x = (T*)W.x[l], *bc = (T*)W.b[l + 1], *xc = (T*)W.x[l + 1];
+  spmv<T, 0>(L.M, nrhs, b, nullptr, nullptr, nullptr, bc, s);
+  vcycle<T>(op, W, l + 1, nrhs, s);
+  spmv<T, 5>(L.U, nrhs, b, xc, nullptr, nullptr, x, s);
 }
 
 // x = C b for a dense n x n matrix and nrhs > 1 interleaved right-hand sides:
@@ -1155,19 +1244,19 @@ static void dense_many(hpdg_operator* op, int n, int nrhs, const T* C, const T* 
 }
 
 template <typename T>
-static void vcycle(hpdg_operator* op, size_t l, int nrhs, hipStream_t s) {
+static void vcycle(hpdg_operator* op, const BWork& W, size_t l, int nrhs, hipStream_t s) {
+  T *b = (T*)W.b[l], *x = (T*)W.x[l];
   if (op->lv[l].use_tail) {
     LevelDev& L = op->lv[l];
     const int n = L.A.nrows;
     if (nrhs == 1)
-      hipLaunchKernelGGL(k_dense_gemv1<T>, dim3((n + 3) / 4), dim3(256), 0, s, n, L.tail.as<T>(), L.b.as<T>(),
-                         L.x.as<T>());
+      hipLaunchKernelGGL(k_dense_gemv1<T>, dim3((n + 3) / 4), dim3(256), 0, s, n, L.tail.as<T>(), b, x);
     else
-      dense_many<T>(op, n, nrhs, L.tail.as<T>(), L.b.as<T>(), L.x.as<T>(), s);
+      dense_many<T>(op, n, nrhs, L.tail.as<T>(), b, x, s);
     return;
   }
   if (l + 1 < op->lv.size() && op->lv[l].fused && (nrhs == 1 || !op->no_fused_multi)) {
-    vcycle_fused<T>(op, l, nrhs, s);
+    vcycle_fused<T>(op, W, l, nrhs, s);
     return;
   }
   LevelDev& L = op->lv[l];
@@ -1177,35 +1266,52 @@ static void vcycle(hpdg_operator* op, size_t l, int nrhs, hipStream_t s) {
     if (nt == 0) return;
     if (nrhs == 1)
       hipLaunchKernelGGL(k_dense_gemv1<T>, dim3((op->ncoarse + 3) / 4), dim3(256), 0, s, op->ncoarse,
-                         op->coarse.as<T>(), L.b.as<T>(), L.x.as<T>());
+                         op->coarse.as<T>(), b, x);
     else
-      dense_many<T>(op, op->ncoarse, nrhs, op->coarse.as<T>(), L.b.as<T>(), L.x.as<T>(), s);
+      dense_many<T>(op, op->ncoarse, nrhs, op->coarse.as<T>(), b, x, s);
     return;
   }
-  LevelDev& C = op->lv[l + 1];
+  T *r = (T*)W.r[l], *t = (T*)W.t[l], *bc = (T*)W.b[l + 1], *xc = (T*)W.x[l + 1];
   // pre-smoothing from zero and residual: x = D b, r = b - A D b; on large
   // levels x is formed first, so that the product gathers one vector
   // instead of two (the same values: x is rounded as in the fused form)
   if (nrhs == 1 && L.A.nnz > op->presplit_nnz) {
-    hipLaunchKernelGGL(k_dscale<T>, dim3(nblk(n)), dim3(256), 0, s, n, L.l1inv.as<T>(), L.b.as<T>(), L.x.as<T>());
-    spmv<T, 1>(L.A, 1, L.x.as<T>(), L.b.as<T>(), nullptr, nullptr, L.r.as<T>(), s);
+    hipLaunchKernelGGL(k_dscale<T>, dim3(nblk(n)), dim3(256), 0, s, n, L.l1inv.as<T>(), b, x);
+    spmv<T, 1>(L.A, 1, x, b, nullptr, nullptr, r, s);
   } else {
-    spmv<T, 3>(L.A, nrhs, L.b.as<T>(), nullptr, L.l1inv.as<T>(), L.x.as<T>(), L.r.as<T>(), s);
+    spmv<T, 3>(L.A, nrhs, b, nullptr, L.l1inv.as<T>(), x, r, s);
   }
   // restriction b_c = P^T r
-  spmv<T, 0>(L.R, nrhs, L.r.as<T>(), nullptr, nullptr, nullptr, C.b.as<T>(), s);
-  vcycle<T>(op, l + 1, nrhs, s);
+  spmv<T, 0>(L.R, nrhs, r, nullptr, nullptr, nullptr, bc, s);
+  vcycle<T>(op, W, l + 1, nrhs, s);
   // t = x + P x_c ; x = t + D (b - A t)
-  spmv<T, 2>(L.P, nrhs, C.x.as<T>(), L.x.as<T>(), nullptr, nullptr, L.t.as<T>(), s);
-  spmv<T, 4>(L.A, nrhs, L.t.as<T>(), L.b.as<T>(), L.l1inv.as<T>(), nullptr, L.x.as<T>(), s);
-  (void)n;
+  spmv<T, 2>(L.P, nrhs, xc, x, nullptr, nullptr, t, s);
+  spmv<T, 4>(L.A, nrhs, t, b, L.l1inv.as<T>(), nullptr, x, s);
+}
+
+// the operator's own work vectors for B
+static BWork op_work(hpdg_operator* op) {
+  BWork W;
+  W.rT = op->rT.p;
+  W.zT = op->zT.p;
+  for (size_t l = 0; l < op->lv.size(); ++l) {
+    W.b[l] = op->lv[l].b.p;
+    W.x[l] = op->lv[l].x.p;
+    W.r[l] = op->lv[l].r.p;
+    W.t[l] = op->lv[l].t.p;
+  }
+  return W;
 }
 
 // ------------------------------------------------------------ autotuner
 // Times y = A x for one sparse matrix of the one-RHS path under every row
 // binning (long-row threshold x lanes per short row) and keeps the fastest.
 template <typename T>
-static void launch_front(hpdg_operator* op, const T* rt, T* zb, hipStream_t s);
+static void launch_front(hpdg_operator* op, const T* rt, T* zb, T* bc0, hipStream_t s);
+// where the block solves write: the DOF itself, or its slot when the V_e overlap
+static const int32_t* blk_out(const hpdg_operator* op) {
+  return op->blk_overlap ? op->blk_out.as<int32_t>() : op->blk_dof.as<int32_t>();
+}
 
 // a candidate replaces the default only when this much faster (timing noise)
 constexpr double kTuneMargin = 0.95;
@@ -1388,16 +1494,16 @@ static int tune_all(hpdg_operator* op, hipStream_t s, int64_t* report, int cap) 
   // P^T runs inside the B front kernel: time that kernel
   T* zb = op->zT.as<T>();
   tune_csr<T>(H.PT, op->PT, op->rT.as<T>(), op->lv[0].b.as<T>(), s, slot(3, 0),
-              [&]() { launch_front<T>(op, op->rT.as<T>(), zb, s); });
+              [&]() { launch_front<T>(op, op->rT.as<T>(), zb, op->lv[0].b.as<T>(), s); });
   // then the lanes per V_e block row of the same kernel
   if (op->blk_rows > 0) {
     hipEvent_t f0, f1;
     HIPCHK(hipEventCreate(&f0));
     HIPCHK(hipEventCreate(&f1));
     auto time_front = [&]() {
-      for (int w = 0; w < 3; ++w) launch_front<T>(op, op->rT.as<T>(), zb, s);
+      for (int w = 0; w < 3; ++w) launch_front<T>(op, op->rT.as<T>(), zb, op->lv[0].b.as<T>(), s);
       HIPCHK(hipEventRecord(f0, s));
-      for (int w = 0; w < 10; ++w) launch_front<T>(op, op->rT.as<T>(), zb, s);
+      for (int w = 0; w < 10; ++w) launch_front<T>(op, op->rT.as<T>(), zb, op->lv[0].b.as<T>(), s);
       HIPCHK(hipEventRecord(f1, s));
       HIPCHK(hipEventSynchronize(f1));
       float ms = 0.f;
@@ -1438,9 +1544,9 @@ static int tune_all(hpdg_operator* op, hipStream_t s, int64_t* report, int cap) 
   HIPCHK(hipEventCreate(&e1));
   for (int l = (int)op->lv.size() - 2; l >= 0; --l) {
     auto time_cycle = [&]() {
-      for (int w = 0; w < 3; ++w) vcycle<T>(op, l, 1, s);
+      for (int w = 0; w < 3; ++w) vcycle<T>(op, op_work(op), l, 1, s);
       HIPCHK(hipEventRecord(e0, s));
-      for (int w = 0; w < 10; ++w) vcycle<T>(op, l, 1, s);
+      for (int w = 0; w < 10; ++w) vcycle<T>(op, op_work(op), l, 1, s);
       HIPCHK(hipEventRecord(e1, s));
       HIPCHK(hipEventSynchronize(e1));
       float ms = 0.f;
@@ -1532,8 +1638,7 @@ extern "C" hpdg_status hpdg_operator_tune(hpdg_operator* op, void* stream, int64
 // front of B with one RHS: point Jacobi, V_e block solves and r_c = P^T r in
 // one launch (k_front)
 template <typename T>
-static void launch_front(hpdg_operator* op, const T* rt, T* zb, hipStream_t s) {
-  LevelDev& L0 = op->lv[0];
+static void launch_front(hpdg_operator* op, const T* rt, T* zb, T* bc0, hipStream_t s) {
   const DevCSR& A = op->PT;
   const int nb_diag = (int)nblk(op->ndof);
   const int nlb = (A.nlong + 3) / 4;
@@ -1545,8 +1650,8 @@ static void launch_front(hpdg_operator* op, const T* rt, T* zb, hipStream_t s) {
     hipLaunchKernelGGL((k_front<T, LB, LP>), dim3(grid), dim3(256), 0, s, op->ndof, nb_diag, op->dinvJ.as<T>(),
                        op->blk_rows, nb_blk, op->blk_rowb.as<int32_t>(), op->blk_rowl.as<int32_t>(),
                        op->blk_ptr.as<int64_t>(), op->blk_off.as<int64_t>(), op->blk_dof.as<int32_t>(),
-                       op->blk_inv.as<T>(), A.nlong, nlb, nshort, A.rows.as<int32_t>(), A.ptr.as<int32_t>(),
-                       A.idx.as<int32_t>(), A.val.as<T>(), rt, zb, L0.b.as<T>());
+                       blk_out(op), op->blk_inv.as<T>(), A.nlong, nlb, nshort, A.rows.as<int32_t>(), A.ptr.as<int32_t>(),
+                       A.idx.as<int32_t>(), A.val.as<T>(), rt, zb, bc0);
   };
   auto with_lprp = [&](auto lprb) {
     switch (A.lpr) {
@@ -1567,30 +1672,31 @@ static void launch_front(hpdg_operator* op, const T* rt, T* zb, hipStream_t s) {
   }
 }
 
-// z = B r. With pdot (one RHS) the last kernel also writes per-block shares
-// of r'z there; returns their count (0 without pdot).
+// z = B r with the work vectors W. With pdot (one RHS) the last kernel also
+// writes per-block shares of r'z there; returns their count (0 without pdot).
 template <typename T>
-static int apply_B_dev(hpdg_operator* op, const double* r, double* z, int nrhs, hipStream_t s,
+static int apply_B_dev(hpdg_operator* op, const BWork& W, const double* r, double* z, int nrhs, hipStream_t s,
                        double* pdot = nullptr, bool r_cast = false) {
   int64_t n = op->ndof * nrhs;
   const T* rt;
-  T* zb = op->zT.as<T>();
+  T* zb = (T*)W.zT;
+  T* rT = (T*)W.rT;
   const bool lowp = !std::is_same<T, double>::value;
   if (!lowp) rt = (const T*)r;
   else if (nrhs == 1 && r_cast) {
-    rt = op->rT.as<T>();   // written by the CG update together with r
+    rt = rT;   // written by the CG update together with r
   } else if (nrhs == 1) {
-    hipLaunchKernelGGL((k_cast<double, T>), dim3(nblk(n)), dim3(256), 0, s, n, r, op->rT.as<T>());
-    rt = op->rT.as<T>();
+    hipLaunchKernelGGL((k_cast<double, T>), dim3(nblk(n)), dim3(256), 0, s, n, r, rT);
+    rt = rT;
   } else {
     // the cast and the point Jacobi part in one pass
-    hipLaunchKernelGGL(k_cast_diag_scale<T>, dim3(nblk(n)), dim3(256), 0, s, n, nrhs, op->dinvJ.as<T>(), r,
-                       op->rT.as<T>(), zb);
-    rt = op->rT.as<T>();
+    hipLaunchKernelGGL(k_cast_diag_scale<T>, dim3(nblk(n)), dim3(256), 0, s, n, nrhs, op->dinvJ.as<T>(), r, rT,
+                       zb);
+    rt = rT;
   }
-  LevelDev& L0 = op->lv[0];
+  T* b0 = (T*)W.b[0];
   if (nrhs == 1) {
-    launch_front<T>(op, rt, zb, s);
+    launch_front<T>(op, rt, zb, b0, s);
   } else {
     if (!lowp)
       hipLaunchKernelGGL(k_diag_scale<T>, dim3(nblk(n)), dim3(256), 0, s, n, nrhs, op->dinvJ.as<T>(), rt, zb);
@@ -1601,24 +1707,27 @@ static int apply_B_dev(hpdg_operator* op, const double* r, double* z, int nrhs, 
         hipLaunchKernelGGL(k_block_mfma<T>, dim3((unsigned)op->nblocks), dim3(256),
                            (size_t)op->max_blk * sizeof(int32_t), s, (int)op->nblocks, nrhs,
                            op->blk_ptr.as<int64_t>(), op->blk_off.as<int64_t>(), op->blk_dof.as<int32_t>(),
-                           op->blk_inv.as<T>(), rt, zb);
+                           blk_out(op), op->blk_inv.as<T>(), rt, zb);
       else if (shm <= 48 * 1024)
         hipLaunchKernelGGL(k_block_gemm<T>, dim3((unsigned)op->nblocks), dim3(256), shm, s, (int)op->nblocks, nrhs,
                            op->blk_ptr.as<int64_t>(), op->blk_off.as<int64_t>(), op->blk_dof.as<int32_t>(),
-                           op->blk_inv.as<T>(), rt, zb);
+                           blk_out(op), op->blk_inv.as<T>(), rt, zb);
       else
         hipLaunchKernelGGL(k_block_gemv<T>, dim3(nblk(nt)), dim3(256), 0, s, op->blk_rows, nrhs,
                            op->blk_rowb.as<int32_t>(), op->blk_rowl.as<int32_t>(), op->blk_ptr.as<int64_t>(),
-                           op->blk_off.as<int64_t>(), op->blk_dof.as<int32_t>(), op->blk_inv.as<T>(), rt, zb);
+                           op->blk_off.as<int64_t>(), op->blk_dof.as<int32_t>(), blk_out(op), op->blk_inv.as<T>(),
+                           rt, zb);
     }
-    spmv<T, 0>(op->PT, nrhs, rt, nullptr, nullptr, nullptr, L0.b.as<T>(), s);
+    spmv<T, 0>(op->PT, nrhs, rt, nullptr, nullptr, nullptr, b0, s);
   }
-  vcycle<T>(op, 0, nrhs, s);
+  if (op->blk_overlap)
+    hipLaunchKernelGGL(k_block_gather<T>, dim3(nblk(op->g_n * nrhs)), dim3(256), 0, s, (int)op->g_n, nrhs,
+                       op->g_dof.as<int32_t>(), op->g_ptr.as<int32_t>(), op->g_slot.as<int32_t>(), zb);
+  vcycle<T>(op, W, 0, nrhs, s);
   int64_t nt = op->ndof * nrhs;
-  (void)L0;
   if (nrhs != 1) pdot = nullptr;
   hipLaunchKernelGGL(k_prolong_out<T>, dim3(nblk(nt)), dim3(256), 0, s, (int)op->ndof, nrhs,
-                     op->P.ptr.as<int32_t>(), op->P.idx.as<int32_t>(), op->P.val.as<T>(), L0.x.as<T>(), zb, z, r,
+                     op->P.ptr.as<int32_t>(), op->P.idx.as<int32_t>(), op->P.val.as<T>(), (T*)W.x[0], zb, z, r,
                      pdot);
   return pdot ? (int)nblk(nt) : 0;
 }
@@ -1648,9 +1757,12 @@ extern "C" hpdg_status hpdg_apply_B(hpdg_operator* op, const double* r, double* 
   hpdg_status st = check_vec_args(op, r, z, nrhs);
   if (st != HPDG_OK) return st;
   if (op->no_prec) return fail(HPDG_E_UNSUPPORTED, "operator was built with no_prec");
+  if (op->run.phase == 1 || op->run.phase == 2)
+    return fail(HPDG_E_INVALID, "operator has a solve in flight (its work vectors are in use)");
   hipStream_t s = (hipStream_t)stream;
-  if (op->prec32) apply_B_dev<float>(op, r, z, nrhs, s);
-  else apply_B_dev<double>(op, r, z, nrhs, s);
+  const BWork W = op_work(op);
+  if (op->prec32) apply_B_dev<float>(op, W, r, z, nrhs, s);
+  else apply_B_dev<double>(op, W, r, z, nrhs, s);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(HPDG_E_HIP, hipGetErrorString(e));
   return HPDG_OK;
@@ -1733,8 +1845,9 @@ static CGScal cg_scal(hpdg_operator* op) {
 // r_cast: the FP32 copy of in is already in rT (one RHS)
 static int apply_B_any(hpdg_operator* op, const double* in, double* outv, int nrhs, hipStream_t s,
                        double* pdot = nullptr, bool r_cast = false) {
-  if (op->prec32) return apply_B_dev<float>(op, in, outv, nrhs, s, pdot, r_cast);
-  return apply_B_dev<double>(op, in, outv, nrhs, s, pdot);
+  const BWork W = op_work(op);
+  if (op->prec32) return apply_B_dev<float>(op, W, in, outv, nrhs, s, pdot, r_cast);
+  return apply_B_dev<double>(op, W, in, outv, nrhs, s, pdot);
 }
 
 // final stage of a dot product whose per-block shares are already in part

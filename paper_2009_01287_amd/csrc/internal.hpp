@@ -146,6 +146,8 @@ CSR prolongation(Mesh& M);
 // labels: 0 interior, 1 V_J, 2 N
 std::vector<int8_t> dof_labels(Mesh& M, int remark_relax);
 std::vector<std::vector<int64_t>> edge_spaces(const Mesh& M, const std::vector<int8_t>& lab);
+// 3D: one space per master face (may overlap)
+std::vector<std::vector<int64_t>> face_spaces(const Mesh& M, const std::vector<int8_t>& lab);
 // LOR block-diagonal matrix applied: returns A~ P (CSR ndof x nconf)
 CSR lor_times(const Mesh& M, const CSR& P);
 

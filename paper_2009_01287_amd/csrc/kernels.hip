@@ -1611,8 +1611,8 @@ __global__ __launch_bounds__(256) void k_front(int64_t ndof, int nb_diag, const 
                                                int64_t brows, int nb_blk, const int32_t* __restrict__ row_blk,
                                                const int32_t* __restrict__ row_loc,
                                                const int64_t* __restrict__ bptr, const int64_t* __restrict__ boff,
-                                               const int32_t* __restrict__ bdof, const T* __restrict__ binv,
-                                               int nlong, int nlong_blk, int nshort,
+                                               const int32_t* __restrict__ bdof, const int32_t* __restrict__ bout,
+                                               const T* __restrict__ binv, int nlong, int nlong_blk, int nshort,
                                                const int32_t* __restrict__ rows, const int32_t* __restrict__ ptr,
                                                const int32_t* __restrict__ idx, const T* __restrict__ val,
                                                const T* __restrict__ r, T* __restrict__ z, T* __restrict__ rc) {
@@ -1643,7 +1643,7 @@ __global__ __launch_bounds__(256) void k_front(int64_t ndof, int nb_diag, const 
 #pragma unroll
     for (int o = LPRB / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, LPRB);
     // V_e DOFs have dinv = 0, so the block result is the whole value there
-    if (sub == 0) z[bdof[s0 + i]] = acc;
+    if (sub == 0) z[bout[s0 + i]] = acc;
     return;
   }
   b -= nb_blk;
@@ -1680,8 +1680,9 @@ __global__ __launch_bounds__(256) void k_block_gemv(int64_t nrows, int nrhs, con
                                                     const int32_t* __restrict__ row_loc,
                                                     const int64_t* __restrict__ bptr,
                                                     const int64_t* __restrict__ boff,
-                                                    const int32_t* __restrict__ bdof, const T* __restrict__ binv,
-                                                    const T* __restrict__ r, T* __restrict__ z) {
+                                                    const int32_t* __restrict__ bdof, const int32_t* __restrict__ bout,
+                                                    const T* __restrict__ binv, const T* __restrict__ r,
+                                                    T* __restrict__ z) {
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t rw = t / nrhs;
   const int c = (int)(t - rw * nrhs);
@@ -1694,7 +1695,7 @@ __global__ __launch_bounds__(256) void k_block_gemv(int64_t nrows, int nrhs, con
   T acc = 0;
 #pragma unroll 4
   for (int j = 0; j < m; ++j) acc += row[j] * r[(int64_t)bdof[s0 + j] * nrhs + c];
-  z[(int64_t)bdof[s0 + i] * nrhs + c] = acc;
+  z[(int64_t)bout[s0 + i] * nrhs + c] = acc;
 }
 
 // exact V_e solves, interleaved RHS: one workgroup per block; the block's
@@ -1703,8 +1704,9 @@ __global__ __launch_bounds__(256) void k_block_gemv(int64_t nrows, int nrhs, con
 template <typename T>
 __global__ __launch_bounds__(256) void k_block_gemm(int nblocks, int nrhs, const int64_t* __restrict__ bptr,
                                                     const int64_t* __restrict__ boff,
-                                                    const int32_t* __restrict__ bdof, const T* __restrict__ binv,
-                                                    const T* __restrict__ r, T* __restrict__ z) {
+                                                    const int32_t* __restrict__ bdof, const int32_t* __restrict__ bout,
+                                                    const T* __restrict__ binv, const T* __restrict__ r,
+                                                    T* __restrict__ z) {
   extern __shared__ unsigned char blk_lds[];
   T* rl = reinterpret_cast<T*>(blk_lds);
   const int b = blockIdx.x;
@@ -1721,7 +1723,7 @@ __global__ __launch_bounds__(256) void k_block_gemm(int nblocks, int nrhs, const
     const int i = t / nrhs, c = t - i * nrhs;
     T acc = 0;
     for (int j = 0; j < m; ++j) acc += B[(int64_t)i * m + j] * rl[j * nrhs + c];
-    z[(int64_t)bdof[s0 + i] * nrhs + c] = acc;
+    z[(int64_t)bout[s0 + i] * nrhs + c] = acc;
   }
 }
 
@@ -1757,8 +1759,9 @@ struct Mfma16<double> {
 template <typename T>
 __global__ __launch_bounds__(256) void k_block_mfma(int nblocks, int nrhs, const int64_t* __restrict__ bptr,
                                                     const int64_t* __restrict__ boff,
-                                                    const int32_t* __restrict__ bdof, const T* __restrict__ binv,
-                                                    const T* __restrict__ r, T* __restrict__ z) {
+                                                    const int32_t* __restrict__ bdof, const int32_t* __restrict__ bout,
+                                                    const T* __restrict__ binv, const T* __restrict__ r,
+                                                    T* __restrict__ z) {
   extern __shared__ unsigned char blk_lds[];
   int32_t* sdof = reinterpret_cast<int32_t*>(blk_lds);
   const int b = blockIdx.x;
@@ -1794,9 +1797,26 @@ __global__ __launch_bounds__(256) void k_block_mfma(int nblocks, int nrhs, const
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int row = i0 + Mfma16<T>::row(lk, v);
-      if (row < m) z[(int64_t)sdof[row] * nrhs + j0 + li] = acc[v];
+      if (row < m) z[(int64_t)bout[s0 + row] * nrhs + j0 + li] = acc[v];
     }
   }
+}
+
+// overlapping V_e (3D): the block solves write one slot per block row past
+// the DG vector; every N-DOF then sums the slots of the blocks that hold it,
+// in block order (fixed, so results do not depend on scheduling):
+// z[dof] = sum_q z[slot_q] (interleaved RHS)
+template <typename T>
+__global__ __launch_bounds__(256) void k_block_gather(int ndofs, int nrhs, const int32_t* __restrict__ gdof,
+                                                      const int32_t* __restrict__ gptr,
+                                                      const int32_t* __restrict__ gslot, T* __restrict__ z) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t row = t / nrhs;
+  const int c = (int)(t - row * nrhs);
+  if (row >= ndofs) return;
+  T acc = 0;
+  for (int q = gptr[row]; q < gptr[row + 1]; ++q) acc += z[(int64_t)gslot[q] * nrhs + c];
+  z[(int64_t)gdof[row] * nrhs + c] = acc;
 }
 
 // dense x = C b for many RHS (nrhs a multiple of 16) on the matrix cores: one

@@ -263,11 +263,12 @@ std::vector<double> dg_submatrix(const Mesh& M, const OpOpts& o, const std::vect
     size_t nc = pos.size();
     // -[[u]] {k du/dn} - {k dv/dn} [[v]] (+ sigma [[u]][[v]]): the jump of a
     // column vanishes unless its node lies on the face, so only those rows
-    // carry the consistency terms
+    // carry the consistency terms, and a face without them adds nothing
     std::vector<size_t> onf;
     for (size_t a = 0; a < nc; ++a)
       for (int g = 0; g < nQ; ++g)
         if (Ju[a][g] != 0.0) { onf.push_back(a); break; }
+    if (onf.empty()) continue;
     for (size_t a : onf)
       for (size_t b = 0; b < nc; ++b) {
         double s = 0;
@@ -283,39 +284,59 @@ std::vector<double> dg_submatrix(const Mesh& M, const OpOpts& o, const std::vect
           S[pos[a] * nb + pos[b]] += s;
         }
     if (o.form == 1) {
-      double c2 = f.ep >= 0 ? 0.25 : 1.0;
+      // c_e^2 eta g_K(u)' M_K^{-1} g_K(v) per side K: g_K(u) is nonzero only
+      // for the columns with a nonzero jump, and M_K^{-1} on the side nodes is
+      // the Kronecker product of the two tangential 1D inverse mass matrices
+      // (times the normal one's diagonal entry and h^-d)
+      const double c2 = f.ep >= 0 ? 0.25 : 1.0;
+      const size_t no = onf.size();
       for (const FaceSide& K : Q.sides) {
         const Basis1D& Bk = basis(M.p[K.e]);
-        int nk = K.n;
+        const int nk = K.n;
         int nsn = 1;
         for (int j = 0; j < Q.nt; ++j) nsn *= nk;
-        // G[r][c] = sum_Q V_K[Q,r] W Ju[c]; r over K's side nodes
-        std::vector<double> G((size_t)nsn * nc, 0.0);
+        // G[r][c] = sum_Q V_K[Q,r] W Ju[onf[c]]; r over K's side nodes
+        std::vector<double> G((size_t)nsn * no, 0.0);
         for (int r = 0; r < nsn; ++r) {
           int rt[2] = {r % nk, r / nk};
-          for (size_t c = 0; c < nc; ++c) {
+          for (size_t c = 0; c < no; ++c) {
+            const std::vector<double>& ju = Ju[onf[c]];
             double s = 0;
             for (int g = 0; g < nQ; ++g) {
               int gg = g;
               double v = 1.0;
               for (int j = 0; j < Q.nt; ++j) { v *= K.Lt[j][(gg % Q.q) * nk + rt[j]]; gg /= Q.q; }
-              s += v * W[g] * Ju[c][g];
+              s += v * W[g] * ju[g];
             }
-            G[(size_t)r * nc + c] = s;
+            G[(size_t)r * no + c] = s;
           }
         }
-        int sk = K.s ? nk - 1 : 0;
-        double mk = Bk.Minv[sk * nk + sk] * std::pow(M.h[K.e], -d);
-        for (int r = 0; r < nsn; ++r)
+        const int sk = K.s ? nk - 1 : 0;
+        const double mk = Bk.Minv[sk * nk + sk] * std::pow(M.h[K.e], -d);
+        // H = (Minv x Minv) G, one tangential direction at a time
+        std::vector<double> Hm = G;
+        for (int j = 0; j < Q.nt; ++j) {
+          std::vector<double> T((size_t)nsn * no, 0.0);
+          const int st = j == 0 ? 1 : nk;
           for (int r2 = 0; r2 < nsn; ++r2) {
-            int a1[2] = {r % nk, r / nk}, a2[2] = {r2 % nk, r2 / nk};
-            double mi = mk;
-            for (int j = 0; j < Q.nt; ++j) mi *= Bk.Minv[a1[j] * nk + a2[j]];
-            for (size_t a = 0; a < nc; ++a) {
-              double ga = G[(size_t)r * nc + a] * mi * c2 * sig;
-              if (ga == 0.0) continue;
-              for (size_t b = 0; b < nc; ++b) S[pos[a] * nb + pos[b]] += ga * G[(size_t)r2 * nc + b];
+            const int a2 = (r2 / st) % nk;
+            const int rb = r2 - a2 * st;
+            for (int a1 = 0; a1 < nk; ++a1) {
+              const double mi = Bk.Minv[a1 * nk + a2];
+              if (mi == 0.0) continue;
+              const double* src = &Hm[(size_t)(rb + a1 * st) * no];
+              double* dst = &T[(size_t)r2 * no];
+              for (size_t c = 0; c < no; ++c) dst[c] += mi * src[c];
             }
+          }
+          Hm.swap(T);
+        }
+        const double w = mk * c2 * sig;
+        for (size_t a = 0; a < no; ++a)
+          for (size_t b = 0; b < no; ++b) {
+            double s = 0;
+            for (int r = 0; r < nsn; ++r) s += Hm[(size_t)r * no + a] * G[(size_t)r * no + b];
+            S[pos[onf[a]] * nb + pos[onf[b]]] += w * s;
           }
       }
     }
@@ -632,6 +653,62 @@ std::vector<std::vector<int64_t>> edge_spaces(const Mesh& M, const std::vector<i
   // components in order of their smallest DOF; DOFs ascending (already)
   std::sort(comps.begin(), comps.end(), [](auto& a, auto& b) { return a[0] < b[0]; });
   return comps;
+}
+
+// V_e in 3D (Sec. 3.3 treats 2D only): the seed-and-grow process with its
+// growth kept inside the master face of the seed, so every space belongs to
+// one master face (a conforming side, the full side of the coarser leaf of a
+// nonconforming interface, or a boundary side) and holds the N-DOFs on that
+// face from the leaves on both of its sides. Built leaf by leaf: each side of
+// a leaf contributes its N-DOFs to the space of the side's master face, found
+// from the sizes of the neighbours across it. Spaces of different master
+// faces overlap on shared element edges and vertices. Order: DOFs ascending
+// within a space, duplicates removed, spaces lexicographically.
+std::vector<std::vector<int64_t>> face_spaces(const Mesh& M, const std::vector<int8_t>& lab) {
+  const int d = M.dim;
+  std::map<std::array<int64_t, 3>, std::vector<int64_t>> by_master;
+  for (int e = 0; e < M.ne; ++e) {
+    const int p = M.p[e], n = p + 1;
+    const int64_t nd = M.off[e + 1] - M.off[e];
+    for (int m = 0; m < d; ++m)
+      for (int s = 0; s < 2; ++s) {
+        // neighbours across side (m, s): faces of e with normal m on that side
+        int nb = -1;
+        bool any = false;
+        for (int q = M.ef_ptr[e]; q < M.ef_ptr[e + 1]; ++q) {
+          const Face& f = M.faces[M.ef_idx[q]];
+          if (f.m != m) continue;
+          const int side = f.ep < 0 ? f.side : (f.em == e ? 1 : 0);
+          if (side != s) continue;
+          any = true;
+          if (f.ep >= 0) nb = f.em == e ? f.ep : f.em;
+        }
+        if (!any) continue;
+        std::array<int64_t, 3> key;
+        if (nb < 0 || M.sz[nb] < M.sz[e]) key = {e, m, s};         // boundary, or e is the coarse leaf
+        else if (M.sz[nb] > M.sz[e]) key = {nb, m, 1 - s};         // the neighbour is the coarse leaf
+        else key = s == 1 ? std::array<int64_t, 3>{e, m, 1} : std::array<int64_t, 3>{nb, m, 1};
+        std::vector<int64_t>& mem = by_master[key];
+        for (int64_t r = 0; r < nd; ++r) {
+          int i[3];
+          multi_index(r, n, d, i);
+          if (i[m] != (s ? p : 0)) continue;
+          const int64_t g = M.off[e] + r;
+          if (lab[g] == 2) mem.push_back(g);
+        }
+      }
+  }
+  std::vector<std::vector<int64_t>> out;
+  for (auto& kv : by_master) {
+    std::vector<int64_t>& v = kv.second;
+    if (v.empty()) continue;
+    std::sort(v.begin(), v.end());
+    v.erase(std::unique(v.begin(), v.end()), v.end());
+    out.push_back(std::move(v));
+  }
+  std::sort(out.begin(), out.end());
+  out.erase(std::unique(out.begin(), out.end()), out.end());
+  return out;
 }
 
 // -------------------------------------------------------------------- LOR

@@ -85,14 +85,10 @@ def test_host_setup_matches_oracle(name, mk, form, eta, cap):
     op = G.Operator(G.Mesh(md), form=form, eta=eta, host_only=True, max_block=cap)
     dO = dg.diagonal(m, opts)
     assert np.abs(op.diag() - dO).max() <= 1e-13 * np.abs(dO).max()
-    inJ, inN = precond.labels(m)
-    if cap:
-        for b in precond.edge_spaces(m, inN):
-            if len(b) > cap:
-                inJ[b], inN[b] = True, False
-    lab = np.where(inJ, 1, np.where(inN, 2, 0)).astype(np.int8)
+    pc = precond.Preconditioner(m, opts, max_block=cap)
+    lab = np.where(pc.inJ, 1, np.where(pc.inN, 2, 0)).astype(np.int8)
     assert np.array_equal(op.labels(), lab)
-    bo = precond.edge_spaces(m, inN)
+    bo = pc.blocks
     bg = op.blocks()
     assert len(bo) == len(bg) and all(np.array_equal(a, b) for a, b in zip(bo, bg))
     # exact V_e solves: the stored inverses times the oracle's A[V_e, V_e]

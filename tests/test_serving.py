@@ -210,6 +210,51 @@ def test_batch_slots_and_statuses():
 
 
 @pytest.mark.gpu
+def test_admitted_operator_is_held_and_guarded():
+    """While a solve is in flight, apply_B and pcg_solve on its operator are
+    refused (they share its work vectors); the binding keeps the operator
+    and vectors alive until poll() returns the tag, even when the caller
+    drops its own references."""
+    import gc
+    import torch
+    md = H.random_mesh(2, 4, 0.3, 2, 1, 5, seed=93)
+    m = G.Mesh(md)
+    op = G.Operator(m)
+    f = torch.from_numpy(H.gaussian_rhs(m.ndof, 94)).cuda()
+    b = torch.empty_like(f)
+    op.rhs(f, b)
+    x = torch.zeros_like(f)
+    torch.cuda.synchronize()
+    bt = G.Batch(2)
+    assert bt.admit(op, b, x, maxit=500, tag=5)
+    with pytest.raises(ValueError):
+        bt.admit(op, b, x, tag=5)
+    r = torch.ones_like(f)
+    z = torch.empty_like(f)
+    with pytest.raises(G.HpdgError) as e:
+        op.apply_B(r, z)
+    assert e.value.code == -1 and "in flight" in str(e.value)
+    with pytest.raises(G.HpdgError) as e:
+        op.pcg_solve(b, torch.zeros_like(f))
+    assert e.value.code == -1
+    ref_b = b.clone()
+    del op, b, x
+    gc.collect()
+    assert 5 in bt._held
+    done = []
+    t0 = time.time()
+    while not done and time.time() - t0 < 30:
+        bt.step(wait_us=500)
+        done += bt.poll()
+    assert done and done[0][0] == 5 and done[0][1] == 0 and 5 not in bt._held
+    # a fresh blocking solve of the same system gives the same iteration count
+    op2 = G.Operator(m)
+    x2 = torch.zeros_like(f)
+    info = op2.pcg_solve(ref_b, x2, rtol=1e-8, maxit=500)
+    assert info[0]["iters"] == done[0][2]["iters"]
+
+
+@pytest.mark.gpu
 def test_served_results_match_oracle():
     import scipy.sparse.linalg as spla
 
