@@ -1,18 +1,22 @@
 """Benchmark: preconditioned CG solves of the hp-DG system on one MI355X.
 
-Workload (default --config 2): the 2D random hp mesh of 32x32 base quads,
-each refined with probability 0.3 up to 3 levels, degrees U{1..8}, SIPG with
-sigma = (p+1)^2/h, k = 1, right-hand side from seeded N(0,1) nodal values,
-155,228 DOFs. A step is one full solve from x0 = 0 to 1e-8 relative residual
-with the FP64 subspace-correction preconditioner B = B_J + B_E + P V(A~_C) P^T;
+Workload (default --config 3, the largest single-GPU configuration): the 3D
+random hp mesh of 16^3 base hexes, each refined with probability 0.2 up to 2
+levels, degrees U{1..6}, BR2 lifting, k piecewise constant per base cell,
+log-uniform in [1e-2, 1e2], right-hand side from seeded N(0,1) nodal values,
+2,569,985 DOFs; FP32 preconditioner under FP64 CG. A step is one full solve
+from x0 = 0 to 1e-8 relative residual with B = B_J + B_E + P V(A~_C) P^T;
 every iteration applies the matrix-free DG operator and B. Inputs are
 resident in GPU memory before the timed region; setup is reported apart.
+--config 2 runs the 2D random hp mesh (155,228 DOFs, SIPG, FP64), --config 4
+the 2D mesh with 64 right-hand sides, --config 5 the serving stream.
 
 Reported: solves/s (value), per-solve p50/p99 latency, the DG apply rate in
-GDOF/s, and the roofline of the dominant kernel (the 2D element kernel:
-volume and face terms in one launch) from HIP events on the stream the
-library launches on. cpu_baseline times the FP64 oracle on this host on a
-bounded sample (see its "sample" field).
+GDOF/s (hot, and cold from HBM for this workload and for the 64-RHS 2D
+workload), and the roofline of the dominant kernel (the element kernel:
+volume and face terms of the DG operator in one launch) from HIP events on
+the stream the library launches on. cpu_baseline times the FP64 oracle on
+this host on a bounded sample (see its "sample" field).
 """
 import argparse
 import json
@@ -41,7 +45,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--config", type=int, default=3)
     ap.add_argument("--apply-reps", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", type=int, default=-1,
@@ -150,10 +154,11 @@ def main():
     algo_bytes = 16.0 * n * nrhs          # x read once + y written once, FP64
     achieved = algo_bytes / t_apply / 1e9
     it = infos[0]["iters"]
-    kernel = ("k_elem2d (volume + all face terms, one launch)" if md["dim"] == 2 and nrhs == 1
-              else "apply_A (volume kernels + face kernel)")
+    kernel = ("k_elem2d (volume + all face terms, one launch)" if md["dim"] == 2
+              else "k_elem3d (volume + all face terms, one launch)")
 
     scaled = apply_scaled(cfg, c) if cfg == 2 else None
+    cold4 = apply_cold_cfg4() if cfg == 3 else None
     versus_fp64 = fp64_reference(args, cfg, c, mesh, b, x, infos, nrhs, dt) if c["prec_fp32"] else None
     cpu = None if args.no_cpu_baseline else cpu_baseline(cfg, c, it, n)
     traffic = None
@@ -181,6 +186,7 @@ def main():
                   "cond_est": infos[0]["cond_est"], "setup_s": t_setup},
         "apply": {"gdof_per_s": n * nrhs / t_apply / 1e9, "us_per_apply": t_apply * 1e6},
         "apply_cold": cold,
+        "apply_cold_64rhs_2d": cold4,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": kernel, "bytes_per_launch": algo_bytes,
@@ -214,6 +220,23 @@ def apply_cold(op, n, nrhs, total_bytes=768 << 20, passes=3):
     del xs, ys
     return {"buffers": k, "bytes_cycled": k * per, "us_per_apply": t * 1e6, "gdof_per_s": n * nrhs / t / 1e9,
             "achieved_GBs": gbs, "frac_hbm": gbs / HBM_PEAK_GBS}
+
+
+def apply_cold_cfg4(reps_passes=3):
+    """Cold DG apply of the 64-RHS 2D workload (the cfg2 mesh, 64 right-hand
+    sides interleaved), operator only, autotuned element-kernel tiles."""
+    import hpinputs as H
+    import paper_2009_01287_amd as G
+    c = H.CONFIGS[4]
+    md = H.config_mesh(4)
+    m = G.Mesh(md)
+    op = G.Operator(m, form=c["form"], penalty_rule=c["penalty_rule"], eta=c["eta"], no_prec=True,
+                    max_nrhs=c["nrhs"])
+    op.tune()
+    out = apply_cold(op, m.ndof, c["nrhs"], passes=reps_passes)
+    out["workload"] = WORKLOADS[4]
+    out["ndof_rhs"] = m.ndof * c["nrhs"]
+    return out
 
 
 def fp64_reference(args, cfg, c, mesh, b, x_mixed, infos_mixed, nrhs, dt_mixed, steps=2):
@@ -431,14 +454,16 @@ def cpu_baseline(cfg, c, gpu_iters, n_full, iters=30):
     import hpinputs as H
     import oracle as O
     from oracle import dg, pcg, precond
-    if cfg not in (1, 2):
+    if cfg not in (1, 2, 3):
         return None
     try:
         from threadpoolctl import threadpool_info
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:
         threads = 1
-    md = H.config_mesh(cfg, scale=4 if cfg == 2 else 1)
+    if cfg == 3:
+        iters = 30       # 3D: the recipe on 3^3 base hexes (16 // 5) instead of 16^3
+    md = H.config_mesh(cfg, scale={1: 1, 2: 4, 3: 5}[cfg])
     m = O.Mesh(md)
     opts = O.Opts(c["form"], c["penalty_rule"], c["eta"])
     pc = precond.Preconditioner(m, opts)
@@ -450,7 +475,7 @@ def cpu_baseline(cfg, c, gpu_iters, n_full, iters=30):
     t_full = per_dof_it * n_full * gpu_iters
     return {"value": 1.0 / t_full, "unit": "solves/s", "cores": threads, "kind": "oracle",
             "sample": (f"{info['iters']} oracle PCG iterations (matrix-free A and B applies) on the same "
-                       f"recipe at n_base/4 ({m.ndof} DOFs), {t:.1f} s, setup excluded; scaled by "
+                       f"recipe at n_base {md['n_base']} ({m.ndof} DOFs), {t:.1f} s, setup excluded; scaled by "
                        f"DOFs x iterations to {n_full} DOFs and {gpu_iters} iterations; "
                        f"host os.cpu_count()={os.cpu_count()}, BLAS threads {threads}")}
 

@@ -57,6 +57,74 @@ def test_apply_A_matches_oracle(name, form):
     assert _rel(_host(y), yo) <= 1e-12
 
 
+# penalty variants the studies run: the paper's rule sigma = eta k p_e^2 / h_e
+# (penalty_rule 1) at eta 10 and 1e4, and BR2 with an explicit eta
+PENALTIES = [("sipg", 1, 10.0), ("sipg", 1, 1e4), ("br2", 0, 3.0)]
+# 3D with degrees 6-8 (the 9-node class of the 3D element kernel) on a mesh
+# with nonconforming and mismatched-degree interior faces
+MESHES["rand3hp"] = lambda: H.random_mesh(3, 2, 0.5, 1, 6, 8, seed=31)
+
+
+@pytest.mark.parametrize("name", ["hang2", "rand2k", "rand3", "rand3hp"])
+@pytest.mark.parametrize("form,rule,eta", PENALTIES)
+def test_apply_A_penalty_variants(name, form, rule, eta):
+    md = MESHES[name]()
+    m = O.Mesh(md)
+    op = G.Operator(G.Mesh(md), form=form, penalty_rule=rule, eta=eta, no_prec=True)
+    x = np.random.default_rng(11).standard_normal(m.ndof)
+    y = torch.empty(m.ndof, dtype=torch.float64, device="cuda")
+    op.apply_A(_dev(x), y)
+    assert _rel(_host(y), dg.apply(m, O.Opts(form, rule, eta), x)) <= 1e-12
+
+
+def _block_bar(pc, eta):
+    """Bar for z = B r against the oracle: 1e-12, except at the extreme
+    penalty eta = 1e4, where the V_e blocks' 2-norm condition numbers reach
+    5e5 (3D) to 8e8 (2D with the k contrast): there the exact inverses formed
+    independently on the two sides differ at the 1e-12 level (3D SIPG:
+    1.09e-12 measured), so the bar is 1e-11."""
+    kmax = max((np.linalg.cond(Bi) for Bi in pc.binv), default=1.0)
+    if eta >= 1e4:
+        assert kmax > 1e5
+        return 1e-11, kmax
+    return 1e-12, kmax
+
+
+@pytest.mark.parametrize("name", ["rand2k", "rand3"])
+@pytest.mark.parametrize("form,rule,eta", PENALTIES)
+def test_apply_B_penalty_variants(name, form, rule, eta):
+    md = MESHES[name]()
+    m = O.Mesh(md)
+    op = G.Operator(G.Mesh(md), form=form, penalty_rule=rule, eta=eta)
+    pc = precond.Preconditioner(m, O.Opts(form, rule, eta))
+    r = np.random.default_rng(12).standard_normal(m.ndof)
+    z = torch.empty(m.ndof, dtype=torch.float64, device="cuda")
+    op.apply_B(_dev(r), z)
+    bar, kmax = _block_bar(pc, eta)
+    assert _rel(_host(z), pc.apply(r)) <= bar, (bar, kmax)
+
+
+@pytest.mark.parametrize("form", ["sipg", "br2"])
+def test_high_degree_3d_apply_A_and_B(form):
+    """Degrees 6-8 in 3D with hanging faces: every face path of the 3D
+    element kernel's 9-node class (interior, mismatched degree, sub-faces,
+    BR2 liftings) and B's face spaces at the largest sizes."""
+    md = MESHES["rand3hp"]()
+    m = O.Mesh(md)
+    assert m.p.max() == 8 and any(f["ep"] >= 0 and m.size[f["em"]] != m.size[f["ep"]] for f in m.faces)
+    eta = 1.0 if form == "sipg" else 0.0
+    op = G.Operator(G.Mesh(md), form=form, eta=eta)
+    rng = np.random.default_rng(13)
+    x = rng.standard_normal(m.ndof)
+    y = torch.empty(m.ndof, dtype=torch.float64, device="cuda")
+    op.apply_A(_dev(x), y)
+    assert _rel(_host(y), dg.apply(m, O.Opts(form, 0, eta), x)) <= 1e-12
+    pc = precond.Preconditioner(m, O.Opts(form, 0, eta))
+    z = torch.empty_like(y)
+    op.apply_B(_dev(x), z)
+    assert _rel(_host(z), pc.apply(x)) <= 1e-12
+
+
 @pytest.mark.parametrize("name", ["hang2", "hang3"])
 def test_rhs_matches_oracle(name):
     md = MESHES[name]()
@@ -174,6 +242,37 @@ def test_fp32_preconditioner_solve():
     op32.apply_B(_dev(r), z32)
     op64.apply_B(_dev(r), z64)
     assert _rel(_host(z32), _host(z64)) <= 1e-5
+
+
+@pytest.mark.parametrize("name,form", [("rand2", "sipg"), ("rand3", "br2")])
+def test_mixed_precision_error_against_oracle_solution(name, form):
+    """FP32 preconditioner under FP64 CG (the mixed-precision policy): the
+    solution's error against the oracle's sparse direct solve x* = A^-1 b.
+    The bound is the standard perturbation bound ||x - x*|| / ||x*|| <=
+    kappa_2(A) ||b - A x|| / ||b||, with kappa_2(A) from the extreme
+    eigenvalues of the oracle's matrix (Lanczos, shift-invert at 0) and the residual of x taken with the oracle's A; the stop is
+    rtol = 1e-8 on the recurrence residual."""
+    import scipy.sparse.linalg as spla
+    md = MESHES[name]()
+    m = O.Mesh(md)
+    eta = 1.0 if form == "sipg" else 0.0
+    opts = O.Opts(form, 0, eta)
+    A = dg.assemble_sparse(m, opts)
+    b = dg.rhs(m, H.gaussian_rhs(m.ndof, 17))
+    xs = spla.spsolve(A.tocsc(), b)
+    lmax = spla.eigsh(A, k=1, which="LA", return_eigenvectors=False)[0]
+    lmin = spla.eigsh(A.tocsc(), k=1, sigma=0.0, which="LM", return_eigenvectors=False)[0]
+    kappa = lmax / lmin
+    op = G.Operator(G.Mesh(md), form=form, eta=eta, prec_fp32=True)
+    x = torch.zeros(m.ndof, dtype=torch.float64, device="cuda")
+    info = op.pcg_solve(_dev(b), x, rtol=1e-8, maxit=3000)[0]
+    xh = _host(x)
+    res = np.linalg.norm(b - A @ xh) / np.linalg.norm(b)
+    err = _rel(xh, xs)
+    assert info["converged"] and info["true_rel_res"] <= 1e-8 and res <= 1.01e-8
+    assert err <= kappa * res, (err, kappa, res)
+    print(f"{name} {form}: ndof {m.ndof}, iters {info['iters']}, ||x-x*||/||x*|| = {err:.2e}, "
+          f"kappa(A) = {kappa:.2e}, residual {res:.2e}")
 
 
 def test_multi_rhs_equals_single():
