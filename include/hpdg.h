@@ -118,6 +118,28 @@ hpdg_status hpdg_apply_A(hpdg_operator* op, const double* x, double* y, int nrhs
  * ndof*nrhs, must not alias. */
 hpdg_status hpdg_apply_B(hpdg_operator* op, const double* r, double* z, int nrhs, void* stream);
 
+/* z = B r like hpdg_apply_B, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the call allocates nothing. B's work vectors (the
+ * preconditioner-precision copies of r and z and the V-cycle vectors of every
+ * AMG level) are carved out of a static 64 MiB device array, one per GPU, that
+ * the library holds until the process ends; the operator's own matrices are
+ * only read. Same kernels, same results as hpdg_apply_B.
+ *  - Limit: the work vectors take (ndof [+ ndof in FP32 mode] + 4 x the rows of
+ *    every AMG level) x nrhs values of the preconditioner's precision, each
+ *    vector rounded up to 256 bytes; more than 64 MiB returns HPDG_E_INVALID
+ *    before any device work (use hpdg_apply_B then).
+ *  - The array is shared by every call on a GPU and keeps the last call's
+ *    contents; no part of it needs to start at zero (each call writes every
+ *    word it reads first). Calls that overlap in time on one GPU (other
+ *    streams or host threads) race on it: the caller orders them.
+ *  - Runs on the current device (the one the operator was set up on); the
+ *    first call on a device looks up the array's address there.
+ *  - Unlike hpdg_apply_B it may run while the operator has a solve in flight,
+ *    since it does not touch the operator's work vectors.
+ * r, z: device, ndof*nrhs, must not alias. */
+hpdg_status hpdg_apply_B_noalloc(hpdg_operator* op, const double* r, double* z, int nrhs, void* stream);
+
 typedef struct {
   int iters, converged;
   double rel_res;       /* recurrence residual ||r_k|| / ||b|| */

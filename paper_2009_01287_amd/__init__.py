@@ -48,7 +48,7 @@ class SolveInfo(C.Structure):
 
 SYMBOLS = ["hpdg_last_error", "hpdg_setup_mesh", "hpdg_mesh_info", "hpdg_mesh_destroy",
            "hpdg_setup_operator", "hpdg_operator_destroy", "hpdg_rhs", "hpdg_apply_A",
-           "hpdg_apply_B", "hpdg_pcg_solve", "hpdg_export", "hpdg_operator_upload",
+           "hpdg_apply_B", "hpdg_apply_B_noalloc", "hpdg_pcg_solve", "hpdg_export", "hpdg_operator_upload",
            "hpdg_operator_device_bytes", "hpdg_batch_create", "hpdg_batch_destroy", "hpdg_batch_admit",
            "hpdg_batch_step", "hpdg_batch_poll", "hpdg_operator_tune"]
 
@@ -77,7 +77,7 @@ def lib():
     L.hpdg_setup_operator.argtypes = [vp, C.POINTER(Opts), vp, C.POINTER(vp)]
     L.hpdg_operator_destroy.argtypes = [vp]
     L.hpdg_operator_destroy.restype = None
-    for f in ("hpdg_rhs", "hpdg_apply_A", "hpdg_apply_B"):
+    for f in ("hpdg_rhs", "hpdg_apply_A", "hpdg_apply_B", "hpdg_apply_B_noalloc"):
         getattr(L, f).argtypes = [vp, vp, vp, C.c_int, vp]
     L.hpdg_pcg_solve.argtypes = [vp, vp, vp, C.c_int, C.c_double, C.c_int, vp, C.POINTER(SolveInfo)]
     L.hpdg_export.argtypes = [vp, C.c_int, vp, C.POINTER(C.c_size_t)]
@@ -176,6 +176,11 @@ class Operator:
 
     def apply_B(self, r, z, nrhs=1, stream=None):
         self._vec("hpdg_apply_B", r, z, nrhs, stream)
+
+    def apply_B_noalloc(self, r, z, nrhs=1, stream=None):
+        """hpdg_apply_B_noalloc: z = B r with the work vectors in the library's
+        static scratch array (no device allocation)."""
+        self._vec("hpdg_apply_B_noalloc", r, z, nrhs, stream)
 
     def pcg_solve(self, b, x, nrhs=1, rtol=1e-8, maxit=1000, stream=None, raise_on_error=True):
         info = (SolveInfo * nrhs)()

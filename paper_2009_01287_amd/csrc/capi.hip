@@ -181,9 +181,9 @@ struct LevelDev {
 
 // Work vectors of one application of B in the preconditioner's precision:
 // the copies of r and z, and per AMG level the right-hand side b, the
-// iterate x, the residual r and the temporary t of the V-cycle (passed as
-// a descriptor, so that the same code can run on other work buffers than
-// the operator's).
+// iterate x, the residual r and the temporary t of the V-cycle. They come
+// from the operator's buffers, or from the static scratch array of
+// hpdg_apply_B_noalloc.
 constexpr int kMaxLevels = 16;
 struct BWork {
   void* rT = nullptr;
@@ -1761,6 +1761,80 @@ extern "C" hpdg_status hpdg_apply_B(hpdg_operator* op, const double* r, double* 
     return fail(HPDG_E_INVALID, "operator has a solve in flight (its work vectors are in use)");
   hipStream_t s = (hipStream_t)stream;
   const BWork W = op_work(op);
+  if (op->prec32) apply_B_dev<float>(op, W, r, z, nrhs, s);
+  else apply_B_dev<double>(op, W, r, z, nrhs, s);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(HPDG_E_HIP, hipGetErrorString(e));
+  return HPDG_OK;
+}
+
+// ------------------------------------------- B without device allocation
+// The work vectors of hpdg_apply_B_noalloc live in this array: one copy per
+// GPU, held until the process ends. Host code never passes the array's name
+// to a kernel or a copy; it uses the device address that hipGetSymbolAddress
+// returns for the current device (kept per device after the first call).
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+static void* g_scratch_ptr[kMaxDevices];
+static std::mutex g_scratch_mu;
+
+static hpdg_status scratch_address(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(HPDG_E_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return fail(HPDG_E_UNSUPPORTED, "device index beyond 63");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(HPDG_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return HPDG_OK;
+}
+
+// carves the work vectors of B for nrhs right-hand sides out of the scratch
+// array at base (256-byte aligned pieces); returns the bytes needed
+static size_t scratch_work(const hpdg_operator* op, int nrhs, char* base, BWork& W) {
+  const size_t es = op->prec32 ? sizeof(float) : sizeof(double);
+  size_t at = 0;
+  auto take = [&](int64_t elems) -> void* {
+    void* p = base ? base + at : nullptr;
+    at += ((size_t)elems * es + 255) / 256 * 256;
+    return p;
+  };
+  const int64_t nv = op->ndof * nrhs;
+  W.rT = op->prec32 ? take(nv) : nullptr;   // FP64 B reads r itself
+  W.zT = take(zt_rows(op) * nrhs);
+  for (size_t l = 0; l < op->lv.size(); ++l) {
+    const int64_t nl = (int64_t)op->lv[l].A.nrows * nrhs;
+    W.b[l] = take(nl);
+    W.x[l] = take(nl);
+    W.r[l] = take(nl);
+    W.t[l] = take(nl);
+  }
+  return at;
+}
+
+extern "C" hpdg_status hpdg_apply_B_noalloc(hpdg_operator* op, const double* r, double* z, int nrhs,
+                                            void* stream) {
+  hpdg_status st = check_vec_args(op, r, z, nrhs);
+  if (st != HPDG_OK) return st;
+  if (op->no_prec) return fail(HPDG_E_UNSUPPORTED, "operator was built with no_prec");
+  BWork W;
+  const size_t need = scratch_work(op, nrhs, nullptr, W);
+  if (need > kScratchBytes)
+    return fail(HPDG_E_INVALID, "hpdg_apply_B_noalloc: the work vectors need " + std::to_string(need) +
+                                    " bytes, more than the " + std::to_string(kScratchBytes) +
+                                    "-byte scratch array (use hpdg_apply_B)");
+  void* base = nullptr;
+  st = scratch_address(&base);
+  if (st != HPDG_OK) return st;
+  scratch_work(op, nrhs, (char*)base, W);
+  hipStream_t s = (hipStream_t)stream;
   if (op->prec32) apply_B_dev<float>(op, W, r, z, nrhs, s);
   else apply_B_dev<double>(op, W, r, z, nrhs, s);
   hipError_t e = hipGetLastError();
