@@ -145,7 +145,9 @@ typedef struct {
   double rel_res;       /* recurrence residual ||r_k|| / ||b|| */
   double true_rel_res;  /* ||b - A x|| / ||b|| recomputed in FP64 at the end */
   double lambda_min, lambda_max, cond_est;  /* Lanczos from the CG coefficients */
-  double t_solve_s;
+  double t_solve_s;     /* host wall time of the solve */
+  double t_setup_s;     /* host wall time of the operator's setup (hpdg_setup_operator, plus
+                           hpdg_operator_upload for a host_only operator) */
 } hpdg_solve_info;
 
 /* PCG (Sec. 4.1) on T = BA, stopping at ||r_k||_2 <= rtol ||b||_2 (per RHS).
@@ -235,6 +237,10 @@ hpdg_status hpdg_batch_poll(hpdg_batch* bt, int cap, int64_t* tags, int* status,
  *    bytes held by the operator
  *  8 inverses of the V_e blocks in FP64, row-major, concatenated in the
  *    order of item 4
+ *  9 CG coefficients of the operator's last finished hpdg_pcg_solve, double:
+ *    rows, stride (= max_nrhs), alpha[rows*stride], beta[rows*stride]
+ *    (iteration-major, RHS c at offset c; beta of the last row unused);
+ *    HPDG_E_INVALID before any finished solve
  *  100+l  AMG level-l matrix A_l as CSR;  200+l  AMG prolongator P_l as CSR;
  *  300+l  aggregate index of every row of level l, int64
  * bytes: in: capacity of buf; out: bytes needed. buf NULL queries the size. */

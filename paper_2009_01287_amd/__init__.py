@@ -40,7 +40,7 @@ class Opts(C.Structure):
 class SolveInfo(C.Structure):
     _fields_ = [("iters", C.c_int), ("converged", C.c_int), ("rel_res", C.c_double),
                 ("true_rel_res", C.c_double), ("lambda_min", C.c_double), ("lambda_max", C.c_double),
-                ("cond_est", C.c_double), ("t_solve_s", C.c_double)]
+                ("cond_est", C.c_double), ("t_solve_s", C.c_double), ("t_setup_s", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -264,6 +264,15 @@ class Operator:
             out.append(v[o:o + k * k].reshape(k, k).copy())
             o += k * k
         return out
+
+    def cg_coefficients(self):
+        """alpha_k, beta_k of the last finished pcg_solve: two arrays of
+        shape (rows, max_nrhs)."""
+        v = self.export(9).view(np.float64)
+        rows, hs = int(v[0]), int(v[1])
+        a = v[2:2 + rows * hs].reshape(rows, hs).copy()
+        b = v[2 + rows * hs:2 + 2 * rows * hs].reshape(rows, hs).copy()
+        return a, b
 
     def node_coords(self):
         return self.export(5).view(np.float64).reshape(-1, self.mesh.dim)

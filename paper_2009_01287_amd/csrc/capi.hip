@@ -200,7 +200,6 @@ constexpr int64_t kPreSplitNnz = 4 << 20;   // pre-smoother in two launches abov
 
 struct hpdg_operator {
   int dim = 2, ne = 0, max_nrhs = 1, form = 0, prec32 = 0, host_only = 0;
-  int generic_faces = 0;   // HPDG_GENERIC_FACES=1: use the one-block-per-element face kernel
   int64_t ndof = 0, nconf = 0;
   hpdg_operator_opts opts{};
   // element data
@@ -229,8 +228,10 @@ struct hpdg_operator {
   // CG work (double)
   DevBuf r, z, pv, Ap, part, scal, iscal, ahist, bhist;
   int64_t hist_cap = 0;      // Lanczos coefficients kept per RHS
+  int64_t hist_rows = 0;     // rows of them copied to hist_pin by the last solve
   int64_t ftab_bytes = 0;
   int64_t dev_bytes = 0;     // device memory held by this operator once uploaded
+  double t_setup = 0.0;      // host wall time of setup (and upload)
   int uploaded = 0;
   int no_prec = 0;           // operator only: apply_B and PCG unsupported
   int use_graph = 0;         // PCG chunks replayed from captured HIP graphs
@@ -331,33 +332,8 @@ static uint8_t sub_code(int64_t a, int64_t b, int64_t lo, int64_t sz) {
 
 static void build_tables(hpdg_operator* op, int max_delta) {
   TableLayout& L = op->TL;
-  L.ncode = 1 << (max_delta + 1);
-  if (L.ncode > 256) throw Error(HPDG_E_UNSUPPORTED, "level jump across a face larger than 7");
+  if (max_delta > 7) throw Error(HPDG_E_UNSUPPORTED, "level jump across a face larger than 7");
   std::vector<double> T;
-  L.interp = 0;
-  T.assign((size_t)8 * 8 * L.ncode * 81, 0.0);
-  for (int p = 1; p <= kMaxP; ++p) {
-    const Basis1D& B = basis(p);
-    for (int q = 2; q <= 9; ++q) {
-      std::vector<double> gx, gw;
-      gauss_rule(q, gx, gw);
-      for (int code = 1; code < L.ncode; ++code) {
-        int delta = 0;
-        while ((2 << delta) <= code) ++delta;
-        int idx = code - (1 << delta);
-        double len = 1.0 / (double)(1 << delta), a = idx * len;
-        double* dst = &T[interp_index(L, p, q, code)];
-        for (int g = 0; g < q; ++g) lagrange_eval(B.x, a + len * gx[g], dst + g * (p + 1));
-      }
-    }
-  }
-  L.gw = (int64_t)T.size();
-  T.resize(T.size() + 100, 0.0);
-  for (int q = 2; q <= 9; ++q) {
-    std::vector<double> gx, gw;
-    gauss_rule(q, gx, gw);
-    for (int g = 0; g < q; ++g) T[L.gw + q * 10 + g] = gw[g];
-  }
   L.dside = (int64_t)T.size();
   T.resize(T.size() + 9 * 2 * 9, 0.0);
   for (int p = 1; p <= kMaxP; ++p)
@@ -749,7 +725,9 @@ extern "C" hpdg_status hpdg_operator_upload(hpdg_operator* op, void* stream) {
   if (!op) return fail(HPDG_E_INVALID, "null operator");
   if (op->uploaded) return HPDG_OK;
   try {
+    const auto t0 = std::chrono::steady_clock::now();
     upload_device(op, (hipStream_t)stream);
+    op->t_setup += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return HPDG_OK;
   } catch (Error& e) {
     return fail(e.code, e.what());
@@ -777,6 +755,7 @@ extern "C" hpdg_status hpdg_setup_operator(const hpdg_mesh* mh, const hpdg_opera
   if (o->max_nrhs < 1 || o->max_nrhs > 256 || (256 % o->max_nrhs) != 0)
     return fail(HPDG_E_INVALID, "max_nrhs must divide 256");
   if (o->penalty_rule != 0 && o->penalty_rule != 1) return fail(HPDG_E_INVALID, "penalty_rule must be 0 or 1");
+  const auto t_setup0 = std::chrono::steady_clock::now();
   auto op = std::make_unique<hpdg_operator>();
   {
     int nt = o->setup_threads;
@@ -916,7 +895,6 @@ extern "C" hpdg_status hpdg_setup_operator(const hpdg_mesh* mh, const hpdg_opera
       sptr.push_back((int32_t)recs.size());
     }
     op->host_only = o->host_only ? 1 : 0;
-    op->generic_faces = std::getenv("HPDG_GENERIC_FACES") != nullptr;
     op->bucket.assign(kMaxP + 1, {});
     for (int e = 0; e < M.ne; ++e) op->bucket[M.p[e]].push_back(e);
     if (ftab.size() > (size_t)INT32_MAX) throw Error(HPDG_E_UNSUPPORTED, "face table too large");
@@ -1039,6 +1017,7 @@ extern "C" hpdg_status hpdg_setup_operator(const hpdg_mesh* mh, const hpdg_opera
       }
     }
     if (!op->host_only) upload_device(op.get(), (hipStream_t)stream);
+    op->t_setup = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_setup0).count();
     *out = op.release();
     return HPDG_OK;
   } catch (Error& e) {
@@ -1051,27 +1030,28 @@ extern "C" hpdg_status hpdg_setup_operator(const hpdg_mesh* mh, const hpdg_opera
 extern "C" void hpdg_operator_destroy(hpdg_operator* op) { delete op; }
 
 // ------------------------------------------------------------- launchers
-template <int DIM, int P, int MODE>
-static void launch_vol_p(hpdg_operator* op, int nrhs, const double* x, double* y, hipStream_t s) {
+template <int DIM, int P>
+static void launch_mass_p(hpdg_operator* op, int nrhs, const double* x, double* y, hipStream_t s) {
   using S = VolShape<DIM, P>;
   int nel = (int)op->bucket[P].size();
   if (nel == 0) return;
   int nitems = nel * nrhs;
   unsigned grid = (unsigned)((nitems + S::E - 1) / S::E);
-  hipLaunchKernelGGL((k_vol<DIM, P, MODE>), dim3(grid), dim3(S::BS), 0, s, op->dbucket[P].as<int32_t>(), nitems,
-                     nrhs, op->off.as<int64_t>(), op->hh.as<double>(), op->kk.as<double>(), x, y);
+  hipLaunchKernelGGL((k_mass<DIM, P>), dim3(grid), dim3(S::BS), 0, s, op->dbucket[P].as<int32_t>(), nitems, nrhs,
+                     op->off.as<int64_t>(), op->hh.as<double>(), x, y);
 }
 
-template <int DIM, int MODE>
-static void launch_vol(hpdg_operator* op, int nrhs, const double* x, double* y, hipStream_t s) {
-  launch_vol_p<DIM, 1, MODE>(op, nrhs, x, y, s);
-  launch_vol_p<DIM, 2, MODE>(op, nrhs, x, y, s);
-  launch_vol_p<DIM, 3, MODE>(op, nrhs, x, y, s);
-  launch_vol_p<DIM, 4, MODE>(op, nrhs, x, y, s);
-  launch_vol_p<DIM, 5, MODE>(op, nrhs, x, y, s);
-  launch_vol_p<DIM, 6, MODE>(op, nrhs, x, y, s);
-  launch_vol_p<DIM, 7, MODE>(op, nrhs, x, y, s);
-  launch_vol_p<DIM, 8, MODE>(op, nrhs, x, y, s);
+// y = M x (element mass matrices), one launch per degree present
+template <int DIM>
+static void launch_mass(hpdg_operator* op, int nrhs, const double* x, double* y, hipStream_t s) {
+  launch_mass_p<DIM, 1>(op, nrhs, x, y, s);
+  launch_mass_p<DIM, 2>(op, nrhs, x, y, s);
+  launch_mass_p<DIM, 3>(op, nrhs, x, y, s);
+  launch_mass_p<DIM, 4>(op, nrhs, x, y, s);
+  launch_mass_p<DIM, 5>(op, nrhs, x, y, s);
+  launch_mass_p<DIM, 6>(op, nrhs, x, y, s);
+  launch_mass_p<DIM, 7>(op, nrhs, x, y, s);
+  launch_mass_p<DIM, 8>(op, nrhs, x, y, s);
 }
 
 // y = A x. With pdot (one RHS) the kernel that supports it also writes
@@ -1081,7 +1061,7 @@ static int apply_A_dev(hpdg_operator* op, const double* x, double* y, int nrhs, 
                        double* pdot = nullptr) {
   if (nrhs != 1) pdot = nullptr;
   const int64_t items = (int64_t)op->ne * nrhs;   // (element, RHS) pairs
-  if (op->dim == 2 && !op->generic_faces) {
+  if (op->dim == 2) {
     const int rg = std::max(1, std::min(nrhs, op->rhs_group));
     const int64_t items2 = (int64_t)op->ne * ((nrhs + rg - 1) / rg);   // (element, RHS group) pairs
     auto launch = [&](auto epb_c, auto fc_c) {
@@ -1106,7 +1086,7 @@ static int apply_A_dev(hpdg_operator* op, const double* x, double* y, int nrhs, 
     if (op->epb == 2) with_fc(I2());
     else with_fc(I1());
     return pdot ? op->ne : 0;
-  } else if (op->dim == 3 && !op->generic_faces) {
+  } else {
     const unsigned grid = 8u * (unsigned)((items + 7) / 8);   // k_elem3d needs a multiple of 8
     auto kern = op->nm3 == 7 ? k_elem3d<7> : k_elem3d<9>;
     hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, s, op->ne, nrhs, op->form, op->off.as<int64_t>(),
@@ -1114,16 +1094,6 @@ static int apply_A_dev(hpdg_operator* op, const double* x, double* y, int nrhs, 
                        op->recs.as<FaceRec>(), op->ftab.as<double>(), op->tab.as<double>(), op->TL, x, y, pdot,
                        op->use_perm ? op->elem_perm.as<int32_t>() : nullptr);
     return pdot ? op->ne : 0;
-  } else if (op->dim == 2) {
-    launch_vol<2, 0>(op, nrhs, x, y, s);
-    hipLaunchKernelGGL(k_faces<2>, dim3(op->ne * nrhs), dim3(64), 0, s, op->ne * nrhs, nrhs, op->form,
-                       op->off.as<int64_t>(), op->pdeg.as<int8_t>(), op->hh.as<double>(), op->kk.as<double>(),
-                       op->sptr.as<int32_t>(), op->recs.as<FaceRec>(), op->tab.as<double>(), op->TL, x, y);
-  } else {
-    launch_vol<3, 0>(op, nrhs, x, y, s);
-    hipLaunchKernelGGL(k_faces<3>, dim3(op->ne * nrhs), dim3(64), 0, s, op->ne * nrhs, nrhs, op->form,
-                       op->off.as<int64_t>(), op->pdeg.as<int8_t>(), op->hh.as<double>(), op->kk.as<double>(),
-                       op->sptr.as<int32_t>(), op->recs.as<FaceRec>(), op->tab.as<double>(), op->TL, x, y);
   }
   return 0;
 }
@@ -1480,11 +1450,11 @@ static int tune_all(hpdg_operator* op, hipStream_t s, int64_t* report, int cap) 
     r[1] = level;
     return r + 2;
   };
-  if (op->dim == 2 && !op->generic_faces) {
+  if (op->dim == 2) {
     tune_elem(op, s, slot(4, 0));
     if (op->max_nrhs > 1) tune_rhs_group(op, s, slot(6, 0));
   }
-  if (op->dim == 3 && !op->generic_faces) tune_elem_order(op, s, slot(10, 0));
+  if (op->dim == 3) tune_elem_order(op, s, slot(10, 0));
   HIPCHK(hipMemsetAsync(op->rT.p, 0, op->rT.bytes, s));
   for (auto& L : op->lv) {
     HIPCHK(hipMemsetAsync(L.b.p, 0, L.b.bytes, s));
@@ -1621,7 +1591,7 @@ extern "C" hpdg_status hpdg_operator_tune(hpdg_operator* op, void* stream, int64
       int64_t* r = cap > 0 ? report : dummy;
       r[0] = 4;
       r[1] = 0;
-      if (op->dim == 2 && !op->generic_faces) {
+      if (op->dim == 2) {
         tune_elem(op, s, r + 2);
         k = 1;
       }
@@ -1846,8 +1816,8 @@ extern "C" hpdg_status hpdg_rhs(hpdg_operator* op, const double* f, double* b, i
   hpdg_status st = check_vec_args(op, f, b, nrhs);
   if (st != HPDG_OK) return st;
   hipStream_t s = (hipStream_t)stream;
-  if (op->dim == 2) launch_vol<2, 1>(op, nrhs, f, b, s);
-  else launch_vol<3, 1>(op, nrhs, f, b, s);
+  if (op->dim == 2) launch_mass<2>(op, nrhs, f, b, s);
+  else launch_mass<3>(op, nrhs, f, b, s);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(HPDG_E_HIP, hipGetErrorString(e));
   return HPDG_OK;
@@ -2085,6 +2055,7 @@ static void pcg_finish_enqueue(hpdg_operator* op) {
   HIPCHK(hipMemcpyAsync(P->trr, S.rr, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
   const int64_t hs = op->max_nrhs;
   const int64_t rows = std::min<int64_t>(R.enq, op->hist_cap);
+  op->hist_rows = rows;
   if (rows > 0) {
     HIPCHK(hipMemcpyAsync(op->hist_pin, S.ahist, (size_t)(rows * hs) * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(op->hist_pin + op->hist_cap * hs, S.bhist, (size_t)(rows * hs) * sizeof(double),
@@ -2123,6 +2094,7 @@ static void pcg_collect(hpdg_operator* op) {
     tridiag_extremes(da, db, In.lambda_min, In.lambda_max);
     In.cond_est = In.lambda_max / In.lambda_min;
     In.t_solve_s = secs;
+    In.t_setup_s = op->t_setup;
   }
   if (breakdown) { R.code = HPDG_E_NOT_SPD; R.msg = "CG breakdown: p'Ap <= 0 or r'z <= 0"; }
   else if (!all_conv) { R.code = HPDG_E_NOT_CONVERGED; R.msg = "maximum number of iterations reached"; }
@@ -2364,6 +2336,18 @@ extern "C" hpdg_status hpdg_export(const hpdg_operator* op, int what, void* buf,
       return put(v.data(), v.size(), buf, bytes);
     }
     case 8: return put(op->up.binv.data(), op->up.binv.size(), buf, bytes);
+    case 9: {
+      // CG coefficients of the last finished solve: rows, stride (max_nrhs),
+      // then alpha[rows * stride] and beta[rows * stride]
+      if (op->run.phase != 3 || !op->hist_pin) return fail(HPDG_E_INVALID, "no finished solve");
+      const int64_t hs = op->max_nrhs, rows = op->hist_rows;
+      std::vector<double> v(2 + 2 * rows * hs);
+      v[0] = (double)rows;
+      v[1] = (double)hs;
+      std::copy(op->hist_pin, op->hist_pin + rows * hs, v.begin() + 2);
+      std::copy(op->hist_pin + op->hist_cap * hs, op->hist_pin + op->hist_cap * hs + rows * hs, v.begin() + 2 + rows * hs);
+      return put(v.data(), v.size(), buf, bytes);
+    }
     default:
       if (what >= 100 && what < 100 + (int)H.amg.lv.size()) {
         auto v = pack_csr(H.amg.lv[what - 100].A);

@@ -6,10 +6,7 @@
 //                  one workgroup, faces through exact 1D face-mass matrices
 //                  (conforming, mismatched-degree and nonconforming sub-faces
 //                  alike); one item per (element, right-hand side).
-//   k_vol<DIM,P>   volume term by degree bucket (mode 0) and the element mass
-//                  matrices for the load vector (mode 1).
-//   k_faces<DIM>   generic face kernel (quadrature at the face points), kept
-//                  as an alternative path for checks.
+//   k_mass<DIM,P>  element mass matrices by degree bucket (the load vector).
 //   k_front        B's point Jacobi, V_e block solves and P^T in one launch.
 //   k_spmv, k_spmm CSR products for P, P^T and the AMG levels, with fused
 //                  smoother / residual / prolongation-add forms and the
@@ -38,17 +35,16 @@ struct VolShape {
   static constexpr int BS = ((E * nn + 63) / 64) * 64;
 };
 
-// mode 0: y = volume(x) (overwrites); mode 1: y = mass(x) (overwrites)
-template <int DIM, int P, int MODE>
-__global__ __launch_bounds__((VolShape<DIM, P>::BS)) void k_vol(
+// y = M x with the exact element mass matrix h^d (M^ x ... x M^), one degree
+// per launch (overwrites y)
+template <int DIM, int P>
+__global__ __launch_bounds__((VolShape<DIM, P>::BS)) void k_mass(
     const int32_t* __restrict__ elems, int nitems, int nrhs, const int64_t* __restrict__ off,
-    const double* __restrict__ hh, const double* __restrict__ kk, const double* __restrict__ x,
-    double* __restrict__ y) {
+    const double* __restrict__ hh, const double* __restrict__ x, double* __restrict__ y) {
   using S = VolShape<DIM, P>;
   constexpr int n = S::n, nn = S::nn, E = S::E;
   __shared__ double sX[E * nn];
   __shared__ double sA[E * nn];
-  __shared__ double sB[E * nn];
   const int slot = threadIdx.x / nn;
   const int r = threadIdx.x - slot * nn;
   const int item = blockIdx.x * E + slot;
@@ -61,313 +57,44 @@ __global__ __launch_bounds__((VolShape<DIM, P>::BS)) void k_vol(
     base = off[e];
   }
   const double* Mt = c_MK[P][0];
-  const double* Kt = c_MK[P][1];
   const int i0 = r % n;
   const int i1 = (r / n) % n;
   const int i2 = DIM == 3 ? r / (n * n) : 0;
   if (slot < E) sX[slot * nn + r] = active ? x[(base + r) * nrhs + rr] : 0.0;
   __syncthreads();
+  // along dim 0
+  if (slot < E) {
+    const double* row = &sX[slot * nn + (i2 * n + i1) * n];
+    double a0 = 0.0;
+#pragma unroll
+    for (int a = 0; a < n; ++a) a0 += row[a] * Mt[a * n + i0];
+    sA[slot * nn + r] = a0;
+  }
+  __syncthreads();
   double out = 0.0;
   if constexpr (DIM == 2) {
-    // T1 = X contracted with K along dim 0, T2 = with M (MODE 1: M only)
-    double t1 = 0.0, t2 = 0.0;
     if (slot < E) {
-      const double* row = &sX[slot * nn + i1 * n];
 #pragma unroll
-      for (int a = 0; a < n; ++a) {
-        double xa = row[a];
-        t1 += xa * Kt[a * n + i0];
-        t2 += xa * Mt[a * n + i0];
-      }
-      sA[slot * nn + r] = t1;
-      sB[slot * nn + r] = t2;
-    }
-    __syncthreads();
-    if (slot < E) {
-      double acc = 0.0;
-#pragma unroll
-      for (int b = 0; b < n; ++b) {
-        if (MODE == 0)
-          acc += Mt[i1 * n + b] * sA[slot * nn + b * n + i0] + Kt[i1 * n + b] * sB[slot * nn + b * n + i0];
-        else
-          acc += Mt[i1 * n + b] * sB[slot * nn + b * n + i0];
-      }
-      out = acc;
+      for (int b = 0; b < n; ++b) out += Mt[i1 * n + b] * sA[slot * nn + b * n + i0];
     }
   } else {
-    __shared__ double sC[E * nn];
-    __shared__ double sD[E * nn];
-    // phase 1: along dim 0
+    // along dim 1 (into sX, no longer needed), then dim 2
     if (slot < E) {
-      const double* row = &sX[slot * nn + (i2 * n + i1) * n];
-      double a0 = 0.0, b0 = 0.0;
+      double aa = 0.0;
 #pragma unroll
-      for (int a = 0; a < n; ++a) {
-        double xa = row[a];
-        a0 += xa * Mt[a * n + i0];
-        b0 += xa * Kt[a * n + i0];
-      }
-      sA[slot * nn + r] = a0;
-      sB[slot * nn + r] = b0;
+      for (int b = 0; b < n; ++b) aa += sA[slot * nn + (i2 * n + b) * n + i0] * Mt[b * n + i1];
+      sX[slot * nn + r] = aa;
     }
     __syncthreads();
-    // phase 2: along dim 1
     if (slot < E) {
-      double aa = 0.0, ab = 0.0, ba = 0.0;
 #pragma unroll
-      for (int b = 0; b < n; ++b) {
-        double av = sA[slot * nn + (i2 * n + b) * n + i0];
-        double bv = sB[slot * nn + (i2 * n + b) * n + i0];
-        double mb = Mt[b * n + i1], kb = Kt[b * n + i1];
-        aa += av * mb;
-        ab += av * kb;
-        ba += bv * mb;
-      }
-      sC[slot * nn + r] = aa;
-      sD[slot * nn + r] = ab + ba;
-    }
-    __syncthreads();
-    // phase 3: along dim 2
-    if (slot < E) {
-      double acc = 0.0;
-#pragma unroll
-      for (int c = 0; c < n; ++c) {
-        double av = sC[slot * nn + (c * n + i1) * n + i0];
-        if (MODE == 0)
-          acc += Kt[c * n + i2] * av + Mt[c * n + i2] * sD[slot * nn + (c * n + i1) * n + i0];
-        else
-          acc += Mt[c * n + i2] * av;
-      }
-      out = acc;
+      for (int c = 0; c < n; ++c) out += Mt[c * n + i2] * sX[slot * nn + (c * n + i1) * n + i0];
     }
   }
   if (active) {
-    double h = hh[e];
-    double sc = MODE == 0 ? kk[e] * (DIM == 3 ? h : 1.0) : (DIM == 3 ? h * h * h : h * h);
-    y[(base + r) * nrhs + rr] = sc * out;
+    const double h = hh[e];
+    y[(base + r) * nrhs + rr] = (DIM == 3 ? h * h * h : h * h) * out;
   }
-}
-
-// ------------------------------------------------------------------ faces
-template <int DIM>
-struct FaceShape {
-  static constexpr int NN = DIM == 2 ? 81 : 729;
-  static constexpr int NS = DIM == 2 ? 9 : 81;
-};
-
-__device__ inline int ipow(int b, int e) {
-  int r = 1;
-  for (int i = 0; i < e; ++i) r *= b;
-  return r;
-}
-
-// value at face point g of a side-nodal function f (tangential layout j0 + n j1)
-template <int DIM>
-__device__ inline double face_interp(const double* I0, const double* I1, int n, int q, int g,
-                                     const double* f) {
-  if (DIM == 2) {
-    double s = 0.0;
-    for (int j = 0; j < n; ++j) s += I0[g * n + j] * f[j];
-    return s;
-  }
-  int g0 = g % q, g1 = g / q;
-  double s = 0.0;
-  for (int j1 = 0; j1 < n; ++j1) {
-    double t = 0.0;
-    for (int j0 = 0; j0 < n; ++j0) t += I0[g0 * n + j0] * f[j1 * n + j0];
-    s += I1[g1 * n + j1] * t;
-  }
-  return s;
-}
-
-// transpose: value at side node j of sum_g I(g,j) R[g]
-template <int DIM>
-__device__ inline double face_test(const double* I0, const double* I1, int n, int q, int j,
-                                   const double* R) {
-  if (DIM == 2) {
-    double s = 0.0;
-    for (int g = 0; g < q; ++g) s += I0[g * n + j] * R[g];
-    return s;
-  }
-  int j0 = j % n, j1 = j / n;
-  double s = 0.0;
-  for (int g1 = 0; g1 < q; ++g1) {
-    double t = 0.0;
-    for (int g0 = 0; g0 < q; ++g0) t += I0[g0 * n + j0] * R[g1 * q + g0];
-    s += I1[g1 * n + j1] * t;
-  }
-  return s;
-}
-
-template <int DIM>
-__global__ __launch_bounds__(64) void k_faces(int nitems, int nrhs, int form,
-                                              const int64_t* __restrict__ off,
-                                              const int8_t* __restrict__ pdeg,
-                                              const double* __restrict__ hh,
-                                              const double* __restrict__ kk,
-                                              const int32_t* __restrict__ sptr,
-                                              const FaceRec* __restrict__ recs,
-                                              const double* __restrict__ tab, TableLayout TL,
-                                              const double* __restrict__ x, double* __restrict__ y) {
-  constexpr int NN = FaceShape<DIM>::NN, NS = FaceShape<DIM>::NS;
-  __shared__ double Yacc[NN];
-  __shared__ double To[NS], Do[NS], Tn[NS], Dn[NS], Jw[NS], Fw[NS], Wq[NS], R1[NS], R2[NS];
-  __shared__ double G1[NS], G2[NS], gv[NS], vv[NS], Lq[NS];
-  const int item = blockIdx.x;
-  if (item >= nitems) return;
-  const int e = item / nrhs, rr = item - (item / nrhs) * nrhs;
-  const int lane = threadIdx.x;
-  const int p = pdeg[e], n = p + 1;
-  const int nn = ipow(n, DIM), ns = ipow(n, DIM - 1);
-  const double h = hh[e], k = kk[e];
-  const int64_t base = off[e];
-  for (int i = lane; i < nn; i += 64) Yacc[i] = 0.0;
-  __syncthreads();
-  for (int sidx = 0; sidx < 2 * DIM; ++sidx) {
-    const int m = sidx >> 1, s = sidx & 1;
-    const int rb = sptr[e * 2 * DIM + sidx], re = sptr[e * 2 * DIM + sidx + 1];
-    if (rb == re) continue;
-    int t0 = m == 0 ? 1 : 0;
-    int t1 = DIM == 3 ? (m == 2 ? 1 : 2) : 0;
-    const int st0 = ipow(n, t0), st1 = ipow(n, t1), stm = ipow(n, m);
-    const double* Ds = tab + TL.dside + (p * 2 + s) * 9;
-    const int sp = s ? p : 0;
-    for (int j = lane; j < ns; j += 64) {
-      int j0 = j % n, j1 = DIM == 3 ? j / n : 0;
-      int64_t nb = base + j0 * st0 + (DIM == 3 ? j1 * st1 : 0);
-      double tv = x[(nb + sp * stm) * nrhs + rr];
-      double dv = 0.0;
-      for (int a = 0; a < n; ++a) dv += Ds[a] * x[(nb + a * stm) * nrhs + rr];
-      To[j] = tv;
-      Do[j] = dv / h;
-      G1[j] = 0.0;
-      G2[j] = 0.0;
-    }
-    __syncthreads();
-    const double sgn = s ? 1.0 : -1.0;
-    for (int ri = rb; ri < re; ++ri) {
-      const FaceRec f = recs[ri];
-      const int q = f.q;
-      const int nq = ipow(q, DIM - 1);
-      const double* I0 = tab + interp_index(TL, p, q, f.oc[0]);
-      const double* I1 = DIM == 3 ? tab + interp_index(TL, p, q, f.oc[1]) : I0;
-      const bool inner = f.nbr >= 0;
-      int po = 0, no = 0;
-      double ho = 1.0, ko = 0.0;
-      const double* J0 = I0;
-      const double* J1 = I1;
-      if (inner) {
-        const int eo = f.nbr;
-        po = pdeg[eo];
-        no = po + 1;
-        ho = hh[eo];
-        ko = kk[eo];
-        const int64_t bo = off[eo];
-        const int so = 1 - s;
-        const int nso = ipow(no, DIM - 1);
-        const int so0 = ipow(no, t0), so1 = ipow(no, t1), som = ipow(no, m);
-        const double* Dso = tab + TL.dside + (po * 2 + so) * 9;
-        const int spo = so ? po : 0;
-        for (int j = lane; j < nso; j += 64) {
-          int j0 = j % no, j1 = DIM == 3 ? j / no : 0;
-          int64_t nb = bo + j0 * so0 + (DIM == 3 ? j1 * so1 : 0);
-          double tv = x[(nb + spo * som) * nrhs + rr];
-          double dv = 0.0;
-          for (int a = 0; a < no; ++a) dv += Dso[a] * x[(nb + a * som) * nrhs + rr];
-          Tn[j] = tv;
-          Dn[j] = dv / ho;
-        }
-        J0 = tab + interp_index(TL, po, q, f.nc[0]);
-        J1 = DIM == 3 ? tab + interp_index(TL, po, q, f.nc[1]) : J0;
-      }
-      __syncthreads();
-      const double* gw = tab + TL.gw + q * 10;
-      const double csym = inner ? 0.5 : 1.0;
-      for (int g = lane; g < nq; g += 64) {
-        double uo = face_interp<DIM>(I0, I1, n, q, g, To);
-        double duo = face_interp<DIM>(I0, I1, n, q, g, Do);
-        double w = gw[g % q] * f.flen;
-        if (DIM == 3) w *= gw[g / q] * f.flen;
-        double J, F;
-        if (inner) {
-          double un = face_interp<DIM>(J0, J1, no, q, g, Tn);
-          double dun = face_interp<DIM>(J0, J1, no, q, g, Dn);
-          J = uo - un;
-          F = 0.5 * (k * duo + ko * dun) * sgn;
-        } else {
-          J = uo;
-          F = k * duo * sgn;
-        }
-        Jw[g] = w * J;
-        Fw[g] = w * F;
-        Wq[g] = w;
-      }
-      __syncthreads();
-      if (form == 0) {
-        for (int g = lane; g < nq; g += 64) {
-          R1[g] = f.sig * Jw[g] - Fw[g];
-          R2[g] = -csym * k * Jw[g] * sgn;
-        }
-      } else {
-        for (int g = lane; g < nq; g += 64) Lq[g] = 0.0;
-        const double c2 = inner ? 0.25 : 1.0;
-        for (int side = 0; side < (inner ? 2 : 1); ++side) {
-          const double* A0 = side == 0 ? I0 : J0;
-          const double* A1 = side == 0 ? I1 : J1;
-          const int nk = side == 0 ? n : no;
-          const int pk = nk - 1;
-          const double hk = side == 0 ? h : ho;
-          const int sk = side == 0 ? s : 1 - s;
-          const int nsk = ipow(nk, DIM - 1);
-          const double* Mi = tab + TL.minv + pk * 81;
-          const double m00 = Mi[(sk ? pk : 0) * nk + (sk ? pk : 0)];
-          double hd = 1.0;
-          for (int d = 0; d < DIM; ++d) hd *= hk;
-          const double scale = m00 / hd;
-          __syncthreads();
-          for (int j = lane; j < nsk; j += 64) gv[j] = face_test<DIM>(A0, A1, nk, q, j, Jw);
-          __syncthreads();
-          for (int j = lane; j < nsk; j += 64) {
-            double acc = 0.0;
-            if (DIM == 2) {
-              for (int a = 0; a < nk; ++a) acc += Mi[j * nk + a] * gv[a];
-            } else {
-              int j0 = j % nk, j1 = j / nk;
-              for (int a1 = 0; a1 < nk; ++a1) {
-                double t = 0.0;
-                for (int a0 = 0; a0 < nk; ++a0) t += Mi[j0 * nk + a0] * gv[a1 * nk + a0];
-                acc += Mi[j1 * nk + a1] * t;
-              }
-            }
-            vv[j] = scale * acc;
-          }
-          __syncthreads();
-          for (int g = lane; g < nq; g += 64) Lq[g] += face_interp<DIM>(A0, A1, nk, q, g, vv);
-        }
-        __syncthreads();
-        for (int g = lane; g < nq; g += 64) {
-          R1[g] = c2 * f.sig * Wq[g] * Lq[g] - Fw[g];
-          R2[g] = -csym * k * Jw[g] * sgn;
-        }
-      }
-      __syncthreads();
-      for (int j = lane; j < ns; j += 64) {
-        G1[j] += face_test<DIM>(I0, I1, n, q, j, R1);
-        G2[j] += face_test<DIM>(I0, I1, n, q, j, R2);
-      }
-      __syncthreads();
-    }
-    for (int i = lane; i < nn; i += 64) {
-      int a = (i / stm) % n;
-      int j0 = (i / st0) % n;
-      int j = j0 + (DIM == 3 ? ((i / st1) % n) * n : 0);
-      double v = Ds[a] / h * G2[j];
-      if (a == sp) v += G1[j];
-      Yacc[i] += v;
-    }
-    __syncthreads();
-  }
-  for (int i = lane; i < nn; i += 64) y[(base + i) * nrhs + rr] += Yacc[i];
 }
 
 // 2D element kernel: volume and face terms of one element per 64-lane block,

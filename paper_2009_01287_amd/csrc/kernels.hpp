@@ -32,17 +32,11 @@ static_assert(sizeof(FaceRec) == 88, "FaceRec layout");
 
 // Tables of the 1D basis, all degrees, in one device buffer (doubles).
 struct TableLayout {
-  int ncode;          // sub-interval codes: 1..ncode-1, code = 2^delta + index
-  int64_t interp;     // offset of I[p][q][code][g][i] blocks of 81
-  int64_t gw;         // Gauss weights gw[q*10+g]
   int64_t dside;      // l_i'(0), l_i'(1): dside[(p*2+s)*9+i]
   int64_t minv;       // inverse 1D mass: minv[p*81+i*(p+1)+j]
   int64_t mk;         // M, K: mk[(p*2+0)*81 + i*(p+1)+j] is M, +1 is K
   int64_t total;
 };
 
-__host__ __device__ inline int64_t interp_index(const TableLayout& L, int p, int q, int code) {
-  return L.interp + ((int64_t)(((p - 1) * 8 + (q - 2)) * L.ncode + code)) * 81;
-}
 
 }  // namespace hpdg

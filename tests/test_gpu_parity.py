@@ -173,6 +173,31 @@ def test_pcg_matches_oracle(name, form):
     assert abs(info["cond_est"] / io["cond"] - 1) < 1e-3
 
 
+@pytest.mark.parametrize("name,form", [("rand2", "sipg"), ("hang3", "br2"), ("rand3", "br2")])
+def test_pcg_trajectory_matches_oracle(name, form):
+    """The CG recurrence itself: alpha_k and beta_k of the GPU solve (FP64 B)
+    against the oracle's PCG with its own B over the first 20 iterations, to
+    1e-10 relative (both apply the same A and B up to rounding; CG amplifies
+    the differences slowly over a few tens of iterations)."""
+    md = MESHES[name]()
+    m = O.Mesh(md)
+    eta = 1.0 if form == "sipg" else 0.0
+    opts = O.Opts(form, 0, eta)
+    op = G.Operator(G.Mesh(md), form=form, eta=eta)
+    pc = precond.Preconditioner(m, opts)
+    b = dg.rhs(m, H.gaussian_rhs(m.ndof, 19))
+    _, io = pcg.pcg(lambda v: dg.apply(m, opts, v), pc.apply, b, 1e-30, 20)
+    x = torch.zeros(m.ndof, dtype=torch.float64, device="cuda")
+    code, info = op.pcg_solve(_dev(b), x, rtol=1e-30, maxit=20, raise_on_error=False)
+    assert code == -5 and info[0]["iters"] == 20
+    a, bt = op.cg_coefficients()
+    assert a.shape[0] == 20
+    ao, bo = np.array(io["alphas"]), np.array(io["betas"])
+    assert len(ao) == 20 and len(bo) >= 19
+    assert np.abs(a[:20, 0] / ao - 1).max() <= 1e-10
+    assert np.abs(bt[:19, 0] / bo[:19] - 1).max() <= 1e-10
+
+
 def test_uniform_manufactured_solve():
     md = H.config_mesh(1)
     m = O.Mesh(md)
