@@ -33,6 +33,9 @@ HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
 # for a 256 MiB copy: 2.0 and 1.0), valid for the kernel source with this
 # digest; reported as null once the source differs
 ELEM2D_TRAFFIC = {"digest": "7c863440eab2e8be", "fetch_bytes": 5669344.3, "write_bytes": 1241952.0}
+# the same for the 3D element kernel on the 2,569,985-DOF 3D workload
+# (profiles/random3d_2.57Mdof_hbm_counters.md)
+ELEM3D_TRAFFIC = {"digest": "e407d62595c2ca0d", "fetch_bytes": 68.39e6, "write_bytes": 34.23e6}
 WORKLOADS = {1: "uniform2d_4x4_p2_sipg_fp64",
              2: "random2d_32x32_q0.3_L3_p1-8_sipg_fp64",
              3: "random3d_16^3_q0.2_L2_p1-6_br2_fp32prec",
@@ -64,6 +67,11 @@ def main():
     ap.add_argument("--serving-auto-cycle", type=int, default=1,
                     help="serving: 1 builds fused V-cycle levels and a small dense tail without timing")
     ap.add_argument("--serving-prec", default="mixed", choices=["mixed", "fp64", "both"])
+    ap.add_argument("--lambda-sweep", type=str, default="",
+                    help="serving: comma-separated multiples of the FP64 capacity (solves/s of the FP64 "
+                         "pipeline with every request at t = 0, measured first) at which Poisson arrival "
+                         "streams of --sweep-requests requests are served in mixed precision, e.g. 0.3,0.5,0.7,0.9")
+    ap.add_argument("--sweep-requests", type=int, default=600)
     ap.add_argument("--study", choices=["eta", "random"], default=None,
                     help="eta: penalty-dependence study (SIPG and BR2, eta = 10..1e4, full B against the "
                          "simplified B with point Jacobi on all of V_B); random: random and uniform "
@@ -92,6 +100,8 @@ def main():
         return eta_study(args)
     if args.study == "random":
         return random_study(args)
+    if cfg == 5 and args.lambda_sweep:
+        return serve_sweep(args)
     if cfg == 5:
         return serve_bench(args)
     c = H.CONFIGS[cfg]
@@ -185,6 +195,8 @@ def main():
     traffic = None
     if cfg == 2 and md["dim"] == 2 and nrhs == 1 and elem2d_digest() == ELEM2D_TRAFFIC["digest"]:
         traffic = ELEM2D_TRAFFIC["fetch_bytes"] + ELEM2D_TRAFFIC["write_bytes"]
+    if cfg == 3 and elem3d_digest() == ELEM3D_TRAFFIC["digest"]:
+        traffic = ELEM3D_TRAFFIC["fetch_bytes"] + ELEM3D_TRAFFIC["write_bytes"]
     lat_ms = np.array(lat) * 1e3
     out = {
         "metric": "DG apply GDOF/s + %HBM peak; solves/s and p50/p99 latency at 1e-8 residual",
@@ -349,10 +361,20 @@ def apply_scaled(cfg, c, n_base=128, reps=50):
 def elem2d_digest():
     """Digest of the 2D element kernel's code and the device data layout
     (comments stripped)."""
+    return kernel_digest("// 2D element kernel:", "void k_elem2d(")
+
+
+def elem3d_digest():
+    """Digest of the 3D element kernel's code and the device data layout
+    (comments stripped)."""
+    return kernel_digest("// 3D element kernel:", "void k_elem3d(")
+
+
+def kernel_digest(start, sig):
     import hashlib
     src = open(os.path.join(ROOT, "paper_2009_01287_amd", "csrc", "kernels.hip")).read()
-    a = src.index("// 2D element kernel:")
-    b = src.index("\n}\n", src.index("void k_elem2d(")) + 3
+    a = src.index(start)
+    b = src.index("\n}\n", src.index(sig)) + 3
     hdr = open(os.path.join(ROOT, "paper_2009_01287_amd", "csrc", "kernels.hpp")).read()
     code = "\n".join(l.split("//")[0].rstrip() for l in (src[a:b] + hdr).splitlines())   # comments do not count
     return hashlib.sha256(code.encode()).hexdigest()[:16]
@@ -487,6 +509,47 @@ def serve_bench(args):
         "serving": out,
     }
     print(json.dumps(line))
+
+
+def _serve(reqs_spec, prec, args, realtime):
+    import hpinputs as H
+    from paper_2009_01287_amd import serving as S
+    reqs = []
+    for r in reqs_spec:
+        md = H.request_mesh(r)
+        reqs.append(S.Request(id=r["id"], mesh=md, form=r["form"], f=H.gaussian_rhs(H.ndof(md), r["rhs_seed"]),
+                              t_arrive=r["t_arrive"]))
+    srv = S.Server(max_active=args.max_active, workers=args.workers, prec_fp32=(prec == "mixed"),
+                   realtime=realtime, graph=bool(args.serving_graph), auto_cycle=bool(args.serving_auto_cycle))
+    t0 = time.perf_counter()
+    res = srv.run(reqs)
+    wall = time.perf_counter() - t0
+    return S.summarize(res, wall)
+
+
+def serve_sweep(args):
+    """Serving latency against load: the FP64 pipeline's capacity C (all
+    --requests requests at t = 0), then Poisson streams of --sweep-requests
+    requests at rate f x C for each f of --lambda-sweep, served with the
+    mixed-precision pipeline; one JSON line with the p50/p99 per rate."""
+    import torch
+    import hpinputs as H
+    torch.zeros(1, device="cuda")
+    cap = _serve(H.serving_stream(args.requests, seed=5005), "fp64", args, False)
+    print(json.dumps({"serving_capacity_fp64": cap}), file=sys.stderr, flush=True)
+    C = cap["solves_per_s"]
+    rows = []
+    for f in [float(v) for v in args.lambda_sweep.split(",") if v]:
+        rate = f * C
+        s = _serve(H.serving_stream(args.sweep_requests, seed=5005, rate=rate), "mixed", args, True)
+        row = {"factor": f, "rate": rate, "solves_per_s": s["solves_per_s"], "p50_ms": s["p50_s"] * 1e3,
+               "p99_ms": s["p99_s"] * 1e3, "ok": s["ok"], "requests": s["requests"],
+               "max_true_rel_res": s["max_true_rel_res"]}
+        rows.append(row)
+        print(json.dumps({"serving_sweep_point": row}), file=sys.stderr, flush=True)
+    print(json.dumps({"serving_sweep": {"fp64_capacity_solves_per_s": C, "capacity_requests": args.requests,
+                                        "points": rows, "workers": args.workers,
+                                        "max_active": args.max_active}}))
 
 
 def cpu_baseline(cfg, c, gpu_iters, n_full, iters=30):

@@ -238,6 +238,11 @@ struct hpdg_operator {
   int epb = 1;               // elements per workgroup of the 2D element kernel
   int nm3 = 9;               // LDS size class of the 3D element kernel: largest n = p + 1 (7 or 9)
   DevBuf elem_perm;          // 3D elements by decreasing cost within each XCD's share
+  // 3D, one RHS: the operator in three passes (k_e3_vol, k_e3_face,
+  // k_e3_lift) with the side buffer and the per-record face contributions
+  int split3 = 1;
+  int e3stage = 1;           // face pass: 1D face matrices staged in LDS (1) or read through the caches (0)
+  DevBuf sboff, faux, sbuf, gbuf;
   int use_perm = 1;          // 3D element kernel dispatched in that order (autotuned)
   int cg_separate = 0;       // one RHS: CG final reductions as kernels of their own
   int64_t presplit_nnz = kPreSplitNnz;   // pre-smoother in two launches above this
@@ -665,6 +670,43 @@ static void upload_device(hpdg_operator* op, hipStream_t s) {
   }
   op->recs.upload(U.recs);
   op->ftab.upload(U.ftab);
+  if (op->dim == 3) {
+    // side-buffer offsets (12 n^2 per element) and the per-record FaceAux
+    const int64_t ne = (int64_t)U.pd.size();
+    std::vector<int64_t> sbo(ne + 1, 0);
+    for (int64_t e = 0; e < ne; ++e) {
+      const int64_t n = U.pd[e] + 1;
+      sbo[e + 1] = sbo[e] + 12 * n * n;
+    }
+    std::vector<FaceAux> ax(U.recs.size());
+    int64_t go = 0;
+    for (int64_t e = 0; e < ne; ++e) {
+      const int64_t n = U.pd[e] + 1;
+      for (int32_t q = U.sptr[e * 6]; q < U.sptr[e * 6 + 6]; ++q) {
+        const FaceRec& r = U.recs[q];
+        FaceAux& a = ax[q];
+        a.h = U.h[e];
+        a.k = U.k[e];
+        a.p = U.pd[e];
+        a.pad = 0;
+        a.sb_own = sbo[e] + (2 * r.m + r.side) * 2 * n * n;
+        if (r.nbr >= 0) {
+          const int64_t nn = U.pd[r.nbr] + 1;
+          a.sb_nbr = sbo[r.nbr] + (2 * r.m + 1 - r.side) * 2 * nn * nn;
+        } else {
+          a.sb_nbr = -1;
+        }
+        a.goff = go;
+        go += 2 * n * n;
+      }
+    }
+    const int64_t sb_total = sbo[ne];
+    sbo.pop_back();
+    op->sboff.upload(sbo);
+    op->faux.upload(ax);
+    op->sbuf.alloc((size_t)sb_total * sizeof(double));
+    op->gbuf.alloc((size_t)go * sizeof(double));
+  }
   build_tables(op, U.max_dlevel);
   op->dbucket.clear();
   op->dbucket.resize(kMaxP + 1);
@@ -919,6 +961,8 @@ extern "C" hpdg_status hpdg_setup_operator(const hpdg_mesh* mh, const hpdg_opera
     if (const char* v = std::getenv("HPDG_NO_MFMA")) op->no_mfma = std::atoi(v) != 0;
     if (const char* v = std::getenv("HPDG_NO_FUSED_MULTI")) op->no_fused_multi = std::atoi(v) != 0;
     if (const char* v = std::getenv("HPDG_ELEM3D_COST_ORDER")) op->use_perm = std::atoi(v) != 0;
+    if (const char* v = std::getenv("HPDG_ELEM3D_SPLIT")) op->split3 = std::atoi(v) != 0;
+    if (const char* v = std::getenv("HPDG_ELEM3D_STAGE")) op->e3stage = std::atoi(v) != 0;
     if (const char* v = std::getenv("HPDG_CG_SEPARATE_FINALS")) op->cg_separate = std::atoi(v) != 0;
     if (const char* v = std::getenv("HPDG_PRESPLIT_NNZ")) op->presplit_nnz = std::max<int64_t>(-1, std::atoll(v));
     if (!op->no_prec) {
@@ -1085,6 +1129,30 @@ static int apply_A_dev(hpdg_operator* op, const double* x, double* y, int nrhs, 
     };
     if (op->epb == 2) with_fc(I2());
     else with_fc(I1());
+    return pdot ? op->ne : 0;
+  } else if (nrhs == 1 && op->split3) {
+    // three passes: volume and side traces, face records, lift
+    const unsigned grid = 8u * (unsigned)((op->ne + 7) / 8);   // XCD-aware order: a multiple of 8
+    const int32_t* perm = op->use_perm ? op->elem_perm.as<int32_t>() : nullptr;
+    const int nrec = (int)(op->recs.bytes / sizeof(FaceRec));
+    if (op->nm3 == 7) {
+      hipLaunchKernelGGL(k_e3_vol<7>, dim3(grid), dim3(256), 0, s, op->ne, op->off.as<int64_t>(),
+                         op->pdeg.as<int8_t>(), op->hh.as<double>(), op->kk.as<double>(), op->sboff.as<int64_t>(),
+                         op->tab.as<double>(), op->TL, x, y, op->sbuf.as<double>(), perm);
+      hipLaunchKernelGGL((op->e3stage ? k_e3_face<7, true> : k_e3_face<7, false>), dim3((nrec + 3) / 4), dim3(256), 0, s, nrec, op->form,
+                         op->recs.as<FaceRec>(), op->faux.as<FaceAux>(), op->ftab.as<double>(), op->tab.as<double>(),
+                         op->TL, op->sbuf.as<double>(), op->gbuf.as<double>());
+    } else {
+      hipLaunchKernelGGL(k_e3_vol<9>, dim3(grid), dim3(256), 0, s, op->ne, op->off.as<int64_t>(),
+                         op->pdeg.as<int8_t>(), op->hh.as<double>(), op->kk.as<double>(), op->sboff.as<int64_t>(),
+                         op->tab.as<double>(), op->TL, x, y, op->sbuf.as<double>(), perm);
+      hipLaunchKernelGGL((op->e3stage ? k_e3_face<9, true> : k_e3_face<9, false>), dim3((nrec + 3) / 4), dim3(256), 0, s, nrec, op->form,
+                         op->recs.as<FaceRec>(), op->faux.as<FaceAux>(), op->ftab.as<double>(), op->tab.as<double>(),
+                         op->TL, op->sbuf.as<double>(), op->gbuf.as<double>());
+    }
+    hipLaunchKernelGGL(k_e3_lift, dim3(op->ne), dim3(256), 0, s, op->ne, op->off.as<int64_t>(),
+                       op->pdeg.as<int8_t>(), op->hh.as<double>(), op->sptr.as<int32_t>(), op->recs.as<FaceRec>(),
+                       op->faux.as<FaceAux>(), op->tab.as<double>(), op->TL, op->gbuf.as<double>(), x, y, pdot);
     return pdot ? op->ne : 0;
   } else {
     const unsigned grid = 8u * (unsigned)((items + 7) / 8);   // k_elem3d needs a multiple of 8

@@ -1034,6 +1034,510 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NM == 7 ? 7
   }
 }
 
+// ---------------------------------------------- 3D operator in three passes
+// The same operator as k_elem3d (same face arithmetic, same record order of
+// the side sums), split so that each pass keeps many items in flight (one
+// RHS):
+//   k_e3_vol   one workgroup per element: the volume term into y and the
+//              element's traces and normal derivatives on its six sides
+//              (To, Do = d/dn / h) into the side buffer sb (12 n^2 values per
+//              element at sboff[e]; side s holds To then Do);
+//   k_e3_face  one wavefront per face record (four per workgroup, only
+//              wave-level synchronisation): the record's contributions to the
+//              tests of its element's side nodes, g1 (against the trace) and
+//              g2 (against the normal derivative), into gbuf at goff[rec];
+//   k_e3_lift  one workgroup per element: the side sums of g1, g2 over its
+//              records in record order, lifted into the element
+//              (y += D_side(i_m) G2 / h + [i_m on the side] G1), with the
+//              element's share of x'y.
+// Per record the host adds FaceAux: the own element's degree, h and k, and
+// the side-buffer offsets of the own side and of the neighbour's side.
+struct FaceAux {
+  double h, k;        // own element
+  int64_t sb_own;     // offset (doubles) of the own side's To in sb
+  int64_t sb_nbr;     // the neighbour's side facing this one (-1 on the boundary)
+  int64_t goff;       // offset of this record's g1 (g2 follows after n^2) in gbuf
+  int32_t p, pad;
+};
+static_assert(sizeof(FaceAux) == 48, "FaceAux layout");
+
+template <int N, int NM>
+__device__ inline void e3v_body(double (*V)[NM * NM * NM], double* tb, int e, const int64_t* __restrict__ off,
+                                const double* __restrict__ hh, const double* __restrict__ kk,
+                                const int64_t* __restrict__ sboff, const double* __restrict__ tab, TableLayout TL,
+                                const double* __restrict__ x, double* __restrict__ y, double* __restrict__ sb) {
+  constexpr int N2 = N * N, N3 = N2 * N, p = N - 1;
+  const int tid = threadIdx.x;
+  const double h = hh[e], k = kk[e];
+  const int64_t base = off[e];
+  double* sX = V[0];
+  for (int i = tid; i < N3; i += 256) sX[i] = x[base + i];
+  {
+    const double* gM = tab + TL.mk + (p * 2 + 0) * 81;
+    const double* gK = tab + TL.mk + (p * 2 + 1) * 81;
+    for (int i = tid; i < N2; i += 256) {
+      tb[i] = gM[i];
+      tb[81 + i] = gK[i];
+    }
+    if (tid < N) {
+      tb[162 + tid] = tab[TL.dside + (p * 2 + 0) * 9 + tid];
+      tb[171 + tid] = tab[TL.dside + (p * 2 + 1) * 9 + tid];
+    }
+  }
+  __syncthreads();
+  const double* Mt = tb;
+  const double* Kt = tb + 81;
+  // phase 1 (dimension 0) and the six sides' traces into the side buffer
+  {
+    double* sA = V[1];
+    double* sB = V[2];
+    for (int r = tid; r < N3; r += 256) {
+      const int i0 = r % N, i12 = r - i0;
+      double a0 = 0.0, b0 = 0.0;
+#pragma unroll
+      for (int a = 0; a < N; ++a) {
+        const double xa = sX[i12 + a];
+        a0 += xa * Mt[a * N + i0];
+        b0 += xa * Kt[a * N + i0];
+      }
+      sA[r] = a0;
+      sB[r] = b0;
+    }
+    double* out = sb + sboff[e];
+    for (int t = tid; t < 6 * N2; t += 256) {
+      const int side = t / N2, q = t - side * N2;
+      const int m = side >> 1, s = side & 1;
+      int t0, t1;
+      tdims3(m, t0, t1);
+      const int st[3] = {1, N, N2};
+      const int j0 = q % N, j1 = q / N;
+      const int o = j0 * st[t0] + j1 * st[t1];
+      const double* Ds = tb + (s ? 171 : 162);
+      double dv = 0.0;
+#pragma unroll
+      for (int a = 0; a < N; ++a) dv += Ds[a] * sX[o + a * st[m]];
+      out[side * 2 * N2 + q] = sX[o + (s ? p : 0) * st[m]];
+      out[side * 2 * N2 + N2 + q] = dv / h;
+    }
+  }
+  __syncthreads();
+  // phase 2 (dimension 1): C into V0 (x is no longer needed), D into V3
+  {
+    const double* sA = V[1];
+    const double* sB = V[2];
+    double* sC = V[0];
+    double* sD = V[3];
+    for (int r = tid; r < N3; r += 256) {
+      const int i0 = r % N, i1 = (r / N) % N, i2 = r / N2;
+      double aa = 0.0, ab = 0.0, ba = 0.0;
+#pragma unroll
+      for (int b = 0; b < N; ++b) {
+        const double av = sA[i0 + N * b + N2 * i2], bv = sB[i0 + N * b + N2 * i2];
+        const double mb = Mt[b * N + i1], kb = Kt[b * N + i1];
+        aa += av * mb;
+        ab += av * kb;
+        ba += bv * mb;
+      }
+      sC[r] = aa;
+      sD[r] = ab + ba;
+    }
+  }
+  __syncthreads();
+  // phase 3 (dimension 2): the volume term into y
+  {
+    const double* sC = V[0];
+    const double* sD = V[3];
+    for (int r = tid; r < N3; r += 256) {
+      const int i01 = r % N2, i2 = r / N2;
+      double acc = 0.0;
+#pragma unroll
+      for (int cc = 0; cc < N; ++cc) acc += Kt[cc * N + i2] * sC[i01 + N2 * cc] + Mt[cc * N + i2] * sD[i01 + N2 * cc];
+      y[base + r] = k * h * acc;
+    }
+  }
+}
+
+template <int NM>
+__global__ __launch_bounds__(256) void k_e3_vol(int ne, const int64_t* __restrict__ off,
+                                                const int8_t* __restrict__ pdeg, const double* __restrict__ hh,
+                                                const double* __restrict__ kk, const int64_t* __restrict__ sboff,
+                                                const double* __restrict__ tab, TableLayout TL,
+                                                const double* __restrict__ x, double* __restrict__ y,
+                                                double* __restrict__ sb, const int32_t* __restrict__ perm) {
+  __shared__ double V[4][NM * NM * NM];
+  __shared__ double tb[180];
+  const int per = (int)(gridDim.x >> 3);
+  const int item = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);   // XCD-aware order
+  if (item >= ne) return;
+  const int e = perm ? perm[item] : item;
+  switch (pdeg[e]) {
+    case 1: e3v_body<2, NM>(V, tb, e, off, hh, kk, sboff, tab, TL, x, y, sb); break;
+    case 2: e3v_body<3, NM>(V, tb, e, off, hh, kk, sboff, tab, TL, x, y, sb); break;
+    case 3: e3v_body<4, NM>(V, tb, e, off, hh, kk, sboff, tab, TL, x, y, sb); break;
+    case 4: e3v_body<5, NM>(V, tb, e, off, hh, kk, sboff, tab, TL, x, y, sb); break;
+    case 5: e3v_body<6, NM>(V, tb, e, off, hh, kk, sboff, tab, TL, x, y, sb); break;
+    case 6: e3v_body<7, NM>(V, tb, e, off, hh, kk, sboff, tab, TL, x, y, sb); break;
+    default:
+      if constexpr (NM >= 9) {
+        if (pdeg[e] == 7) e3v_body<8, NM>(V, tb, e, off, hh, kk, sboff, tab, TL, x, y, sb);
+        else e3v_body<9, NM>(V, tb, e, off, hh, kk, sboff, tab, TL, x, y, sb);
+      }
+      break;
+  }
+}
+
+// floor(q / d) for 0 <= q < 128 and 1 <= d <= 9 by a multiply and a shift
+// (mul = 65536 / d + 1; exact in that range)
+__device__ inline int qdiv(int q, int mul) { return (q * mul) >> 16; }
+
+// one face record per wavefront, the own degree N = n a constant
+template <int N, int NM, bool STAGE>
+__device__ inline void e3f_body(const FaceRec& r, const FaceAux& ax, int form, double* To, double* Do, double* W,
+                                double* Mx, const double* __restrict__ ftab, const double* __restrict__ tab,
+                                TableLayout TL, const double* __restrict__ sb, double* __restrict__ gbuf, int lane) {
+  constexpr int F2 = NM * NM, n = N, n2 = N * N, p = N - 1;
+  const bool inner = r.nbr >= 0;
+  const int po = inner ? (int)r.pn : 0, no = po + 1, no2 = no * no;
+  const int mno = 65536 / no + 1;
+  // the ten 1D face matrices: staged in LDS (STAGE) or read through the
+  // caches from the face table
+  const double* MP[10];
+  if (STAGE) {
+#pragma unroll
+    for (int k = 0; k < 10; ++k) MP[k] = Mx + k * F2;
+  } else {
+    MP[0] = ftab + r.foo[0];
+    MP[1] = ftab + r.foo[1];
+    MP[2] = ftab + r.fon[0];
+    MP[3] = ftab + r.fon[1];
+    MP[4] = ftab + r.fnn[0];
+    MP[5] = ftab + r.fnn[1];
+    MP[6] = ftab + r.loo[0];
+    MP[7] = ftab + r.loo[1];
+    MP[8] = ftab + r.lon[0];
+    MP[9] = ftab + r.lon[1];
+  }
+  // staging: own side (To, Do), neighbour side (Tn, Dn = k_n Do_n), matrices
+  {
+    const double* so = sb + ax.sb_own;
+    for (int q = lane; q < n2; q += 64) {
+      To[q] = so[q];
+      Do[q] = so[n2 + q];
+    }
+    if (inner) {
+      const double* sn = sb + ax.sb_nbr;
+      const double kn = r.kho * r.hn;
+      for (int q = lane; q < no2; q += 64) {
+        W[q] = sn[q];
+        W[F2 + q] = kn * sn[no2 + q];
+      }
+    }
+    // A0oo A1oo (n x n), A0on A1on (n x no), then for BR2 A0nn A1nn (no x no),
+    // L0o L1o (n x n), L0n L1n (n x no)
+    const int nm = !STAGE ? 0 : form == 1 ? 10 : (inner ? 4 : 2);
+    for (int t = lane; t < nm * F2; t += 64) {
+      const int kx = t / F2, i = t - kx * F2;
+      int sz = n2, o = -1;
+      switch (kx) {
+        case 0: o = r.foo[0]; break;
+        case 1: o = r.foo[1]; break;
+        case 2: if (inner) { o = r.fon[0]; sz = n * no; } break;
+        case 3: if (inner) { o = r.fon[1]; sz = n * no; } break;
+        case 4: if (inner) { o = r.fnn[0]; sz = no2; } break;
+        case 5: if (inner) { o = r.fnn[1]; sz = no2; } break;
+        case 6: o = r.loo[0]; break;
+        case 7: o = r.loo[1]; break;
+        case 8: if (inner) { o = r.lon[0]; sz = n * no; } break;
+        default: if (inner) { o = r.lon[1]; sz = n * no; } break;
+      }
+      if (o >= 0 && i < sz) Mx[t] = ftab[o + i];
+    }
+  }
+  wave_sync();
+  // stage 1: U0 = A0oo To, U1 = A0oo Do (n x n), U2 = A0on Tn, U3 = A0on Dn
+  // (n x no); BR2: Y0 = A0on^T To stored transposed, Y0[a1 + n a0] (a0 < no,
+  // a1 < n), Y1 = A0nn Tn (no x no)
+  for (int t = lane; t < 2 * n2; t += 64) {
+    const int which = t / n2, q = t - which * n2;
+    const int j0 = q % n, a1 = q / n;
+    const double* in = which == 0 ? To : Do;
+    double s = 0.0;
+#pragma unroll
+    for (int a0 = 0; a0 < n; ++a0) s += MP[0][j0 * n + a0] * in[a0 + n * a1];
+    W[(2 + which) * F2 + q] = s;
+  }
+  if (inner) {
+    const double* A = MP[2];
+    for (int t = lane; t < 2 * n * no; t += 64) {
+      const int which = t >= n * no ? 1 : 0, q = t - which * n * no;
+      const int j0 = q % n, a1 = q / n;
+      const double* in = W + which * F2;
+      double s = 0.0;
+#pragma unroll
+      for (int a0 = 0; a0 < NM; ++a0)
+        if (a0 < no) s += A[j0 * no + a0] * in[a0 + no * a1];
+      W[(4 + which) * F2 + q] = s;
+    }
+    if (form == 1) {
+      for (int q = lane; q < n * no; q += 64) {
+        const int a1 = q % n, a0 = q / n;
+        double s = 0.0;
+#pragma unroll
+        for (int j0 = 0; j0 < n; ++j0) s += A[j0 * no + a0] * To[j0 + n * a1];
+        W[6 * F2 + q] = s;
+      }
+      const double* Ann = MP[4];
+      for (int q = lane; q < no2; q += 64) {
+        const int a1 = qdiv(q, mno), a0 = q - a1 * no;
+        double s = 0.0;
+#pragma unroll
+        for (int b0 = 0; b0 < NM; ++b0)
+          if (b0 < no) s += Ann[a0 * no + b0] * W[b0 + no * a1];
+        W[7 * F2 + q] = s;
+      }
+    }
+  }
+  wave_sync();
+  const double area = r.flen * r.flen;
+  const double sgn = r.side ? 1.0 : -1.0;
+  const double csym = inner ? 0.5 : 1.0;
+  const double k = ax.k;
+  // stage 2: v, the average and the penalty on the own side nodes; BR2: the
+  // neighbour's jump vn = (A0on x A1on)^T To - (A0nn x A1nn) Tn
+  for (int q = lane; q < n2; q += 64) {
+    const int j0 = q % n, j1 = q / n;
+    const double* A1oo = MP[1];
+    double v = 0.0, ds = 0.0;
+#pragma unroll
+    for (int a1 = 0; a1 < n; ++a1) {
+      const double wv = A1oo[j1 * n + a1];
+      v += wv * W[2 * F2 + j0 + n * a1];
+      ds += k * wv * W[3 * F2 + j0 + n * a1];
+    }
+    if (inner) {
+      const double* A1on = MP[3];
+#pragma unroll
+      for (int a1 = 0; a1 < NM; ++a1)
+        if (a1 < no) {
+          const double wv = A1on[j1 * no + a1];
+          v -= wv * W[4 * F2 + j0 + n * a1];
+          ds += wv * W[5 * F2 + j0 + n * a1];
+        }
+    }
+    double g1 = -area * csym * sgn * ds;
+    if (form == 0) g1 += area * r.sig * v;
+    W[8 * F2 + q] = g1;
+    W[9 * F2 + q] = -csym * k * sgn * area * v;
+    W[q] = v;
+  }
+  if (inner && form == 1) {
+    const double* A1on = MP[3];
+    const double* A1nn = MP[5];
+    for (int q = lane; q < no2; q += 64) {
+      const int b1 = qdiv(q, mno), a0 = q - b1 * no;
+      double vn = 0.0;
+#pragma unroll
+      for (int a1 = 0; a1 < n; ++a1) vn += A1on[a1 * no + b1] * W[6 * F2 + a1 + n * a0];
+#pragma unroll
+      for (int c1 = 0; c1 < NM; ++c1)
+        if (c1 < no) vn -= A1nn[b1 * no + c1] * W[7 * F2 + a0 + no * c1];
+      W[F2 + q] = vn;
+    }
+  }
+  wave_sync();
+  if (form == 1) {
+    // stage 3: P0 = L0o v (n x n), Q0 = L0n vn (n x no)
+    {
+      const double* L0o = MP[6];
+      for (int q = lane; q < n2; q += 64) {
+        const int j0 = q % n, a1 = q / n;
+        double s = 0.0;
+#pragma unroll
+        for (int a0 = 0; a0 < n; ++a0) s += L0o[j0 * n + a0] * W[a0 + n * a1];
+        W[2 * F2 + q] = s;
+      }
+    }
+    if (inner) {
+      const double* L0n = MP[8];
+      for (int q = lane; q < n * no; q += 64) {
+        const int j0 = q % n, a1 = q / n;
+        double s = 0.0;
+#pragma unroll
+        for (int a0 = 0; a0 < NM; ++a0)
+          if (a0 < no) s += L0n[j0 * no + a0] * W[F2 + a0 + no * a1];
+        W[3 * F2 + q] = s;
+      }
+    }
+    wave_sync();
+    // stage 4: slot 1 and the sum into g1
+    double so = 0.0, sn = 0.0;
+    {
+      const double* Mi = tab + TL.minv + p * 81;
+      constexpr int dummy = 0;
+      (void)dummy;
+      const int sk = r.side ? p : 0;
+      so = Mi[sk * n + sk] / (ax.h * ax.h * ax.h);
+      if (inner) {
+        const double* Min = tab + TL.minv + po * 81;
+        const int skn = (1 - r.side) ? po : 0;
+        sn = Min[skn * no + skn] / (r.hn * r.hn * r.hn);
+      }
+    }
+    const double L2 = (inner ? 0.25 : 1.0) * r.sig * area * area;
+    const double* L1o = MP[7];
+    const double* L1n = MP[9];
+    for (int q = lane; q < n2; q += 64) {
+      const int j0 = q % n, j1 = q / n;
+      double so_acc = 0.0, sn_acc = 0.0;
+#pragma unroll
+      for (int a1 = 0; a1 < n; ++a1) so_acc += L1o[j1 * n + a1] * W[2 * F2 + j0 + n * a1];
+      if (inner) {
+#pragma unroll
+        for (int a1 = 0; a1 < NM; ++a1)
+          if (a1 < no) sn_acc += L1n[j1 * no + a1] * W[3 * F2 + j0 + n * a1];
+      }
+      W[8 * F2 + q] += L2 * (so * so_acc + sn * sn_acc);
+    }
+    wave_sync();
+  }
+  double* g = gbuf + ax.goff;
+  for (int q = lane; q < n2; q += 64) {
+    g[q] = W[8 * F2 + q];
+    g[n2 + q] = W[9 * F2 + q];
+  }
+}
+
+// one face record per wavefront (four per workgroup, wave-level
+// synchronisation only); NM: largest n of the mesh
+template <int NM, bool STAGE>
+__global__ __launch_bounds__(256) void k_e3_face(int nrec, int form, const FaceRec* __restrict__ recs,
+                                                 const FaceAux* __restrict__ aux, const double* __restrict__ ftab,
+                                                 const double* __restrict__ tab, TableLayout TL,
+                                                 const double* __restrict__ sb, double* __restrict__ gbuf) {
+  constexpr int F2 = NM * NM;
+  __shared__ FaceRec sR[4];
+  __shared__ FaceAux sAx[4];
+  __shared__ double sO[4][2][F2];     // own To, Do
+  __shared__ double sW[4][10][F2];    // 0 Tn -> v, 1 Dn -> vn, 2 U0 -> P0, 3 U1 -> Q0, 4 U2, 5 U3, 6 Y0, 7 Y1, 8 g1, 9 g2
+  __shared__ double sM[STAGE ? 4 : 1][STAGE ? 10 : 1][STAGE ? F2 : 1];   // A0oo A1oo A0on A1on A0nn A1nn L0o L1o L0n L1n
+  const int w = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+  const int rec = blockIdx.x * 4 + w;
+  if (rec >= nrec) return;            // whole wavefronts only: no block-wide barrier below
+  {
+    constexpr int WR = (int)(sizeof(FaceRec) / 8), WA = (int)(sizeof(FaceAux) / 8);
+    const unsigned long long* s0 = reinterpret_cast<const unsigned long long*>(recs + rec);
+    const unsigned long long* s1 = reinterpret_cast<const unsigned long long*>(aux + rec);
+    if (lane < WR) reinterpret_cast<unsigned long long*>(&sR[w])[lane] = s0[lane];
+    else if (lane < WR + WA) reinterpret_cast<unsigned long long*>(&sAx[w])[lane - WR] = s1[lane - WR];
+  }
+  wave_sync();
+  double* W = &sW[w][0][0];
+  double* Mx = STAGE ? &sM[w][0][0] : nullptr;
+  double* To = sO[w][0];
+  double* Do = sO[w][1];
+  switch (sAx[w].p) {
+    case 1: e3f_body<2, NM, STAGE>(sR[w], sAx[w], form, To, Do, W, Mx, ftab, tab, TL, sb, gbuf, lane); break;
+    case 2: e3f_body<3, NM, STAGE>(sR[w], sAx[w], form, To, Do, W, Mx, ftab, tab, TL, sb, gbuf, lane); break;
+    case 3: e3f_body<4, NM, STAGE>(sR[w], sAx[w], form, To, Do, W, Mx, ftab, tab, TL, sb, gbuf, lane); break;
+    case 4: e3f_body<5, NM, STAGE>(sR[w], sAx[w], form, To, Do, W, Mx, ftab, tab, TL, sb, gbuf, lane); break;
+    case 5: e3f_body<6, NM, STAGE>(sR[w], sAx[w], form, To, Do, W, Mx, ftab, tab, TL, sb, gbuf, lane); break;
+    case 6: e3f_body<7, NM, STAGE>(sR[w], sAx[w], form, To, Do, W, Mx, ftab, tab, TL, sb, gbuf, lane); break;
+    default:
+      if constexpr (NM >= 9) {
+        if (sAx[w].p == 7) e3f_body<8, NM, STAGE>(sR[w], sAx[w], form, To, Do, W, Mx, ftab, tab, TL, sb, gbuf, lane);
+        else e3f_body<9, NM, STAGE>(sR[w], sAx[w], form, To, Do, W, Mx, ftab, tab, TL, sb, gbuf, lane);
+      }
+      break;
+  }
+}
+
+template <int N>
+__device__ inline void e3l_body(double (*S)[81], int* rside, int64_t* rgoff, int e, const int64_t* __restrict__ off,
+                                const double* __restrict__ hh, const int32_t* __restrict__ sptr,
+                                const FaceRec* __restrict__ recs, const FaceAux* __restrict__ aux,
+                                const double* __restrict__ tab, TableLayout TL, const double* __restrict__ gbuf,
+                                const double* __restrict__ x, double* __restrict__ y, double* __restrict__ pdot,
+                                double* red) {
+  constexpr int N2 = N * N, N3 = N2 * N, p = N - 1;
+  const int tid = threadIdx.x;
+  const int f0 = sptr[e * 6], f1 = sptr[e * 6 + 6];
+  // the element's records (side, offset of g1) in LDS, in record order;
+  // elements with more than 64 records take them from memory
+  const int nf = f1 - f0;
+  if (nf <= 64 && tid < nf) {
+    rside[tid] = 2 * recs[f0 + tid].m + recs[f0 + tid].side;
+    rgoff[tid] = aux[f0 + tid].goff;
+  }
+  __syncthreads();
+  // side sums, records in order
+  for (int t = tid; t < 6 * N2; t += 256) {
+    const int side = t / N2, q = t - side * N2;
+    double s1 = 0.0, s2 = 0.0;
+    for (int f = 0; f < nf; ++f) {
+      const int sf = nf <= 64 ? rside[f] : 2 * recs[f0 + f].m + recs[f0 + f].side;
+      if (sf != side) continue;
+      const double* g = gbuf + (nf <= 64 ? rgoff[f] : aux[f0 + f].goff);
+      s1 += g[q];
+      s2 += g[N2 + q];
+    }
+    S[side][q] = s1;
+    S[6 + side][q] = s2;
+  }
+  __syncthreads();
+  const double h = hh[e];
+  const int64_t base = off[e];
+  const double* D0 = tab + TL.dside + (p * 2 + 0) * 9;
+  const double* D1 = tab + TL.dside + (p * 2 + 1) * 9;
+  double xy = 0.0;
+  for (int r = tid; r < N3; r += 256) {
+    const int i[3] = {r % N, (r / N) % N, r / N2};
+    double v = y[base + r];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      int t0, t1;
+      tdims3(m, t0, t1);
+      const int q = i[t0] + N * i[t1];
+      v += (D0[i[m]] * S[6 + 2 * m][q] + D1[i[m]] * S[6 + 2 * m + 1][q]) / h;
+      if (i[m] == 0) v += S[2 * m][q];
+      if (i[m] == p) v += S[2 * m + 1][q];
+    }
+    y[base + r] = v;
+    xy += x[base + r] * v;
+  }
+  if (pdot) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) xy += __shfl_xor(xy, o, 64);
+    if ((tid & 63) == 0) red[tid >> 6] = xy;
+    __syncthreads();
+    if (tid == 0) pdot[e] = (red[0] + red[1]) + (red[2] + red[3]);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_e3_lift(int ne, const int64_t* __restrict__ off,
+                                                 const int8_t* __restrict__ pdeg, const double* __restrict__ hh,
+                                                 const int32_t* __restrict__ sptr, const FaceRec* __restrict__ recs,
+                                                 const FaceAux* __restrict__ aux, const double* __restrict__ tab,
+                                                 TableLayout TL, const double* __restrict__ gbuf,
+                                                 const double* __restrict__ x, double* __restrict__ y,
+                                                 double* __restrict__ pdot) {
+  __shared__ double S[12][81];   // G1 of the six sides, then G2
+  __shared__ double red[4];
+  __shared__ int rside[64];
+  __shared__ int64_t rgoff[64];
+  const int e = blockIdx.x;
+  if (e >= ne) return;
+  switch (pdeg[e]) {
+    case 1: e3l_body<2>(S, rside, rgoff, e, off, hh, sptr, recs, aux, tab, TL, gbuf, x, y, pdot, red); break;
+    case 2: e3l_body<3>(S, rside, rgoff, e, off, hh, sptr, recs, aux, tab, TL, gbuf, x, y, pdot, red); break;
+    case 3: e3l_body<4>(S, rside, rgoff, e, off, hh, sptr, recs, aux, tab, TL, gbuf, x, y, pdot, red); break;
+    case 4: e3l_body<5>(S, rside, rgoff, e, off, hh, sptr, recs, aux, tab, TL, gbuf, x, y, pdot, red); break;
+    case 5: e3l_body<6>(S, rside, rgoff, e, off, hh, sptr, recs, aux, tab, TL, gbuf, x, y, pdot, red); break;
+    case 6: e3l_body<7>(S, rside, rgoff, e, off, hh, sptr, recs, aux, tab, TL, gbuf, x, y, pdot, red); break;
+    case 7: e3l_body<8>(S, rside, rgoff, e, off, hh, sptr, recs, aux, tab, TL, gbuf, x, y, pdot, red); break;
+    default: e3l_body<9>(S, rside, rgoff, e, off, hh, sptr, recs, aux, tab, TL, gbuf, x, y, pdot, red); break;
+  }
+}
+
 // sum over a block of 256 threads in a fixed order; valid in thread 0
 __device__ inline double block_sum256(double v) {
   __shared__ double sw[4];
