@@ -222,122 +222,144 @@ std::vector<double> dg_submatrix(const Mesh& M, const OpOpts& o, const std::vect
     for (int q = M.ef_ptr[kv.first]; q < M.ef_ptr[kv.first + 1]; ++q) fl.push_back(M.ef_idx[q]);
   std::sort(fl.begin(), fl.end());
   fl.erase(std::unique(fl.begin(), fl.end()), fl.end());
+  // Face terms. Every integrand is a product over the tangential dimensions
+  // (traces and normal derivatives of tensor-product GL functions on a face
+  // box), so each face integral is a product of 1D integrals: with the 1D
+  // face-mass factors C_j^{XY}[i, i'] = sum_g w_j(g) l^X_i(x_g) l^Y_i'(x_g) of
+  // the face's sides X, Y in tangential dimension j,
+  //   int [[phi_a]] {k d phi_b / dn} = js_a [a on f] (D_sb(i^b_m) k_b ca_b / h_b) prod_j C_j^{ab}
+  //   int [[phi_a]] [[phi_b]]        = js_a js_b [a, b on f] prod_j C_j^{ab}
+  //   BR2 lifting through side K     = mk_K js_a js_b [a, b on f] prod_j (C_j^{Ka}' Minv_K C_j^{Kb})
+  // (exact: the 1D rules have max(p-, p+) + 1 points), so every block entry
+  // costs O(1) once the small factor matrices of the face are formed.
   for (int fi : fl) {
     const Face& f = M.faces[fi];
     FaceQuad Q = face_quad(M, f);
-    int nQ = 1;
-    for (int j = 0; j < Q.nt; ++j) nQ *= Q.q;
-    std::vector<double> W(nQ, 1.0);
-    for (int g = 0; g < nQ; ++g) {
-      int gg = g;
-      for (int j = 0; j < Q.nt; ++j) { W[g] *= Q.wt[j][gg % Q.q]; gg /= Q.q; }
-    }
-    // columns: (block position, Ju, Fu) for block DOFs on this face's elements
-    std::vector<int> pos;
-    std::vector<std::vector<double>> Ju, Fu;
-    for (const FaceSide& A : Q.sides) {
+    const int ns = (int)Q.sides.size();
+    // block DOFs on each side's element: (block position, multi-index)
+    struct Col { int a; int i[3]; };
+    std::vector<Col> cols[2];
+    bool any = false, anyon = false;
+    for (int x = 0; x < ns; ++x) {
+      const FaceSide& A = Q.sides[x];
       auto it = by_elem.find(A.e);
       if (it == by_elem.end()) continue;
-      const Basis1D& Ba = basis(M.p[A.e]);
-      int n = A.n;
-      int sidx = A.s ? n - 1 : 0;
-      const std::vector<double>& Ds = A.s ? Ba.D1 : Ba.D0;
+      const int sidx = A.s ? A.n - 1 : 0;
       for (auto [r, a] : it->second) {
-        int i[3];
-        multi_index(r, n, d, i);
-        std::vector<double> ju(nQ), fu(nQ);
-        for (int g = 0; g < nQ; ++g) {
-          int gg = g;
-          double t = 1.0;
-          for (int j = 0; j < Q.nt; ++j) { t *= A.Lt[j][(gg % Q.q) * n + i[Q.tdim[j]]]; gg /= Q.q; }
-          ju[g] = (i[Q.m] == sidx ? t : 0.0) * A.js;
-          fu[g] = t * Ds[i[Q.m]] / M.h[A.e] * A.ca * M.k[A.e];
-        }
-        pos.push_back(a);
-        Ju.push_back(std::move(ju));
-        Fu.push_back(std::move(fu));
+        Col c;
+        c.a = a;
+        multi_index(r, A.n, d, c.i);
+        cols[x].push_back(c);
+        any = true;
+        anyon |= c.i[Q.m] == sidx;
       }
     }
-    if (pos.empty()) continue;
-    double sig = penalty_or_br2(M, o, f, eta2);
-    size_t nc = pos.size();
-    // -[[u]] {k du/dn} - {k dv/dn} [[v]] (+ sigma [[u]][[v]]): the jump of a
-    // column vanishes unless its node lies on the face, so only those rows
-    // carry the consistency terms, and a face without them adds nothing
-    std::vector<size_t> onf;
-    for (size_t a = 0; a < nc; ++a)
-      for (int g = 0; g < nQ; ++g)
-        if (Ju[a][g] != 0.0) { onf.push_back(a); break; }
-    if (onf.empty()) continue;
-    for (size_t a : onf)
-      for (size_t b = 0; b < nc; ++b) {
-        double s = 0;
-        for (int g = 0; g < nQ; ++g) s += W[g] * Ju[a][g] * Fu[b][g];
-        S[pos[a] * nb + pos[b]] -= s;
-        S[pos[b] * nb + pos[a]] -= s;
-      }
-    if (o.form == 0)
-      for (size_t a : onf)
-        for (size_t b : onf) {
-          double s = 0;
-          for (int g = 0; g < nQ; ++g) s += W[g] * sig * Ju[a][g] * Ju[b][g];
-          S[pos[a] * nb + pos[b]] += s;
+    // the jump of a column vanishes unless its node lies on the face, so a
+    // face without such columns adds nothing
+    if (!any || !anyon) continue;
+    const double sig = penalty_or_br2(M, o, f, eta2);
+    // C[x][y][j]: n_x x n_y
+    std::vector<double> C[2][2][2];
+    for (int x = 0; x < ns; ++x)
+      for (int y = 0; y < ns; ++y)
+        for (int j = 0; j < Q.nt; ++j) {
+          const int nx = Q.sides[x].n, ny = Q.sides[y].n;
+          std::vector<double>& c = C[x][y][j];
+          c.assign((size_t)nx * ny, 0.0);
+          for (int g = 0; g < Q.q; ++g) {
+            const double w = Q.wt[j][g];
+            const double* lx = &Q.sides[x].Lt[j][g * nx];
+            const double* ly = &Q.sides[y].Lt[j][g * ny];
+            for (int i = 0; i < nx; ++i)
+              for (int i2 = 0; i2 < ny; ++i2) c[i * ny + i2] += w * lx[i] * ly[i2];
+          }
         }
-    if (o.form == 1) {
-      // c_e^2 eta g_K(u)' M_K^{-1} g_K(v) per side K: g_K(u) is nonzero only
-      // for the columns with a nonzero jump, and M_K^{-1} on the side nodes is
-      // the Kronecker product of the two tangential 1D inverse mass matrices
-      // (times the normal one's diagonal entry and h^-d)
+    auto prodC = [&](const std::vector<double>* cj, int ny, const int* ia, const int* ib) {
+      double t = 1.0;
+      for (int j = 0; j < Q.nt; ++j) t *= cj[j][ia[Q.tdim[j]] * ny + ib[Q.tdim[j]]];
+      return t;
+    };
+    // consistency and symmetry terms
+    for (int x = 0; x < ns; ++x) {
+      const FaceSide& X = Q.sides[x];
+      const int sx = X.s ? X.n - 1 : 0;
+      for (int y = 0; y < ns; ++y) {
+        const FaceSide& Y = Q.sides[y];
+        const Basis1D& By = basis(M.p[Y.e]);
+        const std::vector<double>& Dy = Y.s ? By.D1 : By.D0;
+        const double fy = Y.ca * M.k[Y.e] / M.h[Y.e];
+        for (const Col& ca : cols[x]) {
+          if (ca.i[Q.m] != sx) continue;
+          for (const Col& cb : cols[y]) {
+            const double v = X.js * Dy[cb.i[Q.m]] * fy * prodC(C[x][y], Y.n, ca.i, cb.i);
+            S[(size_t)ca.a * nb + cb.a] -= v;
+            S[(size_t)cb.a * nb + ca.a] -= v;
+          }
+        }
+      }
+    }
+    if (o.form == 0) {
+      for (int x = 0; x < ns; ++x) {
+        const FaceSide& X = Q.sides[x];
+        const int sx = X.s ? X.n - 1 : 0;
+        for (int y = 0; y < ns; ++y) {
+          const FaceSide& Y = Q.sides[y];
+          const int sy = Y.s ? Y.n - 1 : 0;
+          for (const Col& ca : cols[x]) {
+            if (ca.i[Q.m] != sx) continue;
+            for (const Col& cb : cols[y]) {
+              if (cb.i[Q.m] != sy) continue;
+              S[(size_t)ca.a * nb + cb.a] += sig * X.js * Y.js * prodC(C[x][y], Y.n, ca.i, cb.i);
+            }
+          }
+        }
+      }
+    } else {
       const double c2 = f.ep >= 0 ? 0.25 : 1.0;
-      const size_t no = onf.size();
-      for (const FaceSide& K : Q.sides) {
+      for (int k = 0; k < ns; ++k) {
+        const FaceSide& K = Q.sides[k];
         const Basis1D& Bk = basis(M.p[K.e]);
         const int nk = K.n;
-        int nsn = 1;
-        for (int j = 0; j < Q.nt; ++j) nsn *= nk;
-        // G[r][c] = sum_Q V_K[Q,r] W Ju[onf[c]]; r over K's side nodes
-        std::vector<double> G((size_t)nsn * no, 0.0);
-        for (int r = 0; r < nsn; ++r) {
-          int rt[2] = {r % nk, r / nk};
-          for (size_t c = 0; c < no; ++c) {
-            const std::vector<double>& ju = Ju[onf[c]];
-            double s = 0;
-            for (int g = 0; g < nQ; ++g) {
-              int gg = g;
-              double v = 1.0;
-              for (int j = 0; j < Q.nt; ++j) { v *= K.Lt[j][(gg % Q.q) * nk + rt[j]]; gg /= Q.q; }
-              s += v * W[g] * ju[g];
-            }
-            G[(size_t)r * no + c] = s;
-          }
-        }
         const int sk = K.s ? nk - 1 : 0;
         const double mk = Bk.Minv[sk * nk + sk] * std::pow(M.h[K.e], -d);
-        // H = (Minv x Minv) G, one tangential direction at a time
-        std::vector<double> Hm = G;
-        for (int j = 0; j < Q.nt; ++j) {
-          std::vector<double> T((size_t)nsn * no, 0.0);
-          const int st = j == 0 ? 1 : nk;
-          for (int r2 = 0; r2 < nsn; ++r2) {
-            const int a2 = (r2 / st) % nk;
-            const int rb = r2 - a2 * st;
-            for (int a1 = 0; a1 < nk; ++a1) {
-              const double mi = Bk.Minv[a1 * nk + a2];
-              if (mi == 0.0) continue;
-              const double* src = &Hm[(size_t)(rb + a1 * st) * no];
-              double* dst = &T[(size_t)r2 * no];
-              for (size_t c = 0; c < no; ++c) dst[c] += mi * src[c];
+        // L[x][y][j] = C_j^{Kx}' Minv_K C_j^{Ky}
+        std::vector<double> L[2][2][2];
+        for (int x = 0; x < ns; ++x)
+          for (int y = 0; y < ns; ++y)
+            for (int j = 0; j < Q.nt; ++j) {
+              const int nx = Q.sides[x].n, ny = Q.sides[y].n;
+              const std::vector<double>& ckx = C[k][x][j];
+              const std::vector<double>& cky = C[k][y][j];
+              std::vector<double> mc((size_t)nk * ny, 0.0);   // Minv C^{Ky}
+              for (int r = 0; r < nk; ++r)
+                for (int r2 = 0; r2 < nk; ++r2) {
+                  const double mi = Bk.Minv[r * nk + r2];
+                  for (int i2 = 0; i2 < ny; ++i2) mc[r * ny + i2] += mi * cky[r2 * ny + i2];
+                }
+              std::vector<double>& l = L[x][y][j];
+              l.assign((size_t)nx * ny, 0.0);
+              for (int r = 0; r < nk; ++r)
+                for (int i = 0; i < nx; ++i) {
+                  const double cv = ckx[r * nx + i];
+                  for (int i2 = 0; i2 < ny; ++i2) l[i * ny + i2] += cv * mc[r * ny + i2];
+                }
+            }
+        for (int x = 0; x < ns; ++x) {
+          const FaceSide& X = Q.sides[x];
+          const int sx = X.s ? X.n - 1 : 0;
+          for (int y = 0; y < ns; ++y) {
+            const FaceSide& Y = Q.sides[y];
+            const int sy = Y.s ? Y.n - 1 : 0;
+            const double w = c2 * sig * mk * X.js * Y.js;
+            for (const Col& ca : cols[x]) {
+              if (ca.i[Q.m] != sx) continue;
+              for (const Col& cb : cols[y]) {
+                if (cb.i[Q.m] != sy) continue;
+                S[(size_t)ca.a * nb + cb.a] += w * prodC(L[x][y], Y.n, ca.i, cb.i);
+              }
             }
           }
-          Hm.swap(T);
         }
-        const double w = mk * c2 * sig;
-        for (size_t a = 0; a < no; ++a)
-          for (size_t b = 0; b < no; ++b) {
-            double s = 0;
-            for (int r = 0; r < nsn; ++r) s += Hm[(size_t)r * no + a] * G[(size_t)r * no + b];
-            S[pos[onf[a]] * nb + pos[onf[b]]] += w * s;
-          }
       }
     }
   }
