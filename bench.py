@@ -33,9 +33,9 @@ HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
 # for a 256 MiB copy: 2.0 and 1.0), valid for the kernel source with this
 # digest; reported as null once the source differs
 ELEM2D_TRAFFIC = {"digest": "7c863440eab2e8be", "fetch_bytes": 5669344.3, "write_bytes": 1241952.0}
-# the same for the 3D element kernel on the 2,569,985-DOF 3D workload
-# (profiles/random3d_2.57Mdof_hbm_counters.md)
-ELEM3D_TRAFFIC = {"digest": "e407d62595c2ca0d", "fetch_bytes": 68.39e6, "write_bytes": 34.23e6}
+# the same for the one-RHS 3D operator (its three kernels summed) on the
+# 2,569,985-DOF 3D workload (profiles/random3d_2.57Mdof_hbm_counters.md)
+ELEM3D_TRAFFIC = {"digest": "05a12fa245f1bad1", "fetch_bytes": 297.05e6, "write_bytes": 142.79e6}
 WORKLOADS = {1: "uniform2d_4x4_p2_sipg_fp64",
              2: "random2d_32x32_q0.3_L3_p1-8_sipg_fp64",
              3: "random3d_16^3_q0.2_L2_p1-6_br2_fp32prec",
@@ -180,6 +180,8 @@ def main():
     achieved = algo_bytes / t_apply / 1e9
     it = infos[0]["iters"]
     kernel = ("k_elem2d (volume + all face terms, one launch)" if md["dim"] == 2
+              else "DG apply in three launches: k_e3_vol (volume, side traces), k_e3_face (one face record "
+                   "per wavefront), k_e3_lift (side sums lifted into y)" if nrhs == 1
               else "k_elem3d (volume + all face terms, one launch)")
 
     scaled = apply_scaled(cfg, c) if cfg == 2 else None
@@ -365,9 +367,10 @@ def elem2d_digest():
 
 
 def elem3d_digest():
-    """Digest of the 3D element kernel's code and the device data layout
-    (comments stripped)."""
-    return kernel_digest("// 3D element kernel:", "void k_elem3d(")
+    """Digest of the one-RHS 3D operator's three kernels and the device data
+    layout (comments stripped)."""
+    return kernel_digest("// ---------------------------------------------- 3D operator in three passes",
+                         "void k_e3_lift(")
 
 
 def kernel_digest(start, sig):

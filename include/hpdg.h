@@ -182,7 +182,9 @@ hpdg_status hpdg_operator_device_bytes(hpdg_operator* op, int64_t* bytes);
  * 16 or 32); the results do not depend on them. report: cap rows of 8 int64
  * (kind 0 A / 1 R / 2 P / 3 P^T / 4 element kernel / 5 fused V-cycle level /
  * 6 right-hand sides per element-kernel item, at the largest nrhs /
- * 7 lanes per V_e block row in the B front (one RHS) / 8 dense tail of the
+ * 7 lanes per V_e block row for the one-RHS block solves (the threshold
+ * column holds 1 when they run as a workgroup per block with the block's r
+ * staged in LDS, 0 when their rows run inside the B front) / 8 dense tail of the
  * V-cycle on the level above the coarsest (chosen lanes 1 if kept) / 10 3D
  * element kernel dispatched by decreasing element cost (chosen lanes 1 if
  * kept; the threshold column holds the ns of that order),

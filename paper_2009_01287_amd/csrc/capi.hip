@@ -218,6 +218,9 @@ struct hpdg_operator {
   int64_t g_n = 0;
   int max_blk = 0;           // largest V_e block
   int lprb = 16;             // lanes per V_e block row in the B front (one RHS)
+  int blk_wg = 1;            // one RHS: V_e solves by k_block_rows (a workgroup per block, r staged in
+                             // LDS) instead of the row-parallel part of the B front
+  DevBuf blk_order;          // blocks by decreasing size (k_block_rows)
   int no_mfma = 0;           // HPDG_NO_MFMA=1: V_e block solves for many RHS without the matrix cores
   int no_fused_multi = 0;    // HPDG_NO_FUSED_MULTI=1: fused V-cycle levels for one RHS only
   DevCSR P, PT;
@@ -542,6 +545,7 @@ static void upload_prec(hpdg_operator* op) {
   for (auto& B : H.blocks) op->max_blk = std::max(op->max_blk, (int)B.size());
   op->blk_rowb.upload(rowb);
   op->blk_rowl.upload(rowl);
+  op->blk_order.upload(border);
   op->blk_ptr.upload(bptr);
   op->blk_off.upload(boff);
   op->blk_dof.upload(bdof);
@@ -962,6 +966,7 @@ extern "C" hpdg_status hpdg_setup_operator(const hpdg_mesh* mh, const hpdg_opera
     if (const char* v = std::getenv("HPDG_NO_FUSED_MULTI")) op->no_fused_multi = std::atoi(v) != 0;
     if (const char* v = std::getenv("HPDG_ELEM3D_COST_ORDER")) op->use_perm = std::atoi(v) != 0;
     if (const char* v = std::getenv("HPDG_ELEM3D_SPLIT")) op->split3 = std::atoi(v) != 0;
+    if (const char* v = std::getenv("HPDG_BLOCK_WG")) op->blk_wg = std::atoi(v) != 0;
     if (const char* v = std::getenv("HPDG_ELEM3D_STAGE")) op->e3stage = std::atoi(v) != 0;
     if (const char* v = std::getenv("HPDG_CG_SEPARATE_FINALS")) op->cg_separate = std::atoi(v) != 0;
     if (const char* v = std::getenv("HPDG_PRESPLIT_NNZ")) op->presplit_nnz = std::max<int64_t>(-1, std::atoll(v));
@@ -1548,22 +1553,27 @@ static int tune_all(hpdg_operator* op, hipStream_t s, int64_t* report, int cap) 
       HIPCHK(hipEventElapsedTime(&ms, f0, f1));
       return (double)ms * 1e6 / 10;
     };
-    const int def = op->lprb;
+    // lanes per row, for the rows of all blocks in the front kernel and for
+    // a workgroup per block (k_block_rows)
+    const int def = op->lprb, def_wg = op->blk_wg;
     const double t_def = time_front();
     double best = t_def * kTuneMargin;
-    int bb = def;
-    for (int lb : {1, 2, 4, 8, 16, 32}) {
-      if (lb == def) continue;
-      op->lprb = lb;
-      const double t = time_front();
-      if (t < best) { best = t; bb = lb; }
-    }
-    if (bb == def) best = t_def;
+    int bb = def, bw = def_wg;
+    for (int wgm : {1, 0})
+      for (int lb : {1, 2, 4, 8, 16, 32}) {
+        if (lb == def && wgm == def_wg) continue;
+        op->lprb = lb;
+        op->blk_wg = wgm;
+        const double t = time_front();
+        if (t < best) { best = t; bb = lb; bw = wgm; }
+      }
+    if (bb == def && bw == def_wg) best = t_def;
     op->lprb = bb;
+    op->blk_wg = bw;
     (void)hipEventDestroy(f0);
     (void)hipEventDestroy(f1);
     int64_t* r = slot(7, 0);
-    r[0] = op->blk_rows; r[1] = op->nblocks; r[2] = 0; r[3] = bb;
+    r[0] = op->blk_rows; r[1] = op->nblocks; r[2] = bw; r[3] = bb;
     r[4] = (int64_t)t_def; r[5] = (int64_t)best;
   }
   for (size_t l = 0; l < op->lv.size(); ++l) {
@@ -1681,12 +1691,14 @@ static void launch_front(hpdg_operator* op, const T* rt, T* zb, T* bc0, hipStrea
   const int nb_diag = (int)nblk(op->ndof);
   const int nlb = (A.nlong + 3) / 4;
   const int nshort = A.nrows - A.nlong;
+  const bool wg = op->blk_wg && op->nblocks > 0 && (size_t)op->max_blk * sizeof(T) <= 64 * 1024;
+  const int64_t brows = wg ? 0 : op->blk_rows;   // block solves in k_block_rows instead
   auto launch = [&](auto lprb, auto lprp) {
     constexpr int LB = decltype(lprb)::value, LP = decltype(lprp)::value;
-    const int nb_blk = (int)nblk(op->blk_rows * LB);
+    const int nb_blk = (int)nblk(brows * LB);
     unsigned grid = (unsigned)(nb_diag + nb_blk + nlb + (int)nblk((int64_t)nshort * LP));
     hipLaunchKernelGGL((k_front<T, LB, LP>), dim3(grid), dim3(256), 0, s, op->ndof, nb_diag, op->dinvJ.as<T>(),
-                       op->blk_rows, nb_blk, op->blk_rowb.as<int32_t>(), op->blk_rowl.as<int32_t>(),
+                       brows, nb_blk, op->blk_rowb.as<int32_t>(), op->blk_rowl.as<int32_t>(),
                        op->blk_ptr.as<int64_t>(), op->blk_off.as<int64_t>(), op->blk_dof.as<int32_t>(),
                        blk_out(op), op->blk_inv.as<T>(), A.nlong, nlb, nshort, A.rows.as<int32_t>(), A.ptr.as<int32_t>(),
                        A.idx.as<int32_t>(), A.val.as<T>(), rt, zb, bc0);
@@ -1707,6 +1719,23 @@ static void launch_front(hpdg_operator* op, const T* rt, T* zb, T* bc0, hipStrea
     case 8: with_lprp(std::integral_constant<int, 8>()); break;
     case 32: with_lprp(std::integral_constant<int, 32>()); break;
     default: with_lprp(std::integral_constant<int, 16>()); break;
+  }
+  if (wg) {
+    const size_t shm = (size_t)op->max_blk * sizeof(T);
+    auto lb = [&](auto lpr) {
+      constexpr int L = decltype(lpr)::value;
+      hipLaunchKernelGGL((k_block_rows<T, L>), dim3((unsigned)op->nblocks), dim3(256), shm, s, (int)op->nblocks,
+                         op->blk_order.as<int32_t>(), op->blk_ptr.as<int64_t>(), op->blk_off.as<int64_t>(),
+                         op->blk_dof.as<int32_t>(), blk_out(op), op->blk_inv.as<T>(), rt, zb);
+    };
+    switch (op->lprb) {
+      case 1: lb(std::integral_constant<int, 1>()); break;
+      case 2: lb(std::integral_constant<int, 2>()); break;
+      case 4: lb(std::integral_constant<int, 4>()); break;
+      case 8: lb(std::integral_constant<int, 8>()); break;
+      case 32: lb(std::integral_constant<int, 32>()); break;
+      default: lb(std::integral_constant<int, 16>()); break;
+    }
   }
 }
 

@@ -2033,6 +2033,38 @@ __global__ __launch_bounds__(256) void k_block_mfma(int nblocks, int nrhs, const
   }
 }
 
+// exact V_e solves for one RHS, one workgroup per block (blocks listed by
+// order[], largest first): the block's r values are gathered into LDS once,
+// then LPR lanes per row stream the row of the stored inverse against them
+// and add their parts in a fixed order. Dynamic LDS: m_max values.
+template <typename T, int LPR>
+__global__ __launch_bounds__(256) void k_block_rows(int nblocks, const int32_t* __restrict__ order,
+                                                    const int64_t* __restrict__ bptr,
+                                                    const int64_t* __restrict__ boff,
+                                                    const int32_t* __restrict__ bdof, const int32_t* __restrict__ bout,
+                                                    const T* __restrict__ binv, const T* __restrict__ r,
+                                                    T* __restrict__ z) {
+  extern __shared__ unsigned char blk_lds[];
+  T* rl = reinterpret_cast<T*>(blk_lds);
+  if ((int)blockIdx.x >= nblocks) return;
+  const int b = order[blockIdx.x];
+  const int64_t s0 = bptr[b];
+  const int m = (int)(bptr[b + 1] - s0);
+  for (int t = threadIdx.x; t < m; t += 256) rl[t] = r[bdof[s0 + t]];
+  __syncthreads();
+  const T* B = binv + boff[b];
+  const int sub = (int)(threadIdx.x % LPR);
+  for (int i = (int)(threadIdx.x / LPR); i < m; i += 256 / LPR) {
+    const T* row = B + (int64_t)i * m;
+    T acc = 0;
+#pragma unroll 4
+    for (int j = sub; j < m; j += LPR) acc += row[j] * rl[j];
+#pragma unroll
+    for (int o = LPR / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, LPR);
+    if (sub == 0) z[bout[s0 + i]] = acc;
+  }
+}
+
 // overlapping V_e (3D): the block solves write one slot per block row past
 // the DG vector; every N-DOF then sums the slots of the blocks that hold it,
 // in block order (fixed, so results do not depend on scheduling):
