@@ -233,7 +233,8 @@ hpdg_status hpdg_batch_poll(hpdg_batch* bt, int cap, int64_t* tags, int* status,
  *    idx[nnz] int32, val[nnz] double
  *  3 A~_C as CSR (same layout)  4 V_e blocks: int64 nblocks, ptr[nb+1] int64,
  *    dofs int64                 5 DG node coordinates [ndof*dim] double
- *  6 AMG level sizes: int64 nlevels, rows[nlevels] int64
+ *  6 AMG level sizes: int64 nlevels, rows[nlevels], nnz of A[nlevels], nnz of
+ *    the prolongation from the next coarser level[nlevels] (0 on the coarsest)
  *  7 summary: int64[10] = ndof, nconf, nblocks, max block, block entries,
  *    amg levels, nnz(A~_C), nnz(P), bytes of the face-matrix table, device
  *    bytes held by the operator

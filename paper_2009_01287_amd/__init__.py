@@ -281,6 +281,12 @@ class Operator:
         v = self.export(6).view(np.int64)
         return v[1:1 + int(v[0])].tolist()
 
+    def amg_level_stats(self):
+        """(rows, nnz of A, nnz of P) per AMG level, finest first."""
+        v = self.export(6).view(np.int64)
+        n = int(v[0])
+        return list(zip(*(v[1 + k * n:1 + (k + 1) * n].tolist() for k in range(3))))
+
     def summary(self):
         keys = ["ndof", "nconf", "nblocks", "max_block", "block_entries", "amg_levels", "nnz_AC", "nnz_P",
                 "face_table_bytes", "device_bytes"]

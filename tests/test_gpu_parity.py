@@ -125,6 +125,60 @@ def test_high_degree_3d_apply_A_and_B(form):
     assert _rel(_host(z), pc.apply(x)) <= 1e-12
 
 
+@pytest.mark.parametrize("name", ["hang3", "rand3hp"])
+@pytest.mark.parametrize("split,stage", [("0", "1"), ("1", "0"), ("1", "1")])
+def test_3d_apply_forms_match_oracle(monkeypatch, name, split, stage):
+    """The 3D operator with one RHS as one element kernel (split 0) or in
+    three passes (volume and side traces, one face record per wavefront,
+    side sums lifted per element), with the face pass's 1D matrices staged
+    in LDS or read through the caches: each against the oracle, the two
+    staging forms bitwise alike, and CG's fused x'y shares through a solve."""
+    monkeypatch.setenv("HPDG_ELEM3D_SPLIT", split)
+    monkeypatch.setenv("HPDG_ELEM3D_STAGE", stage)
+    md = MESHES[name]()
+    m = O.Mesh(md)
+    x = np.random.default_rng(14).standard_normal(m.ndof)
+    for form, eta in (("sipg", 1.0), ("br2", 0.0)):
+        op = G.Operator(G.Mesh(md), form=form, eta=eta)
+        y = torch.empty(m.ndof, dtype=torch.float64, device="cuda")
+        op.apply_A(_dev(x), y)
+        assert _rel(_host(y), dg.apply(m, O.Opts(form, 0, eta), x)) <= 1e-12
+        if split == "1":
+            monkeypatch.setenv("HPDG_ELEM3D_STAGE", "0" if stage == "1" else "1")
+            y2 = torch.empty_like(y)
+            G.Operator(G.Mesh(md), form=form, eta=eta).apply_A(_dev(x), y2)
+            monkeypatch.setenv("HPDG_ELEM3D_STAGE", stage)
+            assert torch.equal(y, y2)
+    b = torch.empty_like(y)
+    op.rhs(_dev(x), b)
+    xs = torch.zeros_like(b)
+    info = op.pcg_solve(b, xs, rtol=1e-8, maxit=1000)[0]
+    assert info["converged"] and info["true_rel_res"] <= 1e-8
+
+
+@pytest.mark.parametrize("name", ["rand2", "hang3", "rand3hp"])
+@pytest.mark.parametrize("wg,lanes", [("0", "4"), ("0", "32"), ("1", "1"), ("1", "4"), ("1", "32")])
+@pytest.mark.parametrize("fp32", [False, True])
+def test_block_solve_forms(monkeypatch, name, wg, lanes, fp32):
+    """The V_e block solves for one RHS by rows of all blocks inside the B
+    front (wg 0) or by a workgroup per block with its r gathered in LDS
+    (wg 1), at several lanes per row; 3D face spaces overlap, so their slots
+    are summed per DOF afterwards. FP64 against the oracle; FP32 against the
+    FP64 operator at the FP32 preconditioner's rounding."""
+    monkeypatch.setenv("HPDG_BLOCK_WG", wg)
+    monkeypatch.setenv("HPDG_BLOCK_LANES", lanes)
+    md = MESHES[name]()
+    m = O.Mesh(md)
+    form = "br2" if m.dim == 3 else "sipg"
+    eta = 0.0 if form == "br2" else 1.0
+    op = G.Operator(G.Mesh(md), form=form, eta=eta, prec_fp32=fp32)
+    r = np.random.default_rng(15).standard_normal(m.ndof)
+    z = torch.empty(m.ndof, dtype=torch.float64, device="cuda")
+    op.apply_B(_dev(r), z)
+    zo = precond.Preconditioner(m, O.Opts(form, 0, eta)).apply(r)
+    assert _rel(_host(z), zo) <= (1e-5 if fp32 else 1e-12)
+
+
 @pytest.mark.parametrize("name", ["hang2", "hang3"])
 def test_rhs_matches_oracle(name):
     md = MESHES[name]()
