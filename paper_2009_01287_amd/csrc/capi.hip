@@ -100,27 +100,48 @@ struct DevCSR {
   int longrow = 32;
   DevBuf ptr, idx, val, rows;  // rows: long rows first, then short rows
 };
-constexpr int kLongRow = 32;
+constexpr int kLongRow = 128;   // entries (32 four-entry chunks)
 
 void bin_rows(const CSR& A, DevCSR& D, int longrow, int lpr);
 
+// Device CSR: every row padded to a multiple of 4 entries (value 0, column
+// of the row's last entry), so that the one-RHS product reads 4-entry
+// chunks with vector loads; kernels that walk a row entry by entry add the
+// padding's zero products and get the same sums.
 template <typename T>
 void upload_csr(const CSR& A, DevCSR& D) {
-  if (A.idx.size() > (size_t)INT32_MAX) throw Error(HPDG_E_UNSUPPORTED, "matrix too large");
-  D.nrows = (int)A.nrows;
+  const int64_t n = A.nrows;
+  std::vector<int32_t> p32((size_t)n + 1);
+  int64_t tot = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    p32[i] = (int32_t)tot;
+    tot += (A.ptr[i + 1] - A.ptr[i] + 3) & ~(int64_t)3;
+    if (tot > (int64_t)INT32_MAX) throw Error(HPDG_E_UNSUPPORTED, "matrix too large");
+  }
+  p32[n] = (int32_t)tot;
+  std::vector<int32_t> idx((size_t)tot, 0);
+  std::vector<T> v((size_t)tot, T(0));
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t o = p32[i];
+    for (int64_t q = A.ptr[i]; q < A.ptr[i + 1]; ++q, ++o) {
+      idx[o] = A.idx[q];
+      v[o] = (T)A.val[q];
+    }
+    const int32_t last = A.ptr[i + 1] > A.ptr[i] ? A.idx[A.ptr[i + 1] - 1] : 0;
+    for (; o < p32[i + 1]; ++o) idx[o] = last;
+  }
+  D.nrows = (int)n;
   D.ncols = (int)A.ncols;
   D.nnz = (int64_t)A.idx.size();
-  std::vector<int32_t> p32(A.ptr.begin(), A.ptr.end());
-  std::vector<T> v(A.val.begin(), A.val.end());
   D.ptr.upload(p32);
-  D.idx.upload(A.idx);
+  D.idx.upload(idx);
   D.val.upload(v);
   bin_rows(A, D, kLongRow, 0);
 }
 
 // Row binning of a CSR matrix for the one-RHS kernels: rows longer than
-// `longrow` get one wavefront each (listed first), the others `lpr` lanes
-// (0: from the average length of the short rows).
+// `longrow` entries get one wavefront each (listed first), the others `lpr`
+// lanes (0: from the average number of 4-entry chunks of the short rows).
 void bin_rows(const CSR& A, DevCSR& D, int longrow, int lpr) {
   std::vector<int32_t> lr, sr;
   int64_t snnz = 0;
@@ -133,7 +154,7 @@ void bin_rows(const CSR& A, DevCSR& D, int longrow, int lpr) {
   D.longrow = longrow;
   lr.insert(lr.end(), sr.begin(), sr.end());
   D.rows.upload(lr);
-  double avg = sr.empty() ? 0.0 : (double)snnz / (double)sr.size();
+  double avg = sr.empty() ? 0.0 : 0.25 * (double)snnz / (double)sr.size();
   D.lpr = lpr > 0 ? lpr : avg > 12 ? 16 : avg > 6 ? 8 : avg > 2.5 ? 4 : avg > 1.5 ? 2 : 1;
 }
 
@@ -515,6 +536,24 @@ static void set_fused(hpdg_operator* op, size_t l, bool on) {
 // the V_e overlap
 static int64_t zt_rows(const hpdg_operator* op) { return op->ndof + (op->blk_overlap ? op->blk_rows : 0); }
 
+// the stored inverses (host: blocks packed m x m one after another) in the
+// device layout, rows padded to blk_ld(m) entries
+template <typename T>
+static std::vector<T> padded_blocks(const std::vector<std::vector<int64_t>>& blocks, const std::vector<double>& binv) {
+  size_t tot = 0;
+  for (auto& B : blocks) tot += B.size() * (size_t)blk_ld((int)B.size());
+  std::vector<T> out(tot, T(0));
+  size_t so = 0, d = 0;
+  for (auto& B : blocks) {
+    const int m = (int)B.size(), ld = blk_ld(m);
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) out[d + (size_t)i * ld + j] = (T)binv[so + (size_t)i * m + j];
+    so += (size_t)m * m;
+    d += (size_t)m * ld;
+  }
+  return out;
+}
+
 template <typename T>
 static void upload_prec(hpdg_operator* op) {
   PrecHost& H = op->host;
@@ -529,7 +568,7 @@ static void upload_prec(hpdg_operator* op) {
     int m = (int)B.size();
     for (int i = 0; i < m; ++i) bdof.push_back((int32_t)B[i]);
     bptr.push_back(bptr.back() + m);
-    boff.push_back(boff.back() + (int64_t)m * m);
+    boff.push_back(boff.back() + (int64_t)m * blk_ld(m));
   }
   // the row list of the row-parallel block solves: largest blocks first (their
   // rows take longest), the rows of a block together
@@ -718,11 +757,10 @@ static void upload_device(hpdg_operator* op, hipStream_t s) {
   if (op->no_prec) {
   } else if (op->prec32) {
     upload_prec<float>(op);
-    std::vector<float> bi(U.binv.begin(), U.binv.end());
-    op->blk_inv.upload(bi);
+    op->blk_inv.upload(padded_blocks<float>(op->host.blocks, U.binv));
   } else {
     upload_prec<double>(op);
-    op->blk_inv.upload(U.binv);
+    op->blk_inv.upload(padded_blocks<double>(op->host.blocks, U.binv));
   }
   const int64_t hs = op->max_nrhs;
   size_t nv = (size_t)op->ndof * hs * sizeof(double);
@@ -967,6 +1005,10 @@ extern "C" hpdg_status hpdg_setup_operator(const hpdg_mesh* mh, const hpdg_opera
     if (const char* v = std::getenv("HPDG_ELEM3D_COST_ORDER")) op->use_perm = std::atoi(v) != 0;
     if (const char* v = std::getenv("HPDG_ELEM3D_SPLIT")) op->split3 = std::atoi(v) != 0;
     if (const char* v = std::getenv("HPDG_BLOCK_WG")) op->blk_wg = std::atoi(v) != 0;
+    if (const char* v = std::getenv("HPDG_BLOCK_LANES")) {
+      const int l = std::atoi(v);
+      op->lprb = (l == 1 || l == 2 || l == 4 || l == 8 || l == 32) ? l : 16;
+    }
     if (const char* v = std::getenv("HPDG_ELEM3D_STAGE")) op->e3stage = std::atoi(v) != 0;
     if (const char* v = std::getenv("HPDG_CG_SEPARATE_FINALS")) op->cg_separate = std::atoi(v) != 0;
     if (const char* v = std::getenv("HPDG_PRESPLIT_NNZ")) op->presplit_nnz = std::max<int64_t>(-1, std::atoll(v));
@@ -1385,7 +1427,7 @@ static void tune_csr(const CSR& H, DevCSR& D, const T* x, T* y, hipStream_t s, i
   const double t_def = time_it();
   double best = t_def * kTuneMargin;
   int bl = def_long, bp = def_lpr;
-  for (int longrow : {32, 64, 128, 1 << 30})
+  for (int longrow : {64, 128, 256, 512, 1 << 30})
     for (int lpr : {1, 2, 4, 8, 16}) {
       bin_rows(H, D, longrow, lpr);
       const double t = time_it();
@@ -1691,7 +1733,7 @@ static void launch_front(hpdg_operator* op, const T* rt, T* zb, T* bc0, hipStrea
   const int nb_diag = (int)nblk(op->ndof);
   const int nlb = (A.nlong + 3) / 4;
   const int nshort = A.nrows - A.nlong;
-  const bool wg = op->blk_wg && op->nblocks > 0 && (size_t)op->max_blk * sizeof(T) <= 64 * 1024;
+  const bool wg = op->blk_wg && op->nblocks > 0 && (size_t)blk_ld(op->max_blk) * sizeof(T) <= 64 * 1024;
   const int64_t brows = wg ? 0 : op->blk_rows;   // block solves in k_block_rows instead
   auto launch = [&](auto lprb, auto lprp) {
     constexpr int LB = decltype(lprb)::value, LP = decltype(lprp)::value;
@@ -1721,7 +1763,7 @@ static void launch_front(hpdg_operator* op, const T* rt, T* zb, T* bc0, hipStrea
     default: with_lprp(std::integral_constant<int, 16>()); break;
   }
   if (wg) {
-    const size_t shm = (size_t)op->max_blk * sizeof(T);
+    const size_t shm = (size_t)blk_ld(op->max_blk) * sizeof(T);
     auto lb = [&](auto lpr) {
       constexpr int L = decltype(lpr)::value;
       hipLaunchKernelGGL((k_block_rows<T, L>), dim3((unsigned)op->nblocks), dim3(256), shm, s, (int)op->nblocks,
@@ -2423,6 +2465,8 @@ extern "C" hpdg_status hpdg_export(const hpdg_operator* op, int what, void* buf,
     case 6: {
       std::vector<int64_t> v{(int64_t)H.amg.lv.size()};
       for (auto& L : H.amg.lv) v.push_back(L.A.nrows);
+      for (auto& L : H.amg.lv) v.push_back((int64_t)L.A.idx.size());
+      for (auto& L : H.amg.lv) v.push_back((int64_t)L.P.idx.size());
       return put(v.data(), v.size(), buf, bytes);
     }
     case 7: {

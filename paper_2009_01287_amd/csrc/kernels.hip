@@ -1303,8 +1303,16 @@ __device__ inline void e3f_body(const FaceRec& r, const FaceAux& ax, int form, d
   const double csym = inner ? 0.5 : 1.0;
   const double k = ax.k;
   // stage 2: v, the average and the penalty on the own side nodes; BR2: the
-  // neighbour's jump vn = (A0on x A1on)^T To - (A0nn x A1nn) Tn
-  for (int q = lane; q < n2; q += 64) {
+  // neighbour's jump vn = (A0on x A1on)^T To - (A0nn x A1nn) Tn. The
+  // record's results g1, g2 stay in registers (node q = lane + 64 t in slot t)
+  constexpr int QN = (n2 + 63) / 64;
+  double G1[QN], G2[QN];
+#pragma unroll
+  for (int t = 0; t < QN; ++t) G1[t] = G2[t] = 0.0;
+#pragma unroll
+  for (int t = 0; t < QN; ++t) {
+    const int q = lane + 64 * t;
+    if (q >= n2) break;
     const int j0 = q % n, j1 = q / n;
     const double* A1oo = MP[1];
     double v = 0.0, ds = 0.0;
@@ -1326,8 +1334,8 @@ __device__ inline void e3f_body(const FaceRec& r, const FaceAux& ax, int form, d
     }
     double g1 = -area * csym * sgn * ds;
     if (form == 0) g1 += area * r.sig * v;
-    W[8 * F2 + q] = g1;
-    W[9 * F2 + q] = -csym * k * sgn * area * v;
+    G1[t] = g1;
+    G2[t] = -csym * k * sgn * area * v;
     W[q] = v;
   }
   if (inner && form == 1) {
@@ -1386,7 +1394,10 @@ __device__ inline void e3f_body(const FaceRec& r, const FaceAux& ax, int form, d
     const double L2 = (inner ? 0.25 : 1.0) * r.sig * area * area;
     const double* L1o = MP[7];
     const double* L1n = MP[9];
-    for (int q = lane; q < n2; q += 64) {
+#pragma unroll
+    for (int t = 0; t < QN; ++t) {
+      const int q = lane + 64 * t;
+      if (q >= n2) break;
       const int j0 = q % n, j1 = q / n;
       double so_acc = 0.0, sn_acc = 0.0;
 #pragma unroll
@@ -1396,14 +1407,16 @@ __device__ inline void e3f_body(const FaceRec& r, const FaceAux& ax, int form, d
         for (int a1 = 0; a1 < NM; ++a1)
           if (a1 < no) sn_acc += L1n[j1 * no + a1] * W[3 * F2 + j0 + n * a1];
       }
-      W[8 * F2 + q] += L2 * (so * so_acc + sn * sn_acc);
+      G1[t] += L2 * (so * so_acc + sn * sn_acc);
     }
-    wave_sync();
   }
   double* g = gbuf + ax.goff;
-  for (int q = lane; q < n2; q += 64) {
-    g[q] = W[8 * F2 + q];
-    g[n2 + q] = W[9 * F2 + q];
+#pragma unroll
+  for (int t = 0; t < QN; ++t) {
+    const int q = lane + 64 * t;
+    if (q >= n2) break;
+    g[q] = G1[t];
+    g[n2 + q] = G2[t];
   }
 }
 
@@ -1417,8 +1430,7 @@ __global__ __launch_bounds__(256) void k_e3_face(int nrec, int form, const FaceR
   constexpr int F2 = NM * NM;
   __shared__ FaceRec sR[4];
   __shared__ FaceAux sAx[4];
-  __shared__ double sO[4][2][F2];     // own To, Do
-  __shared__ double sW[4][10][F2];    // 0 Tn -> v, 1 Dn -> vn, 2 U0 -> P0, 3 U1 -> Q0, 4 U2, 5 U3, 6 Y0, 7 Y1, 8 g1, 9 g2
+  __shared__ double sW[4][10][F2];    // 0 Tn -> v, 1 Dn -> vn, 2 U0 -> P0, 3 U1 -> Q0, 4 U2, 5 U3, 6 Y0, 7 Y1, 8 To, 9 Do
   __shared__ double sM[STAGE ? 4 : 1][STAGE ? 10 : 1][STAGE ? F2 : 1];   // A0oo A1oo A0on A1on A0nn A1nn L0o L1o L0n L1n
   const int w = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
   const int rec = blockIdx.x * 4 + w;
@@ -1433,8 +1445,8 @@ __global__ __launch_bounds__(256) void k_e3_face(int nrec, int form, const FaceR
   wave_sync();
   double* W = &sW[w][0][0];
   double* Mx = STAGE ? &sM[w][0][0] : nullptr;
-  double* To = sO[w][0];
-  double* Do = sO[w][1];
+  double* To = W + 8 * F2;             // last read in stage 1
+  double* Do = W + 9 * F2;
   switch (sAx[w].p) {
     case 1: e3f_body<2, NM, STAGE>(sR[w], sAx[w], form, To, Do, W, Mx, ftab, tab, TL, sb, gbuf, lane); break;
     case 2: e3f_body<3, NM, STAGE>(sR[w], sAx[w], form, To, Do, W, Mx, ftab, tab, TL, sb, gbuf, lane); break;
@@ -1737,6 +1749,21 @@ __device__ inline T spmv_src(int j, int nsplit, const T* __restrict__ x, const T
   return x[j];
 }
 
+// one 4-entry chunk of a padded row, added in entry order
+template <typename T, int MODE>
+__device__ inline T spmv_chunk(T acc, int c, int nsplit, const int4* __restrict__ idx4, const T* __restrict__ val,
+                               const T* __restrict__ x, const T* __restrict__ b, const T* __restrict__ d) {
+  typedef T v4 __attribute__((ext_vector_type(4)));
+  const int4 j = idx4[c];
+  const v4 v = reinterpret_cast<const v4*>(val)[c];
+  acc += v.x * spmv_src<T, MODE>(j.x, nsplit, x, b, d);
+  acc += v.y * spmv_src<T, MODE>(j.y, nsplit, x, b, d);
+  acc += v.z * spmv_src<T, MODE>(j.z, nsplit, x, b, d);
+  acc += v.w * spmv_src<T, MODE>(j.w, nsplit, x, b, d);
+  return acc;
+}
+
+// rows padded to multiples of 4 entries: lanes take 4-entry chunks
 template <typename T, int MODE, int LPR>
 __global__ __launch_bounds__(256) void k_spmv(int nlong, int nlong_blk, int nshort, int nsplit,
                                               const int32_t* __restrict__ rows,
@@ -1744,16 +1771,16 @@ __global__ __launch_bounds__(256) void k_spmv(int nlong, int nlong_blk, int nsho
                                               const int32_t* __restrict__ idx, const T* __restrict__ val,
                                               const T* __restrict__ x, const T* __restrict__ b,
                                               const T* __restrict__ d, T* __restrict__ xo, T* __restrict__ y) {
+  const int4* idx4 = reinterpret_cast<const int4*>(idx);
   if ((int)blockIdx.x < nlong_blk) {
     const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (w >= nlong) return;
     const int row = rows[w];
     T acc = 0;
-#pragma unroll 4
-    for (int q = ptr[row] + lane; q < ptr[row + 1]; q += 64) {
-      acc += val[q] * spmv_src<T, MODE>(idx[q], nsplit, x, b, d);
-    }
+    const int c1 = ptr[row + 1] >> 2;
+#pragma unroll 2
+    for (int c = (ptr[row] >> 2) + lane; c < c1; c += 64) acc = spmv_chunk<T, MODE>(acc, c, nsplit, idx4, val, x, b, d);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
     if (lane == 0) spmv_row_out<T, MODE>(row, acc, x, b, d, xo, y);
@@ -1765,10 +1792,9 @@ __global__ __launch_bounds__(256) void k_spmv(int nlong, int nlong_blk, int nsho
   if (r >= nshort) return;
   const int row = rows[nlong + r];
   T acc = 0;
-#pragma unroll 4
-  for (int q = ptr[row] + sub; q < ptr[row + 1]; q += LPR) {
-    acc += val[q] * spmv_src<T, MODE>(idx[q], nsplit, x, b, d);
-  }
+  const int c1 = ptr[row + 1] >> 2;
+#pragma unroll 2
+  for (int c = (ptr[row] >> 2) + sub; c < c1; c += LPR) acc = spmv_chunk<T, MODE>(acc, c, nsplit, idx4, val, x, b, d);
 #pragma unroll
   for (int o = LPR / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, LPR);
   if (sub == 0) spmv_row_out<T, MODE>(row, acc, x, b, d, xo, y);
@@ -1867,7 +1893,7 @@ __global__ __launch_bounds__(256) void k_front(int64_t ndof, int nb_diag, const 
     const int i = row_loc[rw];
     const int64_t s0 = bptr[bk];
     const int m = (int)(bptr[bk + 1] - s0);
-    const T* row = binv + boff[bk] + (int64_t)i * m;
+    const T* row = binv + boff[bk] + (int64_t)i * blk_ld(m);
     T acc = 0;
 #pragma unroll 4
     for (int j = sub; j < m; j += LPRB) acc += row[j] * r[bdof[s0 + j]];
@@ -1878,14 +1904,17 @@ __global__ __launch_bounds__(256) void k_front(int64_t ndof, int nb_diag, const 
     return;
   }
   b -= nb_blk;
+  const int4* idx4 = reinterpret_cast<const int4*>(idx);
   if (b < nlong_blk) {
     const int w = b * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (w >= nlong) return;
     const int row = rows[w];
     T acc = 0;
-#pragma unroll 4
-    for (int q = ptr[row] + lane; q < ptr[row + 1]; q += 64) acc += val[q] * r[idx[q]];
+    const int c1 = ptr[row + 1] >> 2;
+#pragma unroll 2
+    for (int c = (ptr[row] >> 2) + lane; c < c1; c += 64)
+      acc = spmv_chunk<T, 0>(acc, c, 0, idx4, val, r, nullptr, nullptr);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
     if (lane == 0) rc[row] = acc;
@@ -1898,8 +1927,9 @@ __global__ __launch_bounds__(256) void k_front(int64_t ndof, int nb_diag, const 
   if (rr >= nshort) return;
   const int row = rows[nlong + rr];
   T acc = 0;
-#pragma unroll 4
-  for (int q = ptr[row] + sub; q < ptr[row + 1]; q += LPRP) acc += val[q] * r[idx[q]];
+  const int c1 = ptr[row + 1] >> 2;
+#pragma unroll 2
+  for (int c = (ptr[row] >> 2) + sub; c < c1; c += LPRP) acc = spmv_chunk<T, 0>(acc, c, 0, idx4, val, r, nullptr, nullptr);
 #pragma unroll
   for (int o = LPRP / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, LPRP);
   if (sub == 0) rc[row] = acc;
@@ -1922,7 +1952,7 @@ __global__ __launch_bounds__(256) void k_block_gemv(int64_t nrows, int nrhs, con
   const int i = row_loc[rw];
   const int64_t s0 = bptr[b];
   const int m = (int)(bptr[b + 1] - s0);
-  const T* row = binv + boff[b] + (int64_t)i * m;
+  const T* row = binv + boff[b] + (int64_t)i * blk_ld(m);
   T acc = 0;
 #pragma unroll 4
   for (int j = 0; j < m; ++j) acc += row[j] * r[(int64_t)bdof[s0 + j] * nrhs + c];
@@ -1950,10 +1980,11 @@ __global__ __launch_bounds__(256) void k_block_gemm(int nblocks, int nrhs, const
   }
   __syncthreads();
   const T* B = binv + boff[b];
+  const int ld = blk_ld(m);
   for (int t = threadIdx.x; t < m * nrhs; t += 256) {
     const int i = t / nrhs, c = t - i * nrhs;
     T acc = 0;
-    for (int j = 0; j < m; ++j) acc += B[(int64_t)i * m + j] * rl[j * nrhs + c];
+    for (int j = 0; j < m; ++j) acc += B[(int64_t)i * ld + j] * rl[j * nrhs + c];
     z[(int64_t)bout[s0 + i] * nrhs + c] = acc;
   }
 }
@@ -2002,6 +2033,7 @@ __global__ __launch_bounds__(256) void k_block_mfma(int nblocks, int nrhs, const
   for (int t = threadIdx.x; t < m; t += 256) sdof[t] = bdof[s0 + t];
   __syncthreads();
   const T* B = binv + boff[b];
+  const int ld = blk_ld(m);
   const int lane = (int)(threadIdx.x & 63), wv = (int)(threadIdx.x >> 6);
   const int li = lane & 15, lk = lane >> 4;
   const int nti = (m + 15) >> 4, ntj = nrhs >> 4;
@@ -2018,7 +2050,7 @@ __global__ __launch_bounds__(256) void k_block_mfma(int nblocks, int nrhs, const
         a[u] = 0;
         bv[u] = 0;
         if (k < m) {
-          if (i < m) a[u] = B[(int64_t)k * m + i];
+          if (i < m) a[u] = B[(int64_t)k * ld + i];
           bv[u] = r[(int64_t)sdof[k] * nrhs + j0 + li];
         }
       }
@@ -2034,9 +2066,12 @@ __global__ __launch_bounds__(256) void k_block_mfma(int nblocks, int nrhs, const
 }
 
 // exact V_e solves for one RHS, one workgroup per block (blocks listed by
-// order[], largest first): the block's r values are gathered into LDS once,
-// then LPR lanes per row stream the row of the stored inverse against them
-// and add their parts in a fixed order. Dynamic LDS: m_max values.
+// order[], largest first): the block's r values are gathered into LDS once
+// (zeros up to the padded row length), then LPR lanes per row stream the row
+// of the stored inverse against them in 4-entry vector loads and add their
+// parts in a fixed order. Each lane group takes four rows per pass, so that
+// four rows' loads are in flight together. Dynamic LDS: blk_ld(m_max)
+// values.
 template <typename T, int LPR>
 __global__ __launch_bounds__(256) void k_block_rows(int nblocks, const int32_t* __restrict__ order,
                                                     const int64_t* __restrict__ bptr,
@@ -2050,18 +2085,39 @@ __global__ __launch_bounds__(256) void k_block_rows(int nblocks, const int32_t* 
   const int b = order[blockIdx.x];
   const int64_t s0 = bptr[b];
   const int m = (int)(bptr[b + 1] - s0);
-  for (int t = threadIdx.x; t < m; t += 256) rl[t] = r[bdof[s0 + t]];
+  const int q = blk_ld(m) >> 2;
+  for (int t = threadIdx.x; t < 4 * q; t += 256) rl[t] = t < m ? r[bdof[s0 + t]] : T(0);
   __syncthreads();
-  const T* B = binv + boff[b];
+  typedef T v4 __attribute__((ext_vector_type(4)));
+  const v4* B = reinterpret_cast<const v4*>(binv + boff[b]);
+  const v4* r4 = reinterpret_cast<const v4*>(rl);
   const int sub = (int)(threadIdx.x % LPR);
-  for (int i = (int)(threadIdx.x / LPR); i < m; i += 256 / LPR) {
-    const T* row = B + (int64_t)i * m;
-    T acc = 0;
-#pragma unroll 4
-    for (int j = sub; j < m; j += LPR) acc += row[j] * rl[j];
+  constexpr int G = 256 / LPR, R = 4;
+  for (int i0 = (int)(threadIdx.x / LPR); i0 < m; i0 += R * G) {
+    T acc[R];
 #pragma unroll
-    for (int o = LPR / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, LPR);
-    if (sub == 0) z[bout[s0 + i]] = acc;
+    for (int u = 0; u < R; ++u) acc[u] = 0;
+    for (int j = sub; j < q; j += LPR) {
+      const v4 x = r4[j];
+      v4 a[R];
+#pragma unroll
+      for (int u = 0; u < R; ++u)
+        if (i0 + u * G < m) a[u] = B[(int64_t)(i0 + u * G) * q + j];
+#pragma unroll
+      for (int u = 0; u < R; ++u)
+        if (i0 + u * G < m) {
+          acc[u] += a[u].x * x.x;
+          acc[u] += a[u].y * x.y;
+          acc[u] += a[u].z * x.z;
+          acc[u] += a[u].w * x.w;
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+#pragma unroll
+      for (int o = LPR / 2; o > 0; o >>= 1) acc[u] += __shfl_xor(acc[u], o, LPR);
+      if (sub == 0 && i0 + u * G < m) z[bout[s0 + i0 + u * G]] = acc[u];
+    }
   }
 }
 

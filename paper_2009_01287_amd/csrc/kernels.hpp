@@ -30,6 +30,11 @@ struct FaceRec {
 };
 static_assert(sizeof(FaceRec) == 88, "FaceRec layout");
 
+// Stored V_e block inverses: block b (m x m, row-major) starts at boff[b]
+// with its rows padded to blk_ld(m) entries (zeros past column m), so that
+// every row starts on a 4-entry boundary for vector loads.
+__host__ __device__ inline int blk_ld(int m) { return (m + 3) & ~3; }
+
 // Tables of the 1D basis, all degrees, in one device buffer (doubles).
 struct TableLayout {
   int64_t dside;      // l_i'(0), l_i'(1): dside[(p*2+s)*9+i]
