@@ -367,8 +367,8 @@ def broken_stiffness(mesh):
 
 
 # ------------------------------------------------------------- AMG (project)
-THETA = 0.08
-THETAS = (0.08, 0.04, 0.02, 0.01, 0.0)   # retried in order when a level stalls
+THETA = 0.04
+THETAS = (0.04, 0.02, 0.01, 0.005, 0.0)   # retried in order when a level stalls
 TIE = 1e-10
 
 
@@ -447,14 +447,14 @@ class AMG:
     P_l = (I - w D_F^{-1} A_F) P^_l, P^ the 0/1 aggregate indicator, A_F the
     filtered matrix (rows whose filtered diagonal is at most 1e-8 a_ii, e.g. a
     structural zero from a zero row sum, are not smoothed), w = (4/3)/rho, rho = max_i sum_j |a^F_ij| / a^F_ii;
-    A_{l+1} = P_l^T A_l P_l. A level that would keep more than 0.8 of its
-    rows is retried with theta = 0.04, 0.02, 0.01 and 0 (every connection
+    A_{l+1} = P_l^T A_l P_l. A level that would keep more than 0.4 of its
+    rows is retried with theta = 0.02, 0.01, 0.005 and 0 (every connection
     strong); if it still stalls, or at n <= 256 or 12 levels, coarsening
     stops. Coarsest level: dense
     Cholesky. Smoother: l1-Jacobi (d_i = sum_j |a_ij|), one pre- and one
     post-sweep from a zero initial guess. The V(1,1) cycle is symmetric."""
 
-    def __init__(self, A, max_levels=12, min_rows=256, max_ratio=0.8):
+    def __init__(self, A, max_levels=12, min_rows=256, max_ratio=0.4):
         self.A = [A.tocsr()]
         self.P = []
         self.aggs = []

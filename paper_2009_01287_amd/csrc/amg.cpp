@@ -4,7 +4,7 @@
 // V-cycle, whose settings it does not state).
 //
 // Project specification:
-//   strength  j in S_i iff j != i and |a_ij| >= 0.08 sqrt(a_ii a_jj)
+//   strength  j in S_i iff j != i and |a_ij| >= 0.04 sqrt(a_ii a_jj)
 //   phase 1   in row order, a free row whose strong neighbours are all free
 //             forms the aggregate {i} + S_i
 //   phase 2   a free row joins the phase-1 aggregate of its strongest
@@ -15,12 +15,14 @@
 //   filtered matrix (weak off-diagonals dropped and added to the diagonal;
 //   rows whose filtered diagonal is at most 1e-8 a_ii are not smoothed),
 //   w = (4/3)/rho, rho = max_i sum_j |a^F_ij| / a^F_ii; A_{l+1} = P_l^T A_l P_l
-//   a level keeping > 0.8 of its rows is retried with theta = 0.04, 0.02,
-//   0.01 and 0 (every connection strong);
+//   a level keeping > 0.4 of its rows is retried with theta = 0.02, 0.01,
+//   0.005 and 0 (every connection strong);
 //   stop at <= 256 rows, 12 levels, or a level that still stalls;
 //   the coarsest level is solved exactly (dense Cholesky, stored inverse).
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <string>
 
 #include <thread>
@@ -246,7 +248,7 @@ AMGHier amg_setup(const CSR& A0, int max_levels, int64_t min_rows, double max_ra
     if (n <= min_rows || (int)H.lv.size() >= max_levels) break;
     std::vector<int64_t> agg;
     int64_t na = 0;
-    const double thetas[5] = {0.08, 0.04, 0.02, 0.01, 0.0};
+    const double thetas[5] = {0.04, 0.02, 0.01, 0.005, 0.0};
     double theta = thetas[0];
     for (int tr = 0; tr < 5; ++tr) {
       theta = thetas[tr];
@@ -310,6 +312,10 @@ AMGHier amg_setup(const CSR& A0, int max_levels, int64_t min_rows, double max_ra
     }
     CSR R = csr_transpose(P);
     CSR Ac = csr_matmul(R, csr_matmul(A, P));
+    if (std::getenv("HPDG_VERBOSE"))
+      std::fprintf(stderr, "hpdg amg: level %zu rows %lld nnz %lld theta %.3g -> %lld aggregates, nnz(P) %lld, nnz(A_c) %lld\n",
+                   H.lv.size() - 1, (long long)n, (long long)A.idx.size(), theta, (long long)na,
+                   (long long)P.idx.size(), (long long)Ac.idx.size());
     H.lv.back().P = std::move(P);
     H.lv.back().R = std::move(R);
     H.aggs.push_back(std::move(agg));

@@ -162,7 +162,7 @@ struct AMGHier {
   int64_t nc = 0;
   std::vector<std::vector<int64_t>> aggs;
 };
-AMGHier amg_setup(const CSR& A, int max_levels = 12, int64_t min_rows = 256, double max_ratio = 0.8);
+AMGHier amg_setup(const CSR& A, int max_levels = 12, int64_t min_rows = 256, double max_ratio = 0.4);
 void aggregate(const CSR& A, std::vector<int64_t>& agg, int64_t& na, double theta);
 
 }  // namespace hpdg
