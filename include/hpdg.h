@@ -173,9 +173,10 @@ hpdg_status hpdg_operator_upload(hpdg_operator* op, void* stream);
 hpdg_status hpdg_operator_device_bytes(hpdg_operator* op, int64_t* bytes);
 
 /* Autotuner for the one-RHS path: for P^T and every AMG level matrix A_l,
- * R_l, P_l, times y = A x under each row binning (rows longer than 32, 64,
- * 128 or no threshold get a wavefront each; the others 1, 2, 4, 8 or 16
- * lanes) on `stream` and keeps the fastest. Changes the summation order and
+ * R_l, P_l, times y = A x under each row binning (rows longer than 64, 128,
+ * 256 or 512 entries or no threshold get a wavefront each; the others 1, 2,
+ * 4, 8 or 16 lanes, each lane taking 4-entry chunks) on `stream` and keeps
+ * the fastest. Changes the summation order and
  * so the last bits of B r; drops captured graphs. With no_prec only the
  * element kernel is tuned. In 2D it also picks, for the element kernel, the
  * elements per workgroup (1 or 2) and the face records staged per pass (8,
@@ -187,7 +188,9 @@ hpdg_status hpdg_operator_device_bytes(hpdg_operator* op, int64_t* bytes);
  * staged in LDS, 0 when their rows run inside the B front) / 8 dense tail of the
  * V-cycle on the level above the coarsest (chosen lanes 1 if kept) / 10 3D
  * element kernel dispatched by decreasing element cost (chosen lanes 1 if
- * kept; the threshold column holds the ns of that order),
+ * kept; the threshold column holds the ns of that order) / 11 V_e block
+ * solves on the operator's second stream, concurrent with the V-cycle
+ * (chosen lanes 1 if kept; rows and nnz hold ndof and the block count),
  * level, rows (ndof), nnz (elements), chosen threshold (records per pass),
  * chosen lanes (elements per workgroup; 1 if the level is fused), ns before,
  * ns after); *n rows written. A fused level (one RHS, at most 4M nonzeros)

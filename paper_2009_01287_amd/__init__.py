@@ -202,7 +202,7 @@ class Operator:
         rep = (C.c_int64 * (8 * cap))()
         n = C.c_int()
         _check(lib().hpdg_operator_tune(self.h, _stream(stream), rep, cap, C.byref(n)))
-        kinds = {0: "A", 1: "R", 2: "P", 3: "PT", 4: "elem", 5: "vcycle_fused", 6: "elem_rhs_group", 7: "front_block_lanes", 8: "vcycle_dense_tail", 10: "elem_order"}
+        kinds = {0: "A", 1: "R", 2: "P", 3: "PT", 4: "elem", 5: "vcycle_fused", 6: "elem_rhs_group", 7: "front_block_lanes", 8: "vcycle_dense_tail", 10: "elem_order", 11: "B_fork"}
         out = []
         for i in range(n.value):
             r = rep[8 * i:8 * i + 8]

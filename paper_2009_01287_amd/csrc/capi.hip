@@ -290,10 +290,20 @@ struct hpdg_operator {
   PinArea* pin = nullptr;    // pinned host mirror of the CG flags and norms
   double* hist_pin = nullptr;
   hipEvent_t ev = nullptr;   // completion of the last enqueued PCG chunk
+  // one RHS: the V_e block solves on a second stream, concurrent with the
+  // V-cycle (both only read r; they write disjoint parts of B's work
+  // vectors), joined before z = z_B + P e
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  int b_fork = 0;
+  int b_fork_env = -1;       // HPDG_B_FORK, when set
   PcgRun run;
   ~hpdg_operator() {
     for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (aux) (void)hipStreamDestroy(aux);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
     if (pin) (void)hipHostFree(pin);
     if (hist_pin) (void)hipHostFree(hist_pin);
     if (ev) (void)hipEventDestroy(ev);
@@ -675,6 +685,13 @@ static int64_t part_off2(const hpdg_operator* op) {
   return std::max<int64_t>(op->ne, (op->ndof + 255) / 256) + 64;
 }
 
+// the second stream and its two events, created on first use
+static void ensure_aux(hpdg_operator* op) {
+  if (!op->aux) HIPCHK(hipStreamCreateWithFlags(&op->aux, hipStreamNonBlocking));
+  if (!op->ev_fork) HIPCHK(hipEventCreateWithFlags(&op->ev_fork, hipEventDisableTiming));
+  if (!op->ev_join) HIPCHK(hipEventCreateWithFlags(&op->ev_join, hipEventDisableTiming));
+}
+
 // All device buffers of an operator from its host data. In a counting pass
 // (g_dry) only the sizes are recorded. Copies are synchronous; the call ends
 // with a synchronisation of `s`.
@@ -781,6 +798,10 @@ static void upload_device(hpdg_operator* op, hipStream_t s) {
   if (!op->hist_pin)
     HIPCHK(hipHostMalloc((void**)&op->hist_pin, (size_t)2 * kHistCap * hs * sizeof(double), hipHostMallocDefault));
   if (!op->ev) HIPCHK(hipEventCreateWithFlags(&op->ev, hipEventDisableTiming));
+  // default: blocks on the second stream when their stored inverses reach
+  // 32 MB (the autotuner times both)
+  op->b_fork = op->b_fork_env >= 0 ? op->b_fork_env : op->blk_inv.bytes >= ((size_t)32 << 20) ? 1 : 0;
+  if (op->b_fork) ensure_aux(op);
   HIPCHK(hipStreamSynchronize(s));
   op->dev_bytes = g_dev_bytes - b0;
   op->uploaded = 1;
@@ -1005,6 +1026,7 @@ extern "C" hpdg_status hpdg_setup_operator(const hpdg_mesh* mh, const hpdg_opera
     if (const char* v = std::getenv("HPDG_ELEM3D_COST_ORDER")) op->use_perm = std::atoi(v) != 0;
     if (const char* v = std::getenv("HPDG_ELEM3D_SPLIT")) op->split3 = std::atoi(v) != 0;
     if (const char* v = std::getenv("HPDG_BLOCK_WG")) op->blk_wg = std::atoi(v) != 0;
+    if (const char* v = std::getenv("HPDG_B_FORK")) op->b_fork_env = std::atoi(v) != 0 ? 1 : 0;
     if (const char* v = std::getenv("HPDG_BLOCK_LANES")) {
       const int l = std::atoi(v);
       op->lprb = (l == 1 || l == 2 || l == 4 || l == 8 || l == 32) ? l : 16;
@@ -1243,7 +1265,8 @@ static void spmv(const DevCSR& A, int nrhs, const T* x, const T* b, const T* d, 
 }
 
 template <typename T>
-static void vcycle(hpdg_operator* op, const BWork& W, size_t l, int nrhs, hipStream_t s);
+static void vcycle(hpdg_operator* op, const BWork& W, size_t l, int nrhs, hipStream_t s,
+                   const std::function<void()>* at_coarse = nullptr);
 
 // Dense tail of the V-cycle: on the level just above the coarsest, one
 // V(1,1) cycle is a fixed linear map of that level's right-hand side,
@@ -1328,9 +1351,16 @@ static void dense_many(hpdg_operator* op, int n, int nrhs, const T* C, const T* 
     hipLaunchKernelGGL(k_dense_gemm<T>, dim3(n), dim3(256), 0, s, n, nrhs, C, b, x);
 }
 
+// at_coarse (if set) is called once the level's own down-leg is enqueued,
+// before the coarser levels (at the start where the level has no down-leg of
+// its own)
 template <typename T>
-static void vcycle(hpdg_operator* op, const BWork& W, size_t l, int nrhs, hipStream_t s) {
+static void vcycle(hpdg_operator* op, const BWork& W, size_t l, int nrhs, hipStream_t s,
+                   const std::function<void()>* at_coarse) {
   T *b = (T*)W.b[l], *x = (T*)W.x[l];
+  if (at_coarse && (op->lv[l].use_tail || (l + 1 < op->lv.size() && op->lv[l].fused && (nrhs == 1 || !op->no_fused_multi)) ||
+                    l + 1 == op->lv.size()))
+    (*at_coarse)();
   if (op->lv[l].use_tail) {
     LevelDev& L = op->lv[l];
     const int n = L.A.nrows;
@@ -1368,6 +1398,7 @@ static void vcycle(hpdg_operator* op, const BWork& W, size_t l, int nrhs, hipStr
   }
   // restriction b_c = P^T r
   spmv<T, 0>(L.R, nrhs, r, nullptr, nullptr, nullptr, bc, s);
+  if (at_coarse) (*at_coarse)();
   vcycle<T>(op, W, l + 1, nrhs, s);
   // t = x + P x_c ; x = t + D (b - A t)
   spmv<T, 2>(L.P, nrhs, xc, x, nullptr, nullptr, t, s);
@@ -1392,7 +1423,7 @@ static BWork op_work(hpdg_operator* op) {
 // Times y = A x for one sparse matrix of the one-RHS path under every row
 // binning (long-row threshold x lanes per short row) and keeps the fastest.
 template <typename T>
-static void launch_front(hpdg_operator* op, const T* rt, T* zb, T* bc0, hipStream_t s);
+static bool launch_front(hpdg_operator* op, const T* rt, T* zb, T* bc0, hipStream_t s, bool fork = false);
 // where the block solves write: the DOF itself, or its slot when the V_e overlap
 static const int32_t* blk_out(const hpdg_operator* op) {
   return op->blk_overlap ? op->blk_out.as<int32_t>() : op->blk_dof.as<int32_t>();
@@ -1554,6 +1585,10 @@ static void tune_rhs_group(hpdg_operator* op, hipStream_t s, int64_t* rep) {
 }
 
 template <typename T>
+static int apply_B_dev(hpdg_operator* op, const BWork& W, const double* r, double* z, int nrhs, hipStream_t s,
+                       double* pdot = nullptr, bool r_cast = false, bool allow_fork = true);
+
+template <typename T>
 static int tune_all(hpdg_operator* op, hipStream_t s, int64_t* report, int cap) {
   PrecHost& H = op->host;
   int k = 0;
@@ -1691,6 +1726,39 @@ static int tune_all(hpdg_operator* op, hipStream_t s, int64_t* report, int cap) 
       q[5] = (int64_t)(kt ? tt : tb);
     }
   }
+  // the V_e block solves on the second stream, concurrent with the V-cycle,
+  // against one stream: whole applications of B
+  if (op->nblocks > 0 && op->blk_wg && op->b_fork_env < 0) {
+    ensure_aux(op);
+    const BWork W = op_work(op);
+    double* rin = op->pv.as<double>();
+    double* zout = op->Ap.as<double>();
+    HIPCHK(hipMemsetAsync(rin, 0, (size_t)op->ndof * sizeof(double), s));
+    auto time_b = [&]() {
+      for (int w = 0; w < 3; ++w) apply_B_dev<T>(op, W, rin, zout, 1, s);
+      HIPCHK(hipEventRecord(e0, s));
+      const int reps = 10;
+      for (int w = 0; w < reps; ++w) apply_B_dev<T>(op, W, rin, zout, 1, s);
+      HIPCHK(hipEventRecord(e1, s));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      return (double)ms * 1e6 / reps;
+    };
+    const int def = op->b_fork;
+    const double t_def = time_b();
+    op->b_fork = 1 - def;
+    const double t_alt = time_b();
+    const bool flip = t_alt < kTuneMargin * t_def;
+    if (!flip) op->b_fork = def;
+    int64_t* r = slot(11, 0);
+    r[0] = op->ndof;
+    r[1] = op->nblocks;
+    r[2] = 0;
+    r[3] = op->b_fork;
+    r[4] = (int64_t)t_def;
+    r[5] = (int64_t)(flip ? t_alt : t_def);
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   HIPCHK(hipStreamSynchronize(s));
@@ -1727,8 +1795,31 @@ extern "C" hpdg_status hpdg_operator_tune(hpdg_operator* op, void* stream, int64
 
 // front of B with one RHS: point Jacobi, V_e block solves and r_c = P^T r in
 // one launch (k_front)
+// V_e block solves for one RHS as a workgroup per block (k_block_rows)
 template <typename T>
-static void launch_front(hpdg_operator* op, const T* rt, T* zb, T* bc0, hipStream_t s) {
+static void launch_block_rows(hpdg_operator* op, const T* rt, T* zb, hipStream_t s) {
+  const size_t shm = (size_t)blk_ld(op->max_blk) * sizeof(T);
+  auto lb = [&](auto lpr) {
+    constexpr int L = decltype(lpr)::value;
+    hipLaunchKernelGGL((k_block_rows<T, L>), dim3((unsigned)op->nblocks), dim3(256), shm, s, (int)op->nblocks,
+                       op->blk_order.as<int32_t>(), op->blk_ptr.as<int64_t>(), op->blk_off.as<int64_t>(),
+                       op->blk_dof.as<int32_t>(), blk_out(op), op->blk_inv.as<T>(), rt, zb);
+  };
+  switch (op->lprb) {
+    case 1: lb(std::integral_constant<int, 1>()); break;
+    case 2: lb(std::integral_constant<int, 2>()); break;
+    case 4: lb(std::integral_constant<int, 4>()); break;
+    case 8: lb(std::integral_constant<int, 8>()); break;
+    case 32: lb(std::integral_constant<int, 32>()); break;
+    default: lb(std::integral_constant<int, 16>()); break;
+  }
+}
+
+// With fork (and the workgroup-per-block form) the block solves are left to
+// the caller, which runs them on the operator's second stream; returns
+// whether it must.
+template <typename T>
+static bool launch_front(hpdg_operator* op, const T* rt, T* zb, T* bc0, hipStream_t s, bool fork) {
   const DevCSR& A = op->PT;
   const int nb_diag = (int)nblk(op->ndof);
   const int nlb = (A.nlong + 3) / 4;
@@ -1762,30 +1853,18 @@ static void launch_front(hpdg_operator* op, const T* rt, T* zb, T* bc0, hipStrea
     case 32: with_lprp(std::integral_constant<int, 32>()); break;
     default: with_lprp(std::integral_constant<int, 16>()); break;
   }
-  if (wg) {
-    const size_t shm = (size_t)blk_ld(op->max_blk) * sizeof(T);
-    auto lb = [&](auto lpr) {
-      constexpr int L = decltype(lpr)::value;
-      hipLaunchKernelGGL((k_block_rows<T, L>), dim3((unsigned)op->nblocks), dim3(256), shm, s, (int)op->nblocks,
-                         op->blk_order.as<int32_t>(), op->blk_ptr.as<int64_t>(), op->blk_off.as<int64_t>(),
-                         op->blk_dof.as<int32_t>(), blk_out(op), op->blk_inv.as<T>(), rt, zb);
-    };
-    switch (op->lprb) {
-      case 1: lb(std::integral_constant<int, 1>()); break;
-      case 2: lb(std::integral_constant<int, 2>()); break;
-      case 4: lb(std::integral_constant<int, 4>()); break;
-      case 8: lb(std::integral_constant<int, 8>()); break;
-      case 32: lb(std::integral_constant<int, 32>()); break;
-      default: lb(std::integral_constant<int, 16>()); break;
-    }
-  }
+  fork = fork && wg && op->aux;
+  if (wg && !fork) launch_block_rows<T>(op, rt, zb, s);
+  return fork;
 }
 
 // z = B r with the work vectors W. With pdot (one RHS) the last kernel also
 // writes per-block shares of r'z there; returns their count (0 without pdot).
+// allow_fork: the block solves may use the operator's second stream (not for
+// callers that may overlap another call on the same operator)
 template <typename T>
 static int apply_B_dev(hpdg_operator* op, const BWork& W, const double* r, double* z, int nrhs, hipStream_t s,
-                       double* pdot = nullptr, bool r_cast = false) {
+                       double* pdot, bool r_cast, bool allow_fork) {
   int64_t n = op->ndof * nrhs;
   const T* rt;
   T* zb = (T*)W.zT;
@@ -1804,8 +1883,9 @@ static int apply_B_dev(hpdg_operator* op, const BWork& W, const double* r, doubl
     rt = rT;
   }
   T* b0 = (T*)W.b[0];
+  bool forked = false;
   if (nrhs == 1) {
-    launch_front<T>(op, rt, zb, b0, s);
+    forked = launch_front<T>(op, rt, zb, b0, s, allow_fork && op->b_fork);
   } else {
     if (!lowp)
       hipLaunchKernelGGL(k_diag_scale<T>, dim3(nblk(n)), dim3(256), 0, s, n, nrhs, op->dinvJ.as<T>(), rt, zb);
@@ -1829,10 +1909,25 @@ static int apply_B_dev(hpdg_operator* op, const BWork& W, const double* r, doubl
     }
     spmv<T, 0>(op->PT, nrhs, rt, nullptr, nullptr, nullptr, b0, s);
   }
-  if (op->blk_overlap)
-    hipLaunchKernelGGL(k_block_gather<T>, dim3(nblk(op->g_n * nrhs)), dim3(256), 0, s, (int)op->g_n, nrhs,
-                       op->g_dof.as<int32_t>(), op->g_ptr.as<int32_t>(), op->g_slot.as<int32_t>(), zb);
-  vcycle<T>(op, W, 0, nrhs, s);
+  auto gather = [&](hipStream_t g) {
+    if (op->blk_overlap)
+      hipLaunchKernelGGL(k_block_gather<T>, dim3(nblk(op->g_n * nrhs)), dim3(256), 0, g, (int)op->g_n, nrhs,
+                         op->g_dof.as<int32_t>(), op->g_ptr.as<int32_t>(), op->g_slot.as<int32_t>(), zb);
+  };
+  // forked: the block solves (they read only r and write only their own
+  // entries of z_B) start on the second stream once level 0's down-leg is
+  // enqueued, so that they overlap the latency-bound coarse levels rather
+  // than the bandwidth-bound level-0 smoothing product
+  std::function<void()> fork_blocks = [&]() {
+    HIPCHK(hipEventRecord(op->ev_fork, s));
+    HIPCHK(hipStreamWaitEvent(op->aux, op->ev_fork, 0));
+    launch_block_rows<T>(op, rt, zb, op->aux);
+    gather(op->aux);
+    HIPCHK(hipEventRecord(op->ev_join, op->aux));
+  };
+  if (!forked) gather(s);
+  vcycle<T>(op, W, 0, nrhs, s, forked ? &fork_blocks : nullptr);
+  if (forked) HIPCHK(hipStreamWaitEvent(s, op->ev_join, 0));
   int64_t nt = op->ndof * nrhs;
   if (nrhs != 1) pdot = nullptr;
   hipLaunchKernelGGL(k_prolong_out<T>, dim3(nblk(nt)), dim3(256), 0, s, (int)op->ndof, nrhs,
@@ -1944,8 +2039,8 @@ extern "C" hpdg_status hpdg_apply_B_noalloc(hpdg_operator* op, const double* r, 
   if (st != HPDG_OK) return st;
   scratch_work(op, nrhs, (char*)base, W);
   hipStream_t s = (hipStream_t)stream;
-  if (op->prec32) apply_B_dev<float>(op, W, r, z, nrhs, s);
-  else apply_B_dev<double>(op, W, r, z, nrhs, s);
+  if (op->prec32) apply_B_dev<float>(op, W, r, z, nrhs, s, nullptr, false, false);
+  else apply_B_dev<double>(op, W, r, z, nrhs, s, nullptr, false, false);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(HPDG_E_HIP, hipGetErrorString(e));
   return HPDG_OK;

@@ -179,6 +179,34 @@ def test_block_solve_forms(monkeypatch, name, wg, lanes, fp32):
     assert _rel(_host(z), zo) <= (1e-5 if fp32 else 1e-12)
 
 
+@pytest.mark.parametrize("name", ["rand2", "rand3hp"])
+@pytest.mark.parametrize("fp32", [False, True])
+def test_block_solves_on_second_stream_bitwise(monkeypatch, name, fp32):
+    """One RHS: the V_e block solves on the operator's second stream,
+    concurrent with the V-cycle and joined before z = z_B + P e, give bitwise
+    the same B r and the same PCG iterates as on one stream, in blocking
+    solves and in HIP-graph replays."""
+    md = MESHES[name]()
+    m = G.Mesh(md)
+    f = torch.from_numpy(H.gaussian_rhs(m.ndof, 61)).cuda()
+    out = []
+    for flag in ("0", "1"):
+        monkeypatch.setenv("HPDG_BLOCK_WG", "1")
+        monkeypatch.setenv("HPDG_B_FORK", flag)
+        for graph in (False, True):
+            op = G.Operator(m, prec_fp32=fp32, graph=graph)
+            z = torch.empty_like(f)
+            op.apply_B(f, z)
+            b = torch.empty_like(f)
+            op.rhs(f, b)
+            x = torch.zeros_like(b)
+            info = op.pcg_solve(b, x, rtol=1e-8, maxit=1000)[0]
+            assert info["converged"]
+            out.append((z, x, info["iters"]))
+    for z, x, it in out[1:]:
+        assert torch.equal(z, out[0][0]) and torch.equal(x, out[0][1]) and it == out[0][2]
+
+
 @pytest.mark.parametrize("name", ["hang2", "hang3"])
 def test_rhs_matches_oracle(name):
     md = MESHES[name]()
@@ -462,7 +490,7 @@ def test_autotuned_binning_same_results(fp32):
     assert rep and {r["matrix"] for r in rep} >= {"A", "PT"}
     for r in rep:
         assert r["ns_tuned"] <= r["ns_default"]
-        if r["matrix"] in ("vcycle_fused", "vcycle_dense_tail", "elem_order"):
+        if r["matrix"] in ("vcycle_fused", "vcycle_dense_tail", "elem_order", "B_fork"):
             assert r["lanes"] in (0, 1)
         elif r["matrix"] == "elem_rhs_group":
             assert r["lanes"] in (1, 2, 4, 8, 16, 32, 64)
