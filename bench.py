@@ -68,9 +68,10 @@ def main():
                     help="serving: 1 builds fused V-cycle levels and a small dense tail without timing")
     ap.add_argument("--serving-prec", default="mixed", choices=["mixed", "fp64", "both"])
     ap.add_argument("--lambda-sweep", type=str, default="",
-                    help="serving: comma-separated multiples of the FP64 capacity (solves/s of the FP64 "
-                         "pipeline with every request at t = 0, measured first) at which Poisson arrival "
-                         "streams of --sweep-requests requests are served in mixed precision, e.g. 0.3,0.5,0.7,0.9")
+                    help="serving: comma-separated multiples of the capacity (solves/s of the "
+                         "mixed-precision pipeline with every request at t = 0, measured first) at which "
+                         "Poisson arrival streams of --sweep-requests requests are served by the same "
+                         "pipeline, e.g. 0.3,0.5,0.7,0.9")
     ap.add_argument("--sweep-requests", type=int, default=600)
     ap.add_argument("--study", choices=["eta", "random"], default=None,
                     help="eta: penalty-dependence study (SIPG and BR2, eta = 10..1e4, full B against the "
@@ -531,15 +532,15 @@ def _serve(reqs_spec, prec, args, realtime):
 
 
 def serve_sweep(args):
-    """Serving latency against load: the FP64 pipeline's capacity C (all
-    --requests requests at t = 0), then Poisson streams of --sweep-requests
-    requests at rate f x C for each f of --lambda-sweep, served with the
-    mixed-precision pipeline; one JSON line with the p50/p99 per rate."""
+    """Serving latency against load: the mixed-precision pipeline's own
+    capacity C (all --requests requests at t = 0), then Poisson streams of
+    --sweep-requests requests at rate f x C for each f of --lambda-sweep,
+    served by the same pipeline; one JSON line with the p50/p99 per rate."""
     import torch
     import hpinputs as H
     torch.zeros(1, device="cuda")
-    cap = _serve(H.serving_stream(args.requests, seed=5005), "fp64", args, False)
-    print(json.dumps({"serving_capacity_fp64": cap}), file=sys.stderr, flush=True)
+    cap = _serve(H.serving_stream(args.requests, seed=5005), "mixed", args, False)
+    print(json.dumps({"serving_capacity": cap}), file=sys.stderr, flush=True)
     C = cap["solves_per_s"]
     rows = []
     for f in [float(v) for v in args.lambda_sweep.split(",") if v]:
@@ -550,7 +551,8 @@ def serve_sweep(args):
                "max_true_rel_res": s["max_true_rel_res"]}
         rows.append(row)
         print(json.dumps({"serving_sweep_point": row}), file=sys.stderr, flush=True)
-    print(json.dumps({"serving_sweep": {"fp64_capacity_solves_per_s": C, "capacity_requests": args.requests,
+    print(json.dumps({"serving_sweep": {"capacity_solves_per_s": C, "capacity_prec": "mixed",
+                                        "capacity_requests": args.requests,
                                         "points": rows, "workers": args.workers,
                                         "max_active": args.max_active}}))
 

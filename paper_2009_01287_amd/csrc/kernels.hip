@@ -1257,26 +1257,40 @@ __device__ inline void e3f_body(const FaceRec& r, const FaceAux& ax, int form, d
   // stage 1: U0 = A0oo To, U1 = A0oo Do (n x n), U2 = A0on Tn, U3 = A0on Dn
   // (n x no); BR2: Y0 = A0on^T To stored transposed, Y0[a1 + n a0] (a0 < no,
   // a1 < n), Y1 = A0nn Tn (no x no)
-  for (int t = lane; t < 2 * n2; t += 64) {
-    const int which = t / n2, q = t - which * n2;
-    const int j0 = q % n, a1 = q / n;
-    const double* in = which == 0 ? To : Do;
-    double s = 0.0;
+  // (a lane forms both products of its node, reading each matrix entry once)
+  constexpr int QF = (F2 + 63) / 64;
 #pragma unroll
-    for (int a0 = 0; a0 < n; ++a0) s += MP[0][j0 * n + a0] * in[a0 + n * a1];
-    W[(2 + which) * F2 + q] = s;
+  for (int t = 0; t < QF; ++t) {
+    const int q = lane + 64 * t;
+    if (q >= n2) break;
+    const int j0 = q % n, a1 = q / n;
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int a0 = 0; a0 < n; ++a0) {
+      const double mv = MP[0][j0 * n + a0];
+      s0 += mv * To[a0 + n * a1];
+      s1 += mv * Do[a0 + n * a1];
+    }
+    W[2 * F2 + q] = s0;
+    W[3 * F2 + q] = s1;
   }
   if (inner) {
     const double* A = MP[2];
-    for (int t = lane; t < 2 * n * no; t += 64) {
-      const int which = t >= n * no ? 1 : 0, q = t - which * n * no;
+#pragma unroll
+    for (int t = 0; t < QF; ++t) {
+      const int q = lane + 64 * t;
+      if (q >= n * no) break;
       const int j0 = q % n, a1 = q / n;
-      const double* in = W + which * F2;
-      double s = 0.0;
+      double s0 = 0.0, s1 = 0.0;
 #pragma unroll
       for (int a0 = 0; a0 < NM; ++a0)
-        if (a0 < no) s += A[j0 * no + a0] * in[a0 + no * a1];
-      W[(4 + which) * F2 + q] = s;
+        if (a0 < no) {
+          const double av = A[j0 * no + a0];
+          s0 += av * W[a0 + no * a1];
+          s1 += av * W[F2 + a0 + no * a1];
+        }
+      W[4 * F2 + q] = s0;
+      W[5 * F2 + q] = s1;
     }
     if (form == 1) {
       for (int q = lane; q < n * no; q += 64) {
@@ -1354,26 +1368,27 @@ __device__ inline void e3f_body(const FaceRec& r, const FaceAux& ax, int form, d
   }
   wave_sync();
   if (form == 1) {
-    // stage 3: P0 = L0o v (n x n), Q0 = L0n vn (n x no)
+    // stage 3: P0 = L0o v (n x n), Q0 = L0n vn (n x no), one lane per node
     {
       const double* L0o = MP[6];
-      for (int q = lane; q < n2; q += 64) {
-        const int j0 = q % n, a1 = q / n;
-        double s = 0.0;
-#pragma unroll
-        for (int a0 = 0; a0 < n; ++a0) s += L0o[j0 * n + a0] * W[a0 + n * a1];
-        W[2 * F2 + q] = s;
-      }
-    }
-    if (inner) {
       const double* L0n = MP[8];
-      for (int q = lane; q < n * no; q += 64) {
-        const int j0 = q % n, a1 = q / n;
-        double s = 0.0;
 #pragma unroll
-        for (int a0 = 0; a0 < NM; ++a0)
-          if (a0 < no) s += L0n[j0 * no + a0] * W[F2 + a0 + no * a1];
-        W[3 * F2 + q] = s;
+      for (int t = 0; t < QF; ++t) {
+        const int q = lane + 64 * t;
+        const int j0 = q % n, a1 = q / n;
+        if (q < n2) {
+          double s = 0.0;
+#pragma unroll
+          for (int a0 = 0; a0 < n; ++a0) s += L0o[j0 * n + a0] * W[a0 + n * a1];
+          W[2 * F2 + q] = s;
+        }
+        if (inner && q < n * no) {
+          double s = 0.0;
+#pragma unroll
+          for (int a0 = 0; a0 < NM; ++a0)
+            if (a0 < no) s += L0n[j0 * no + a0] * W[F2 + a0 + no * a1];
+          W[3 * F2 + q] = s;
+        }
       }
     }
     wave_sync();
