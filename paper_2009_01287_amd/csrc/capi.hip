@@ -415,21 +415,34 @@ static void build_tables(hpdg_operator* op, int max_delta) {
   }
 }
 
-// inverse of an SPD matrix (row-major, in place) by Cholesky A = L L^T,
-// W = L^{-1}, A^{-1} = W^T W; throws if A is not positive definite
+// sum_k a[k] b[k] in four interleaved partial sums (vectorisable; fixed order)
+static inline double dot4(const double* a, const double* b, int n) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int k = 0;
+  for (; k + 4 <= n; k += 4) {
+    s0 += a[k] * b[k];
+    s1 += a[k + 1] * b[k + 1];
+    s2 += a[k + 2] * b[k + 2];
+    s3 += a[k + 3] * b[k + 3];
+  }
+  for (; k < n; ++k) s0 += a[k] * b[k];
+  return (s0 + s1) + (s2 + s3);
+}
+
+// inverse of an SPD matrix (row-major, in place) by Cholesky A = L L^T (row
+// by row, each entry one dot product of two rows), W = L^{-1},
+// A^{-1} = W^T W; throws if A is not positive definite
 static void spd_inverse(std::vector<double>& A, int n) {
   std::vector<double> L(A);
-  for (int j = 0; j < n; ++j) {
-    double s = L[j * n + j];
-    for (int k = 0; k < j; ++k) s -= L[j * n + k] * L[j * n + k];
-    if (!(s > 0)) throw Error(HPDG_E_NOT_SPD, "V_e block is not positive definite");
-    double d = std::sqrt(s);
-    L[j * n + j] = d;
-    for (int i = j + 1; i < n; ++i) {
-      double t = L[i * n + j];
-      for (int k = 0; k < j; ++k) t -= L[i * n + k] * L[j * n + k];
-      L[i * n + j] = t / d;
+  for (int i = 0; i < n; ++i) {
+    double* li = &L[(size_t)i * n];
+    for (int j = 0; j < i; ++j) {
+      const double* lj = &L[(size_t)j * n];
+      li[j] = (li[j] - dot4(li, lj, j)) / lj[j];
     }
+    const double s = li[i] - dot4(li, li, i);
+    if (!(s > 0)) throw Error(HPDG_E_NOT_SPD, "V_e block is not positive definite");
+    li[i] = std::sqrt(s);
   }
   // W lower triangular, row by row: W[i][j] = (delta_ij - sum_{j<=k<i} L[i][k] W[k][j]) / L[i][i]
   std::vector<double> W((size_t)n * n, 0.0);
@@ -444,14 +457,18 @@ static void spd_inverse(std::vector<double>& A, int n) {
     for (int j = 0; j < i; ++j) wi[j] *= inv;
     wi[i] = inv;
   }
-  // A^{-1}[i][k] = sum_{m >= max(i,k)} W[m][i] W[m][k]
+  // A^{-1}[i][k] = sum_{m >= max(i,k)} W[m][i] W[m][k]: rows of A in groups
+  // of four, each row of W read once per group
   std::fill(A.begin(), A.end(), 0.0);
-  for (int m = 0; m < n; ++m) {
-    const double* wm = &W[(size_t)m * n];
-    for (int i = 0; i <= m; ++i) {
-      const double a = wm[i];
-      double* ai = &A[(size_t)i * n];
-      for (int k = 0; k <= i; ++k) ai[k] += a * wm[k];
+  for (int i0 = 0; i0 < n; i0 += 4) {
+    const int i1 = std::min(n, i0 + 4);
+    for (int m = i0; m < n; ++m) {
+      const double* wm = &W[(size_t)m * n];
+      for (int i = i0; i < i1 && i <= m; ++i) {
+        const double a = wm[i];
+        double* ai = &A[(size_t)i * n];
+        for (int k = 0; k <= i; ++k) ai[k] += a * wm[k];
+      }
     }
   }
   for (int i = 0; i < n; ++i)
