@@ -190,7 +190,9 @@ hpdg_status hpdg_operator_device_bytes(hpdg_operator* op, int64_t* bytes);
  * element kernel dispatched by decreasing element cost (chosen lanes 1 if
  * kept; the threshold column holds the ns of that order) / 11 V_e block
  * solves on the operator's second stream, concurrent with the V-cycle
- * (chosen lanes 1 if kept; rows and nnz hold ndof and the block count),
+ * (chosen lanes 1 if kept; the threshold column holds the V-cycle level
+ * after whose down-leg they start; rows and nnz hold ndof and the block
+ * count),
  * level, rows (ndof), nnz (elements), chosen threshold (records per pass),
  * chosen lanes (elements per workgroup; 1 if the level is fused), ns before,
  * ns after); *n rows written. A fused level (one RHS, at most 4M nonzeros)

@@ -297,6 +297,7 @@ struct hpdg_operator {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int b_fork = 0;
   int b_fork_env = -1;       // HPDG_B_FORK, when set
+  int fork_level = 0;        // the block solves start after this V-cycle level's down-leg (autotuned)
   PcgRun run;
   ~hpdg_operator() {
     for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
@@ -434,28 +435,52 @@ static inline double dot4(const double* a, const double* b, int n) {
 // A^{-1} = W^T W; throws if A is not positive definite
 static void spd_inverse(std::vector<double>& A, int n) {
   std::vector<double> L(A);
-  for (int i = 0; i < n; ++i) {
-    double* li = &L[(size_t)i * n];
-    for (int j = 0; j < i; ++j) {
+  // rows in groups of four: each finished row j below the group is read once
+  // for the four rows' entries in column j (same sums as row by row)
+  for (int i0 = 0; i0 < n; i0 += 4) {
+    const int i1 = std::min(n, i0 + 4);
+    for (int j = 0; j < i0; ++j) {
       const double* lj = &L[(size_t)j * n];
-      li[j] = (li[j] - dot4(li, lj, j)) / lj[j];
+      for (int i = i0; i < i1; ++i) {
+        double* li = &L[(size_t)i * n];
+        li[j] = (li[j] - dot4(li, lj, j)) / lj[j];
+      }
     }
-    const double s = li[i] - dot4(li, li, i);
-    if (!(s > 0)) throw Error(HPDG_E_NOT_SPD, "V_e block is not positive definite");
-    li[i] = std::sqrt(s);
+    for (int i = i0; i < i1; ++i) {
+      double* li = &L[(size_t)i * n];
+      for (int j = i0; j < i; ++j) {
+        const double* lj = &L[(size_t)j * n];
+        li[j] = (li[j] - dot4(li, lj, j)) / lj[j];
+      }
+      const double s = li[i] - dot4(li, li, i);
+      if (!(s > 0)) throw Error(HPDG_E_NOT_SPD, "V_e block is not positive definite");
+      li[i] = std::sqrt(s);
+    }
   }
   // W lower triangular, row by row: W[i][j] = (delta_ij - sum_{j<=k<i} L[i][k] W[k][j]) / L[i][i]
   std::vector<double> W((size_t)n * n, 0.0);
-  for (int i = 0; i < n; ++i) {
-    const double inv = 1.0 / L[i * n + i];
-    double* wi = &W[(size_t)i * n];
-    for (int k = 0; k < i; ++k) {
-      const double lik = L[i * n + k];
+  for (int i0 = 0; i0 < n; i0 += 4) {
+    const int i1 = std::min(n, i0 + 4);
+    // rows of W below the group are final: each is read once for the group
+    for (int k = 0; k < i0; ++k) {
       const double* wk = &W[(size_t)k * n];
-      for (int j = 0; j <= k; ++j) wi[j] -= lik * wk[j];
+      for (int i = i0; i < i1; ++i) {
+        const double lik = L[(size_t)i * n + k];
+        double* wi = &W[(size_t)i * n];
+        for (int j = 0; j <= k; ++j) wi[j] -= lik * wk[j];
+      }
     }
-    for (int j = 0; j < i; ++j) wi[j] *= inv;
-    wi[i] = inv;
+    for (int i = i0; i < i1; ++i) {
+      const double inv = 1.0 / L[(size_t)i * n + i];
+      double* wi = &W[(size_t)i * n];
+      for (int k = i0; k < i; ++k) {
+        const double lik = L[(size_t)i * n + k];
+        const double* wk = &W[(size_t)k * n];
+        for (int j = 0; j <= k; ++j) wi[j] -= lik * wk[j];
+      }
+      for (int j = 0; j < i; ++j) wi[j] *= inv;
+      wi[i] = inv;
+    }
   }
   // A^{-1}[i][k] = sum_{m >= max(i,k)} W[m][i] W[m][k]: rows of A in groups
   // of four, each row of W read once per group
@@ -1044,6 +1069,7 @@ extern "C" hpdg_status hpdg_setup_operator(const hpdg_mesh* mh, const hpdg_opera
     if (const char* v = std::getenv("HPDG_ELEM3D_SPLIT")) op->split3 = std::atoi(v) != 0;
     if (const char* v = std::getenv("HPDG_BLOCK_WG")) op->blk_wg = std::atoi(v) != 0;
     if (const char* v = std::getenv("HPDG_B_FORK")) op->b_fork_env = std::atoi(v) != 0 ? 1 : 0;
+    if (const char* v = std::getenv("HPDG_FORK_LEVEL")) op->fork_level = std::max(0, std::atoi(v));
     if (const char* v = std::getenv("HPDG_BLOCK_LANES")) {
       const int l = std::atoi(v);
       op->lprb = (l == 1 || l == 2 || l == 4 || l == 8 || l == 32) ? l : 16;
@@ -1368,9 +1394,9 @@ static void dense_many(hpdg_operator* op, int n, int nrhs, const T* C, const T* 
     hipLaunchKernelGGL(k_dense_gemm<T>, dim3(n), dim3(256), 0, s, n, nrhs, C, b, x);
 }
 
-// at_coarse (if set) is called once the level's own down-leg is enqueued,
-// before the coarser levels (at the start where the level has no down-leg of
-// its own)
+// at_coarse (if set) is called once, after the down-leg of level
+// op->fork_level is enqueued (at the start of the first level below it that
+// has no down-leg of its own: fused, dense tail or coarsest)
 template <typename T>
 static void vcycle(hpdg_operator* op, const BWork& W, size_t l, int nrhs, hipStream_t s,
                    const std::function<void()>* at_coarse) {
@@ -1415,8 +1441,9 @@ static void vcycle(hpdg_operator* op, const BWork& W, size_t l, int nrhs, hipStr
   }
   // restriction b_c = P^T r
   spmv<T, 0>(L.R, nrhs, r, nullptr, nullptr, nullptr, bc, s);
-  if (at_coarse) (*at_coarse)();
-  vcycle<T>(op, W, l + 1, nrhs, s);
+  const bool here = at_coarse && (int)l >= op->fork_level;
+  if (here) (*at_coarse)();
+  vcycle<T>(op, W, l + 1, nrhs, s, here ? nullptr : at_coarse);
   // t = x + P x_c ; x = t + D (b - A t)
   spmv<T, 2>(L.P, nrhs, xc, x, nullptr, nullptr, t, s);
   spmv<T, 4>(L.A, nrhs, t, b, L.l1inv.as<T>(), nullptr, x, s);
@@ -1762,19 +1789,29 @@ static int tune_all(hpdg_operator* op, hipStream_t s, int64_t* report, int cap) 
       HIPCHK(hipEventElapsedTime(&ms, e0, e1));
       return (double)ms * 1e6 / reps;
     };
-    const int def = op->b_fork;
+    const int def = op->b_fork, def_lv = op->fork_level;
     const double t_def = time_b();
-    op->b_fork = 1 - def;
-    const double t_alt = time_b();
-    const bool flip = t_alt < kTuneMargin * t_def;
-    if (!flip) op->b_fork = def;
+    double best = t_def * kTuneMargin;
+    int bf = def, bl = def_lv;
+    const int nlv = std::min<int>(3, (int)op->lv.size());
+    for (int f : {0, 1})
+      for (int lv = 0; lv < (f ? nlv : 1); ++lv) {
+        if (f == def && (f == 0 || lv == def_lv)) continue;
+        op->b_fork = f;
+        op->fork_level = lv;
+        const double t = time_b();
+        if (t < best) { best = t; bf = f; bl = lv; }
+      }
+    if (bf == def && (bf == 0 || bl == def_lv)) best = t_def;
+    op->b_fork = bf;
+    op->fork_level = bl;
     int64_t* r = slot(11, 0);
     r[0] = op->ndof;
     r[1] = op->nblocks;
-    r[2] = 0;
+    r[2] = op->fork_level;
     r[3] = op->b_fork;
     r[4] = (int64_t)t_def;
-    r[5] = (int64_t)(flip ? t_alt : t_def);
+    r[5] = (int64_t)best;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
