@@ -61,7 +61,7 @@ def main():
     ap.add_argument("--requests", type=int, default=2000, help="serving (--config 5): number of requests")
     ap.add_argument("--rate", type=float, default=0.0,
                     help="serving: Poisson arrival rate in requests/s (0: all arrive at the start)")
-    ap.add_argument("--workers", type=int, default=8, help="serving: host setup threads")
+    ap.add_argument("--workers", type=int, default=14, help="serving: host setup threads")
     ap.add_argument("--max-active", type=int, default=16, help="serving: solves in flight")
     ap.add_argument("--serving-graph", type=int, default=0, help="serving: 1 replays CG chunks from HIP graphs")
     ap.add_argument("--serving-auto-cycle", type=int, default=1,

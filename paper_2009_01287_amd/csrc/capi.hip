@@ -107,15 +107,17 @@ void bin_rows(const CSR& A, DevCSR& D, int longrow, int lpr);
 // Device CSR: every row padded to a multiple of 4 entries (value 0, column
 // of the row's last entry), so that the one-RHS product reads 4-entry
 // chunks with vector loads; kernels that walk a row entry by entry add the
-// padding's zero products and get the same sums.
+// padding's zero products and get the same sums. pad = false keeps the rows
+// as they are (a matrix only such kernels read).
 template <typename T>
-void upload_csr(const CSR& A, DevCSR& D) {
+void upload_csr(const CSR& A, DevCSR& D, bool pad = true) {
   const int64_t n = A.nrows;
+  const int64_t rm = pad ? 3 : 0;
   std::vector<int32_t> p32((size_t)n + 1);
   int64_t tot = 0;
   for (int64_t i = 0; i < n; ++i) {
     p32[i] = (int32_t)tot;
-    tot += (A.ptr[i + 1] - A.ptr[i] + 3) & ~(int64_t)3;
+    tot += (A.ptr[i + 1] - A.ptr[i] + rm) & ~rm;
     if (tot > (int64_t)INT32_MAX) throw Error(HPDG_E_UNSUPPORTED, "matrix too large");
   }
   p32[n] = (int32_t)tot;
@@ -677,7 +679,7 @@ static void upload_prec(hpdg_operator* op) {
   }
   // block inverses were computed in FP64 (binv64) during setup
   op->blk_inv.alloc(0);
-  upload_csr<T>(H.P, op->P);
+  upload_csr<T>(H.P, op->P, false);   // read row by row (k_prolong_out): no padding
   upload_csr<T>(H.PT, op->PT);
   if (H.amg.lv.size() > (size_t)kMaxLevels) throw Error(HPDG_E_UNSUPPORTED, "too many AMG levels");
   op->lv.clear();
@@ -1123,14 +1125,22 @@ extern "C" hpdg_status hpdg_setup_operator(const hpdg_mesh* mh, const hpdg_opera
         std::mutex emu;
         int ecode = 0;
         std::string emsg;
+        std::atomic<int64_t> ns_asm{0}, ns_inv{0};   // summed over threads (verbose timing)
         parallel_chunks(std::min<int64_t>(setup_threads(), std::max<int64_t>(1, nbk)),
                         [&](int64_t, int64_t, int) {
                           for (;;) {
                             const int64_t b = next.fetch_add(1);
                             if (b >= nbk) break;
                             try {
+                              const auto c0 = std::chrono::steady_clock::now();
                               std::vector<double> S = dg_submatrix(M, oo, H.blocks[b], eta2);
+                              const auto c1 = std::chrono::steady_clock::now();
                               spd_inverse(S, (int)H.blocks[b].size());
+                              const auto c2 = std::chrono::steady_clock::now();
+                              if (verbose) {
+                                ns_asm += std::chrono::duration_cast<std::chrono::nanoseconds>(c1 - c0).count();
+                                ns_inv += std::chrono::duration_cast<std::chrono::nanoseconds>(c2 - c1).count();
+                              }
                               std::copy(S.begin(), S.end(), binv.begin() + boff[b]);
                             } catch (Error& e) {
                               std::lock_guard<std::mutex> lk(emu);
@@ -1145,6 +1155,9 @@ extern "C" hpdg_status hpdg_setup_operator(const hpdg_mesh* mh, const hpdg_opera
                         },
                         1);
         if (ecode) throw Error(ecode, emsg);
+        if (verbose)
+          std::fprintf(stderr, "hpdg setup:   block assembly %.3f s, inverses %.3f s (summed over threads)\n",
+                       1e-9 * (double)ns_asm.load(), 1e-9 * (double)ns_inv.load());
       }
       phase("blocks");
       H.P = prolongation(M);
