@@ -367,3 +367,117 @@ def test_labels_match_geometric_definition(md):
     assert np.array_equal(inJ, gJ) and np.array_equal(inN, gN)
     if len(set(m.p.tolist())) > 1 and m.size.min() < m.size.max():
         assert inN.any()
+
+
+def _labels_by_geometry_3d(m):
+    """3D counterpart of _labels_by_geometry on integer coordinates: a
+    vertex or edge is hanging when some leaf whose closed cube contains it
+    does not have it as a corner or edge, and hp when the leaves containing
+    it have more than one degree; a DOF is in V_J if its node is a regular
+    vertex, lies inside a face shared whole with one neighbour of the same
+    degree (or on the domain boundary), or lies on a face of its leaf whose
+    master (the face of a larger neighbour containing it, else the face
+    itself) contains no hp vertex or edge in its closed square."""
+    ne, d = m.ne, 3
+    lo = [tuple(int(v) for v in m.lo[e]) for e in range(ne)]
+    sz = [int(m.size[e]) for e in range(ne)]
+    pe = [int(m.p[e]) for e in range(ne)]
+
+    def box_contains(e, a, b):
+        # closed cube of e contains the closed box [a, b]
+        return all(lo[e][k] <= a[k] and b[k] <= lo[e][k] + sz[e] for k in range(d))
+
+    def corners(e):
+        return {tuple(lo[e][k] + (sz[e] if (c >> k) & 1 else 0) for k in range(d)) for c in range(8)}
+
+    def edges(e):
+        out = set()
+        for k in range(d):
+            for c in range(8):
+                if (c >> k) & 1:
+                    continue
+                a = tuple(lo[e][j] + (sz[e] if (c >> j) & 1 else 0) for j in range(d))
+                b = tuple(a[j] + (sz[e] if j == k else 0) for j in range(d))
+                out.add((a, b))
+        return out
+
+    verts = set().union(*(corners(e) for e in range(ne)))
+    eds = set().union(*(edges(e) for e in range(ne)))
+    hp = []
+    for v in verts:
+        cont = [e for e in range(ne) if box_contains(e, v, v)]
+        if any(v not in corners(e) for e in cont) and len({pe[e] for e in cont}) > 1:
+            hp.append((v, v))
+    for a, b in eds:
+        cont = [e for e in range(ne) if box_contains(e, a, b)]
+        if any((a, b) not in edges(e) for e in cont) and len({pe[e] for e in cont}) > 1:
+            hp.append((a, b))
+
+    def face(e, k, s):
+        x = lo[e][k] + s * sz[e]
+        a = tuple(x if j == k else lo[e][j] for j in range(d))
+        b = tuple(x if j == k else lo[e][j] + sz[e] for j in range(d))
+        return a, b
+
+    def across(e, k, s):
+        a, b = face(e, k, s)
+        out = []
+        for f in range(ne):
+            if f == e or lo[f][k] + (1 - s) * sz[f] != a[k]:
+                continue
+            if all(lo[f][j] < b[j] and a[j] < lo[f][j] + sz[f] for j in range(d) if j != k):
+                out.append(f)
+        return out
+
+    def master(e, k, s):
+        big = [f for f in across(e, k, s) if sz[f] > sz[e]]
+        return face(big[0], k, 1 - s) if big else face(e, k, s)
+
+    def hp_free(F):
+        a, b = F
+        return not any(all(a[j] <= x[j] and y[j] <= b[j] for j in range(d)) for x, y in hp)
+
+    inJ = np.zeros(m.ndof, dtype=bool)
+    inN = np.zeros(m.ndof, dtype=bool)
+    for e in range(ne):
+        p = pe[e]
+        for r, idx in enumerate(m.node_index(e)):
+            on = [k for k in range(d) if idx[k] in (0, p)]
+            if not on:
+                continue
+            g = int(m.off[e]) + r
+            sides = [(k, 1 if idx[k] == p else 0) for k in on]
+            j = False
+            if len(on) == 3:
+                v = tuple(lo[e][k] + (sz[e] if idx[k] == p else 0) for k in range(d))
+                j = not any(v not in corners(f) for f in range(ne) if box_contains(f, v, v))
+            elif len(on) == 1:
+                k, s = sides[0]
+                nb = across(e, k, s)
+                whole = len(nb) == 1 and sz[nb[0]] == sz[e]
+                j = not nb or (whole and pe[nb[0]] == p)
+            if not j:
+                j = any(hp_free(master(e, k, s)) for k, s in sides)
+            inJ[g] = j
+            inN[g] = not j
+    return inJ, inN
+
+
+@pytest.mark.parametrize("md", [
+    H.hanging_mesh(3, 2, seed=2, pmin=1, pmax=4),
+    H.random_mesh(3, 2, 0.5, 1, 1, 4, seed=2),
+    H.random_mesh(3, 2, 0.4, 2, 1, 3, seed=5),
+    H.random_mesh(3, 2, 0.5, 1, 2, 2, seed=9),
+    H.random_mesh(3, 2, 0.5, 2, 1, 4, seed=2),
+])
+def test_labels_match_geometric_definition_3d(md):
+    """3D: the oracle's V_J / N split agrees DOF by DOF with the Sec. 3.3
+    definitions (hp vertices and edges, whole conforming faces, masters
+    free of hp entities) evaluated on the leaf cubes' integer coordinates.
+    (The last mesh has a fine face whose master holds an hp vertex outside
+    the fine face; hp edges add nothing here, their end points being hp
+    vertices of the same leaves.)"""
+    m = O.Mesh(md)
+    inJ, inN = precond.labels(m)
+    gJ, gN = _labels_by_geometry_3d(m)
+    assert np.array_equal(inJ, gJ) and np.array_equal(inN, gN), (int((inJ != gJ).sum()), int(inJ.sum()))
