@@ -1199,12 +1199,17 @@ __device__ inline void e3f_body(const FaceRec& r, const FaceAux& ax, int form, d
   const bool inner = r.nbr >= 0;
   const int po = inner ? (int)r.pn : 0, no = po + 1, no2 = no * no;
   const int mno = 65536 / no + 1;
-  // the ten 1D face matrices: staged in LDS (STAGE) or read through the
-  // caches from the face table
+  // the ten 1D face matrices: with STAGE the six of stages 1-2 staged in
+  // LDS and the four BR2 lifting matrices (stages 3-4, read once per node)
+  // through the caches; without, all ten through the caches
   const double* MP[10];
   if (STAGE) {
 #pragma unroll
-    for (int k = 0; k < 10; ++k) MP[k] = Mx + k * F2;
+    for (int k = 0; k < 6; ++k) MP[k] = Mx + k * F2;
+    MP[6] = ftab + r.loo[0];
+    MP[7] = ftab + r.loo[1];
+    MP[8] = ftab + r.lon[0];
+    MP[9] = ftab + r.lon[1];
   } else {
     MP[0] = ftab + r.foo[0];
     MP[1] = ftab + r.foo[1];
@@ -1232,9 +1237,8 @@ __device__ inline void e3f_body(const FaceRec& r, const FaceAux& ax, int form, d
         W[F2 + q] = kn * sn[no2 + q];
       }
     }
-    // A0oo A1oo (n x n), A0on A1on (n x no), then for BR2 A0nn A1nn (no x no),
-    // L0o L1o (n x n), L0n L1n (n x no)
-    const int nm = !STAGE ? 0 : form == 1 ? 10 : (inner ? 4 : 2);
+    // A0oo A1oo (n x n), A0on A1on (n x no), then for BR2 A0nn A1nn (no x no)
+    const int nm = !STAGE ? 0 : form == 1 ? 6 : (inner ? 4 : 2);
     for (int t = lane; t < nm * F2; t += 64) {
       const int kx = t / F2, i = t - kx * F2;
       int sz = n2, o = -1;
@@ -1446,7 +1450,7 @@ __global__ __launch_bounds__(256) void k_e3_face(int nrec, int form, const FaceR
   __shared__ FaceRec sR[4];
   __shared__ FaceAux sAx[4];
   __shared__ double sW[4][10][F2];    // 0 Tn -> v, 1 Dn -> vn, 2 U0 -> P0, 3 U1 -> Q0, 4 U2, 5 U3, 6 Y0, 7 Y1, 8 To, 9 Do
-  __shared__ double sM[STAGE ? 4 : 1][STAGE ? 10 : 1][STAGE ? F2 : 1];   // A0oo A1oo A0on A1on A0nn A1nn L0o L1o L0n L1n
+  __shared__ double sM[STAGE ? 4 : 1][STAGE ? 6 : 1][STAGE ? F2 : 1];    // A0oo A1oo A0on A1on A0nn A1nn
   const int w = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
   const int rec = blockIdx.x * 4 + w;
   if (rec >= nrec) return;            // whole wavefronts only: no block-wide barrier below
