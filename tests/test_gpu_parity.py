@@ -207,6 +207,28 @@ def test_block_solves_on_second_stream_bitwise(monkeypatch, name, fp32):
         assert torch.equal(z, out[0][0]) and torch.equal(x, out[0][1]) and it == out[0][2]
 
 
+@pytest.mark.parametrize("fp32", [False, True])
+def test_block_solve_start_level_bitwise(monkeypatch, fp32):
+    """The block solves on the second stream started after the down-leg of
+    V-cycle level 0, 1 or 2 give bitwise the same B r (only the overlap
+    changes), on a 3D mesh whose AMG has at least three levels."""
+    md = H.random_mesh(3, 6, 0.3, 1, 1, 4, seed=91)
+    m = G.Mesh(md)
+    r = torch.from_numpy(H.gaussian_rhs(m.ndof, 92)).cuda()
+    out = []
+    for lv in ("0", "1", "2"):
+        monkeypatch.setenv("HPDG_BLOCK_WG", "1")
+        monkeypatch.setenv("HPDG_B_FORK", "1")
+        monkeypatch.setenv("HPDG_FORK_LEVEL", lv)
+        op = G.Operator(m, prec_fp32=fp32, max_block=256)
+        if lv == "0":
+            assert len(op.amg_levels()) >= 3
+        z = torch.empty_like(r)
+        op.apply_B(r, z)
+        out.append(z)
+    assert torch.equal(out[0], out[1]) and torch.equal(out[0], out[2])
+
+
 @pytest.mark.parametrize("name", ["hang2", "hang3"])
 def test_rhs_matches_oracle(name):
     md = MESHES[name]()
