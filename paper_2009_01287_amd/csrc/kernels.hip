@@ -1260,8 +1260,10 @@ __device__ inline void e3f_body(const FaceRec& r, const FaceAux& ax, int form, d
   wave_sync();
   // stage 1: U0 = A0oo To, U1 = A0oo Do (n x n), U2 = A0on Tn, U3 = A0on Dn
   // (n x no); BR2: Y0 = A0on^T To stored transposed, Y0[a1 + n a0] (a0 < no,
-  // a1 < n), Y1 = A0nn Tn (no x no)
-  // (a lane forms both products of its node, reading each matrix entry once)
+  // a1 < n), Y1 = A0nn Tn (no x no). In two halves: first the products of
+  // the own traces (slots 2, 3, 4), then those of the neighbour's into the
+  // own traces' slots 6, 7 and slot 5 (a lane forms both products of its
+  // node, reading each matrix entry once)
   constexpr int QF = (F2 + 63) / 64;
 #pragma unroll
   for (int t = 0; t < QF; ++t) {
@@ -1278,6 +1280,17 @@ __device__ inline void e3f_body(const FaceRec& r, const FaceAux& ax, int form, d
     W[2 * F2 + q] = s0;
     W[3 * F2 + q] = s1;
   }
+  if (inner && form == 1) {
+    const double* A = MP[2];
+    for (int q = lane; q < n * no; q += 64) {
+      const int a1 = q % n, a0 = q / n;
+      double s = 0.0;
+#pragma unroll
+      for (int j0 = 0; j0 < n; ++j0) s += A[j0 * no + a0] * To[j0 + n * a1];
+      W[4 * F2 + q] = s;
+    }
+  }
+  wave_sync();
   if (inner) {
     const double* A = MP[2];
 #pragma unroll
@@ -1293,17 +1306,10 @@ __device__ inline void e3f_body(const FaceRec& r, const FaceAux& ax, int form, d
           s0 += av * W[a0 + no * a1];
           s1 += av * W[F2 + a0 + no * a1];
         }
-      W[4 * F2 + q] = s0;
-      W[5 * F2 + q] = s1;
+      W[6 * F2 + q] = s0;
+      W[7 * F2 + q] = s1;
     }
     if (form == 1) {
-      for (int q = lane; q < n * no; q += 64) {
-        const int a1 = q % n, a0 = q / n;
-        double s = 0.0;
-#pragma unroll
-        for (int j0 = 0; j0 < n; ++j0) s += A[j0 * no + a0] * To[j0 + n * a1];
-        W[6 * F2 + q] = s;
-      }
       const double* Ann = MP[4];
       for (int q = lane; q < no2; q += 64) {
         const int a1 = qdiv(q, mno), a0 = q - a1 * no;
@@ -1311,7 +1317,7 @@ __device__ inline void e3f_body(const FaceRec& r, const FaceAux& ax, int form, d
 #pragma unroll
         for (int b0 = 0; b0 < NM; ++b0)
           if (b0 < no) s += Ann[a0 * no + b0] * W[b0 + no * a1];
-        W[7 * F2 + q] = s;
+        W[5 * F2 + q] = s;
       }
     }
   }
@@ -1346,8 +1352,8 @@ __device__ inline void e3f_body(const FaceRec& r, const FaceAux& ax, int form, d
       for (int a1 = 0; a1 < NM; ++a1)
         if (a1 < no) {
           const double wv = A1on[j1 * no + a1];
-          v -= wv * W[4 * F2 + j0 + n * a1];
-          ds += wv * W[5 * F2 + j0 + n * a1];
+          v -= wv * W[6 * F2 + j0 + n * a1];
+          ds += wv * W[7 * F2 + j0 + n * a1];
         }
     }
     double g1 = -area * csym * sgn * ds;
@@ -1363,10 +1369,10 @@ __device__ inline void e3f_body(const FaceRec& r, const FaceAux& ax, int form, d
       const int b1 = qdiv(q, mno), a0 = q - b1 * no;
       double vn = 0.0;
 #pragma unroll
-      for (int a1 = 0; a1 < n; ++a1) vn += A1on[a1 * no + b1] * W[6 * F2 + a1 + n * a0];
+      for (int a1 = 0; a1 < n; ++a1) vn += A1on[a1 * no + b1] * W[4 * F2 + a1 + n * a0];
 #pragma unroll
       for (int c1 = 0; c1 < NM; ++c1)
-        if (c1 < no) vn -= A1nn[b1 * no + c1] * W[7 * F2 + a0 + no * c1];
+        if (c1 < no) vn -= A1nn[b1 * no + c1] * W[5 * F2 + a0 + no * c1];
       W[F2 + q] = vn;
     }
   }
@@ -1449,7 +1455,7 @@ __global__ __launch_bounds__(256) void k_e3_face(int nrec, int form, const FaceR
   constexpr int F2 = NM * NM;
   __shared__ FaceRec sR[4];
   __shared__ FaceAux sAx[4];
-  __shared__ double sW[4][10][F2];    // 0 Tn -> v, 1 Dn -> vn, 2 U0 -> P0, 3 U1 -> Q0, 4 U2, 5 U3, 6 Y0, 7 Y1, 8 To, 9 Do
+  __shared__ double sW[4][8][F2];     // 0 Tn -> v, 1 Dn -> vn, 2 U0 -> P0, 3 U1 -> Q0, 4 Y0, 5 Y1, 6 To -> U2, 7 Do -> U3
   __shared__ double sM[STAGE ? 4 : 1][STAGE ? 6 : 1][STAGE ? F2 : 1];    // A0oo A1oo A0on A1on A0nn A1nn
   const int w = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
   const int rec = blockIdx.x * 4 + w;
@@ -1464,8 +1470,8 @@ __global__ __launch_bounds__(256) void k_e3_face(int nrec, int form, const FaceR
   wave_sync();
   double* W = &sW[w][0][0];
   double* Mx = STAGE ? &sM[w][0][0] : nullptr;
-  double* To = W + 8 * F2;             // last read in stage 1
-  double* Do = W + 9 * F2;
+  double* To = W + 6 * F2;             // last read in the first half of stage 1
+  double* Do = W + 7 * F2;
   switch (sAx[w].p) {
     case 1: e3f_body<2, NM, STAGE>(sR[w], sAx[w], form, To, Do, W, Mx, ftab, tab, TL, sb, gbuf, lane); break;
     case 2: e3f_body<3, NM, STAGE>(sR[w], sAx[w], form, To, Do, W, Mx, ftab, tab, TL, sb, gbuf, lane); break;
