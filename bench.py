@@ -116,6 +116,8 @@ def main():
                     max_block=0, graph=use_graph)
     t_setup = time.time() - t0
     tuned = None if args.no_tune else op.tune()
+    if tuned:
+        print(json.dumps({"autotune": tuned}), file=sys.stderr, flush=True)
     n = mesh.ndof
     if cfg == 1:
         X = op.node_coords()

@@ -299,7 +299,8 @@ struct hpdg_operator {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int b_fork = 0;
   int b_fork_env = -1;       // HPDG_B_FORK, when set
-  int fork_level = 0;        // the block solves start after this V-cycle level's down-leg (autotuned)
+  int fork_level = 0;        // the block solves start after this V-cycle level's down-leg, -1: before the
+                             // B front (autotuned)
   PcgRun run;
   ~hpdg_operator() {
     for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
@@ -1071,7 +1072,7 @@ extern "C" hpdg_status hpdg_setup_operator(const hpdg_mesh* mh, const hpdg_opera
     if (const char* v = std::getenv("HPDG_ELEM3D_SPLIT")) op->split3 = std::atoi(v) != 0;
     if (const char* v = std::getenv("HPDG_BLOCK_WG")) op->blk_wg = std::atoi(v) != 0;
     if (const char* v = std::getenv("HPDG_B_FORK")) op->b_fork_env = std::atoi(v) != 0 ? 1 : 0;
-    if (const char* v = std::getenv("HPDG_FORK_LEVEL")) op->fork_level = std::max(0, std::atoi(v));
+    if (const char* v = std::getenv("HPDG_FORK_LEVEL")) op->fork_level = std::max(-1, std::atoi(v));
     if (const char* v = std::getenv("HPDG_BLOCK_LANES")) {
       const int l = std::atoi(v);
       op->lprb = (l == 1 || l == 2 || l == 4 || l == 8 || l == 32) ? l : 16;
@@ -1808,7 +1809,7 @@ static int tune_all(hpdg_operator* op, hipStream_t s, int64_t* report, int cap) 
     int bf = def, bl = def_lv;
     const int nlv = std::min<int>(3, (int)op->lv.size());
     for (int f : {0, 1})
-      for (int lv = 0; lv < (f ? nlv : 1); ++lv) {
+      for (int lv = f ? -1 : 0; lv < (f ? nlv : 1); ++lv) {
         if (f == def && (f == 0 || lv == def_lv)) continue;
         op->b_fork = f;
         op->fork_level = lv;
@@ -1950,9 +1951,32 @@ static int apply_B_dev(hpdg_operator* op, const BWork& W, const double* r, doubl
     rt = rT;
   }
   T* b0 = (T*)W.b[0];
-  bool forked = false;
+  auto gather = [&](hipStream_t g) {
+    if (op->blk_overlap)
+      hipLaunchKernelGGL(k_block_gather<T>, dim3(nblk(op->g_n * nrhs)), dim3(256), 0, g, (int)op->g_n, nrhs,
+                         op->g_dof.as<int32_t>(), op->g_ptr.as<int32_t>(), op->g_slot.as<int32_t>(), zb);
+  };
+  // forked: the block solves (they read only r and write only their own
+  // entries of z_B) run on the second stream, started once level
+  // op->fork_level's down-leg of the V-cycle is enqueued (or before the B
+  // front for level -1), so that they overlap latency-bound kernels, and
+  // are joined before z = z_B + P e
+  std::function<void()> fork_blocks = [&]() {
+    HIPCHK(hipEventRecord(op->ev_fork, s));
+    HIPCHK(hipStreamWaitEvent(op->aux, op->ev_fork, 0));
+    launch_block_rows<T>(op, rt, zb, op->aux);
+    gather(op->aux);
+    HIPCHK(hipEventRecord(op->ev_join, op->aux));
+  };
+  bool forked = false, early = false;
   if (nrhs == 1) {
-    forked = launch_front<T>(op, rt, zb, b0, s, allow_fork && op->b_fork);
+    const bool want = allow_fork && op->b_fork && op->aux && op->blk_wg && op->nblocks > 0 &&
+                      (size_t)blk_ld(op->max_blk) * sizeof(T) <= 64 * 1024;
+    if (want && op->fork_level < 0) {
+      fork_blocks();
+      early = true;
+    }
+    forked = launch_front<T>(op, rt, zb, b0, s, want);
   } else {
     if (!lowp)
       hipLaunchKernelGGL(k_diag_scale<T>, dim3(nblk(n)), dim3(256), 0, s, n, nrhs, op->dinvJ.as<T>(), rt, zb);
@@ -1976,24 +2000,8 @@ static int apply_B_dev(hpdg_operator* op, const BWork& W, const double* r, doubl
     }
     spmv<T, 0>(op->PT, nrhs, rt, nullptr, nullptr, nullptr, b0, s);
   }
-  auto gather = [&](hipStream_t g) {
-    if (op->blk_overlap)
-      hipLaunchKernelGGL(k_block_gather<T>, dim3(nblk(op->g_n * nrhs)), dim3(256), 0, g, (int)op->g_n, nrhs,
-                         op->g_dof.as<int32_t>(), op->g_ptr.as<int32_t>(), op->g_slot.as<int32_t>(), zb);
-  };
-  // forked: the block solves (they read only r and write only their own
-  // entries of z_B) start on the second stream once level 0's down-leg is
-  // enqueued, so that they overlap the latency-bound coarse levels rather
-  // than the bandwidth-bound level-0 smoothing product
-  std::function<void()> fork_blocks = [&]() {
-    HIPCHK(hipEventRecord(op->ev_fork, s));
-    HIPCHK(hipStreamWaitEvent(op->aux, op->ev_fork, 0));
-    launch_block_rows<T>(op, rt, zb, op->aux);
-    gather(op->aux);
-    HIPCHK(hipEventRecord(op->ev_join, op->aux));
-  };
   if (!forked) gather(s);
-  vcycle<T>(op, W, 0, nrhs, s, forked ? &fork_blocks : nullptr);
+  vcycle<T>(op, W, 0, nrhs, s, forked && !early ? &fork_blocks : nullptr);
   if (forked) HIPCHK(hipStreamWaitEvent(s, op->ev_join, 0));
   int64_t nt = op->ndof * nrhs;
   if (nrhs != 1) pdot = nullptr;
