@@ -71,7 +71,8 @@ def main():
                     help="serving: comma-separated multiples of the capacity (solves/s of the "
                          "mixed-precision pipeline with every request at t = 0, measured first) at which "
                          "Poisson arrival streams of --sweep-requests requests are served by the same "
-                         "pipeline, e.g. 0.3,0.5,0.7,0.9")
+                         "pipeline, e.g. 0.3,0.5,0.7,0.9; one more stream runs at 0.7 x the FP64 "
+                         "pipeline's capacity")
     ap.add_argument("--sweep-requests", type=int, default=600)
     ap.add_argument("--study", choices=["eta", "random"], default=None,
                     help="eta: penalty-dependence study (SIPG and BR2, eta = 10..1e4, full B against the "
@@ -535,25 +536,29 @@ def _serve(reqs_spec, prec, args, realtime):
 
 def serve_sweep(args):
     """Serving latency against load: the mixed-precision pipeline's own
-    capacity C (all --requests requests at t = 0), then Poisson streams of
-    --sweep-requests requests at rate f x C for each f of --lambda-sweep,
-    served by the same pipeline; one JSON line with the p50/p99 per rate."""
+    capacity C and the FP64 pipeline's capacity C64 (all --requests requests
+    at t = 0), then Poisson streams of --sweep-requests requests served by
+    the mixed pipeline at rate f x C for each f of --lambda-sweep and at
+    0.7 x C64; one JSON line with the p50/p99 per rate."""
     import torch
     import hpinputs as H
     torch.zeros(1, device="cuda")
     cap = _serve(H.serving_stream(args.requests, seed=5005), "mixed", args, False)
     print(json.dumps({"serving_capacity": cap}), file=sys.stderr, flush=True)
-    C = cap["solves_per_s"]
+    cap64 = _serve(H.serving_stream(args.requests, seed=5005), "fp64", args, False)
+    print(json.dumps({"serving_capacity_fp64": cap64}), file=sys.stderr, flush=True)
+    C, C64 = cap["solves_per_s"], cap64["solves_per_s"]
     rows = []
-    for f in [float(v) for v in args.lambda_sweep.split(",") if v]:
-        rate = f * C
+    points = [("capacity", float(v)) for v in args.lambda_sweep.split(",") if v] + [("fp64_capacity", 0.7)]
+    for base, f in points:
+        rate = f * (C if base == "capacity" else C64)
         s = _serve(H.serving_stream(args.sweep_requests, seed=5005, rate=rate), "mixed", args, True)
-        row = {"factor": f, "rate": rate, "solves_per_s": s["solves_per_s"], "p50_ms": s["p50_s"] * 1e3,
-               "p99_ms": s["p99_s"] * 1e3, "ok": s["ok"], "requests": s["requests"],
+        row = {"factor": f, "of": base, "rate": rate, "solves_per_s": s["solves_per_s"],
+               "p50_ms": s["p50_s"] * 1e3, "p99_ms": s["p99_s"] * 1e3, "ok": s["ok"], "requests": s["requests"],
                "max_true_rel_res": s["max_true_rel_res"]}
         rows.append(row)
         print(json.dumps({"serving_sweep_point": row}), file=sys.stderr, flush=True)
-    print(json.dumps({"serving_sweep": {"capacity_solves_per_s": C, "capacity_prec": "mixed",
+    print(json.dumps({"serving_sweep": {"capacity_solves_per_s": C, "fp64_capacity_solves_per_s": C64,
                                         "capacity_requests": args.requests,
                                         "points": rows, "workers": args.workers,
                                         "max_active": args.max_active}}))
