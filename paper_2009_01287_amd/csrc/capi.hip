@@ -264,6 +264,11 @@ struct hpdg_operator {
   int epb = 1;               // elements per workgroup of the 2D element kernel
   int nm3 = 9;               // LDS size class of the 3D element kernel: largest n = p + 1 (7 or 9)
   DevBuf elem_perm;          // 3D elements by decreasing cost within each XCD's share
+  // 2D elements of degree <= c and > c in mesh order, c = 5..8 (index c - 5):
+  // the lane-per-right-hand-side kernel and the grouped kernel of the
+  // several-RHS apply
+  DevBuf e2r_lo[4], e2r_hi[4];
+  int n_e2r_lo[4] = {0, 0, 0, 0}, n_e2r_hi[4] = {0, 0, 0, 0};
   // 3D, one RHS: the operator in three passes (k_e3_vol, k_e3_face,
   // k_e3_lift) with the side buffer and the per-record face contributions
   int split3 = 1;
@@ -281,7 +286,10 @@ struct hpdg_operator {
   };
   std::vector<HostCycle> hcyc;
   int fchunk = 16;           // face records per pass of the 2D element kernel
-  int rhs_group = 1;         // right-hand sides per item of the 2D element kernel
+  int rhs_group = 1;         // right-hand sides per item of the 2D element kernel; 0: a lane per
+                             // right-hand side (k_elem2d_rhs) for degrees <= 5 when nrhs > 1
+  int rhs_group_hi = 4;      // with rhs_group 0: the group size of the degrees above e2r_split
+  int e2r_split = 5;         // with rhs_group 0: the highest degree on the lane form (5..8)
   struct GraphEntry {
     int k, nrhs;
     double* x;
@@ -816,6 +824,19 @@ static void upload_device(hpdg_operator* op, hipStream_t s) {
   op->dbucket.clear();
   op->dbucket.resize(kMaxP + 1);
   for (int p = 1; p <= kMaxP; ++p) op->dbucket[p].upload(op->bucket[p]);
+  if (op->dim == 2) {
+    for (int c = 5; c <= 8; ++c) {
+      std::vector<int32_t> lo, hi;
+      for (int p = 1; p <= kMaxP; ++p)
+        for (int32_t e : op->bucket[p]) (p <= c ? lo : hi).push_back(e);
+      std::sort(lo.begin(), lo.end());
+      std::sort(hi.begin(), hi.end());
+      op->n_e2r_lo[c - 5] = (int)lo.size();
+      op->n_e2r_hi[c - 5] = (int)hi.size();
+      op->e2r_lo[c - 5].upload(lo);
+      op->e2r_hi[c - 5].upload(hi);
+    }
+  }
   if (op->no_prec) {
   } else if (op->prec32) {
     upload_prec<float>(op);
@@ -1065,7 +1086,9 @@ extern "C" hpdg_status hpdg_setup_operator(const hpdg_mesh* mh, const hpdg_opera
     op->use_graph = o->graph ? 1 : 0;
     if (const char* v = std::getenv("HPDG_ELEM2D_EPB")) op->epb = std::atoi(v) == 2 ? 2 : 1;
     if (const char* v = std::getenv("HPDG_ELEM2D_FCHUNK")) op->fchunk = std::atoi(v) == 8 ? 8 : std::atoi(v) == 32 ? 32 : 16;
-    if (const char* v = std::getenv("HPDG_ELEM2D_RHSGROUP")) op->rhs_group = std::max(1, std::atoi(v));
+    if (const char* v = std::getenv("HPDG_ELEM2D_RHSGROUP")) op->rhs_group = std::max(0, std::atoi(v));
+    if (const char* v = std::getenv("HPDG_ELEM2D_RHSGROUP_HI")) op->rhs_group_hi = std::max(1, std::atoi(v));
+    if (const char* v = std::getenv("HPDG_ELEM2D_LANE_DEG")) op->e2r_split = std::min(8, std::max(5, std::atoi(v)));
     if (const char* v = std::getenv("HPDG_NO_MFMA")) op->no_mfma = std::atoi(v) != 0;
     if (const char* v = std::getenv("HPDG_NO_FUSED_MULTI")) op->no_fused_multi = std::atoi(v) != 0;
     if (const char* v = std::getenv("HPDG_ELEM3D_COST_ORDER")) op->use_perm = std::atoi(v) != 0;
@@ -1232,29 +1255,51 @@ static int apply_A_dev(hpdg_operator* op, const double* x, double* y, int nrhs, 
   if (nrhs != 1) pdot = nullptr;
   const int64_t items = (int64_t)op->ne * nrhs;   // (element, RHS) pairs
   if (op->dim == 2) {
-    const int rg = std::max(1, std::min(nrhs, op->rhs_group));
-    const int64_t items2 = (int64_t)op->ne * ((nrhs + rg - 1) / rg);   // (element, RHS group) pairs
-    auto launch = [&](auto epb_c, auto fc_c) {
-      constexpr int EPB = decltype(epb_c)::value, FC = decltype(fc_c)::value;
-      // grid a multiple of 8 workgroups of EPB items (XCD-aware order)
-      const unsigned grid = 8u * (unsigned)((items2 + 8 * EPB - 1) / (8 * EPB));
-      auto kern = rg > 1 ? k_elem2d<EPB, FC, true> : k_elem2d<EPB, FC, false>;
-      hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * EPB), 0, s, op->ne, nrhs, rg, op->form,
-                         op->off.as<int64_t>(), op->pdeg.as<int8_t>(), op->hh.as<double>(), op->kk.as<double>(),
-                         op->sptr.as<int32_t>(), op->recs.as<FaceRec>(), op->ftab.as<double>(),
-                         op->tab.as<double>(), op->TL, x, y, pdot);
+    // the element kernel with groups of rg right-hand sides per item over the
+    // elements of elist (all when null)
+    auto grouped = [&](int nel, const int32_t* elist, int rg) {
+      const int64_t items2 = (int64_t)nel * ((nrhs + rg - 1) / rg);   // (element, RHS group) pairs
+      auto launch = [&](auto epb_c, auto fc_c) {
+        constexpr int EPB = decltype(epb_c)::value, FC = decltype(fc_c)::value;
+        // grid a multiple of 8 workgroups of EPB items (XCD-aware order)
+        const unsigned grid = 8u * (unsigned)((items2 + 8 * EPB - 1) / (8 * EPB));
+        auto kern = rg > 1 ? k_elem2d<EPB, FC, true> : k_elem2d<EPB, FC, false>;
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * EPB), 0, s, nel, elist, nrhs, rg, op->form,
+                           op->off.as<int64_t>(), op->pdeg.as<int8_t>(), op->hh.as<double>(), op->kk.as<double>(),
+                           op->sptr.as<int32_t>(), op->recs.as<FaceRec>(), op->ftab.as<double>(),
+                           op->tab.as<double>(), op->TL, x, y, pdot);
+      };
+      using I1 = std::integral_constant<int, 1>;
+      using I2 = std::integral_constant<int, 2>;
+      auto with_fc = [&](auto epb_c) {
+        switch (op->fchunk) {
+          case 8: launch(epb_c, std::integral_constant<int, 8>()); break;
+          case 32: launch(epb_c, std::integral_constant<int, 32>()); break;
+          default: launch(epb_c, std::integral_constant<int, 16>()); break;
+        }
+      };
+      if (op->epb == 2) with_fc(I2());
+      else with_fc(I1());
     };
-    using I1 = std::integral_constant<int, 1>;
-    using I2 = std::integral_constant<int, 2>;
-    auto with_fc = [&](auto epb_c) {
-      switch (op->fchunk) {
-        case 8: launch(epb_c, std::integral_constant<int, 8>()); break;
-        case 32: launch(epb_c, std::integral_constant<int, 32>()); break;
-        default: launch(epb_c, std::integral_constant<int, 16>()); break;
+    if (nrhs > 1 && op->rhs_group == 0) {
+      // degrees up to e2r_split with a lane per right-hand side (one
+      // wavefront per element and 64 RHS), the others grouped: at high
+      // degree a wavefront of the lane form holds many values per lane and
+      // runs long, which the last wavefronts of the launch wait for
+      const int c = std::min(8, std::max(5, op->e2r_split)) - 5;
+      const int ng = (nrhs + 63) / 64;
+      const int nlo = op->n_e2r_lo[c], nhi = op->n_e2r_hi[c];
+      if (nlo > 0) {
+        const unsigned grid = 8u * (unsigned)(((int64_t)nlo * ng + 7) / 8);   // XCD-aware: multiple of 8
+        hipLaunchKernelGGL((c == 0 ? k_elem2d_rhs<6> : k_elem2d_rhs<9>), dim3(grid), dim3(64), 0, s, nlo,
+                           op->e2r_lo[c].as<int32_t>(), nrhs, op->form, op->off.as<int64_t>(),
+                           op->pdeg.as<int8_t>(), op->hh.as<double>(), op->kk.as<double>(), op->sptr.as<int32_t>(),
+                           op->recs.as<FaceRec>(), op->ftab.as<double>(), op->tab.as<double>(), op->TL, x, y);
       }
-    };
-    if (op->epb == 2) with_fc(I2());
-    else with_fc(I1());
+      if (nhi > 0) grouped(nhi, op->e2r_hi[c].as<int32_t>(), std::max(1, std::min(nrhs, op->rhs_group_hi)));
+      return 0;
+    }
+    grouped(op->ne, nullptr, std::max(1, std::min(nrhs, op->rhs_group)));
     return pdot ? op->ne : 0;
   } else if (nrhs == 1 && op->split3) {
     // three passes: volume and side traces, face records, lift
@@ -1624,21 +1669,37 @@ static void tune_rhs_group(hpdg_operator* op, hipStream_t s, int64_t* rep) {
     HIPCHK(hipEventElapsedTime(&ms, e0, e1));
     return (double)ms * 1e6 / reps;
   };
-  const int def = op->rhs_group;
+  const int def = op->rhs_group, def_hi = op->rhs_group_hi, def_c = op->e2r_split;
   const double t_def = time_it();
   double best = t_def * kTuneMargin;
-  int bg = def;
+  int bg = def, bh = def_hi, bc = def_c;
+  // groups for every degree, then (0) the lane form for degrees <= 5 with the
+  // best group size for the others
+  double tg = 0.0;
+  int gg = 0;
   for (int g : {1, 2, 4, 8, 16, 32, 64}) {
     if (g > nr) break;
     op->rhs_group = g;
     const double t = time_it();
+    if (gg == 0 || t < tg) { tg = t; gg = g; }
     if (t < best) { best = t; bg = g; }
   }
-  if (bg == def) best = t_def;
+  if (nr > 1 && gg > 0) {
+    op->rhs_group = 0;
+    op->rhs_group_hi = gg;
+    for (int c = 5; c <= 8; ++c) {
+      op->e2r_split = c;
+      const double t = time_it();
+      if (t < best) { best = t; bg = 0; bh = gg; bc = c; }
+    }
+  }
+  if (bg == def && bh == def_hi && bc == def_c) best = t_def;
   op->rhs_group = bg;
+  op->rhs_group_hi = bh;
+  op->e2r_split = bc;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  rep[0] = op->ndof; rep[1] = op->ne; rep[2] = nr; rep[3] = bg;
+  rep[0] = op->ndof; rep[1] = op->ne; rep[2] = bg == 0 ? bc : nr; rep[3] = bg;
   rep[4] = (int64_t)t_def; rep[5] = (int64_t)best;
 }
 

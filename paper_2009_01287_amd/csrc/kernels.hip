@@ -127,7 +127,8 @@ __device__ inline void wave_sync() {
 }
 
 template <int EPB, int kFChunk, bool GROUPED>
-__global__ __launch_bounds__(64 * EPB) void k_elem2d(int ne, int nrhs, int rg, int form, const int64_t* __restrict__ off,
+__global__ __launch_bounds__(64 * EPB) void k_elem2d(int ne, const int32_t* __restrict__ elist, int nrhs, int rg,
+                                               int form, const int64_t* __restrict__ off,
                                                const int8_t* __restrict__ pdeg, const double* __restrict__ hh,
                                                const double* __restrict__ kk, const int32_t* __restrict__ sptr,
                                                const FaceRec* __restrict__ recs, const double* __restrict__ ftab,
@@ -168,7 +169,9 @@ __global__ __launch_bounds__(64 * EPB) void k_elem2d(int ne, int nrhs, int rg, i
   const int ngrp = (nrhs + rgc - 1) / rgc;
   const int item = ((int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3)) * EPB + wv;
   if (item >= ne * ngrp) return;
-  const int e = item / ngrp, r0 = (item - e * ngrp) * rgc, r1 = GROUPED ? min(nrhs, r0 + rgc) : r0 + 1;
+  // elist: the elements to apply (all when null)
+  const int il = item / ngrp, r0 = (item - il * ngrp) * rgc, r1 = GROUPED ? min(nrhs, r0 + rgc) : r0 + 1;
+  const int e = elist ? elist[il] : il;
   const int lane = (int)(threadIdx.x & 63);
   const int gq = lane / 9, jq = lane - 9 * (lane / 9);   // face groups of 9 lanes
   const int p = pdeg[e], n = p + 1, nn = n * n;
@@ -415,6 +418,391 @@ __global__ __launch_bounds__(64 * EPB) void k_elem2d(int ne, int nrhs, int rg, i
     if (lane == 0) pdot[e] = xy;
   }
   if (GROUPED) wave_sync();   // the next right-hand side rewrites the LDS
+  }
+}
+
+// 2D element kernel for several right-hand sides: one wavefront per (element,
+// 64 right-hand sides), lane = right-hand side. Each lane applies the whole
+// element operator (the terms of k_elem2d) to its own column of x. The
+// element's n, and each face's neighbour n, is a compile-time constant of the
+// code path taken, so the lane's values stay in registers. The 1D tables of
+// the element and the matrices of each face are wave-uniform: they are copied
+// into the wavefront's LDS with one batch of vector loads and read from there
+// as broadcasts (scalar loads of them would each wait on a cache miss in
+// turn); x is read and y written in rows of 64 consecutive values (x and y
+// interleave the right-hand sides).
+
+// LDS of one wavefront (doubles): the element's M, K, Minv and l_i'(0),
+// l_i'(1), then the current face's A_oo, A_on, A_nn, the neighbour's Minv and
+// l_i'(side)
+struct E2RLds {
+  double M[81], K[81], Mi[81], D[18];
+  double Aoo[81], Aon[81], Ann[81], Mn[81], Dso[9];
+};
+
+// dst[0, CNT) = src[0, CNT) by the 64 lanes, loads issued together
+template <int CNT>
+__device__ __forceinline__ void e2r_stage(double* __restrict__ dst, const double* __restrict__ src, int lane) {
+  constexpr int T = (CNT + 63) / 64;
+  double v[T];
+#pragma unroll
+  for (int u = 0; u < T; ++u) v[u] = src[min(lane + 64 * u, CNT - 1)];
+#pragma unroll
+  for (int u = 0; u < T; ++u)
+    if (lane + 64 * u < CNT) dst[lane + 64 * u] = v[u];
+}
+
+// a wave-uniform pointer the compiler cannot see through: the table reads
+// behind it are issued where they are used instead of being hoisted and kept
+// live across the unrolled loops (which would exhaust the registers)
+template <typename T>
+__device__ __forceinline__ const T* e2r_opaque(const T* p) {
+  int o = 0;   // an opaque zero offset keeps the pointer's provenance
+  asm volatile("" : "+s"(o));
+  return p + o;
+}
+
+// One face of an element of n = N against a neighbour of n = NO (NO = 0 on
+// the boundary): the face's g1 (tests against phi) and g2 (against d phi/dn,
+// before the division by h) added to the side sums G1, G2 at the side's
+// nodes. To, Do: own trace and normal derivative / h at those nodes.
+template <int N, int NO>
+__device__ __forceinline__ void e2r_face(const FaceRec& R, int form, double k, double h, const double (&To)[N],
+                                         const double (&Do)[N], const double* __restrict__ xs, int nrhs,
+                                         const double* __restrict__ ftab, const double* __restrict__ tab,
+                                         const TableLayout& TL, E2RLds& L, int lane, double (&G1)[N],
+                                         double (&G2)[N]) {
+  constexpr int P = N - 1;
+  constexpr bool inner = NO > 0;
+  constexpr int NA = inner ? NO : 1;
+  const double fsgn = R.side ? 1.0 : -1.0;
+  const double csym = inner ? 0.5 : 1.0;
+  const double flen = R.flen, sig = R.sig;
+  // the face's matrices into LDS (the previous face's reads are done)
+  wave_sync();
+  e2r_stage<N * N>(L.Aoo, ftab + R.foo[0], lane);
+  if constexpr (inner) {
+    e2r_stage<N * NO>(L.Aon, ftab + R.fon[0], lane);
+    e2r_stage<9>(L.Dso, tab + TL.dside + ((NO - 1) * 2 + 1 - R.side) * 9, lane);
+    if (form == 1) {
+      e2r_stage<NO * NO>(L.Ann, ftab + R.fnn[0], lane);
+      e2r_stage<NO * NO>(L.Mn, tab + TL.minv + (NO - 1) * 81, lane);
+    }
+  }
+  wave_sync();
+  const double* __restrict__ Aoo = L.Aoo;
+  double Tn[NA], Dn[NA];
+  if constexpr (inner) {
+    // neighbour trace and k_n/h_n-scaled normal derivative at its side nodes
+    const int so = 1 - R.side;
+    const int som = R.m == 0 ? 1 : NO, sot = R.m == 0 ? NO : 1;
+    const double* __restrict__ Dso = L.Dso;
+    const double* __restrict__ xn = xs + (int64_t)R.nbase * nrhs;
+    const int c0 = so ? NO - 1 : 0;
+#pragma unroll
+    for (int j = 0; j < NO; ++j) {
+      double dv = 0.0;
+#pragma unroll
+      for (int a = 0; a < NO; ++a) dv += Dso[a] * xn[(int64_t)(a * som + j * sot) * nrhs];
+      Tn[j] = xn[(int64_t)(c0 * som + j * sot) * nrhs];
+      Dn[j] = R.kho * dv;
+    }
+  }
+  const double* __restrict__ Aon = L.Aon;
+  double v[N], g1[N];
+  // one opaque base per loop: no reuse of table reads across the loops,
+  // free scheduling of the reads within each
+  const double* __restrict__ A1 = e2r_opaque(Aoo);
+  const double* __restrict__ B1 = e2r_opaque(Aon);
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    double vv = 0.0, ds = 0.0;
+    const double* __restrict__ Ar = A1 + j * N;
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+      vv += Ar[a] * To[a];
+      ds += k * Ar[a] * Do[a];
+    }
+    if constexpr (inner) {
+      const double* __restrict__ Br = B1 + j * NO;
+#pragma unroll
+      for (int a = 0; a < NO; ++a) {
+        vv -= Br[a] * Tn[a];
+        ds += Br[a] * Dn[a];
+      }
+    }
+    v[j] = vv;
+    g1[j] = -flen * csym * fsgn * ds;
+    G2[j] += -csym * k * fsgn * flen * vv;
+    if (form == 0) g1[j] += flen * sig * vv;
+  }
+  if (form == 1) {
+    // BR2: own lifting L2 s_o A_oo Minv_o v, neighbour lifting
+    // L2 s_n A_on Minv_n (A_on^T To - A_nn Tn)
+    const double L2 = (inner ? 0.25 : 1.0) * sig * flen * flen;
+    const double* __restrict__ Mi = L.Mi;
+    const int sk = R.side ? P : 0;
+    const double so_ = Mi[sk * N + sk] / (h * h);
+    double w[N];
+    const double* __restrict__ M1 = e2r_opaque(Mi);
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      double acc = 0.0;
+      const double* __restrict__ Mr = M1 + j * N;
+#pragma unroll
+      for (int a = 0; a < N; ++a) acc += Mr[a] * v[a];
+      w[j] = acc;
+    }
+    const double* __restrict__ A2 = e2r_opaque(Aoo);
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      double acc = 0.0;
+      const double* __restrict__ Ar = A2 + j * N;
+#pragma unroll
+      for (int a = 0; a < N; ++a) acc += Ar[a] * w[a];
+      g1[j] += L2 * so_ * acc;
+    }
+    if constexpr (inner) {
+      const double* __restrict__ Ann = L.Ann;
+      const double* __restrict__ Mn = L.Mn;
+      double vn[NO], wn[NO];
+      const double* __restrict__ B2 = e2r_opaque(Aon);
+      const double* __restrict__ C1 = e2r_opaque(Ann);
+#pragma unroll
+      for (int j = 0; j < NO; ++j) {
+        double acc = 0.0;
+        const double* __restrict__ Bc = B2 + j;
+        const double* __restrict__ Cr = C1 + j * NO;
+#pragma unroll
+        for (int a = 0; a < N; ++a) acc += Bc[a * NO] * To[a];
+#pragma unroll
+        for (int a = 0; a < NO; ++a) acc -= Cr[a] * Tn[a];
+        vn[j] = acc;
+      }
+      const double* __restrict__ M2 = e2r_opaque(Mn);
+#pragma unroll
+      for (int j = 0; j < NO; ++j) {
+        double acc = 0.0;
+        const double* __restrict__ Mr = M2 + j * NO;
+#pragma unroll
+        for (int a = 0; a < NO; ++a) acc += Mr[a] * vn[a];
+        wn[j] = acc;
+      }
+      const int skn = R.side ? 0 : NO - 1;
+      const double sn = Mn[skn * NO + skn] / (R.hn * R.hn);
+      const double* __restrict__ B3 = e2r_opaque(Aon);
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        double acc = 0.0;
+        const double* __restrict__ Br = B3 + j * NO;
+#pragma unroll
+        for (int a = 0; a < NO; ++a) acc += Br[a] * wn[a];
+        g1[j] += L2 * sn * acc;
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < N; ++j) G1[j] += g1[j];
+}
+
+// the sums G1, G2 (before the division by h) of side s over its face
+// records, in record order
+template <int N>
+__device__ __forceinline__ void e2r_side(int e, int s, int nrhs, int form, double h, double k,
+                                         const int32_t* __restrict__ sptr, const FaceRec* __restrict__ recs,
+                                         const double* __restrict__ ftab, const double* __restrict__ tab,
+                                         const TableLayout& TL, const double* __restrict__ xs,
+                                         const double* __restrict__ xe, E2RLds& L, int lane, double (&G1)[N],
+                                         double (&G2)[N]) {
+  constexpr int P = N - 1;
+  const int f0 = sptr[e * 4 + s], f1 = sptr[e * 4 + s + 1];
+  const int m = s >> 1, sd = s & 1;
+  const int stm = m == 0 ? 1 : N, stt = m == 0 ? N : 1;
+  const double* __restrict__ Ds = L.D + sd * 9;   // l_i'(sd)
+  const int c0 = sd ? P : 0;
+  double To[N], Do[N];
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    double dv = 0.0;
+#pragma unroll
+    for (int a = 0; a < N; ++a) dv += Ds[a] * xe[(int64_t)(a * stm + j * stt) * nrhs];
+    To[j] = xe[(int64_t)(c0 * stm + j * stt) * nrhs];
+    Do[j] = dv / h;
+    G1[j] = 0.0;
+    G2[j] = 0.0;
+  }
+#pragma unroll 1
+  for (int f = f0; f < f1; ++f) {
+    const FaceRec R = recs[f];
+    const int no = R.nbr >= 0 ? (int)R.pn + 1 : 0;
+    switch (no) {
+      case 0: e2r_face<N, 0>(R, form, k, h, To, Do, xs, nrhs, ftab, tab, TL, L, lane, G1, G2); break;
+      case 2: e2r_face<N, 2>(R, form, k, h, To, Do, xs, nrhs, ftab, tab, TL, L, lane, G1, G2); break;
+      case 3: e2r_face<N, 3>(R, form, k, h, To, Do, xs, nrhs, ftab, tab, TL, L, lane, G1, G2); break;
+      case 4: e2r_face<N, 4>(R, form, k, h, To, Do, xs, nrhs, ftab, tab, TL, L, lane, G1, G2); break;
+      case 5: e2r_face<N, 5>(R, form, k, h, To, Do, xs, nrhs, ftab, tab, TL, L, lane, G1, G2); break;
+      case 6: e2r_face<N, 6>(R, form, k, h, To, Do, xs, nrhs, ftab, tab, TL, L, lane, G1, G2); break;
+      case 7: e2r_face<N, 7>(R, form, k, h, To, Do, xs, nrhs, ftab, tab, TL, L, lane, G1, G2); break;
+      case 8: e2r_face<N, 8>(R, form, k, h, To, Do, xs, nrhs, ftab, tab, TL, L, lane, G1, G2); break;
+      default: e2r_face<N, 9>(R, form, k, h, To, Do, xs, nrhs, ftab, tab, TL, L, lane, G1, G2); break;
+    }
+  }
+}
+
+// side s's sums into the element's y: G2 (divided by h) along the normal
+// through l_i'(sd), G1 at the side's nodes
+template <int N>
+__device__ __forceinline__ void e2r_spread(int s, const double* __restrict__ D, const double (&G1)[N],
+                                           const double (&G2)[N], double (&Y)[N * N]) {
+  constexpr int P = N - 1;
+  const int m = s >> 1, sd = s & 1;
+  const double* __restrict__ Ds = D + sd * 9;   // l_i'(sd)
+  if (m == 0) {
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+#pragma unroll
+      for (int c = 0; c < N; ++c) Y[j * N + c] += Ds[c] * G2[j];
+    if (sd == 0) {
+#pragma unroll
+      for (int j = 0; j < N; ++j) Y[j * N] += G1[j];
+    } else {
+#pragma unroll
+      for (int j = 0; j < N; ++j) Y[j * N + P] += G1[j];
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+#pragma unroll
+      for (int c = 0; c < N; ++c) Y[c * N + j] += Ds[c] * G2[j];
+    if (sd == 0) {
+#pragma unroll
+      for (int j = 0; j < N; ++j) Y[j] += G1[j];
+    } else {
+#pragma unroll
+      for (int j = 0; j < N; ++j) Y[P * N + j] += G1[j];
+    }
+  }
+}
+
+// volume, y = k (M X K + K X M) over the node rows of X, (row, column) =
+// (i1, i0): the row's products with K and M, then its outer products. The 1D
+// M and K (in L) are symmetric (up to the rounding of their quadrature sums),
+// so their rows serve as columns and are read as contiguous runs.
+template <int N>
+__device__ __forceinline__ void e2r_volume(double k, const double* __restrict__ xe, int nrhs, const E2RLds& L,
+                                           double (&Y)[N * N]) {
+  constexpr int NN = N * N;
+#pragma unroll
+  for (int i = 0; i < NN; ++i) Y[i] = 0.0;
+#pragma unroll
+  for (int b = 0; b < N; ++b) {
+    double xr[N], ta[N], tb[N];
+#pragma unroll
+    for (int a = 0; a < N; ++a) xr[a] = xe[(int64_t)(b * N + a) * nrhs];
+    // one opaque base per row: the table reads are not kept across rows
+    const double* __restrict__ Kr = e2r_opaque(L.K);
+    const double* __restrict__ Mr = e2r_opaque(L.M);
+#pragma unroll
+    for (int i0 = 0; i0 < N; ++i0) {
+      const double* __restrict__ Kc = Kr + i0 * N;
+      const double* __restrict__ Mc = Mr + i0 * N;
+      double sa = 0.0, sb = 0.0;
+#pragma unroll
+      for (int a = 0; a < N; ++a) {
+        sa += xr[a] * Kc[a];
+        sb += xr[a] * Mc[a];
+      }
+      ta[i0] = sa;
+      tb[i0] = sb;
+    }
+    const double* __restrict__ Mb = Mr + b * N;
+    const double* __restrict__ Kb = Kr + b * N;
+#pragma unroll
+    for (int i1 = 0; i1 < N; ++i1) {
+      const double mb = Mb[i1], kb = Kb[i1];
+#pragma unroll
+      for (int i0 = 0; i0 < N; ++i0) Y[i1 * N + i0] += mb * ta[i0] + kb * tb[i0];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NN; ++i) Y[i] *= k;
+}
+
+template <int N>
+__device__ __forceinline__ void e2r_element(int e, int nrhs, int form, const int64_t* __restrict__ off,
+                                            const double* __restrict__ hh, const double* __restrict__ kk,
+                                            const int32_t* __restrict__ sptr, const FaceRec* __restrict__ recs,
+                                            const double* __restrict__ ftab, const double* __restrict__ tab,
+                                            const TableLayout& TL, const double* __restrict__ xs,
+                                            double* __restrict__ ys, bool act, E2RLds& L, int lane) {
+  constexpr int P = N - 1, NN = N * N;
+  const double h = hh[e], k = kk[e];
+  const int64_t base = off[e];
+  e2r_stage<NN>(L.M, tab + TL.mk + P * 162, lane);
+  e2r_stage<NN>(L.K, tab + TL.mk + P * 162 + 81, lane);
+  if (form == 1) e2r_stage<NN>(L.Mi, tab + TL.minv + P * 81, lane);
+  e2r_stage<18>(L.D, tab + TL.dside + P * 18, lane);
+  wave_sync();
+  const double* __restrict__ xe = xs + base * nrhs;
+  double Y[NN];
+  e2r_volume<N>(k, xe, nrhs, L, Y);
+  // faces, side by side (m = normal dimension, sd = lower / upper), each
+  // side's sums added into y in turn
+#pragma unroll 1
+  for (int s = 0; s < 4; ++s) {
+    double G1[N], G2[N];
+    e2r_side<N>(e, s, nrhs, form, h, k, sptr, recs, ftab, tab, TL, xs, xe, L, lane, G1, G2);
+#pragma unroll
+    for (int j = 0; j < N; ++j) G2[j] /= h;
+    e2r_spread<N>(s, L.D, G1, G2, Y);
+  }
+  if (act) {
+    double* __restrict__ ye = ys + base * nrhs;
+#pragma unroll
+    for (int i = 0; i < NN; ++i) ye[(int64_t)i * nrhs] = Y[i];
+  }
+}
+
+// grid: a multiple of 8 workgroups of one wavefront, items (element of
+// elist, group of 64 right-hand sides) in XCD-aware order as in k_elem2d.
+// NMAX: the largest n compiled in (the registers follow it); elist holds
+// elements of n <= NMAX only.
+template <int NMAX>
+__global__ __launch_bounds__(64) void k_elem2d_rhs(int ne, const int32_t* __restrict__ elist, int nrhs, int form,
+                                                   const int64_t* __restrict__ off,
+                                                   const int8_t* __restrict__ pdeg, const double* __restrict__ hh,
+                                                   const double* __restrict__ kk, const int32_t* __restrict__ sptr,
+                                                   const FaceRec* __restrict__ recs, const double* __restrict__ ftab,
+                                                   const double* __restrict__ tab, TableLayout TL,
+                                                   const double* __restrict__ x, double* __restrict__ y) {
+  const int ngrp = (nrhs + 63) >> 6;
+  const int per = (int)(gridDim.x >> 3);
+  const int item = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+  if (item >= ne * ngrp) return;
+  const int il = item / ngrp, g = item - il * ngrp;
+  const int e = elist[il];
+  const int r = g * 64 + (int)threadIdx.x;
+  const bool act = r < nrhs;
+  const int rc = act ? r : nrhs - 1;
+  const double* xs = x + rc;
+  double* ys = y + rc;
+  __shared__ E2RLds L;
+  const int lane = (int)threadIdx.x;
+  switch (pdeg[e]) {
+    case 1: e2r_element<2>(e, nrhs, form, off, hh, kk, sptr, recs, ftab, tab, TL, xs, ys, act, L, lane); break;
+    case 2: e2r_element<3>(e, nrhs, form, off, hh, kk, sptr, recs, ftab, tab, TL, xs, ys, act, L, lane); break;
+    case 3: e2r_element<4>(e, nrhs, form, off, hh, kk, sptr, recs, ftab, tab, TL, xs, ys, act, L, lane); break;
+    case 4: e2r_element<5>(e, nrhs, form, off, hh, kk, sptr, recs, ftab, tab, TL, xs, ys, act, L, lane); break;
+    case 5: e2r_element<6>(e, nrhs, form, off, hh, kk, sptr, recs, ftab, tab, TL, xs, ys, act, L, lane); break;
+    default:
+      if constexpr (NMAX > 6) {
+        switch (pdeg[e]) {
+          case 6: e2r_element<7>(e, nrhs, form, off, hh, kk, sptr, recs, ftab, tab, TL, xs, ys, act, L, lane); break;
+          case 7: e2r_element<8>(e, nrhs, form, off, hh, kk, sptr, recs, ftab, tab, TL, xs, ys, act, L, lane); break;
+          default: e2r_element<9>(e, nrhs, form, off, hh, kk, sptr, recs, ftab, tab, TL, xs, ys, act, L, lane); break;
+        }
+      }
+      break;
   }
 }
 

@@ -516,7 +516,7 @@ def test_autotuned_binning_same_results(fp32):
         if r["matrix"] in ("vcycle_fused", "vcycle_dense_tail", "elem_order", "B_fork"):
             assert r["lanes"] in (0, 1)
         elif r["matrix"] == "elem_rhs_group":
-            assert r["lanes"] in (1, 2, 4, 8, 16, 32, 64)
+            assert r["lanes"] in (0, 1, 2, 4, 8, 16, 32, 64)
         elif r["matrix"] == "front_block_lanes":
             assert r["lanes"] in (1, 2, 4, 8, 16, 32)
         else:
@@ -856,6 +856,35 @@ def test_block_solves_mfma(monkeypatch, name, nr, fp32):
     for c in range(0, nr, 5):
         assert _rel(outs[0][:, c], pc.apply(R[:, c])) <= tol
     assert _rel(outs[0], outs[1]) <= (1e-6 if fp32 else 1e-14)
+
+
+@pytest.mark.parametrize("name", ["fig1", "hang2", "rand2", "rand2k"])
+@pytest.mark.parametrize("form,rule,eta", [("sipg", 0, 1.0), ("br2", 0, 0.0), ("sipg", 1, 10.0)])
+@pytest.mark.parametrize("nr", [2, 32, 128])
+@pytest.mark.parametrize("lane_deg", ["5", "6", "8"])
+def test_elem2d_rhs_lanes_match_oracle(monkeypatch, name, form, rule, eta, nr, lane_deg):
+    """The 2D element kernel with a lane per right-hand side (a wavefront per
+    element and 64 right-hand sides; 2 and 32 leave most or half of the lanes
+    idle, 128 takes two groups) against the oracle's apply column by column,
+    and against the kernel with one right-hand side per item. lane_deg: the
+    highest degree on the lane form (the others grouped in a second launch;
+    8: all degrees)."""
+    md = MESHES[name]()
+    m = O.Mesh(md)
+    X = H.gaussian_rhs(m.ndof, 45, nrhs=nr)
+    x = _dev(X.reshape(-1))
+    outs = []
+    monkeypatch.setenv("HPDG_ELEM2D_LANE_DEG", lane_deg)
+    for g in ("1", "0"):
+        monkeypatch.setenv("HPDG_ELEM2D_RHSGROUP", g)
+        op = G.Operator(G.Mesh(md), form=form, penalty_rule=rule, eta=eta, no_prec=True, max_nrhs=nr)
+        y = torch.empty_like(x)
+        op.apply_A(x, y, nrhs=nr)
+        outs.append(_host(y).reshape(m.ndof, nr))
+    opts = O.Opts(form, rule, eta)
+    for c in sorted({0, nr // 2, nr - 1}):
+        assert _rel(outs[1][:, c], dg.apply(m, opts, X[:, c])) <= 1e-12
+    assert _rel(outs[1], outs[0]) <= 1e-13
 
 
 @pytest.mark.parametrize("group", ["1", "4", "64"])
