@@ -289,7 +289,8 @@ struct hpdg_operator {
   int rhs_group = 1;         // right-hand sides per item of the 2D element kernel; 0: a lane per
                              // right-hand side (k_elem2d_rhs) for degrees <= 5 when nrhs > 1
   int rhs_group_hi = 4;      // with rhs_group 0: the group size of the degrees above e2r_split
-  int e2r_split = 5;         // with rhs_group 0: the highest degree on the lane form (5..8)
+  int e2r_split = 5;         // with rhs_group 0: the highest degree on the lane form (5..8), the
+                             // others grouped; 9: all on the lane form in two launches (<= 5, >= 6)
   struct GraphEntry {
     int k, nrhs;
     double* x;
@@ -1088,7 +1089,7 @@ extern "C" hpdg_status hpdg_setup_operator(const hpdg_mesh* mh, const hpdg_opera
     if (const char* v = std::getenv("HPDG_ELEM2D_FCHUNK")) op->fchunk = std::atoi(v) == 8 ? 8 : std::atoi(v) == 32 ? 32 : 16;
     if (const char* v = std::getenv("HPDG_ELEM2D_RHSGROUP")) op->rhs_group = std::max(0, std::atoi(v));
     if (const char* v = std::getenv("HPDG_ELEM2D_RHSGROUP_HI")) op->rhs_group_hi = std::max(1, std::atoi(v));
-    if (const char* v = std::getenv("HPDG_ELEM2D_LANE_DEG")) op->e2r_split = std::min(8, std::max(5, std::atoi(v)));
+    if (const char* v = std::getenv("HPDG_ELEM2D_LANE_DEG")) op->e2r_split = std::min(9, std::max(5, std::atoi(v)));
     if (const char* v = std::getenv("HPDG_NO_MFMA")) op->no_mfma = std::atoi(v) != 0;
     if (const char* v = std::getenv("HPDG_NO_FUSED_MULTI")) op->no_fused_multi = std::atoi(v) != 0;
     if (const char* v = std::getenv("HPDG_ELEM3D_COST_ORDER")) op->use_perm = std::atoi(v) != 0;
@@ -1286,17 +1287,27 @@ static int apply_A_dev(hpdg_operator* op, const double* x, double* y, int nrhs, 
       // wavefront per element and 64 RHS), the others grouped: at high
       // degree a wavefront of the lane form holds many values per lane and
       // runs long, which the last wavefronts of the launch wait for
-      const int c = std::min(8, std::max(5, op->e2r_split)) - 5;
+      const int split = std::min(9, std::max(5, op->e2r_split));
+      const int c = std::min(8, split) - 5;
       const int ng = (nrhs + 63) / 64;
-      const int nlo = op->n_e2r_lo[c], nhi = op->n_e2r_hi[c];
-      if (nlo > 0) {
-        const unsigned grid = 8u * (unsigned)(((int64_t)nlo * ng + 7) / 8);   // XCD-aware: multiple of 8
-        hipLaunchKernelGGL((c == 0 ? k_elem2d_rhs<6> : k_elem2d_rhs<9>), dim3(grid), dim3(64), 0, s, nlo,
-                           op->e2r_lo[c].as<int32_t>(), nrhs, op->form, op->off.as<int64_t>(),
-                           op->pdeg.as<int8_t>(), op->hh.as<double>(), op->kk.as<double>(), op->sptr.as<int32_t>(),
-                           op->recs.as<FaceRec>(), op->ftab.as<double>(), op->tab.as<double>(), op->TL, x, y);
+      // the lane kernel over a list: up to degree 5 with two wavefronts per
+      // SIMD (face loads not overlapped), higher with one (overlapped)
+      auto lanes = [&](int nl, const int32_t* list, bool low) {
+        if (nl <= 0) return;
+        const unsigned grid = 8u * (unsigned)(((int64_t)nl * ng + 7) / 8);   // XCD-aware: multiple of 8
+        hipLaunchKernelGGL((low ? k_elem2d_rhs<6, false> : k_elem2d_rhs<9, true>), dim3(grid), dim3(64), 0, s, nl,
+                           list, nrhs, op->form, op->off.as<int64_t>(), op->pdeg.as<int8_t>(), op->hh.as<double>(),
+                           op->kk.as<double>(), op->sptr.as<int32_t>(), op->recs.as<FaceRec>(),
+                           op->ftab.as<double>(), op->tab.as<double>(), op->TL, x, y);
+      };
+      if (split == 9) {
+        lanes(op->n_e2r_hi[0], op->e2r_hi[0].as<int32_t>(), false);
+        lanes(op->n_e2r_lo[0], op->e2r_lo[0].as<int32_t>(), true);
+        return 0;
       }
-      if (nhi > 0) grouped(nhi, op->e2r_hi[c].as<int32_t>(), std::max(1, std::min(nrhs, op->rhs_group_hi)));
+      lanes(op->n_e2r_lo[c], op->e2r_lo[c].as<int32_t>(), c == 0);
+      if (op->n_e2r_hi[c] > 0)
+        grouped(op->n_e2r_hi[c], op->e2r_hi[c].as<int32_t>(), std::max(1, std::min(nrhs, op->rhs_group_hi)));
       return 0;
     }
     grouped(op->ne, nullptr, std::max(1, std::min(nrhs, op->rhs_group)));
@@ -1687,7 +1698,7 @@ static void tune_rhs_group(hpdg_operator* op, hipStream_t s, int64_t* rep) {
   if (nr > 1 && gg > 0) {
     op->rhs_group = 0;
     op->rhs_group_hi = gg;
-    for (int c = 5; c <= 8; ++c) {
+    for (int c = 5; c <= 9; ++c) {
       op->e2r_split = c;
       const double t = time_it();
       if (t < best) { best = t; bg = 0; bh = gg; bc = c; }

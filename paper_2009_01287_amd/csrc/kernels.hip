@@ -452,6 +452,22 @@ __device__ __forceinline__ void e2r_stage(double* __restrict__ dst, const double
     if (lane + 64 * u < CNT) dst[lane + 64 * u] = v[u];
 }
 
+// the same in two halves: the loads (into v) and, later, the LDS stores
+template <int CNT>
+struct E2RStaged {
+  static constexpr int T = (CNT + 63) / 64;
+  double v[T];
+  __device__ __forceinline__ void load(const double* __restrict__ src, int lane) {
+#pragma unroll
+    for (int u = 0; u < T; ++u) v[u] = src[min(lane + 64 * u, CNT - 1)];
+  }
+  __device__ __forceinline__ void store(double* __restrict__ dst, int lane) const {
+#pragma unroll
+    for (int u = 0; u < T; ++u)
+      if (lane + 64 * u < CNT) dst[lane + 64 * u] = v[u];
+  }
+};
+
 // a wave-uniform pointer the compiler cannot see through: the table reads
 // behind it are issued where they are used instead of being hoisted and kept
 // live across the unrolled loops (which would exhaust the registers)
@@ -466,7 +482,7 @@ __device__ __forceinline__ const T* e2r_opaque(const T* p) {
 // the boundary): the face's g1 (tests against phi) and g2 (against d phi/dn,
 // before the division by h) added to the side sums G1, G2 at the side's
 // nodes. To, Do: own trace and normal derivative / h at those nodes.
-template <int N, int NO>
+template <int N, int NO, bool OVL>
 __device__ __forceinline__ void e2r_face(const FaceRec& R, int form, double k, double h, const double (&To)[N],
                                          const double (&Do)[N], const double* __restrict__ xs, int nrhs,
                                          const double* __restrict__ ftab, const double* __restrict__ tab,
@@ -478,36 +494,68 @@ __device__ __forceinline__ void e2r_face(const FaceRec& R, int form, double k, d
   const double fsgn = R.side ? 1.0 : -1.0;
   const double csym = inner ? 0.5 : 1.0;
   const double flen = R.flen, sig = R.sig;
-  // the face's matrices into LDS (the previous face's reads are done)
-  wave_sync();
-  e2r_stage<N * N>(L.Aoo, ftab + R.foo[0], lane);
-  if constexpr (inner) {
-    e2r_stage<N * NO>(L.Aon, ftab + R.fon[0], lane);
-    e2r_stage<9>(L.Dso, tab + TL.dside + ((NO - 1) * 2 + 1 - R.side) * 9, lane);
-    if (form == 1) {
-      e2r_stage<NO * NO>(L.Ann, ftab + R.fnn[0], lane);
-      e2r_stage<NO * NO>(L.Mn, tab + TL.minv + (NO - 1) * 81, lane);
+  // the face's matrices go to LDS. OVL: their loads and the neighbour's
+  // values are issued together (one round trip; the neighbour's l_i'(side)
+  // read as scalars so that its traces are formed before the LDS
+  // hand-over), at the cost of more values in flight per lane; otherwise
+  // the neighbour's values are read after the hand-over
+  wave_sync();   // the previous face's LDS reads are done
+  E2RStaged<N * N> sAoo;
+  E2RStaged<inner ? N * NO : 1> sAon;
+  E2RStaged<inner ? NO * NO : 1> sAnn, sMn;
+  if constexpr (OVL) {
+    sAoo.load(ftab + R.foo[0], lane);
+    if constexpr (inner) {
+      sAon.load(ftab + R.fon[0], lane);
+      if (form == 1) {
+        sAnn.load(ftab + R.fnn[0], lane);
+        sMn.load(tab + TL.minv + (NO - 1) * 81, lane);
+      }
     }
   }
-  wave_sync();
-  const double* __restrict__ Aoo = L.Aoo;
   double Tn[NA], Dn[NA];
-  if constexpr (inner) {
-    // neighbour trace and k_n/h_n-scaled normal derivative at its side nodes
-    const int so = 1 - R.side;
-    const int som = R.m == 0 ? 1 : NO, sot = R.m == 0 ? NO : 1;
-    const double* __restrict__ Dso = L.Dso;
-    const double* __restrict__ xn = xs + (int64_t)R.nbase * nrhs;
-    const int c0 = so ? NO - 1 : 0;
+  // neighbour trace and k_n/h_n-scaled normal derivative at its side nodes
+  auto neighbour = [&]() {
+    if constexpr (inner) {
+      const int so = 1 - R.side;
+      const int som = R.m == 0 ? 1 : NO, sot = R.m == 0 ? NO : 1;
+      const double* __restrict__ Dso = OVL ? tab + TL.dside + ((NO - 1) * 2 + so) * 9 : L.Dso;
+      const double* __restrict__ xn = xs + (int64_t)R.nbase * nrhs;
+      const int c0 = so ? NO - 1 : 0;
 #pragma unroll
-    for (int j = 0; j < NO; ++j) {
-      double dv = 0.0;
+      for (int j = 0; j < NO; ++j) {
+        double dv = 0.0;
 #pragma unroll
-      for (int a = 0; a < NO; ++a) dv += Dso[a] * xn[(int64_t)(a * som + j * sot) * nrhs];
-      Tn[j] = xn[(int64_t)(c0 * som + j * sot) * nrhs];
-      Dn[j] = R.kho * dv;
+        for (int a = 0; a < NO; ++a) dv += Dso[a] * xn[(int64_t)(a * som + j * sot) * nrhs];
+        Tn[j] = xn[(int64_t)(c0 * som + j * sot) * nrhs];
+        Dn[j] = R.kho * dv;
+      }
+    }
+  };
+  if constexpr (OVL) {
+    neighbour();
+    sAoo.store(L.Aoo, lane);
+    if constexpr (inner) {
+      sAon.store(L.Aon, lane);
+      if (form == 1) {
+        sAnn.store(L.Ann, lane);
+        sMn.store(L.Mn, lane);
+      }
+    }
+  } else {
+    e2r_stage<N * N>(L.Aoo, ftab + R.foo[0], lane);
+    if constexpr (inner) {
+      e2r_stage<N * NO>(L.Aon, ftab + R.fon[0], lane);
+      e2r_stage<9>(L.Dso, tab + TL.dside + ((NO - 1) * 2 + 1 - R.side) * 9, lane);
+      if (form == 1) {
+        e2r_stage<NO * NO>(L.Ann, ftab + R.fnn[0], lane);
+        e2r_stage<NO * NO>(L.Mn, tab + TL.minv + (NO - 1) * 81, lane);
+      }
     }
   }
+  wave_sync();
+  if constexpr (!OVL) neighbour();
+  const double* __restrict__ Aoo = L.Aoo;
   const double* __restrict__ Aon = L.Aon;
   double v[N], g1[N];
   // one opaque base per loop: no reuse of table reads across the loops,
@@ -607,7 +655,7 @@ __device__ __forceinline__ void e2r_face(const FaceRec& R, int form, double k, d
 
 // the sums G1, G2 (before the division by h) of side s over its face
 // records, in record order
-template <int N>
+template <int N, bool OVL>
 __device__ __forceinline__ void e2r_side(int e, int s, int nrhs, int form, double h, double k,
                                          const int32_t* __restrict__ sptr, const FaceRec* __restrict__ recs,
                                          const double* __restrict__ ftab, const double* __restrict__ tab,
@@ -636,15 +684,15 @@ __device__ __forceinline__ void e2r_side(int e, int s, int nrhs, int form, doubl
     const FaceRec R = recs[f];
     const int no = R.nbr >= 0 ? (int)R.pn + 1 : 0;
     switch (no) {
-      case 0: e2r_face<N, 0>(R, form, k, h, To, Do, xs, nrhs, ftab, tab, TL, L, lane, G1, G2); break;
-      case 2: e2r_face<N, 2>(R, form, k, h, To, Do, xs, nrhs, ftab, tab, TL, L, lane, G1, G2); break;
-      case 3: e2r_face<N, 3>(R, form, k, h, To, Do, xs, nrhs, ftab, tab, TL, L, lane, G1, G2); break;
-      case 4: e2r_face<N, 4>(R, form, k, h, To, Do, xs, nrhs, ftab, tab, TL, L, lane, G1, G2); break;
-      case 5: e2r_face<N, 5>(R, form, k, h, To, Do, xs, nrhs, ftab, tab, TL, L, lane, G1, G2); break;
-      case 6: e2r_face<N, 6>(R, form, k, h, To, Do, xs, nrhs, ftab, tab, TL, L, lane, G1, G2); break;
-      case 7: e2r_face<N, 7>(R, form, k, h, To, Do, xs, nrhs, ftab, tab, TL, L, lane, G1, G2); break;
-      case 8: e2r_face<N, 8>(R, form, k, h, To, Do, xs, nrhs, ftab, tab, TL, L, lane, G1, G2); break;
-      default: e2r_face<N, 9>(R, form, k, h, To, Do, xs, nrhs, ftab, tab, TL, L, lane, G1, G2); break;
+      case 0: e2r_face<N, 0, OVL>(R, form, k, h, To, Do, xs, nrhs, ftab, tab, TL, L, lane, G1, G2); break;
+      case 2: e2r_face<N, 2, OVL>(R, form, k, h, To, Do, xs, nrhs, ftab, tab, TL, L, lane, G1, G2); break;
+      case 3: e2r_face<N, 3, OVL>(R, form, k, h, To, Do, xs, nrhs, ftab, tab, TL, L, lane, G1, G2); break;
+      case 4: e2r_face<N, 4, OVL>(R, form, k, h, To, Do, xs, nrhs, ftab, tab, TL, L, lane, G1, G2); break;
+      case 5: e2r_face<N, 5, OVL>(R, form, k, h, To, Do, xs, nrhs, ftab, tab, TL, L, lane, G1, G2); break;
+      case 6: e2r_face<N, 6, OVL>(R, form, k, h, To, Do, xs, nrhs, ftab, tab, TL, L, lane, G1, G2); break;
+      case 7: e2r_face<N, 7, OVL>(R, form, k, h, To, Do, xs, nrhs, ftab, tab, TL, L, lane, G1, G2); break;
+      case 8: e2r_face<N, 8, OVL>(R, form, k, h, To, Do, xs, nrhs, ftab, tab, TL, L, lane, G1, G2); break;
+      default: e2r_face<N, 9, OVL>(R, form, k, h, To, Do, xs, nrhs, ftab, tab, TL, L, lane, G1, G2); break;
     }
   }
 }
@@ -688,17 +736,32 @@ __device__ __forceinline__ void e2r_spread(int s, const double* __restrict__ D, 
 // (i1, i0): the row's products with K and M, then its outer products. The 1D
 // M and K (in L) are symmetric (up to the rounding of their quadrature sums),
 // so their rows serve as columns and are read as contiguous runs.
-template <int N>
+template <int N, bool PF>
 __device__ __forceinline__ void e2r_volume(double k, const double* __restrict__ xe, int nrhs, const E2RLds& L,
                                            double (&Y)[N * N]) {
   constexpr int NN = N * N;
 #pragma unroll
   for (int i = 0; i < NN; ++i) Y[i] = 0.0;
+  // PF: each row of X loaded one row ahead (more values per lane in flight)
+  double xr[N], xq[N];
+  if constexpr (PF) {
+#pragma unroll
+    for (int a = 0; a < N; ++a) xq[a] = xe[(int64_t)a * nrhs];
+  }
 #pragma unroll
   for (int b = 0; b < N; ++b) {
-    double xr[N], ta[N], tb[N];
+    double ta[N], tb[N];
+    if constexpr (PF) {
 #pragma unroll
-    for (int a = 0; a < N; ++a) xr[a] = xe[(int64_t)(b * N + a) * nrhs];
+      for (int a = 0; a < N; ++a) xr[a] = xq[a];
+      if (b + 1 < N) {
+#pragma unroll
+        for (int a = 0; a < N; ++a) xq[a] = xe[(int64_t)((b + 1) * N + a) * nrhs];
+      }
+    } else {
+#pragma unroll
+      for (int a = 0; a < N; ++a) xr[a] = xe[(int64_t)(b * N + a) * nrhs];
+    }
     // one opaque base per row: the table reads are not kept across rows
     const double* __restrict__ Kr = e2r_opaque(L.K);
     const double* __restrict__ Mr = e2r_opaque(L.M);
@@ -728,7 +791,7 @@ __device__ __forceinline__ void e2r_volume(double k, const double* __restrict__ 
   for (int i = 0; i < NN; ++i) Y[i] *= k;
 }
 
-template <int N>
+template <int N, bool OVL>
 __device__ __forceinline__ void e2r_element(int e, int nrhs, int form, const int64_t* __restrict__ off,
                                             const double* __restrict__ hh, const double* __restrict__ kk,
                                             const int32_t* __restrict__ sptr, const FaceRec* __restrict__ recs,
@@ -745,13 +808,13 @@ __device__ __forceinline__ void e2r_element(int e, int nrhs, int form, const int
   wave_sync();
   const double* __restrict__ xe = xs + base * nrhs;
   double Y[NN];
-  e2r_volume<N>(k, xe, nrhs, L, Y);
+  e2r_volume<N, OVL>(k, xe, nrhs, L, Y);
   // faces, side by side (m = normal dimension, sd = lower / upper), each
   // side's sums added into y in turn
 #pragma unroll 1
   for (int s = 0; s < 4; ++s) {
     double G1[N], G2[N];
-    e2r_side<N>(e, s, nrhs, form, h, k, sptr, recs, ftab, tab, TL, xs, xe, L, lane, G1, G2);
+    e2r_side<N, OVL>(e, s, nrhs, form, h, k, sptr, recs, ftab, tab, TL, xs, xe, L, lane, G1, G2);
 #pragma unroll
     for (int j = 0; j < N; ++j) G2[j] /= h;
     e2r_spread<N>(s, L.D, G1, G2, Y);
@@ -766,8 +829,8 @@ __device__ __forceinline__ void e2r_element(int e, int nrhs, int form, const int
 // grid: a multiple of 8 workgroups of one wavefront, items (element of
 // elist, group of 64 right-hand sides) in XCD-aware order as in k_elem2d.
 // NMAX: the largest n compiled in (the registers follow it); elist holds
-// elements of n <= NMAX only.
-template <int NMAX>
+// elements of n <= NMAX only. OVL: see e2r_face.
+template <int NMAX, bool OVL>
 __global__ __launch_bounds__(64) void k_elem2d_rhs(int ne, const int32_t* __restrict__ elist, int nrhs, int form,
                                                    const int64_t* __restrict__ off,
                                                    const int8_t* __restrict__ pdeg, const double* __restrict__ hh,
@@ -789,17 +852,17 @@ __global__ __launch_bounds__(64) void k_elem2d_rhs(int ne, const int32_t* __rest
   __shared__ E2RLds L;
   const int lane = (int)threadIdx.x;
   switch (pdeg[e]) {
-    case 1: e2r_element<2>(e, nrhs, form, off, hh, kk, sptr, recs, ftab, tab, TL, xs, ys, act, L, lane); break;
-    case 2: e2r_element<3>(e, nrhs, form, off, hh, kk, sptr, recs, ftab, tab, TL, xs, ys, act, L, lane); break;
-    case 3: e2r_element<4>(e, nrhs, form, off, hh, kk, sptr, recs, ftab, tab, TL, xs, ys, act, L, lane); break;
-    case 4: e2r_element<5>(e, nrhs, form, off, hh, kk, sptr, recs, ftab, tab, TL, xs, ys, act, L, lane); break;
-    case 5: e2r_element<6>(e, nrhs, form, off, hh, kk, sptr, recs, ftab, tab, TL, xs, ys, act, L, lane); break;
+    case 1: e2r_element<2, OVL>(e, nrhs, form, off, hh, kk, sptr, recs, ftab, tab, TL, xs, ys, act, L, lane); break;
+    case 2: e2r_element<3, OVL>(e, nrhs, form, off, hh, kk, sptr, recs, ftab, tab, TL, xs, ys, act, L, lane); break;
+    case 3: e2r_element<4, OVL>(e, nrhs, form, off, hh, kk, sptr, recs, ftab, tab, TL, xs, ys, act, L, lane); break;
+    case 4: e2r_element<5, OVL>(e, nrhs, form, off, hh, kk, sptr, recs, ftab, tab, TL, xs, ys, act, L, lane); break;
+    case 5: e2r_element<6, OVL>(e, nrhs, form, off, hh, kk, sptr, recs, ftab, tab, TL, xs, ys, act, L, lane); break;
     default:
       if constexpr (NMAX > 6) {
         switch (pdeg[e]) {
-          case 6: e2r_element<7>(e, nrhs, form, off, hh, kk, sptr, recs, ftab, tab, TL, xs, ys, act, L, lane); break;
-          case 7: e2r_element<8>(e, nrhs, form, off, hh, kk, sptr, recs, ftab, tab, TL, xs, ys, act, L, lane); break;
-          default: e2r_element<9>(e, nrhs, form, off, hh, kk, sptr, recs, ftab, tab, TL, xs, ys, act, L, lane); break;
+          case 6: e2r_element<7, OVL>(e, nrhs, form, off, hh, kk, sptr, recs, ftab, tab, TL, xs, ys, act, L, lane); break;
+          case 7: e2r_element<8, OVL>(e, nrhs, form, off, hh, kk, sptr, recs, ftab, tab, TL, xs, ys, act, L, lane); break;
+          default: e2r_element<9, OVL>(e, nrhs, form, off, hh, kk, sptr, recs, ftab, tab, TL, xs, ys, act, L, lane); break;
         }
       }
       break;

@@ -694,8 +694,10 @@ def test_random3d_br2_full_size_sampled():
 
 def test_random2d_64rhs_full_size():
     """64 right-hand sides on the 2D random mesh at full size (155k DOFs x 64 RHS, FP32 preconditioner): the
-    batched apply equals the single-RHS apply bitwise on sampled columns, and
-    every column of the batched solve reaches 1e-8 like its single solve."""
+    batched apply equals the single-RHS apply on sampled columns (to rounding:
+    the tuned batched form, a lane per right-hand side, sums the volume terms
+    row by row and adds the side sums in another order), and every column of
+    the batched solve reaches 1e-8 like its single solve."""
     md = H.config_mesh(4)
     m = O.Mesh(md)
     nr = 64
@@ -715,7 +717,7 @@ def test_random2d_64rhs_full_size():
         b1 = _dev(Bh[:, r])
         y1, x1 = torch.empty_like(b1), torch.zeros_like(b1)
         op.apply_A(b1, y1)
-        assert np.array_equal(Yh[:, r], _host(y1))
+        assert _rel(Yh[:, r], _host(y1)) <= 1e-14
         i1 = op.pcg_solve(b1, x1, rtol=1e-8, maxit=2000)[0]
         assert abs(infos[r]["iters"] - i1["iters"]) <= 1
         assert _rel(Xh[:, r], _host(x1)) <= 1e-7
@@ -861,14 +863,14 @@ def test_block_solves_mfma(monkeypatch, name, nr, fp32):
 @pytest.mark.parametrize("name", ["fig1", "hang2", "rand2", "rand2k"])
 @pytest.mark.parametrize("form,rule,eta", [("sipg", 0, 1.0), ("br2", 0, 0.0), ("sipg", 1, 10.0)])
 @pytest.mark.parametrize("nr", [2, 32, 128])
-@pytest.mark.parametrize("lane_deg", ["5", "6", "8"])
+@pytest.mark.parametrize("lane_deg", ["5", "6", "8", "9"])
 def test_elem2d_rhs_lanes_match_oracle(monkeypatch, name, form, rule, eta, nr, lane_deg):
     """The 2D element kernel with a lane per right-hand side (a wavefront per
     element and 64 right-hand sides; 2 and 32 leave most or half of the lanes
     idle, 128 takes two groups) against the oracle's apply column by column,
     and against the kernel with one right-hand side per item. lane_deg: the
     highest degree on the lane form (the others grouped in a second launch;
-    8: all degrees)."""
+    8: all degrees; 9: all, in two launches)."""
     md = MESHES[name]()
     m = O.Mesh(md)
     X = H.gaussian_rhs(m.ndof, 45, nrhs=nr)
