@@ -183,7 +183,12 @@ def main():
     algo_bytes = 16.0 * n * nrhs          # x read once + y written once, FP64
     achieved = algo_bytes / t_apply / 1e9
     it = infos[0]["iters"]
-    kernel = ("k_elem2d (volume + all face terms, one launch)" if md["dim"] == 2
+    lane_form = any(r["matrix"] == "elem_rhs_group" and r["lanes"] == 0 for r in (tuned or []))
+    kernel = ("k_elem2d_rhs (a lane per right-hand side, one wavefront per element and 64 RHS, "
+              "volume + all face terms)" + ("" if any(r["matrix"] == "elem_rhs_group" and r["longrow"] == 8
+                                                      for r in tuned) else " + k_elem2d for the higher degrees")
+              if md["dim"] == 2 and nrhs > 1 and lane_form
+              else "k_elem2d (volume + all face terms, one launch)" if md["dim"] == 2
               else "DG apply in three launches: k_e3_vol (volume, side traces), k_e3_face (one face record "
                    "per wavefront), k_e3_lift (side sums lifted into y)" if nrhs == 1
               else "k_elem3d (volume + all face terms, one launch)")

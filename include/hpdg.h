@@ -182,7 +182,11 @@ hpdg_status hpdg_operator_device_bytes(hpdg_operator* op, int64_t* bytes);
  * elements per workgroup (1 or 2) and the face records staged per pass (8,
  * 16 or 32); the results do not depend on them. report: cap rows of 8 int64
  * (kind 0 A / 1 R / 2 P / 3 P^T / 4 element kernel / 5 fused V-cycle level /
- * 6 right-hand sides per element-kernel item, at the largest nrhs /
+ * 6 right-hand sides per element-kernel item, at the largest nrhs (chosen
+ * lanes 0: a lane per right-hand side, one wavefront per element and 64
+ * RHS, for the degrees up to the threshold column's, the others grouped;
+ * 9 there: every degree on the lane form in two launches; the threshold
+ * column holds nrhs otherwise) /
  * 7 lanes per V_e block row for the one-RHS block solves (the threshold
  * column holds 1 when they run as a workgroup per block with the block's r
  * staged in LDS, 0 when their rows run inside the B front) / 8 dense tail of the
