@@ -98,6 +98,9 @@ struct DevCSR {
   int lpr = 1;                 // lanes per short row
   int nlong = 0;               // rows longer than longrow, one wavefront each
   int longrow = 32;
+  // several RHS with nrhs a multiple of 64: a thread per (row, RHS) instead
+  // of a wavefront per (row, 64 RHS) (HPDG_SPMM_THREAD=1 at upload; same results)
+  bool spmm_thread = false;
   DevBuf ptr, idx, val, rows;  // rows: long rows first, then short rows
 };
 constexpr int kLongRow = 128;   // entries (32 four-entry chunks)
@@ -112,6 +115,10 @@ void bin_rows(const CSR& A, DevCSR& D, int longrow, int lpr);
 template <typename T>
 void upload_csr(const CSR& A, DevCSR& D, bool pad = true) {
   const int64_t n = A.nrows;
+  {
+    const char* v = std::getenv("HPDG_SPMM_THREAD");
+    D.spmm_thread = v && std::atoi(v) != 0;
+  }
   const int64_t rm = pad ? 3 : 0;
   std::vector<int32_t> p32((size_t)n + 1);
   int64_t tot = 0;
@@ -1372,8 +1379,12 @@ static void spmv(const DevCSR& A, int nrhs, const T* x, const T* b, const T* d, 
   } else {
     // MODE 5: the first nrows columns read x, the others b
     int64_t nt = (int64_t)A.nrows * nrhs;
-    hipLaunchKernelGGL((k_spmm<T, MODE>), dim3(nblk(nt)), dim3(256), 0, s, A.nrows, nrhs, A.nrows, A.ptr.as<int32_t>(),
-                       A.idx.as<int32_t>(), A.val.as<T>(), x, b, d, xo, y);
+    if (nrhs % 64 == 0 && !A.spmm_thread)
+      hipLaunchKernelGGL((k_spmm64<T, MODE>), dim3(nblk(nt)), dim3(256), 0, s, A.nrows, nrhs, A.nrows,
+                         A.ptr.as<int32_t>(), A.idx.as<int32_t>(), A.val.as<T>(), x, b, d, xo, y);
+    else
+      hipLaunchKernelGGL((k_spmm<T, MODE>), dim3(nblk(nt)), dim3(256), 0, s, A.nrows, nrhs, A.nrows,
+                         A.ptr.as<int32_t>(), A.idx.as<int32_t>(), A.val.as<T>(), x, b, d, xo, y);
   }
 }
 

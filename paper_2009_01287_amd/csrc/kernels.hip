@@ -2308,6 +2308,71 @@ __global__ __launch_bounds__(256) void k_spmm(int nrows, int nrhs, int nsplit, c
   }
 }
 
+// lane l's value of v, for a wave-uniform l (a scalar)
+__device__ __forceinline__ int e_readlane(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ float e_readlane(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double e_readlane(double v, int l) {
+  const long long u = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(u & 0xffffffffLL), l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(u >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// k_spmm for nrhs a multiple of 64: one wavefront per (row, 64 RHS). The
+// row's column indices and values are loaded by the lanes, up to 64 at a
+// time, and read back as scalars, so the x loads of the row go out together
+// instead of each waiting for its index; the same terms in the same order
+// (bitwise the same results).
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void k_spmm64(int nrows, int nrhs, int nsplit, const int32_t* __restrict__ ptr,
+                                                const int32_t* __restrict__ idx, const T* __restrict__ val,
+                                                const T* __restrict__ x, const T* __restrict__ b,
+                                                const T* __restrict__ d, T* __restrict__ xo, T* __restrict__ y) {
+  const int lane = (int)(threadIdx.x & 63);
+  const int ng = nrhs >> 6;
+  const int64_t w = __builtin_amdgcn_readfirstlane((int)(((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6));
+  const int64_t row = w / ng;
+  if (row >= nrows) return;   // the whole wavefront
+  const int c = (int)(w - row * ng) * 64 + lane;
+  auto xload = [&](int64_t j) -> T {
+    if (MODE == 3) return d[j] * x[j * nrhs + c];
+    if (MODE == 5) return *(j < nsplit ? x + j * nrhs + c : b + (j - nsplit) * nrhs + c);
+    return x[j * nrhs + c];
+  };
+  const int q0 = ptr[row], q1 = ptr[row + 1];
+  T acc = 0;
+  for (int qb = q0; qb < q1; qb += 64) {
+    const int nq = min(64, q1 - qb);
+    const int ql = qb + min(lane, nq - 1);
+    const int jl = idx[ql];
+    const T vl = val[ql];
+    int u = 0;
+    for (; u + 8 <= nq; u += 8) {
+      T xv[8], vv[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        vv[k] = e_readlane(vl, u + k);
+        xv[k] = xload(e_readlane(jl, u + k));
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) acc += vv[k] * xv[k];
+    }
+    for (; u < nq; ++u) acc += e_readlane(vl, u) * xload(e_readlane(jl, u));
+  }
+  const int64_t o = row * nrhs + c;
+  if (MODE == 0 || MODE == 5) y[o] = acc;
+  else if (MODE == 1) y[o] = b[o] - acc;
+  else if (MODE == 2) y[o] = b[o] + acc;
+  else if (MODE == 3) {
+    xo[o] = d[row] * x[o];
+    y[o] = x[o] - acc;
+  } else {
+    y[o] = x[o] + d[row] * (b[o] - acc);
+  }
+}
+
 // z_out (double) = zb + P e   (prolongation of the conforming correction)
 template <typename T>
 __global__ __launch_bounds__(256) void k_prolong_out(int nrows, int nrhs, const int32_t* __restrict__ ptr,

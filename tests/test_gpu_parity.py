@@ -889,6 +889,29 @@ def test_elem2d_rhs_lanes_match_oracle(monkeypatch, name, form, rule, eta, nr, l
     assert _rel(outs[1], outs[0]) <= 1e-13
 
 
+@pytest.mark.parametrize("name", ["rand2", "hang3"])
+@pytest.mark.parametrize("fp32", [False, True])
+def test_spmm_wavefront_rows_bitwise(monkeypatch, name, fp32):
+    """The several-RHS sparse products with a wavefront per (row, 64 RHS)
+    (indices and values loaded once per row and read back as scalars) give
+    bitwise the same B r and PCG iterates for 128 RHS as a thread per
+    (row, RHS)."""
+    md = MESHES[name]()
+    nr = 128
+    R = _dev(H.gaussian_rhs(H.ndof(md), 47, nrhs=nr).reshape(-1))
+    outs = []
+    for flag in ("1", "0"):
+        monkeypatch.setenv("HPDG_SPMM_THREAD", flag)
+        op = G.Operator(G.Mesh(md), prec_fp32=fp32, max_nrhs=nr, max_block=0)
+        z = torch.empty_like(R)
+        op.apply_B(R, z, nrhs=nr)
+        x = torch.zeros_like(R)
+        infos = op.pcg_solve(R, x, nrhs=nr, rtol=1e-8, maxit=400)
+        outs.append((z, x, [i["iters"] for i in infos]))
+    assert torch.equal(outs[0][0], outs[1][0])
+    assert torch.equal(outs[0][1], outs[1][1]) and outs[0][2] == outs[1][2]
+
+
 @pytest.mark.parametrize("group", ["1", "4", "64"])
 def test_elem2d_rhs_groups_bitwise(monkeypatch, group):
     """The 2D element kernel with groups of right-hand sides per item gives
