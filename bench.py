@@ -32,7 +32,7 @@ HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
 # rocprofv3 FETCH_SIZE and WRITE_SIZE (each scaled by what the counter reads
 # for a 256 MiB copy: 2.0 and 1.0), valid for the kernel source with this
 # digest; reported as null once the source differs
-ELEM2D_TRAFFIC = {"digest": "7d6f39b6fcafb831", "fetch_bytes": 5654528.0, "write_bytes": 1241952.0}
+ELEM2D_TRAFFIC = {"digest": "899127e01a1c8329", "fetch_bytes": 5671936.0, "write_bytes": 1241952.0}
 # the same for the one-RHS 3D operator (its three kernels summed) on the
 # 2,569,985-DOF 3D workload (profiles/random3d_2.57Mdof_hbm_counters.md)
 ELEM3D_TRAFFIC = {"digest": "f9b52b352b322645", "fetch_bytes": 297.05e6, "write_bytes": 142.80e6}
