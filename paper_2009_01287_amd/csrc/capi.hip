@@ -274,8 +274,10 @@ struct hpdg_operator {
   // 2D elements of degree <= c and > c in mesh order, c = 5..8 (index c - 5):
   // the lane-per-right-hand-side kernel and the grouped kernel of the
   // several-RHS apply
-  DevBuf e2r_lo[4], e2r_hi[4];
-  int n_e2r_lo[4] = {0, 0, 0, 0}, n_e2r_hi[4] = {0, 0, 0, 0};
+  // index 4: every element, each XCD's eighth of the mesh order sorted by
+  // decreasing degree (the costly elements start first)
+  DevBuf e2r_lo[5], e2r_hi[5];
+  int n_e2r_lo[5] = {0, 0, 0, 0, 0}, n_e2r_hi[5] = {0, 0, 0, 0, 0};
   // 3D, one RHS: the operator in three passes (k_e3_vol, k_e3_face,
   // k_e3_lift) with the side buffer and the per-record face contributions
   int split3 = 1;
@@ -297,7 +299,8 @@ struct hpdg_operator {
                              // right-hand side (k_elem2d_rhs) for degrees <= 5 when nrhs > 1
   int rhs_group_hi = 4;      // with rhs_group 0: the group size of the degrees above e2r_split
   int e2r_split = 5;         // with rhs_group 0: the highest degree on the lane form (5..8), the
-                             // others grouped; 9: all on the lane form in two launches (<= 5, >= 6)
+                             // others grouped; 9: all on the lane form in two launches (<= 5, >= 6);
+                             // 10: all in one launch, by decreasing degree within each XCD's share
   struct GraphEntry {
     int k, nrhs;
     double* x;
@@ -833,6 +836,9 @@ static void upload_device(hpdg_operator* op, hipStream_t s) {
   op->dbucket.resize(kMaxP + 1);
   for (int p = 1; p <= kMaxP; ++p) op->dbucket[p].upload(op->bucket[p]);
   if (op->dim == 2) {
+    std::vector<int8_t> degh((size_t)op->ne, 0);
+    for (int p = 1; p <= kMaxP; ++p)
+      for (int32_t e : op->bucket[p]) degh[e] = (int8_t)p;
     for (int c = 5; c <= 8; ++c) {
       std::vector<int32_t> lo, hi;
       for (int p = 1; p <= kMaxP; ++p)
@@ -843,6 +849,18 @@ static void upload_device(hpdg_operator* op, hipStream_t s) {
       op->n_e2r_hi[c - 5] = (int)hi.size();
       op->e2r_lo[c - 5].upload(lo);
       op->e2r_hi[c - 5].upload(hi);
+      if (c == 8) {
+        // the XCD-aware order gives XCD x the list positions [x per, (x+1) per)
+        // for 64 RHS (per = ceil(n / 8)), started in list order
+        const int n = (int)lo.size(), per = (n + 7) / 8;
+        std::vector<int32_t> cost = lo;
+        for (int x = 0; x < 8; ++x) {
+          auto b0 = cost.begin() + std::min(n, x * per), b1 = cost.begin() + std::min(n, (x + 1) * per);
+          std::stable_sort(b0, b1, [&](int32_t a, int32_t b) { return degh[a] > degh[b]; });
+        }
+        op->n_e2r_lo[4] = n;
+        op->e2r_lo[4].upload(cost);
+      }
     }
   }
   if (op->no_prec) {
@@ -1096,7 +1114,7 @@ extern "C" hpdg_status hpdg_setup_operator(const hpdg_mesh* mh, const hpdg_opera
     if (const char* v = std::getenv("HPDG_ELEM2D_FCHUNK")) op->fchunk = std::atoi(v) == 8 ? 8 : std::atoi(v) == 32 ? 32 : 16;
     if (const char* v = std::getenv("HPDG_ELEM2D_RHSGROUP")) op->rhs_group = std::max(0, std::atoi(v));
     if (const char* v = std::getenv("HPDG_ELEM2D_RHSGROUP_HI")) op->rhs_group_hi = std::max(1, std::atoi(v));
-    if (const char* v = std::getenv("HPDG_ELEM2D_LANE_DEG")) op->e2r_split = std::min(9, std::max(5, std::atoi(v)));
+    if (const char* v = std::getenv("HPDG_ELEM2D_LANE_DEG")) op->e2r_split = std::min(10, std::max(5, std::atoi(v)));
     if (const char* v = std::getenv("HPDG_NO_MFMA")) op->no_mfma = std::atoi(v) != 0;
     if (const char* v = std::getenv("HPDG_NO_FUSED_MULTI")) op->no_fused_multi = std::atoi(v) != 0;
     if (const char* v = std::getenv("HPDG_ELEM3D_COST_ORDER")) op->use_perm = std::atoi(v) != 0;
@@ -1294,7 +1312,7 @@ static int apply_A_dev(hpdg_operator* op, const double* x, double* y, int nrhs, 
       // wavefront per element and 64 RHS), the others grouped: at high
       // degree a wavefront of the lane form holds many values per lane and
       // runs long, which the last wavefronts of the launch wait for
-      const int split = std::min(9, std::max(5, op->e2r_split));
+      const int split = std::min(10, std::max(5, op->e2r_split));
       const int c = std::min(8, split) - 5;
       const int ng = (nrhs + 63) / 64;
       // the lane kernel over a list: up to degree 5 with two wavefronts per
@@ -1307,6 +1325,10 @@ static int apply_A_dev(hpdg_operator* op, const double* x, double* y, int nrhs, 
                            op->kk.as<double>(), op->sptr.as<int32_t>(), op->recs.as<FaceRec>(),
                            op->ftab.as<double>(), op->tab.as<double>(), op->TL, x, y);
       };
+      if (split == 10) {
+        lanes(op->n_e2r_lo[4], op->e2r_lo[4].as<int32_t>(), false);
+        return 0;
+      }
       if (split == 9) {
         lanes(op->n_e2r_hi[0], op->e2r_hi[0].as<int32_t>(), false);
         lanes(op->n_e2r_lo[0], op->e2r_lo[0].as<int32_t>(), true);
@@ -1709,7 +1731,7 @@ static void tune_rhs_group(hpdg_operator* op, hipStream_t s, int64_t* rep) {
   if (nr > 1 && gg > 0) {
     op->rhs_group = 0;
     op->rhs_group_hi = gg;
-    for (int c = 5; c <= 9; ++c) {
+    for (int c = 5; c <= 10; ++c) {
       op->e2r_split = c;
       const double t = time_it();
       if (t < best) { best = t; bg = 0; bh = gg; bc = c; }

@@ -863,14 +863,15 @@ def test_block_solves_mfma(monkeypatch, name, nr, fp32):
 @pytest.mark.parametrize("name", ["fig1", "hang2", "rand2", "rand2k"])
 @pytest.mark.parametrize("form,rule,eta", [("sipg", 0, 1.0), ("br2", 0, 0.0), ("sipg", 1, 10.0)])
 @pytest.mark.parametrize("nr", [2, 32, 128])
-@pytest.mark.parametrize("lane_deg", ["5", "6", "8", "9"])
+@pytest.mark.parametrize("lane_deg", ["5", "6", "8", "9", "10"])
 def test_elem2d_rhs_lanes_match_oracle(monkeypatch, name, form, rule, eta, nr, lane_deg):
     """The 2D element kernel with a lane per right-hand side (a wavefront per
     element and 64 right-hand sides; 2 and 32 leave most or half of the lanes
     idle, 128 takes two groups) against the oracle's apply column by column,
     and against the kernel with one right-hand side per item. lane_deg: the
     highest degree on the lane form (the others grouped in a second launch;
-    8: all degrees; 9: all, in two launches)."""
+    8: all degrees; 9: all, in two launches; 10: all, by decreasing degree
+    within each XCD's share)."""
     md = MESHES[name]()
     m = O.Mesh(md)
     X = H.gaussian_rhs(m.ndof, 45, nrhs=nr)
