@@ -185,7 +185,7 @@ def main():
     it = infos[0]["iters"]
     lane_form = any(r["matrix"] == "elem_rhs_group" and r["lanes"] == 0 for r in (tuned or []))
     kernel = ("k_elem2d_rhs (a lane per right-hand side, one wavefront per element and 64 RHS, "
-              "volume + all face terms)" + ("" if any(r["matrix"] == "elem_rhs_group" and r["longrow"] == 8
+              "volume + all face terms)" + ("" if any(r["matrix"] == "elem_rhs_group" and r["longrow"] >= 8
                                                       for r in tuned) else " + k_elem2d for the higher degrees")
               if md["dim"] == 2 and nrhs > 1 and lane_form
               else "k_elem2d (volume + all face terms, one launch)" if md["dim"] == 2

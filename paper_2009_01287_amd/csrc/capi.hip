@@ -275,7 +275,7 @@ struct hpdg_operator {
   // the lane-per-right-hand-side kernel and the grouped kernel of the
   // several-RHS apply
   // index 4: every element, each XCD's eighth of the mesh order sorted by
-  // decreasing degree (the costly elements start first)
+  // decreasing estimated cost (the costly elements start first)
   DevBuf e2r_lo[5], e2r_hi[5];
   int n_e2r_lo[5] = {0, 0, 0, 0, 0}, n_e2r_hi[5] = {0, 0, 0, 0, 0};
   // 3D, one RHS: the operator in three passes (k_e3_vol, k_e3_face,
@@ -300,7 +300,7 @@ struct hpdg_operator {
   int rhs_group_hi = 4;      // with rhs_group 0: the group size of the degrees above e2r_split
   int e2r_split = 5;         // with rhs_group 0: the highest degree on the lane form (5..8), the
                              // others grouped; 9: all on the lane form in two launches (<= 5, >= 6);
-                             // 10: all in one launch, by decreasing degree within each XCD's share
+                             // 10: all in one launch, by decreasing cost within each XCD's share
   struct GraphEntry {
     int k, nrhs;
     double* x;
@@ -852,11 +852,16 @@ static void upload_device(hpdg_operator* op, hipStream_t s) {
       if (c == 8) {
         // the XCD-aware order gives XCD x the list positions [x per, (x+1) per)
         // for 64 RHS (per = ceil(n / 8)), started in list order
+        // estimated cost: the volume's 4 n^3 and about 3 n^2 per face record
         const int n = (int)lo.size(), per = (n + 7) / 8;
+        auto est = [&](int32_t e) {
+          const int64_t q = degh[e] + 1, nrec = U.sptr[4 * (size_t)e + 4] - U.sptr[4 * (size_t)e];
+          return 4 * q * q * q + 3 * nrec * q * q;
+        };
         std::vector<int32_t> cost = lo;
         for (int x = 0; x < 8; ++x) {
           auto b0 = cost.begin() + std::min(n, x * per), b1 = cost.begin() + std::min(n, (x + 1) * per);
-          std::stable_sort(b0, b1, [&](int32_t a, int32_t b) { return degh[a] > degh[b]; });
+          std::stable_sort(b0, b1, [&](int32_t a, int32_t b) { return est(a) > est(b); });
         }
         op->n_e2r_lo[4] = n;
         op->e2r_lo[4].upload(cost);
