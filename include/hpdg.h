@@ -178,7 +178,8 @@ hpdg_status hpdg_operator_device_bytes(hpdg_operator* op, int64_t* bytes);
  * 4, 8 or 16 lanes, each lane taking 4-entry chunks) on `stream` and keeps
  * the fastest. Changes the summation order and
  * so the last bits of B r; drops captured graphs. With no_prec only the
- * element kernel is tuned. In 2D it also picks, for the element kernel, the
+ * element kernel is tuned (in 2D its tiles and, for max_nrhs > 1, its
+ * right-hand-side form: kinds 4 and 6). In 2D it also picks, for the element kernel, the
  * elements per workgroup (1 or 2) and the face records staged per pass (8,
  * 16 or 32); the results do not depend on them. report: cap rows of 8 int64
  * (kind 0 A / 1 R / 2 P / 3 P^T / 4 element kernel / 5 fused V-cycle level /

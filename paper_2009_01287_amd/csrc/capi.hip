@@ -1960,6 +1960,13 @@ extern "C" hpdg_status hpdg_operator_tune(hpdg_operator* op, void* stream, int64
       if (op->dim == 2) {
         tune_elem(op, s, r + 2);
         k = 1;
+        if (op->max_nrhs > 1) {
+          int64_t* r2 = cap > 1 ? report + 8 : dummy;
+          r2[0] = 6;
+          r2[1] = 0;
+          tune_rhs_group(op, s, r2 + 2);
+          k = 2;
+        }
       }
     } else {
       k = op->prec32 ? tune_all<float>(op, s, report, cap) : tune_all<double>(op, s, report, cap);
