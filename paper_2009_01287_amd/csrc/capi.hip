@@ -1407,7 +1407,7 @@ static void spmv(const DevCSR& A, int nrhs, const T* x, const T* b, const T* d, 
     // MODE 5: the first nrows columns read x, the others b
     int64_t nt = (int64_t)A.nrows * nrhs;
     if (nrhs % 64 == 0 && !A.spmm_thread)
-      hipLaunchKernelGGL((k_spmm64<T, MODE>), dim3(nblk(nt)), dim3(256), 0, s, A.nrows, nrhs, A.nrows,
+      hipLaunchKernelGGL((k_spmm64<T, MODE, 16>), dim3(nblk(nt)), dim3(256), 0, s, A.nrows, nrhs, A.nrows,
                          A.ptr.as<int32_t>(), A.idx.as<int32_t>(), A.val.as<T>(), x, b, d, xo, y);
     else
       hipLaunchKernelGGL((k_spmm<T, MODE>), dim3(nblk(nt)), dim3(256), 0, s, A.nrows, nrhs, A.nrows,

@@ -2323,9 +2323,9 @@ __device__ __forceinline__ double e_readlane(double v, int l) {
 // k_spmm for nrhs a multiple of 64: one wavefront per (row, 64 RHS). The
 // row's column indices and values are loaded by the lanes, up to 64 at a
 // time, and read back as scalars, so the x loads of the row go out together
-// instead of each waiting for its index; the same terms in the same order
-// (bitwise the same results).
-template <typename T, int MODE>
+// instead of each waiting for its index, G at a time; the same terms in the
+// same order (bitwise the same results).
+template <typename T, int MODE, int G>
 __global__ __launch_bounds__(256) void k_spmm64(int nrows, int nrhs, int nsplit, const int32_t* __restrict__ ptr,
                                                 const int32_t* __restrict__ idx, const T* __restrict__ val,
                                                 const T* __restrict__ x, const T* __restrict__ b,
@@ -2349,15 +2349,15 @@ __global__ __launch_bounds__(256) void k_spmm64(int nrows, int nrhs, int nsplit,
     const int jl = idx[ql];
     const T vl = val[ql];
     int u = 0;
-    for (; u + 8 <= nq; u += 8) {
-      T xv[8], vv[8];
+    for (; u + G <= nq; u += G) {
+      T xv[G], vv[G];
 #pragma unroll
-      for (int k = 0; k < 8; ++k) {
+      for (int k = 0; k < G; ++k) {
         vv[k] = e_readlane(vl, u + k);
         xv[k] = xload(e_readlane(jl, u + k));
       }
 #pragma unroll
-      for (int k = 0; k < 8; ++k) acc += vv[k] * xv[k];
+      for (int k = 0; k < G; ++k) acc += vv[k] * xv[k];
     }
     for (; u < nq; ++u) acc += e_readlane(vl, u) * xload(e_readlane(jl, u));
   }
