@@ -6,11 +6,18 @@
 //                  one workgroup, faces through exact 1D face-mass matrices
 //                  (conforming, mismatched-degree and nonconforming sub-faces
 //                  alike); one item per (element, right-hand side).
+//   k_e3_vol, k_e3_face, k_e3_lift  the 3D operator for one right-hand side
+//                  in three passes (volume and side traces, one face record
+//                  per wavefront, side sums lifted per element).
+//   k_elem2d_rhs   the 2D operator for several right-hand sides with a lane
+//                  per right-hand side (one wavefront per element and 64 RHS).
 //   k_mass<DIM,P>  element mass matrices by degree bucket (the load vector).
 //   k_front        B's point Jacobi, V_e block solves and P^T in one launch.
-//   k_spmv, k_spmm CSR products for P, P^T and the AMG levels, with fused
-//                  smoother / residual / prolongation-add forms and the
-//                  two-vector product of a fused V-cycle level's up-leg.
+//   k_spmv, k_spmm, k_spmm64  CSR products for P, P^T and the AMG levels
+//                  (one RHS; several: a thread per row and RHS, or a
+//                  wavefront per row and 64 RHS), with fused smoother /
+//                  residual / prolongation-add forms and the two-vector
+//                  product of a fused V-cycle level's up-leg.
 //   k_block_mfma, k_block_gemm, k_block_gemv, k_diag_scale  multi-RHS pieces
 //                  of B (V_e block solves on the matrix cores for nrhs a
 //                  multiple of 16).
