@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
 ELEM2D_TRAFFIC = {"digest": "899127e01a1c8329", "fetch_bytes": 5671936.0, "write_bytes": 1241952.0}
 # the same for the one-RHS 3D operator (its three kernels summed) on the
 # 2,569,985-DOF 3D workload (profiles/random3d_2.57Mdof_hbm_counters.md)
-ELEM3D_TRAFFIC = {"digest": "f9b52b352b322645", "fetch_bytes": 297.05e6, "write_bytes": 142.80e6}
+ELEM3D_TRAFFIC = {"digest": "5efda7d6cf2d89f5", "fetch_bytes": 218.09e6, "write_bytes": 141.72e6}
 WORKLOADS = {1: "uniform2d_4x4_p2_sipg_fp64",
              2: "random2d_32x32_q0.3_L3_p1-8_sipg_fp64",
              3: "random3d_16^3_q0.2_L2_p1-6_br2_fp32prec",

@@ -281,6 +281,7 @@ struct hpdg_operator {
   // 3D, one RHS: the operator in three passes (k_e3_vol, k_e3_face,
   // k_e3_lift) with the side buffer and the per-record face contributions
   int split3 = 1;
+  int e3xcd = 1;             // face and lift passes in XCD-aware order (HPDG_E3_FACE_XCD=0: plain)
   int e3stage = 1;           // face pass: 1D face matrices staged in LDS (1) or read through the caches (0)
   DevBuf sboff, faux, sbuf, gbuf;
   int use_perm = 1;          // 3D element kernel dispatched in that order (autotuned)
@@ -1124,6 +1125,7 @@ extern "C" hpdg_status hpdg_setup_operator(const hpdg_mesh* mh, const hpdg_opera
     if (const char* v = std::getenv("HPDG_NO_FUSED_MULTI")) op->no_fused_multi = std::atoi(v) != 0;
     if (const char* v = std::getenv("HPDG_ELEM3D_COST_ORDER")) op->use_perm = std::atoi(v) != 0;
     if (const char* v = std::getenv("HPDG_ELEM3D_SPLIT")) op->split3 = std::atoi(v) != 0;
+    if (const char* v = std::getenv("HPDG_E3_FACE_XCD")) op->e3xcd = std::atoi(v) != 0;
     if (const char* v = std::getenv("HPDG_BLOCK_WG")) op->blk_wg = std::atoi(v) != 0;
     if (const char* v = std::getenv("HPDG_B_FORK")) op->b_fork_env = std::atoi(v) != 0 ? 1 : 0;
     if (const char* v = std::getenv("HPDG_FORK_LEVEL")) op->fork_level = std::max(-1, std::atoi(v));
@@ -1351,22 +1353,25 @@ static int apply_A_dev(hpdg_operator* op, const double* x, double* y, int nrhs, 
     const unsigned grid = 8u * (unsigned)((op->ne + 7) / 8);   // XCD-aware order: a multiple of 8
     const int32_t* perm = op->use_perm ? op->elem_perm.as<int32_t>() : nullptr;
     const int nrec = (int)(op->recs.bytes / sizeof(FaceRec));
+    // face pass: four records per workgroup; XCD-aware order needs a multiple of 8
+    const unsigned fgrid = op->e3xcd ? 8u * (unsigned)(((nrec + 3) / 4 + 7) / 8) : (unsigned)((nrec + 3) / 4);
     if (op->nm3 == 7) {
       hipLaunchKernelGGL(k_e3_vol<7>, dim3(grid), dim3(256), 0, s, op->ne, op->off.as<int64_t>(),
                          op->pdeg.as<int8_t>(), op->hh.as<double>(), op->kk.as<double>(), op->sboff.as<int64_t>(),
                          op->tab.as<double>(), op->TL, x, y, op->sbuf.as<double>(), perm);
-      hipLaunchKernelGGL((op->e3stage ? k_e3_face<7, true> : k_e3_face<7, false>), dim3((nrec + 3) / 4), dim3(256), 0, s, nrec, op->form,
+      hipLaunchKernelGGL((op->e3stage ? k_e3_face<7, true> : k_e3_face<7, false>), dim3(fgrid), dim3(256), 0, s, nrec, op->e3xcd, op->form,
                          op->recs.as<FaceRec>(), op->faux.as<FaceAux>(), op->ftab.as<double>(), op->tab.as<double>(),
                          op->TL, op->sbuf.as<double>(), op->gbuf.as<double>());
     } else {
       hipLaunchKernelGGL(k_e3_vol<9>, dim3(grid), dim3(256), 0, s, op->ne, op->off.as<int64_t>(),
                          op->pdeg.as<int8_t>(), op->hh.as<double>(), op->kk.as<double>(), op->sboff.as<int64_t>(),
                          op->tab.as<double>(), op->TL, x, y, op->sbuf.as<double>(), perm);
-      hipLaunchKernelGGL((op->e3stage ? k_e3_face<9, true> : k_e3_face<9, false>), dim3((nrec + 3) / 4), dim3(256), 0, s, nrec, op->form,
+      hipLaunchKernelGGL((op->e3stage ? k_e3_face<9, true> : k_e3_face<9, false>), dim3(fgrid), dim3(256), 0, s, nrec, op->e3xcd, op->form,
                          op->recs.as<FaceRec>(), op->faux.as<FaceAux>(), op->ftab.as<double>(), op->tab.as<double>(),
                          op->TL, op->sbuf.as<double>(), op->gbuf.as<double>());
     }
-    hipLaunchKernelGGL(k_e3_lift, dim3(op->ne), dim3(256), 0, s, op->ne, op->off.as<int64_t>(),
+    hipLaunchKernelGGL(k_e3_lift, dim3(op->e3xcd ? grid : (unsigned)op->ne), dim3(256), 0, s, op->ne, op->e3xcd,
+                       op->off.as<int64_t>(),
                        op->pdeg.as<int8_t>(), op->hh.as<double>(), op->sptr.as<int32_t>(), op->recs.as<FaceRec>(),
                        op->faux.as<FaceAux>(), op->tab.as<double>(), op->TL, op->gbuf.as<double>(), x, y, pdot);
     return pdot ? op->ne : 0;

@@ -1906,7 +1906,7 @@ __device__ inline void e3f_body(const FaceRec& r, const FaceAux& ax, int form, d
 // one face record per wavefront (four per workgroup, wave-level
 // synchronisation only); NM: largest n of the mesh
 template <int NM, bool STAGE>
-__global__ __launch_bounds__(256) void k_e3_face(int nrec, int form, const FaceRec* __restrict__ recs,
+__global__ __launch_bounds__(256) void k_e3_face(int nrec, int xcd, int form, const FaceRec* __restrict__ recs,
                                                  const FaceAux* __restrict__ aux, const double* __restrict__ ftab,
                                                  const double* __restrict__ tab, TableLayout TL,
                                                  const double* __restrict__ sb, double* __restrict__ gbuf) {
@@ -1916,7 +1916,11 @@ __global__ __launch_bounds__(256) void k_e3_face(int nrec, int form, const FaceR
   __shared__ double sW[4][8][F2];     // 0 Tn -> v, 1 Dn -> vn, 2 U0 -> P0, 3 U1 -> Q0, 4 Y0, 5 Y1, 6 To -> U2, 7 Do -> U3
   __shared__ double sM[STAGE ? 4 : 1][STAGE ? 6 : 1][STAGE ? F2 : 1];    // A0oo A1oo A0on A1on A0nn A1nn
   const int w = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
-  const int rec = blockIdx.x * 4 + w;
+  // xcd: XCD-aware order (grid a multiple of 8): workgroups go round-robin to
+  // the 8 XCDs, so block b takes record group (b % 8) per + b / 8 and each
+  // XCD a contiguous range of records (a piece of the mesh, as in k_e3_vol)
+  const int grp = xcd ? (int)(blockIdx.x & 7) * (int)(gridDim.x >> 3) + (int)(blockIdx.x >> 3) : (int)blockIdx.x;
+  const int rec = grp * 4 + w;
   if (rec >= nrec) return;            // whole wavefronts only: no block-wide barrier below
   {
     constexpr int WR = (int)(sizeof(FaceRec) / 8), WA = (int)(sizeof(FaceAux) / 8);
@@ -2008,7 +2012,7 @@ __device__ inline void e3l_body(double (*S)[81], int* rside, int64_t* rgoff, int
   }
 }
 
-__global__ __launch_bounds__(256) void k_e3_lift(int ne, const int64_t* __restrict__ off,
+__global__ __launch_bounds__(256) void k_e3_lift(int ne, int xcd, const int64_t* __restrict__ off,
                                                  const int8_t* __restrict__ pdeg, const double* __restrict__ hh,
                                                  const int32_t* __restrict__ sptr, const FaceRec* __restrict__ recs,
                                                  const FaceAux* __restrict__ aux, const double* __restrict__ tab,
@@ -2019,7 +2023,9 @@ __global__ __launch_bounds__(256) void k_e3_lift(int ne, const int64_t* __restri
   __shared__ double red[4];
   __shared__ int rside[64];
   __shared__ int64_t rgoff[64];
-  const int e = blockIdx.x;
+  // xcd: XCD-aware order (grid a multiple of 8), each XCD a contiguous range
+  // of elements as in k_e3_vol and the face pass
+  const int e = xcd ? (int)(blockIdx.x & 7) * (int)(gridDim.x >> 3) + (int)(blockIdx.x >> 3) : (int)blockIdx.x;
   if (e >= ne) return;
   switch (pdeg[e]) {
     case 1: e3l_body<2>(S, rside, rgoff, e, off, hh, sptr, recs, aux, tab, TL, gbuf, x, y, pdot, red); break;

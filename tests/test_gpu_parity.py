@@ -913,6 +913,26 @@ def test_spmm_wavefront_rows_bitwise(monkeypatch, name, fp32):
     assert torch.equal(outs[0][1], outs[1][1]) and outs[0][2] == outs[1][2]
 
 
+@pytest.mark.parametrize("name", ["hang3", "rand3", "rand3hp"])
+def test_3d_face_pass_xcd_order_bitwise(monkeypatch, name):
+    """The one-RHS 3D apply with the face and lift passes in XCD-aware order
+    (each XCD a contiguous range of records and elements) gives bitwise the
+    same y = A x and PCG iterates as in plain order."""
+    md = MESHES[name]()
+    x = _dev(np.random.default_rng(48).standard_normal(H.ndof(md)))
+    outs = []
+    for flag in ("0", "1"):
+        monkeypatch.setenv("HPDG_E3_FACE_XCD", flag)
+        op = G.Operator(G.Mesh(md), form="br2", eta=0.0, max_block=128)
+        y = torch.empty_like(x)
+        op.apply_A(x, y)
+        u = torch.zeros_like(x)
+        info = op.pcg_solve(x, u, rtol=1e-8, maxit=500)[0]
+        outs.append((y, u, info["iters"]))
+    assert torch.equal(outs[0][0], outs[1][0])
+    assert torch.equal(outs[0][1], outs[1][1]) and outs[0][2] == outs[1][2]
+
+
 @pytest.mark.parametrize("group", ["1", "4", "64"])
 def test_elem2d_rhs_groups_bitwise(monkeypatch, group):
     """The 2D element kernel with groups of right-hand sides per item gives
