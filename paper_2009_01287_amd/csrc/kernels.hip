@@ -435,9 +435,9 @@ __global__ __launch_bounds__(64 * EPB) void k_elem2d(int ne, const int32_t* __re
 // code path taken, so the lane's values stay in registers. The 1D tables of
 // the element and the matrices of each face are wave-uniform: they are copied
 // into the wavefront's LDS with one batch of vector loads and read from there
-// as broadcasts (scalar loads of them would each wait on a cache miss in
-// turn); x is read and y written in rows of 64 consecutive values (x and y
-// interleave the right-hand sides).
+// as broadcasts (LDS reads complete in order, so several stay in flight;
+// scalar loads are waited for all at once); x is read and y written in rows
+// of 64 consecutive values (x and y interleave the right-hand sides).
 
 // LDS of one wavefront (doubles): the element's M, K, Minv and l_i'(0),
 // l_i'(1), then the current face's A_oo, A_on, A_nn, the neighbour's Minv and
