@@ -186,8 +186,9 @@ hpdg_status hpdg_operator_device_bytes(hpdg_operator* op, int64_t* bytes);
  * 6 right-hand sides per element-kernel item, at the largest nrhs (chosen
  * lanes 0: a lane per right-hand side, one wavefront per element and 64
  * RHS, for the degrees up to the threshold column's, the others grouped;
- * 9 there: every degree on the lane form in two launches; the threshold
- * column holds nrhs otherwise) /
+ * 9 there: every degree on the lane form in two launches; 10: every degree
+ * in one launch, elements by decreasing cost within each XCD's share; the
+ * threshold column holds nrhs otherwise) /
  * 7 lanes per V_e block row for the one-RHS block solves (the threshold
  * column holds 1 when they run as a workgroup per block with the block's r
  * staged in LDS, 0 when their rows run inside the B front) / 8 dense tail of the
